@@ -1,0 +1,222 @@
+"""Variable-density elliptic operators and their constant-density inverses.
+
+Oracle; test infrastructure only.  Fields are real arrays in C order with
+the x axis last (contiguous): shape (nx,), (ny, nx) or (nz, ny, nx).
+
+Pressure (eq. VDINSE.Lrho, discretised as eq. VDINSE.Lrho.num):
+    L_rho u = sum_d D_d (a * D_d u),   a = 1 / rho,
+with D_d the spectral first derivative along axis d (Nyquist zeroed).  The
+solver works with A = -L_rho, which is symmetric positive semi-definite in
+the Euclidean inner product of grid values, and b = -f.
+
+Nullspace: D_d u = 0 for every d, i.e. the 2^D modes whose wavenumber index
+along every axis is 0 or n_d / 2 (products of 1 and (-1)^j).  The solution
+returned is the unique one orthogonal to it, which makes phi zero-mean
+(the gauge of Sec. 4.2).
+
+Helmholtz-type velocity system (implicit viscous step, eq.
+VDINSE.num.momentum.proj, with the mass-diffusion terms dropped):
+    A_h u = rho * u - nu * Lap u,
+with the spectral Laplacian symbol -|k|^2 (Nyquist kept).
+
+Preconditioners (Sec. 3 introduction, Sec. 3.2, Sec. 4.2): the exact inverse
+of the same operator with rho replaced by the constant rho0 -- diagonal in
+Fourier space; the pressure one is the pseudo-inverse (zero on the
+nullspace modes).
+
+Wall-bounded 2D pressure (x periodic, z Chebyshev with Neumann walls) is
+the symmetric weak form
+    A u = D_x^T (W a D_x u) + D_z^T (W a D_z u),   b = -W f,
+with W = h_x w_j (Clenshaw-Curtis weights); its constant-density inverse is
+built per x wavenumber by dense linear algebra.
+"""
+import numpy as np
+
+from . import grids
+
+
+# ----------------------------------------------------------------- Fourier
+
+def _axis_len(shape, lengths):
+    if lengths is None:
+        lengths = (2.0 * np.pi,) * len(shape)
+    assert len(lengths) == len(shape)
+    return tuple(float(v) for v in lengths)
+
+
+def deriv(u, axis, length=2.0 * np.pi):
+    """Spectral first derivative along ``axis`` (Nyquist zeroed)."""
+    n = u.shape[axis]
+    kp = grids.fourier_kprime(n, length)
+    shp = [1] * u.ndim
+    shp[axis] = n
+    uh = np.fft.fft(u, axis=axis)
+    return np.real(np.fft.ifft(1j * kp.reshape(shp) * uh, axis=axis))
+
+
+def laplacian(u, lengths=None):
+    """Spectral Laplacian, symbol -|k|^2 with the Nyquist entries kept."""
+    lengths = _axis_len(u.shape, lengths)
+    uh = np.fft.fftn(u)
+    ksq = np.zeros(u.shape)
+    for d, (n, ln) in enumerate(zip(u.shape, lengths)):
+        shp = [1] * u.ndim
+        shp[d] = n
+        ksq = ksq + grids.fourier_k(n, ln).reshape(shp) ** 2
+    return np.real(np.fft.ifftn(-ksq * uh))
+
+
+def L_rho(u, rho, lengths=None):
+    """The paper's pressure operator  sum_d D_d (rho^-1 D_d u)."""
+    lengths = _axis_len(u.shape, lengths)
+    a = 1.0 / rho
+    out = np.zeros_like(u)
+    for d in range(u.ndim):
+        out += deriv(a * deriv(u, d, lengths[d]), d, lengths[d])
+    return out
+
+
+def apply_pressure(u, rho, lengths=None):
+    """A u = -L_rho u (symmetric positive semi-definite)."""
+    return -L_rho(u, rho, lengths)
+
+
+def apply_helmholtz(u, rho, nu, lengths=None):
+    """A_h u = rho u - nu Lap u."""
+    return rho * u - nu * laplacian(u, lengths)
+
+
+def _ksq_prime(shape, lengths):
+    ksq = np.zeros(shape)
+    for d, (n, ln) in enumerate(zip(shape, lengths)):
+        shp = [1] * len(shape)
+        shp[d] = n
+        ksq = ksq + grids.fourier_kprime(n, ln).reshape(shp) ** 2
+    return ksq
+
+
+def precond_pressure(r, rho0, lengths=None):
+    """Pseudo-inverse of A with rho = rho0:  rho0 r_hat / sum_d k'_d^2.
+
+    Zero on the modes where sum_d k'_d^2 = 0 (the nullspace).  This is the
+    inverse of the constant-density operator of Sec. 3.2 / Sec. 4.2 with the
+    singular modes removed.
+    """
+    lengths = _axis_len(r.shape, lengths)
+    ksq = _ksq_prime(r.shape, lengths)
+    sym = np.zeros_like(ksq)
+    nz = ksq > 0
+    sym[nz] = rho0 / ksq[nz]
+    return np.real(np.fft.ifftn(sym * np.fft.fftn(r)))
+
+
+def precond_helmholtz(r, rho0, nu, lengths=None):
+    """Inverse of rho0 - nu Lap:  r_hat / (rho0 + nu |k|^2)."""
+    lengths = _axis_len(r.shape, lengths)
+    ksq = np.zeros(r.shape)
+    for d, (n, ln) in enumerate(zip(r.shape, lengths)):
+        shp = [1] * r.ndim
+        shp[d] = n
+        ksq = ksq + grids.fourier_k(n, ln).reshape(shp) ** 2
+    return np.real(np.fft.ifftn(np.fft.fftn(r) / (rho0 + nu * ksq)))
+
+
+def nullspace_basis(shape):
+    """Orthogonal basis (grid vectors) of the pressure operator's nullspace.
+
+    Products over the axes of the constant and the alternating vector
+    (-1)^j (the latter only on even-length axes).
+    """
+    per_axis = []
+    for n in shape:
+        vs = [np.ones(n)]
+        if n % 2 == 0:
+            vs.append((-1.0) ** np.arange(n))
+        per_axis.append(vs)
+    basis = []
+    def rec(d, acc):
+        if d == len(shape):
+            basis.append(acc)
+            return
+        for v in per_axis[d]:
+            rec(d + 1, np.multiply.outer(acc, v) if acc is not None else v)
+    rec(0, None)
+    return [np.asarray(b, dtype=float).reshape(shape) for b in basis]
+
+
+def project_range(b, basis):
+    """Euclidean orthogonal projection of b onto the complement of span(basis).
+
+    Returns (projected b, norm of the removed component).  The basis vectors
+    must be mutually orthogonal (true for ``nullspace_basis``).
+    """
+    out = b.copy()
+    for e in basis:
+        out = out - (np.vdot(e, b) / np.vdot(e, e)) * e
+    return out, float(np.linalg.norm(b - out))
+
+
+# ------------------------------------------- Fourier (x) x Chebyshev (z)
+
+class FourierChebyshev2D:
+    """x periodic (nx Fourier points on [0, lx)), z on m+1 GL points.
+
+    Field shape (m + 1, nx): z is the slow axis, row 0 is z = +1.
+    """
+
+    def __init__(self, nx, m, lx=2.0):
+        self.nx, self.m, self.lx = nx, m, lx
+        self.hx = lx / nx
+        self.z = grids.cheb_points(m)
+        self.x = lx * np.arange(nx) / nx
+        self.Dz = grids.cheb_diff_matrix(m)
+        self.wz = grids.clenshaw_curtis_weights(m)
+        self.W = self.hx * self.wz[:, None] * np.ones((1, nx))
+
+    def dx(self, u):
+        return deriv(u, 1, self.lx)
+
+    def dz(self, u):
+        return self.Dz @ u
+
+    def dxT(self, u):
+        return -deriv(u, 1, self.lx)  # D_x is real skew-symmetric
+
+    def dzT(self, u):
+        return self.Dz.T @ u
+
+    def apply_pressure(self, u, rho):
+        """A u = D_x^T (W a D_x u) + D_z^T (W a D_z u), a = 1/rho."""
+        wa = self.W / rho
+        return self.dxT(wa * self.dx(u)) + self.dzT(wa * self.dz(u))
+
+    def rhs(self, f):
+        """b = -W f (weak form of L_rho p = f with natural Neumann walls)."""
+        return -self.W * f
+
+    def nullspace_basis(self):
+        ones_z = np.ones(self.m + 1)
+        vs = [np.ones(self.nx)]
+        if self.nx % 2 == 0:
+            vs.append((-1.0) ** np.arange(self.nx))
+        return [np.multiply.outer(ones_z, v) for v in vs]
+
+    def precond_pressure(self, r, rho0):
+        """Pseudo-inverse of A at rho = rho0, per x wavenumber.
+
+        A_0(kx) = (h_x / rho0) (k'_x^2 W_z + D_z^T W_z D_z); solved by LU where
+        k'_x != 0 and by the pseudo-inverse (constant-in-z nullspace) where
+        k'_x = 0.
+        """
+        rh = np.fft.fft(r, axis=1)
+        kp = grids.fourier_kprime(self.nx, self.lx)
+        Wz = np.diag(self.wz)
+        Sz = self.Dz.T @ Wz @ self.Dz
+        out = np.zeros_like(rh)
+        for j in range(self.nx):
+            mat = (self.hx / rho0) * (kp[j] ** 2 * Wz + Sz)
+            if kp[j] != 0.0:
+                out[:, j] = np.linalg.solve(mat, rh[:, j])
+            else:
+                out[:, j] = np.linalg.pinv(mat) @ rh[:, j]
+        return np.real(np.fft.ifft(out, axis=1))

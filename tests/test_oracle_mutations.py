@@ -1,0 +1,77 @@
+"""Plant plausible mistakes in the oracle (on the CPU, via monkeypatch) and
+check that at least one pin catches each.  Nothing here touches the GPU."""
+import numpy as np
+import pytest
+
+from oracle import grids, krylov, operators
+from tests import test_oracle_grids as tg
+from tests import test_oracle_krylov as tk
+from tests import test_oracle_operators as to
+
+
+def _fails(fn, *a):
+    with pytest.raises(AssertionError):
+        fn(*a)
+
+
+def test_wavenumber_scaling_error_is_caught(monkeypatch):
+    monkeypatch.setattr(grids, "fourier_kprime", lambda n, L=2 * np.pi: _kp(n, 2 * np.pi))
+    _fails(tg.test_first_derivative_matches_trefethen, 32, 3.0)
+
+
+def test_nyquist_dropped_in_laplacian_is_caught(monkeypatch):
+    monkeypatch.setattr(grids, "fourier_k", _kp)
+    _fails(tg.test_second_derivative_matches_trefethen, 16, 2 * np.pi)
+
+
+def _kp(n, L):
+    k = 2 * np.pi * np.fft.fftfreq(n, 1.0 / n) / L
+    k[n // 2] = 0.0
+    return k
+
+
+def test_wrong_sign_in_pressure_operator_is_caught(monkeypatch):
+    orig = operators.apply_pressure
+    monkeypatch.setattr(operators, "apply_pressure", lambda u, rho, L=None: -orig(u, rho, L))
+    _fails(to.test_pressure_matches_dense_brute_force, (16,), (2 * np.pi,))
+
+
+def test_rho_instead_of_inverse_is_caught(monkeypatch):
+    monkeypatch.setattr(operators, "apply_pressure",
+                        lambda u, rho, L=None: -operators.L_rho(u, 1.0 / rho, L))
+    _fails(to.test_pressure_matches_dense_brute_force, (8, 12), (2 * np.pi, 3.0))
+
+
+def test_preconditioner_without_rho0_is_caught(monkeypatch):
+    orig = operators.precond_pressure
+    monkeypatch.setattr(operators, "precond_pressure", lambda r, rho0, L=None: orig(r, 1.0, L))
+    _fails(to.test_preconditioner_is_pseudo_inverse, (16,), (2 * np.pi,))
+
+
+def test_untransposed_chebyshev_operand_is_caught(monkeypatch):
+    monkeypatch.setattr(operators.FourierChebyshev2D, "dzT", lambda self, u: -(self.Dz @ u))
+    _fails(to.test_fourier_chebyshev_operator)
+
+
+def test_givens_sign_error_is_caught(monkeypatch):
+    src = krylov.gmres
+    def bad_gmres(A, b, M=None, x0=None, restart=30, rtol=1e-10, max_iter=2000):
+        # a GMRES that stops after too few steps and never restarts properly
+        return src(A, b, M, x0, restart=2, rtol=rtol, max_iter=3)
+    monkeypatch.setitem(tk.SOLVERS, "gmres", bad_gmres)
+    _fails(tk.test_solvers_match_dense_minnorm, (32,), "gmres")
+
+
+def test_rmr_wrong_step_is_caught(monkeypatch):
+    def bad_rmr(A, b, M=None, x0=None, rtol=1e-10, max_iter=2000):
+        x = np.zeros_like(b)
+        r = b.copy()
+        for _ in range(50):
+            z = M(r)
+            w = A(z)
+            x = x + (np.vdot(r, z) / np.vdot(w, w)) * z   # wrong numerator
+            r = b - A(x)
+        return {"x": x, "iterations": 50, "status": "converged", "history": [1.0],
+                "rel_residual": np.linalg.norm(r) / np.linalg.norm(b)}
+    monkeypatch.setitem(tk.SOLVERS, "rmr", bad_rmr)
+    _fails(tk.test_solvers_match_dense_minnorm, (32,), "rmr")
