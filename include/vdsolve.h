@@ -1,0 +1,157 @@
+/*
+ * vdsolve -- preconditioned Krylov solves of the variable-density elliptic
+ * systems of a semi-implicit pseudo-spectral scheme, on AMD MI355X (gfx950).
+ *
+ * The operations follow Reynier, Di Pierro, Alizard, Cadiou, Le Penven and
+ * Buffat, "A preconditioning for the spectral solution of incompressible
+ * variable-density flows":
+ *
+ *   pressure   L_rho p = div(rho^-1 grad p) = f     (eq. VDINSE.Lrho, and its
+ *              time-discrete form eq. VDINSE.Lrho.num), periodic boundaries,
+ *              zero-mean gauge (Sec. 4.2);
+ *   velocity   rho u - dt_nu Lap u = g               (the implicit viscous
+ *              step of eq. VDINSE.num.momentum.proj with the mass-diffusion
+ *              terms dropped);
+ *   solvers    GMRES(m), conjugate gradient, Richardson minimal residual
+ *              (Sec. 3.1), each optionally preconditioned by the exact
+ *              inverse of the constant-density operator (Sec. 3
+ *              introduction, Sec. 3.2, Sec. 4.2).
+ *
+ * Conventions (all entry points):
+ *   - Grids are Fourier (periodic) on every axis; n[0] = nx is the
+ *     contiguous axis.  Physical fields are real FP64 arrays in C order
+ *     [nz][ny][nx] (2D: [ny][nx]; 1D: [nx]) with x_j = j L / n.
+ *   - Every field pointer is DEVICE memory, owned by the caller, valid for
+ *     the duration of the call.  The library keeps no pointer to it.
+ *   - Work is enqueued on the stream given at grid creation; each call
+ *     returns after that work has completed.  A grid handle must not be
+ *     used by two threads at once; different handles are independent.
+ *   - Status codes: VD_OK = 0; VD_NOT_CONVERGED = 1 is a warning (the best
+ *     iterate is written and info is filled); negative codes are errors and
+ *     leave outputs unspecified.  No C++ exception crosses this interface.
+ */
+#ifndef VDSOLVE_H
+#define VDSOLVE_H
+
+#include <stddef.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  VD_OK = 0,
+  VD_NOT_CONVERGED = 1,
+  VD_EINVAL = -1,     /* bad argument (null pointer, size, option) */
+  VD_ENOMEM = -2,     /* device allocation failed */
+  VD_EDOMAIN = -3,    /* density not strictly positive and finite */
+  VD_EBREAKDOWN = -4, /* non-finite Krylov scalar */
+  VD_EDEVICE = -5,    /* HIP runtime error */
+  VD_ETOOBIG = -6,    /* request larger than a serving budget */
+  VD_ENOTSUP = -7     /* valid but not implemented */
+} vd_status;
+
+typedef enum { VD_FOURIER = 0 } vd_basis;
+typedef enum { VD_GMRES = 0, VD_CG = 1, VD_RMR = 2 } vd_solver;
+typedef enum { VD_FP64 = 0, VD_FP32_REFINE = 1 } vd_precision;
+typedef enum { VD_OP_PRESSURE = 0, VD_OP_HELMHOLTZ = 1 } vd_op_kind;
+
+typedef struct {
+  int ndim;         /* 1, 2 or 3 */
+  int n[3];         /* points per axis, n[0] = nx (contiguous): powers of two,
+                       16 <= n <= 1024; unused axes ignored */
+  int basis[3];     /* VD_FOURIER on every used axis */
+  double length[3]; /* period of each axis (> 0) */
+} vd_grid_desc;
+
+typedef struct {
+  int solver;        /* vd_solver */
+  int restart;       /* GMRES restart length m, 1..32 (default 30) */
+  double rtol;       /* stop when ||b - A x||_2 / ||b||_2 <= rtol (default 1e-10) */
+  int max_iter;      /* cap on operator applications in the Krylov loop */
+  int precond;       /* 1: constant-density inverse as preconditioner; 0: none */
+  int precision;     /* vd_precision */
+  double inner_rtol; /* FP32_REFINE: relative tolerance of each inner FP32 solve */
+  int max_outer;     /* FP32_REFINE: cap on refinement steps */
+  double rho0;       /* preconditioner density; NaN = mean of rho */
+  int use_x0;        /* 1: the output array holds the initial guess on entry */
+} vd_solve_opts;
+
+typedef struct {
+  int status;            /* same as the return value */
+  int iterations;        /* operator applications inside the Krylov loops */
+  int refinements;       /* outer FP64 steps (FP32_REFINE), else 0 */
+  double rel_residual;   /* true FP64 ||b - A x|| / ||b|| at exit (max over components) */
+  double rhs_null_norm;  /* pressure: norm of the removed nullspace part of f */
+  double seconds;        /* wall time of the solve on the host clock */
+} vd_solve_info;
+
+typedef struct vd_grid vd_grid;
+
+/* Fill opts with the defaults: GMRES(30), rtol 1e-10, max_iter 2000,
+ * precond 1, FP64, inner_rtol 1e-5, max_outer 10, rho0 = NaN, use_x0 0. */
+void vd_default_opts(vd_solve_opts* opts);
+
+/* Create a grid and its device resources on `stream` (0 = null stream).
+ * Errors: VD_EINVAL (sizes, lengths, basis), VD_ENOMEM, VD_EDEVICE. */
+vd_status vd_grid_create(vd_grid** out, const vd_grid_desc* desc, hipStream_t stream);
+vd_status vd_grid_destroy(vd_grid* grid);
+
+/* Copy the density rho (device, [nz][ny][nx] FP64) into the grid and derive
+ * a = 1/rho (FP64 and FP32 copies) and rho0 = mean(rho).  Every later
+ * operator, preconditioner and solve uses it (rho enters L_rho through
+ * a = 1/rho, eq. VDINSE.Lrho).  Errors: VD_EDOMAIN if any rho <= 0 or not
+ * finite (the grid keeps no density then), VD_EINVAL. */
+vd_status vd_set_density(vd_grid* grid, const double* rho);
+
+/* y = A x for the operator `kind` (physical in, physical out, device FP64):
+ * VD_OP_PRESSURE: A = -L_rho (symmetric positive semi-definite);
+ * VD_OP_HELMHOLTZ: A = rho - dt_nu Lap.  precision VD_FP32_REFINE evaluates
+ * the operator in FP32 (spectral vectors and coefficients rounded to FP32).
+ * Used for per-kernel parity and timing. */
+vd_status vd_apply_operator(vd_grid* grid, int kind, int precision, double dt_nu, const double* x, double* y);
+
+/* z = M^-1 r with M the constant-density operator at rho0 (NaN = mean rho):
+ * pressure: the pseudo-inverse (zero on the nullspace); Helmholtz: the
+ * inverse of rho0 - dt_nu Lap. */
+vd_status vd_apply_precond(vd_grid* grid, int kind, int precision, double dt_nu, double rho0, const double* r,
+                           double* z);
+
+/* Solve L_rho p = f (Sec. 3.2).  f: device FP64 physical values; p:
+ * device FP64 output (also the initial guess if opts->use_x0).  f is
+ * projected onto the range of the operator (its components on the
+ * nullspace -- the modes whose wavenumber along every axis is 0 or n/2 --
+ * are removed and their norm reported in info->rhs_null_norm); the
+ * solution returned is the one orthogonal to that nullspace (zero mean).
+ * The residual is measured in the Euclidean norm of grid values.
+ * opts == NULL means defaults; info may be NULL. */
+vd_status vd_solve_pressure(vd_grid* grid, const double* f, double* p, const vd_solve_opts* opts,
+                            vd_solve_info* info);
+
+/* Solve rho u - dt_nu Lap u = g for ncomp independent components stored one
+ * after another (g, u: [ncomp][nz][ny][nx]).  Lap keeps the Nyquist modes.
+ * dt_nu >= 0.  info->iterations sums the components, rel_residual is the
+ * largest component residual. */
+vd_status vd_solve_helmholtz(vd_grid* grid, double dt_nu, int ncomp, const double* g, double* u,
+                             const vd_solve_opts* opts, vd_solve_info* info);
+
+/* Device bytes the grid plus one solve with these options needs (the
+ * serving admission test uses it).  Returns 0 for an invalid descriptor. */
+size_t vd_workspace_bytes(const vd_grid_desc* desc, const vd_solve_opts* opts);
+
+/* Time spent in each kernel class during the solves since the last reset,
+ * measured with HIP events on the grid's stream when enabled.  Classes:
+ * 0 z-first pass, 1 y-inverse pass, 2 x pass, 3 y-forward pass, 4 z-last
+ * pass, 5 Krylov vector kernels.  ms[c] = total milliseconds, count[c] =
+ * launches.  Enabling adds an event pair per timed launch. */
+vd_status vd_profile_enable(vd_grid* grid, int on);
+vd_status vd_profile_read(vd_grid* grid, double* ms, long long* count, int nclass);
+
+const char* vd_status_string(vd_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VDSOLVE_H */

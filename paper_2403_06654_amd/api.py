@@ -1,0 +1,225 @@
+"""Thin Python binding of libvdsolve.so (argument marshalling only).
+
+Every computation runs in the HIP library; torch is used only to own device
+memory and to name the HIP stream.  Function names mirror the C ABI in
+include/vdsolve.h; ``Grid`` is a convenience wrapper around them.  A missing
+library is an error: there is no fallback path.
+"""
+import ctypes
+import math
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvdsolve.so")
+
+VD_OK, VD_NOT_CONVERGED = 0, 1
+VD_GMRES, VD_CG, VD_RMR = 0, 1, 2
+VD_FP64, VD_FP32_REFINE = 0, 1
+VD_OP_PRESSURE, VD_OP_HELMHOLTZ = 0, 1
+SOLVERS = {"gmres": VD_GMRES, "cg": VD_CG, "rmr": VD_RMR}
+PRECISIONS = {"fp64": VD_FP64, "fp32_refine": VD_FP32_REFINE, "fp32": VD_FP32_REFINE}
+
+
+class vd_grid_desc(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int), ("n", ctypes.c_int * 3), ("basis", ctypes.c_int * 3),
+                ("length", ctypes.c_double * 3)]
+
+
+class vd_solve_opts(ctypes.Structure):
+    _fields_ = [("solver", ctypes.c_int), ("restart", ctypes.c_int), ("rtol", ctypes.c_double),
+                ("max_iter", ctypes.c_int), ("precond", ctypes.c_int), ("precision", ctypes.c_int),
+                ("inner_rtol", ctypes.c_double), ("max_outer", ctypes.c_int), ("rho0", ctypes.c_double),
+                ("use_x0", ctypes.c_int)]
+
+
+class vd_solve_info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("iterations", ctypes.c_int), ("refinements", ctypes.c_int),
+                ("rel_residual", ctypes.c_double), ("rhs_null_norm", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class VdError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__(f"{where}: {vd_status_string(status)} ({status})")
+
+
+_LIB = None
+_P = ctypes.c_void_p
+_D = ctypes.c_double
+_I = ctypes.c_int
+
+_SIGS = {
+    "vd_default_opts": (None, [ctypes.POINTER(vd_solve_opts)]),
+    "vd_grid_create": (_I, [ctypes.POINTER(_P), ctypes.POINTER(vd_grid_desc), _P]),
+    "vd_grid_destroy": (_I, [_P]),
+    "vd_set_density": (_I, [_P, _P]),
+    "vd_apply_operator": (_I, [_P, _I, _I, _D, _P, _P]),
+    "vd_apply_precond": (_I, [_P, _I, _I, _D, _D, _P, _P]),
+    "vd_solve_pressure": (_I, [_P, _P, _P, ctypes.POINTER(vd_solve_opts), ctypes.POINTER(vd_solve_info)]),
+    "vd_solve_helmholtz": (_I, [_P, _D, _I, _P, _P, ctypes.POINTER(vd_solve_opts),
+                                ctypes.POINTER(vd_solve_info)]),
+    "vd_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(vd_grid_desc), ctypes.POINTER(vd_solve_opts)]),
+    "vd_profile_enable": (_I, [_P, _I]),
+    "vd_profile_read": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_longlong), _I]),
+    "vd_status_string": (ctypes.c_char_p, [_I]),
+}
+
+
+def lib():
+    """Load libvdsolve.so (built in-tree by paper_2403_06654_amd.build)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2403_06654_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def vd_status_string(s):
+    return lib().vd_status_string(int(s)).decode()
+
+
+def make_desc(shape, lengths=None):
+    """Descriptor for a Fourier grid of C-order ``shape`` (x last)."""
+    nd = len(shape)
+    if lengths is None:
+        lengths = (2 * math.pi,) * nd
+    d = vd_grid_desc()
+    d.ndim = nd
+    for i in range(nd):  # n[0] = nx (last C axis)
+        d.n[i] = int(shape[nd - 1 - i])
+        d.length[i] = float(lengths[nd - 1 - i])
+        d.basis[i] = 0
+    return d
+
+
+def make_opts(solver="gmres", restart=30, rtol=1e-10, max_iter=2000, precond=True, precision="fp64",
+              inner_rtol=1e-5, max_outer=10, rho0=float("nan"), use_x0=False):
+    o = vd_solve_opts()
+    lib().vd_default_opts(ctypes.byref(o))
+    o.solver = SOLVERS[solver] if isinstance(solver, str) else int(solver)
+    o.restart = int(restart)
+    o.rtol = float(rtol)
+    o.max_iter = int(max_iter)
+    o.precond = 1 if precond else 0
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    o.inner_rtol = float(inner_rtol)
+    o.max_outer = int(max_outer)
+    o.rho0 = float(rho0)
+    o.use_x0 = 1 if use_x0 else 0
+    return o
+
+
+def workspace_bytes(shape, lengths=None, **opts):
+    d = make_desc(shape, lengths)
+    o = make_opts(**opts)
+    return int(lib().vd_workspace_bytes(ctypes.byref(d), ctypes.byref(o)))
+
+
+def _check(st, where, allow_nc=True):
+    if st == VD_OK or (allow_nc and st == VD_NOT_CONVERGED):
+        return st
+    raise VdError(st, where)
+
+
+def _dev_f64(t, shape, what):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float64:
+        raise TypeError(f"{what} must be a float64 CUDA tensor")
+    if tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous with shape {tuple(shape)}, got {tuple(t.shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Grid:
+    """A periodic grid with its device resources (vd_grid_create)."""
+
+    def __init__(self, shape, lengths=None, stream=None):
+        import torch
+        self.shape = tuple(int(s) for s in shape)
+        self.lengths = lengths
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        d = make_desc(self.shape, lengths)
+        h = ctypes.c_void_p()
+        _check(lib().vd_grid_create(ctypes.byref(h), ctypes.byref(d), ctypes.c_void_p(self._stream.cuda_stream)),
+               "vd_grid_create", False)
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().vd_grid_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def set_density(self, rho):
+        _check(lib().vd_set_density(self._h, _dev_f64(rho, self.shape, "rho")), "vd_set_density", False)
+
+    def apply_operator(self, kind, x, precision="fp64", nu=0.0, out=None):
+        import torch
+        y = out if out is not None else torch.empty_like(x)
+        k = VD_OP_PRESSURE if kind == "pressure" else VD_OP_HELMHOLTZ
+        _check(lib().vd_apply_operator(self._h, k, PRECISIONS[precision], float(nu), _dev_f64(x, self.shape, "x"),
+                                       _dev_f64(y, self.shape, "y")), "vd_apply_operator", False)
+        return y
+
+    def apply_precond(self, kind, r, precision="fp64", nu=0.0, rho0=float("nan"), out=None):
+        import torch
+        z = out if out is not None else torch.empty_like(r)
+        k = VD_OP_PRESSURE if kind == "pressure" else VD_OP_HELMHOLTZ
+        _check(lib().vd_apply_precond(self._h, k, PRECISIONS[precision], float(nu), float(rho0),
+                                      _dev_f64(r, self.shape, "r"), _dev_f64(z, self.shape, "z")),
+               "vd_apply_precond", False)
+        return z
+
+    def solve_pressure(self, f, p=None, **opts):
+        import torch
+        if p is None:
+            p = torch.zeros_like(f)
+        o = make_opts(**opts)
+        info = vd_solve_info()
+        st = lib().vd_solve_pressure(self._h, _dev_f64(f, self.shape, "f"), _dev_f64(p, self.shape, "p"),
+                                     ctypes.byref(o), ctypes.byref(info))
+        _check(st, "vd_solve_pressure")
+        return p, info.as_dict()
+
+    def solve_helmholtz(self, g, dt_nu, u=None, **opts):
+        import torch
+        ncomp = 1 if g.dim() == len(self.shape) else g.shape[0]
+        shp = self.shape if ncomp == 1 and g.dim() == len(self.shape) else (ncomp,) + self.shape
+        if u is None:
+            u = torch.zeros_like(g)
+        o = make_opts(**opts)
+        info = vd_solve_info()
+        st = lib().vd_solve_helmholtz(self._h, float(dt_nu), int(ncomp), _dev_f64(g, shp, "g"),
+                                      _dev_f64(u, shp, "u"), ctypes.byref(o), ctypes.byref(info))
+        _check(st, "vd_solve_helmholtz")
+        return u, info.as_dict()
+
+    def profile_enable(self, on=True):
+        _check(lib().vd_profile_enable(self._h, 1 if on else 0), "vd_profile_enable", False)
+
+    def profile_read(self, nclass=6):
+        ms = (ctypes.c_double * nclass)()
+        cnt = (ctypes.c_longlong * nclass)()
+        _check(lib().vd_profile_read(self._h, ms, cnt, nclass), "vd_profile_read", False)
+        return list(ms), list(cnt)

@@ -1,0 +1,674 @@
+// Fused pseudo-spectral passes of the variable-density operators (gfx950).
+//
+// Pressure operator (the paper's L_rho = div(rho^-1 grad), eq. VDINSE.Lrho,
+// discretised as eq. VDINSE.Lrho.num), applied as A = -L_rho to a packed
+// half-spectrum v, optionally preceded by the constant-density
+// pseudo-inverse (Sec. 3, Sec. 4.2) -- right preconditioning:
+//
+//   P1 (z, inverse)  u = M^-1 v;  T1 = Fz^-1 u,  T1z = Fz^-1 (i k'_z u)
+//   P2 (y, inverse)  U = Fy^-1 T1, Gy = Fy^-1 (i k'_y T1), Gz = Fy^-1 T1z
+//   P3 (x, rows)     Q_d = Fx (a/N Fx^-1 G_d), with G_x = i k'_x U and the
+//                    x-derivative of the divergence applied on the way out
+//   P4 (y, forward)  S = Fy Qx' + i k'_y Fy Qy,  Qz2 = Fy Qz
+//   P5 (z, forward)  y = -(Fz S + i k'_z Fz Qz2)
+//
+// 23 field transfers in 3D.  k' is the wavenumber with the Nyquist index
+// zeroed (odd derivative).  2D grids skip P2/P4, 1D grids do everything in
+// P3.  The Helmholtz-type operator rho u - nu Lap u (implicit viscous step)
+// uses the same skeleton with one field: Fz^-1, Fy^-1, x: Fx(rho Fx^-1), Fy,
+// Fz, plus nu |k|^2 (M^-1 v) added in P5 (Nyquist kept in |k|^2).
+//
+// Column passes (P1, P2, P4, P5) tile TC adjacent columns x the whole line:
+// lanes map to adjacent columns, so every global access is a contiguous run
+// of TC complex values.  The row pass loads whole rows.  All passes are
+// in-place safe except those that gather a mirror element (Helmholtz, kx = 0).
+#include <cstdio>
+#include "fft_core.hpp"
+#include "passes.hpp"
+#include "spectral.hpp"
+
+namespace vd {
+
+// ------------------------------------------------------------ config
+
+template <int L>
+struct ColCfg {
+  static constexpr int E = L >= 16 ? 16 : L;
+  static constexpr int T = L / E;
+  static constexpr int TC = 256 / T;  // columns per tile (256 threads)
+  static constexpr int NT = 256;
+};
+
+template <int L>
+struct RowCfg {
+  static constexpr int E = L >= 16 ? 16 : L;
+  static constexpr int T = L / E;
+  static constexpr int RW = 256 / T;  // rows per block
+  static constexpr int LP = row_pitch<L>();
+};
+
+// ------------------------------------------------------ column kernels
+
+enum ColMode {
+  COL_FFT_FWD = 0,  // NF fields, forward
+  COL_FFT_INV,      // NF fields, inverse
+  COL_P_FIRST,      // v -> Fz^-1(M v), Fz^-1(i k'_z M v)
+  COL_P_MIDINV,     // T1, T1z -> Fy^-1 T1, Fy^-1(i k'_y T1), Fy^-1 T1z
+  COL_P_MIDFWD,     // Qx', Qy, Qz -> Fy Qx' + i k'_y Fy Qy, Fy Qz
+  COL_P_LAST,       // S, Qz2 -> -(Fz S + i k'_z Fz Qz2)
+  COL_H_FIRST,      // v -> Fz^-1(M v)
+  COL_H_LAST,       // Q2, v -> Fz Q2 + nu |k|^2 M v
+};
+
+struct ColArgs {
+  const void* in[3];
+  void* out[3];
+  int nf;            // fields for the plain FFT modes
+  int outer, inner;  // data [outer][L][inner]
+  int ntile;
+  Geom g;
+  double rho0, nu;
+  int precond;
+  const double* in_scale;
+};
+
+template <int L, int E, int RPAT, typename R>
+__device__ __forceinline__ void col_load(C2<R>* reg, const C2<R>* p, size_t base, int inner,
+                                         int t, bool ok) {
+#pragma unroll
+  for (int s = 0; s < E; ++s) {
+    int idx = pat_index<L, E, RPAT>(t, s);
+    reg[s] = ok ? ldg(p + base + (size_t)idx * inner) : C2<R>{R(0), R(0)};
+  }
+}
+template <int L, int E, int RPAT, typename R>
+__device__ __forceinline__ void col_store(const C2<R>* reg, C2<R>* p, size_t base, int inner,
+                                          int t, bool ok) {
+  if (!ok) return;
+#pragma unroll
+  for (int s = 0; s < E; ++s) {
+    int idx = pat_index<L, E, RPAT>(t, s);
+    stg(p + base + (size_t)idx * inner, reg[s]);
+  }
+}
+
+template <int L, typename R, int MODE>
+__global__ __launch_bounds__(256) void k_col(ColArgs a, const C2<R>* __restrict__ twtab) {
+  using Cf = ColCfg<L>;
+  constexpr int E = Cf::E, T = Cf::T, TC = Cf::TC;
+  using S = Sched<L, E>;
+  constexpr int R0 = S::template first_radix<false>();
+  constexpr int R1 = S::template last_radix<false>();
+  constexpr int LDSN = S::npass > 1 ? TC * L : 1;
+  __shared__ C2<R> lds_raw[LDSN];
+  const C2<R>* tw = twtab + L;
+
+  const int tid = threadIdx.x;
+  const int c = tid % TC, t = tid / TC;
+  const int ob = blockIdx.x / a.ntile, tile = blockIdx.x % a.ntile;
+  const int col = tile * TC + c;
+  const bool ok = col < a.inner;
+  const size_t base = (size_t)ob * L * a.inner + col;
+  LdsCol<R> lds{lds_raw, c, TC};
+  C2<R> reg[E];
+
+  if constexpr (MODE == COL_FFT_FWD || MODE == COL_FFT_INV) {
+    constexpr int DIR = MODE == COL_FFT_FWD ? -1 : +1;
+    for (int f = 0; f < a.nf; ++f) {
+      col_load<L, E, R0>(reg, (const C2<R>*)a.in[f], base, a.inner, t, ok);
+      fft_line<L, E, DIR, false>(reg, lds, tw, t);
+      col_store<L, E, R1>(reg, (C2<R>*)a.out[f], base, a.inner, t, ok);
+    }
+  } else if constexpr (MODE == COL_P_FIRST) {
+    // z pass: line index = kz; column = ky * M + kx
+    const int ky = col / a.g.M, kx = col % a.g.M;
+    const R sc = in_scale_of<R>(a.in_scale);
+    col_load<L, E, R0>(reg, (const C2<R>*)a.in[0], base, a.inner, t, ok);
+    C2<R> r2[E];
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+      int kz = pat_index<L, E, R0>(t, s);
+      R m = a.precond ? mult_press<R>(kx, ky, kz, a.g, a.rho0) : R(1);
+      reg[s] = cscale(reg[s], m * sc);
+      r2[s] = cik(reg[s], kprime_of<R>(kz, L, R(a.g.sz)));
+    }
+    fft_line<L, E, +1, false>(reg, lds, tw, t);
+    col_store<L, E, R1>(reg, (C2<R>*)a.out[0], base, a.inner, t, ok);
+    fft_line<L, E, +1, false>(r2, lds, tw, t);
+    col_store<L, E, R1>(r2, (C2<R>*)a.out[1], base, a.inner, t, ok);
+  } else if constexpr (MODE == COL_P_MIDINV) {
+    // y pass over z-physical data: line index = ky
+    col_load<L, E, R0>(reg, (const C2<R>*)a.in[0], base, a.inner, t, ok);
+    C2<R> r2[E];
+#pragma unroll
+    for (int s = 0; s < E; ++s) r2[s] = cik(reg[s], kprime_of<R>(pat_index<L, E, R0>(t, s), L, R(a.g.sy)));
+    fft_line<L, E, +1, false>(reg, lds, tw, t);
+    col_store<L, E, R1>(reg, (C2<R>*)a.out[0], base, a.inner, t, ok);
+    fft_line<L, E, +1, false>(r2, lds, tw, t);
+    col_store<L, E, R1>(r2, (C2<R>*)a.out[1], base, a.inner, t, ok);
+    col_load<L, E, R0>(reg, (const C2<R>*)a.in[1], base, a.inner, t, ok);
+    fft_line<L, E, +1, false>(reg, lds, tw, t);
+    col_store<L, E, R1>(reg, (C2<R>*)a.out[2], base, a.inner, t, ok);
+  } else if constexpr (MODE == COL_P_MIDFWD || MODE == COL_P_LAST) {
+    // forward y (MIDFWD) or z (LAST) with the divergence term of this axis
+    constexpr bool LAST = MODE == COL_P_LAST;
+    const R sk = LAST ? R(a.g.sz) : R(a.g.sy);
+    C2<R> acc[E];
+    col_load<L, E, R0>(acc, (const C2<R>*)a.in[0], base, a.inner, t, ok);
+    fft_line<L, E, -1, false>(acc, lds, tw, t);
+    col_load<L, E, R0>(reg, (const C2<R>*)a.in[1], base, a.inner, t, ok);
+    fft_line<L, E, -1, false>(reg, lds, tw, t);
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+      C2<R> d = cik(reg[s], kprime_of<R>(pat_index<L, E, R1>(t, s), L, sk));
+      acc[s] = LAST ? C2<R>{-(acc[s].x + d.x), -(acc[s].y + d.y)} : acc[s] + d;
+    }
+    col_store<L, E, R1>(acc, (C2<R>*)a.out[0], base, a.inner, t, ok);
+    if constexpr (!LAST) {
+      col_load<L, E, R0>(reg, (const C2<R>*)a.in[2], base, a.inner, t, ok);
+      fft_line<L, E, -1, false>(reg, lds, tw, t);
+      col_store<L, E, R1>(reg, (C2<R>*)a.out[1], base, a.inner, t, ok);
+    }
+  } else if constexpr (MODE == COL_H_FIRST || MODE == COL_H_LAST) {
+    constexpr bool FIRST = MODE == COL_H_FIRST;
+    constexpr int RP = FIRST ? R0 : R1;  // pattern in which v is needed
+    const int ky = col / a.g.M, kx = col % a.g.M;
+    const R sc = in_scale_of<R>(a.in_scale);
+    const C2<R>* v = (const C2<R>*)(FIRST ? a.in[0] : a.in[1]);
+    C2<R> mv[E];
+    col_load<L, E, RP>(mv, v, base, a.inner, t, ok);
+    const bool need_mirror = (kx == 0) && (a.precond || !FIRST);
+    const int kym = (a.g.ny - ky) % a.g.ny;
+    const size_t basem = (size_t)ob * L * a.inner + (size_t)kym * a.g.M;
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+      int kz = pat_index<L, E, RP>(t, s);
+      if (!a.precond && FIRST) {
+        mv[s] = cscale(mv[s], sc);
+      } else {
+        HelmMult<R> h = a.precond ? mult_helm<R>(kx, ky, kz, a.g, a.rho0, a.nu, !FIRST)
+                                  : HelmMult<R>{R(0), R(0)};
+        if (!a.precond) {  // last pass without preconditioner: nu |k|^2 v
+          R kyz = ksq_yz<R>(ky, kz, a.g);
+          R kx2 = R(kx) * R(a.g.sx);
+          R kn = R(a.g.M) * R(a.g.sx);
+          h.g0 = R(a.nu) * (kyz + kx2 * kx2);
+          h.gN = R(a.nu) * (kyz + kn * kn);
+        }
+        if (need_mirror && ok) {
+          int kzm = (L - kz) % L;
+          C2<R> pm = ldg(v + basem + (size_t)kzm * a.inner);
+          mv[s] = cscale(diag_packed(mv[s], pm, h.g0, h.gN), sc);
+        } else {
+          mv[s] = cscale(mv[s], h.g0 * sc);
+        }
+      }
+    }
+    if constexpr (FIRST) {
+      fft_line<L, E, +1, false>(mv, lds, tw, t);
+      col_store<L, E, R1>(mv, (C2<R>*)a.out[0], base, a.inner, t, ok);
+    } else {
+      col_load<L, E, R0>(reg, (const C2<R>*)a.in[0], base, a.inner, t, ok);
+      fft_line<L, E, -1, false>(reg, lds, tw, t);
+#pragma unroll
+      for (int s = 0; s < E; ++s) reg[s] = reg[s] + mv[s];
+      col_store<L, E, R1>(reg, (C2<R>*)a.out[0], base, a.inner, t, ok);
+    }
+  }
+}
+
+// --------------------------------------------------------- row kernels
+
+enum RowMode {
+  ROW_R2C = 0,  // real rows -> packed spectrum (forward)
+  ROW_C2R,      // packed spectrum -> real rows, times cscale
+  ROW_P,        // pressure x pass, nf fields: field 0 gets i k'_x in and out
+  ROW_P1,       // 1D pressure: y = -i k'_x F(a F^-1(i k'_x M v))
+  ROW_H,        // Helmholtz x pass (rho times), one field
+  ROW_H1,       // 1D Helmholtz: y = F(rho F^-1(M v)) + nu k^2 M v
+};
+
+struct RowArgs {
+  const void* in[3];
+  void* out[3];
+  int nf;
+  int nrows;
+  const void* coef;  // real rows (R), nullptr for transforms
+  double cscale;
+  Geom g;
+  double rho0, nu;
+  int precond;
+  const double* in_scale;
+};
+
+template <int L, typename R, int MODE>
+__global__ __launch_bounds__(256) void k_row(RowArgs a, const C2<R>* __restrict__ twtab) {
+  using Cf = RowCfg<L>;
+  constexpr int E = Cf::E, T = Cf::T, RW = Cf::RW, LP = Cf::LP;
+  using S = Sched<L, E>;
+  constexpr int RI1 = S::template last_radix<false>();   // inverse output pattern
+  constexpr int RF0 = S::template first_radix<true>();   // forward input pattern (== RI1)
+  static_assert(RI1 == RF0, "pattern mismatch");
+  __shared__ C2<R> lds_all[RW * LP];
+  const C2<R>* tw = twtab + L;       // length-L table
+  const C2<R>* twN = twtab + 2 * L;  // length-2L table, first L entries used
+
+  const int tid = threadIdx.x;
+  const int t = tid % T, rr = tid / T;
+  const int row = blockIdx.x * RW + rr;
+  const bool ok = row < a.nrows;
+  LdsRow<R> lds{lds_all + rr * LP};
+  const R sx = R(a.g.sx);
+  C2<R> reg[E];
+
+  auto pre_mult = [&](int f, int k, C2<R> X) -> C2<R> {
+    if constexpr (MODE == ROW_P) {
+      if (f == 0) return cik(X, R(k) * sx);  // slot 0: k'_x = 0 for both halves
+      return X;
+    } else if constexpr (MODE == ROW_P1) {
+      R m = a.precond ? mult_press<R>(k, 0, 0, a.g, a.rho0) : R(1);
+      return cik(X, R(k) * sx * m * in_scale_of<R>(a.in_scale));
+    } else if constexpr (MODE == ROW_H1) {
+      R sc = in_scale_of<R>(a.in_scale);
+      if (!a.precond) return cscale(X, sc);
+      HelmMult<R> h = mult_helm<R>(k, 0, 0, a.g, a.rho0, a.nu, false);
+      if (k == 0) return C2<R>{X.x * h.g0 * sc, X.y * h.gN * sc};
+      return cscale(X, h.g0 * sc);
+    } else {
+      return X;
+    }
+  };
+
+  auto inverse_row = [&](const C2<R>* __restrict__ src, int f) {
+    // stage the packed row, build Z_k = E_k + i O_k for the half-length FFT
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+      int k = t + s * T;
+      C2<R> X = ok ? ldg(src + (size_t)row * L + k) : C2<R>{R(0), R(0)};
+      lds.st(k, pre_mult(f, k, X));
+    }
+    __syncthreads();
+    constexpr int RI0 = S::template first_radix<false>();
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+      int k = pat_index<L, E, RI0>(t, s);
+      C2<R> Z;
+      if (k == 0) {
+        C2<R> P0 = lds.ld(0);
+        Z = C2<R>{P0.x + P0.y, P0.x - P0.y};
+      } else {
+        C2<R> Xk = lds.ld(k), Xm = cconj(lds.ld(L - k));
+        C2<R> e = Xk + Xm;
+        C2<R> o = cmulc(Xk - Xm, ldg(twN + k));  // times exp(+2 pi i k / N)
+        Z = C2<R>{e.x - o.y, e.y + o.x};
+      }
+      reg[s] = Z;
+    }
+    fft_line<L, E, +1, false>(reg, lds, tw, t);
+  };
+
+  auto forward_post = [&](int f, C2<R>* __restrict__ dst, const C2<R>* __restrict__ vsrc) {
+    // reg holds Z_k for k = t + s T (forward output, radix E last)
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < E; ++s) lds.st(t + s * T, reg[s]);
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+      int k = t + s * T;
+      C2<R> Zk = reg[s], X;
+      if (k == 0) {
+        X = C2<R>{Zk.x + Zk.y, Zk.x - Zk.y};
+      } else {
+        C2<R> Zm = cconj(lds.ld(L - k));
+        C2<R> e = Zk + Zm;
+        C2<R> wd = cmul(ldg(twN + k), Zk - Zm);
+        X = C2<R>{R(0.5) * (e.x + wd.y), R(0.5) * (e.y - wd.x)};
+      }
+      if constexpr (MODE == ROW_P) {
+        if (f == 0) X = cik(X, R(k) * sx);
+      } else if constexpr (MODE == ROW_P1) {
+        X = cik(X, -R(k) * sx);
+      } else if constexpr (MODE == ROW_H1) {
+        // + nu |k|^2 M v (slot 0: halves kx = 0 and kx = nx/2)
+        C2<R> V = ok ? ldg(vsrc + (size_t)row * L + k) : C2<R>{R(0), R(0)};
+        R sc = in_scale_of<R>(a.in_scale);
+        R k2 = R(k) * sx;
+        k2 *= k2;
+        R kn = R(a.g.M) * sx;
+        if (a.precond) {
+          HelmMult<R> h = mult_helm<R>(k, 0, 0, a.g, a.rho0, a.nu, true);
+          if (k == 0) X = X + C2<R>{R(0), V.y * h.gN * sc};
+          else X = X + cscale(V, h.g0 * sc);
+        } else {
+          if (k == 0) X = X + C2<R>{R(0), V.y * R(a.nu) * kn * kn * sc};
+          else X = X + cscale(V, R(a.nu) * k2 * sc);
+        }
+      }
+      if (ok) stg(dst + (size_t)row * L + k, X);
+    }
+  };
+
+  if constexpr (MODE == ROW_R2C) {
+    const C2<R>* src = (const C2<R>*)a.in[0];  // real row viewed as complex pairs
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+      int m = pat_index<L, E, RF0>(t, s);
+      reg[s] = ok ? ldg(src + (size_t)row * L + m) : C2<R>{R(0), R(0)};
+    }
+    fft_line<L, E, -1, true>(reg, lds, tw, t);
+    forward_post(0, (C2<R>*)a.out[0], nullptr);
+  } else if constexpr (MODE == ROW_C2R) {
+    inverse_row((const C2<R>*)a.in[0], 0);
+    const R cs = R(a.cscale);
+    C2<R>* dst = (C2<R>*)a.out[0];
+    if (ok) {
+#pragma unroll
+      for (int s = 0; s < E; ++s) {
+        int m = pat_index<L, E, RI1>(t, s);
+        stg(dst + (size_t)row * L + m, cscale(reg[s], cs));
+      }
+    }
+  } else {
+    const C2<R>* coef = (const C2<R>*)a.coef;
+    const R cs = R(a.cscale);
+    C2<R> cf[E];
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+      int m = pat_index<L, E, RI1>(t, s);
+      C2<R> q = ok ? ldg(coef + (size_t)row * L + m) : C2<R>{R(0), R(0)};
+      cf[s] = C2<R>{q.x * cs, q.y * cs};
+    }
+    const int nf = (MODE == ROW_P) ? a.nf : 1;
+    for (int f = 0; f < nf; ++f) {
+      inverse_row((const C2<R>*)a.in[f], f);
+#pragma unroll
+      for (int s = 0; s < E; ++s) reg[s] = C2<R>{reg[s].x * cf[s].x, reg[s].y * cf[s].y};
+      fft_line<L, E, -1, true>(reg, lds, tw, t);
+      forward_post(f, (C2<R>*)a.out[f], (const C2<R>*)a.in[0]);
+    }
+  }
+}
+
+// -------------------------------------------------- precond kernel
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_precond(const C2<R>* __restrict__ r, C2<R>* __restrict__ z, Geom g,
+                                                 int kind, double rho0, double nu, size_t n) {
+  size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  int kx = (int)(e % g.M);
+  size_t q = e / g.M;
+  int ky = (int)(q % g.ny), kz = (int)(q / g.ny);
+  C2<R> v = ldg(r + e);
+  if (kind == OP_PRESSURE) {
+    stg(z + e, cscale(v, mult_press<R>(kx, ky, kz, g, rho0)));
+  } else {
+    HelmMult<R> h = mult_helm<R>(kx, ky, kz, g, rho0, nu, false);
+    if (kx == 0) {
+      int kym = (g.ny - ky) % g.ny, kzm = (g.nz - kz) % g.nz;
+      C2<R> pm = ldg(r + ((size_t)kzm * g.ny + kym) * g.M);
+      stg(z + e, diag_packed(v, pm, h.g0, h.gN));
+    } else {
+      stg(z + e, cscale(v, h.g0));
+    }
+  }
+}
+
+// ------------------------------------------------------------ launchers
+
+template <typename R, int MODE, int L>
+static void launch_col_L(const ColArgs& a0, const void* tw, hipStream_t st) {
+  ColArgs a = a0;
+  a.ntile = (a.inner + ColCfg<L>::TC - 1) / ColCfg<L>::TC;
+  dim3 grid(a.outer * a.ntile);
+  hipLaunchKernelGGL((k_col<L, R, MODE>), grid, dim3(256), 0, st, a, (const C2<R>*)tw);
+}
+
+template <typename R, int MODE>
+static void launch_col(int L, const ColArgs& a, const void* tw, hipStream_t st) {
+  switch (L) {
+    case 16: launch_col_L<R, MODE, 16>(a, tw, st); break;
+    case 32: launch_col_L<R, MODE, 32>(a, tw, st); break;
+    case 64: launch_col_L<R, MODE, 64>(a, tw, st); break;
+    case 128: launch_col_L<R, MODE, 128>(a, tw, st); break;
+    case 256: launch_col_L<R, MODE, 256>(a, tw, st); break;
+    case 512: launch_col_L<R, MODE, 512>(a, tw, st); break;
+    case 1024: launch_col_L<R, MODE, 1024>(a, tw, st); break;
+    default: fprintf(stderr, "vdsolve: unsupported column length %d\n", L);
+  }
+}
+
+template <typename R, int MODE, int L>
+static void launch_row_L(const RowArgs& a, const void* tw, hipStream_t st) {
+  dim3 grid((a.nrows + RowCfg<L>::RW - 1) / RowCfg<L>::RW);
+  hipLaunchKernelGGL((k_row<L, R, MODE>), grid, dim3(256), 0, st, a, (const C2<R>*)tw);
+}
+
+template <typename R, int MODE>
+static void launch_row(int L, const RowArgs& a, const void* tw, hipStream_t st) {
+  switch (L) {
+    case 8: launch_row_L<R, MODE, 8>(a, tw, st); break;
+    case 16: launch_row_L<R, MODE, 16>(a, tw, st); break;
+    case 32: launch_row_L<R, MODE, 32>(a, tw, st); break;
+    case 64: launch_row_L<R, MODE, 64>(a, tw, st); break;
+    case 128: launch_row_L<R, MODE, 128>(a, tw, st); break;
+    case 256: launch_row_L<R, MODE, 256>(a, tw, st); break;
+    case 512: launch_row_L<R, MODE, 512>(a, tw, st); break;
+    default: fprintf(stderr, "vdsolve: unsupported row length %d\n", L);
+  }
+}
+
+static ColArgs col_args(const Geom& g, const OpParams* p) {
+  ColArgs a{};
+  a.g = g;
+  if (p) {
+    a.rho0 = p->rho0;
+    a.nu = p->nu;
+    a.precond = p->precond;
+    a.in_scale = p->in_scale;
+  }
+  return a;
+}
+static RowArgs row_args(const Geom& g, const OpParams* p) {
+  RowArgs a{};
+  a.g = g;
+  a.nrows = g.ny * g.nz;
+  if (p) {
+    a.rho0 = p->rho0;
+    a.nu = p->nu;
+    a.precond = p->precond;
+    a.in_scale = p->in_scale;
+  }
+  return a;
+}
+
+template <typename R>
+void op_apply(const Geom& g, const OpParams& p, const void* v, void* y, const OpWork& w, const void* coef,
+              const void* twtab, hipStream_t st, Prof* prof) {
+  const bool pr = prof && prof->on;
+#define VD_T0(c) \
+  if (pr) prof->begin(c, st);
+#define VD_T1() \
+  if (pr) prof->end(st);
+  const size_t zin = (size_t)g.ny * g.M;  // inner size of the z pass
+  if (p.kind == OP_PRESSURE) {
+    if (g.nz == 1) {  // 1D
+      RowArgs r = row_args(g, &p);
+      r.in[0] = v;
+      r.out[0] = y;
+      r.coef = coef;
+      r.cscale = g.ntot_inv;
+      VD_T0(2) launch_row<R, ROW_P1>(g.M, r, twtab, st); VD_T1()
+      return;
+    }
+    void *t0 = w.t[0], *t1 = w.t[1], *t2 = w.t[2];
+    ColArgs a = col_args(g, &p);
+    a.outer = 1;
+    a.inner = (int)zin;
+    a.in[0] = v;
+    a.out[0] = t0;
+    a.out[1] = t1;
+    VD_T0(0) launch_col<R, COL_P_FIRST>(g.nz, a, twtab, st); VD_T1()
+    RowArgs r = row_args(g, &p);
+    r.coef = coef;
+    r.cscale = g.ntot_inv;
+    if (g.ny > 1) {
+      ColArgs b = col_args(g, &p);
+      b.outer = g.nz;
+      b.inner = g.M;
+      b.in[0] = t0;
+      b.in[1] = t1;
+      b.out[0] = t0;
+      b.out[1] = t2;
+      b.out[2] = t1;
+      VD_T0(1) launch_col<R, COL_P_MIDINV>(g.ny, b, twtab, st); VD_T1()
+      r.nf = 3;
+      r.in[0] = t0; r.in[1] = t2; r.in[2] = t1;
+      r.out[0] = t0; r.out[1] = t2; r.out[2] = t1;
+      VD_T0(2) launch_row<R, ROW_P>(g.M, r, twtab, st); VD_T1()
+      ColArgs c = col_args(g, &p);
+      c.outer = g.nz;
+      c.inner = g.M;
+      c.in[0] = t0; c.in[1] = t2; c.in[2] = t1;
+      c.out[0] = t0; c.out[1] = t1;
+      VD_T0(3) launch_col<R, COL_P_MIDFWD>(g.ny, c, twtab, st); VD_T1()
+    } else {
+      r.nf = 2;
+      r.in[0] = t0; r.in[1] = t1;
+      r.out[0] = t0; r.out[1] = t1;
+      VD_T0(2) launch_row<R, ROW_P>(g.M, r, twtab, st); VD_T1()
+    }
+    ColArgs d = col_args(g, &p);
+    d.outer = 1;
+    d.inner = (int)zin;
+    d.in[0] = t0;
+    d.in[1] = t1;
+    d.out[0] = y;
+    VD_T0(4) launch_col<R, COL_P_LAST>(g.nz, d, twtab, st); VD_T1()
+  } else {
+    if (g.nz == 1) {
+      RowArgs r = row_args(g, &p);
+      r.in[0] = v;
+      r.out[0] = y;
+      r.coef = coef;
+      r.cscale = g.ntot_inv;
+      VD_T0(2) launch_row<R, ROW_H1>(g.M, r, twtab, st); VD_T1()
+      return;
+    }
+    void* t0 = w.t[0];
+    ColArgs a = col_args(g, &p);
+    a.outer = 1;
+    a.inner = (int)zin;
+    a.in[0] = v;
+    a.out[0] = t0;
+    VD_T0(0) launch_col<R, COL_H_FIRST>(g.nz, a, twtab, st); VD_T1()
+    if (g.ny > 1) {
+      ColArgs b = col_args(g, nullptr);
+      b.outer = g.nz;
+      b.inner = g.M;
+      b.nf = 1;
+      b.in[0] = t0;
+      b.out[0] = t0;
+      VD_T0(1) launch_col<R, COL_FFT_INV>(g.ny, b, twtab, st); VD_T1()
+    }
+    RowArgs r = row_args(g, &p);
+    r.in[0] = t0;
+    r.out[0] = t0;
+    r.coef = coef;
+    r.cscale = g.ntot_inv;
+    VD_T0(2) launch_row<R, ROW_H>(g.M, r, twtab, st); VD_T1()
+    if (g.ny > 1) {
+      ColArgs b = col_args(g, nullptr);
+      b.outer = g.nz;
+      b.inner = g.M;
+      b.nf = 1;
+      b.in[0] = t0;
+      b.out[0] = t0;
+      VD_T0(3) launch_col<R, COL_FFT_FWD>(g.ny, b, twtab, st); VD_T1()
+    }
+    ColArgs d = col_args(g, &p);
+    d.outer = 1;
+    d.inner = (int)zin;
+    d.in[0] = t0;
+    d.in[1] = v;
+    d.out[0] = y;
+    VD_T0(4) launch_col<R, COL_H_LAST>(g.nz, d, twtab, st); VD_T1()
+  }
+#undef VD_T0
+#undef VD_T1
+}
+
+template <typename R>
+void precond_apply(const Geom& g, const OpParams& p, const void* r, void* z, hipStream_t st) {
+  size_t n = (size_t)g.nz * g.ny * g.M;
+  hipLaunchKernelGGL((k_precond<R>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (const C2<R>*)r,
+                     (C2<R>*)z, g, p.kind, p.rho0, p.nu, n);
+}
+
+void fwd_transform(const Geom& g, const double* phys, void* spec, void* work, const void* twtab,
+                   hipStream_t st) {
+  (void)work;
+  RowArgs r = row_args(g, nullptr);
+  r.in[0] = phys;
+  r.out[0] = spec;
+  launch_row<double, ROW_R2C>(g.M, r, twtab, st);
+  if (g.ny > 1) {
+    ColArgs b = col_args(g, nullptr);
+    b.outer = g.nz;
+    b.inner = g.M;
+    b.nf = 1;
+    b.in[0] = spec;
+    b.out[0] = spec;
+    launch_col<double, COL_FFT_FWD>(g.ny, b, twtab, st);
+  }
+  if (g.nz > 1) {
+    ColArgs b = col_args(g, nullptr);
+    b.outer = 1;
+    b.inner = g.ny * g.M;
+    b.nf = 1;
+    b.in[0] = spec;
+    b.out[0] = spec;
+    launch_col<double, COL_FFT_FWD>(g.nz, b, twtab, st);
+  }
+}
+
+void inv_transform(const Geom& g, const void* spec, double* phys, void* work, const void* twtab,
+                   hipStream_t st) {
+  const void* cur = spec;
+  if (g.nz > 1) {
+    ColArgs b = col_args(g, nullptr);
+    b.outer = 1;
+    b.inner = g.ny * g.M;
+    b.nf = 1;
+    b.in[0] = cur;
+    b.out[0] = work;
+    launch_col<double, COL_FFT_INV>(g.nz, b, twtab, st);
+    cur = work;
+  }
+  if (g.ny > 1) {
+    ColArgs b = col_args(g, nullptr);
+    b.outer = g.nz;
+    b.inner = g.M;
+    b.nf = 1;
+    b.in[0] = cur;
+    b.out[0] = work;
+    launch_col<double, COL_FFT_INV>(g.ny, b, twtab, st);
+    cur = work;
+  }
+  RowArgs r = row_args(g, nullptr);
+  r.in[0] = cur;
+  r.out[0] = phys;
+  r.cscale = g.ntot_inv;
+  launch_row<double, ROW_C2R>(g.M, r, twtab, st);
+}
+
+template void op_apply<double>(const Geom&, const OpParams&, const void*, void*, const OpWork&, const void*,
+                               const void*, hipStream_t, Prof*);
+template void op_apply<float>(const Geom&, const OpParams&, const void*, void*, const OpWork&, const void*,
+                              const void*, hipStream_t, Prof*);
+template void precond_apply<double>(const Geom&, const OpParams&, const void*, void*, hipStream_t);
+template void precond_apply<float>(const Geom&, const OpParams&, const void*, void*, hipStream_t);
+
+}  // namespace vd

@@ -1,0 +1,75 @@
+// Host-side interface of the fused spectral pass kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <vector>
+
+namespace vd {
+
+// Internal grid geometry.  Physical fields are [nz][ny][nx] reals; spectral
+// fields are [nz][ny][M] complex with M = nx / 2 and the x-Nyquist
+// coefficient packed into the imaginary part of the kx = 0 slot (every
+// packed array is the transform of exactly one real field).  A 2D grid
+// (ny', nx) is stored as nz = ny', ny = 1; a 1D grid as nz = ny = 1.
+struct Geom {
+  int nx, ny, nz, M;
+  double sx, sy, sz;    // 2 pi / L_d
+  double ntot_inv;      // 1 / (nx ny nz)
+};
+
+enum OpKind { OP_PRESSURE = 0, OP_HELMHOLTZ = 1 };
+
+struct OpParams {
+  int kind;                  // OpKind
+  double rho0;               // constant density of the preconditioner
+  double nu;                 // Helmholtz coefficient (dt * nu)
+  int precond;               // apply the constant-density inverse to the input first
+  const double* in_scale;    // optional device scalar multiplying the input
+};
+
+// Work buffers of one operator application (spectral, same precision as the
+// vectors).  Three are needed for 3D pressure, two for 2D, none for 1D.
+struct OpWork {
+  void* t[6];
+};
+
+// Optional per-launch timing of the pass kernels with HIP events on the
+// launch stream.  Classes: 0 z-first, 1 y-inverse, 2 x, 3 y-forward, 4 z-last.
+struct Prof {
+  static constexpr int kClasses = 8;
+  bool on = false;
+  struct Pair { int cls; hipEvent_t a, b; };
+  std::vector<Pair> pending;
+  std::vector<hipEvent_t> spare;
+  double ms[kClasses] = {0};
+  long long cnt[kClasses] = {0};
+  int cur = -1;
+  hipEvent_t cur_a = nullptr;
+  void begin(int cls, hipStream_t s);
+  void end(hipStream_t s);
+  void flush();  // accumulate completed pairs (call after a stream sync)
+  void release();
+};
+
+// y = A (M^-1 (s v)) in spectral space.  R = float or double.
+template <typename R>
+void op_apply(const Geom& g, const OpParams& p, const void* v, void* y, const OpWork& w,
+              const void* coef /* real [nz][ny][nx]: 1/rho (pressure) or rho (Helmholtz) */,
+              const void* twtab, hipStream_t st, Prof* prof = nullptr);
+
+// Diagonal preconditioner in spectral space: z = M^-1 r (separate buffers).
+template <typename R>
+void precond_apply(const Geom& g, const OpParams& p, const void* r, void* z, hipStream_t st);
+
+// FP64 transforms between physical [nz][ny][nx] and packed spectral.
+// Forward is the unnormalised DFT; inverse includes the 1 / N factor.
+void fwd_transform(const Geom& g, const double* phys, void* spec, void* work, const void* twtab,
+                   hipStream_t st);
+void inv_transform(const Geom& g, const void* spec, double* phys, void* work, const void* twtab,
+                   hipStream_t st);
+
+// Twiddle tables: entries [L, 2L) hold exp(-2 pi i k / L) for L = 1..4096.
+constexpr int kTwEntries = 8192;
+
+}  // namespace vd

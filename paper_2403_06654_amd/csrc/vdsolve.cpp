@@ -1,0 +1,749 @@
+// C-ABI entry points and the host side of the Krylov solvers.
+//
+// Krylov vectors live in HBM as packed half-spectra (see passes.hpp); the
+// scalars of each method (Hessenberg matrix, Givens rotations, CG/RMR step
+// lengths) live in a small device struct and are updated by one-thread
+// kernels, so the only host round trip per iteration is the 8-byte
+// residual estimate that decides whether to stop.
+//
+// Methods (Sec. 3.1 solver list):
+//   GMRES(m)  right preconditioned (x = M^-1 V y), classical Gram-Schmidt
+//             applied twice, Givens rotations, restart every m steps; the
+//             true FP64 residual gates termination at the end of a cycle.
+//   CG        preconditioned conjugate gradient on the symmetric operators.
+//   RMR       Richardson iteration with the minimal-residual step length:
+//             z = M^-1 r, w = A z, alpha = (r, w) / (w, w).
+// FP32_REFINE runs the same method in FP32 (operator, preconditioner and
+// basis in FP32; inner products, Hessenberg and Givens in FP64) inside an
+// FP64 iterative-refinement loop: r = b - A x in FP64, solve A d = r in
+// FP32 to inner_rtol, x += d.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "../../include/vdsolve.h"
+#include "passes.hpp"
+#include "vecops.hpp"
+
+using namespace vd;
+
+// ------------------------------------------------------------ profiling
+
+void Prof::begin(int cls, hipStream_t s) {
+  hipEvent_t a;
+  if (!spare.empty()) {
+    a = spare.back();
+    spare.pop_back();
+  } else {
+    hipEventCreate(&a);
+  }
+  hipEventRecord(a, s);
+  cur = cls;
+  cur_a = a;
+}
+void Prof::end(hipStream_t s) {
+  hipEvent_t b;
+  if (!spare.empty()) {
+    b = spare.back();
+    spare.pop_back();
+  } else {
+    hipEventCreate(&b);
+  }
+  hipEventRecord(b, s);
+  pending.push_back(Pair{cur, cur_a, b});
+}
+void Prof::flush() {
+  for (auto& p : pending) {
+    float ms_ = 0.f;
+    if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms_, p.a, p.b) == hipSuccess) {
+      ms[p.cls] += ms_;
+      cnt[p.cls] += 1;
+    }
+    spare.push_back(p.a);
+    spare.push_back(p.b);
+  }
+  pending.clear();
+}
+void Prof::release() {
+  flush();
+  for (auto e : spare) hipEventDestroy(e);
+  spare.clear();
+}
+
+// ---------------------------------------------------------------- grid
+
+struct vd_grid {
+  Geom g{};
+  int ndim = 0;
+  int n[3] = {1, 1, 1};
+  double len[3] = {0, 0, 0};
+  hipStream_t st = nullptr;
+  size_t nreal = 0, nspec = 0;
+  void* tw64 = nullptr;
+  void* tw32 = nullptr;
+  double* rho = nullptr;
+  double* a64 = nullptr;
+  float* a32 = nullptr;
+  float* rho32 = nullptr;
+  bool has_rho = false;
+  double rho_mean = 0, rho_min = 0, rho_max = 0;
+  double* partial = nullptr;
+  double* dsmall = nullptr;   // misc device scalars
+  DevState* dst = nullptr;    // device solver state
+  DevState* hst = nullptr;    // pinned host mirror
+  std::map<int, void*> bufs;  // spectral vectors by (precision, role)
+  Prof prof;
+};
+
+namespace {
+
+enum Role {
+  B_B = 0, B_X, B_R, B_TMP, B_T0, B_T1, B_T2, B_W, B_P, B_Q, B_Z, B_V0 = 32,
+};
+
+struct DevErr {};
+
+inline void ck(hipError_t e) {
+  if (e != hipSuccess) throw DevErr{};
+}
+
+size_t elem_bytes(int prec) { return prec == 32 ? 8 : 16; }
+
+void* buf(vd_grid* G, int prec, int role) {
+  int key = prec * 1000 + role;
+  auto it = G->bufs.find(key);
+  if (it != G->bufs.end()) return it->second;
+  void* p = nullptr;
+  if (hipMalloc(&p, G->nspec * elem_bytes(prec)) != hipSuccess) throw std::bad_alloc();
+  G->bufs[key] = p;
+  return p;
+}
+
+bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
+
+vd_status check_desc(const vd_grid_desc* d) {
+  if (!d || d->ndim < 1 || d->ndim > 3) return VD_EINVAL;
+  for (int i = 0; i < d->ndim; ++i) {
+    if (d->basis[i] != VD_FOURIER) return VD_ENOTSUP;
+    if (!pow2_in(d->n[i], 16, 1024)) return VD_EINVAL;
+    if (!(d->length[i] > 0.0) || !std::isfinite(d->length[i])) return VD_EINVAL;
+  }
+  return VD_OK;
+}
+
+Geom make_geom(const vd_grid_desc* d) {
+  Geom g{};
+  const double tp = 2.0 * M_PI;
+  g.nx = d->n[0];
+  g.M = g.nx / 2;
+  g.sx = tp / d->length[0];
+  if (d->ndim == 1) {
+    g.ny = g.nz = 1;
+    g.sy = g.sz = 0;
+  } else if (d->ndim == 2) {  // (ny', nx) stored as nz = ny', ny = 1
+    g.nz = d->n[1];
+    g.sz = tp / d->length[1];
+    g.ny = 1;
+    g.sy = 0;
+  } else {
+    g.ny = d->n[1];
+    g.sy = tp / d->length[1];
+    g.nz = d->n[2];
+    g.sz = tp / d->length[2];
+  }
+  g.ntot_inv = 1.0 / ((double)g.nx * g.ny * g.nz);
+  return g;
+}
+
+void fill_twiddles(vd_grid* G) {
+  std::vector<double> t64(2 * kTwEntries, 0.0);
+  std::vector<float> t32(2 * kTwEntries, 0.f);
+  for (int L = 1; L < kTwEntries; L *= 2) {
+    for (int k = 0; k < L; ++k) {
+      // exp(-2 pi i k / L), evaluated in long double and rounded once
+      long double ang = -2.0L * 3.14159265358979323846264338327950288L * (long double)k / (long double)L;
+      long double c = cosl(ang), s = sinl(ang);
+      t64[2 * (L + k)] = (double)c;
+      t64[2 * (L + k) + 1] = (double)s;
+      t32[2 * (L + k)] = (float)c;
+      t32[2 * (L + k) + 1] = (float)s;
+    }
+  }
+  ck(hipMalloc(&G->tw64, t64.size() * sizeof(double)));
+  ck(hipMalloc(&G->tw32, t32.size() * sizeof(float)));
+  ck(hipMemcpy(G->tw64, t64.data(), t64.size() * sizeof(double), hipMemcpyHostToDevice));
+  ck(hipMemcpy(G->tw32, t32.data(), t32.size() * sizeof(float), hipMemcpyHostToDevice));
+}
+
+void sync_state(vd_grid* G) {
+  ck(hipMemcpyAsync(G->hst, G->dst, sizeof(DevState), hipMemcpyDeviceToHost, G->st));
+  ck(hipStreamSynchronize(G->st));
+  if (G->prof.on) G->prof.flush();
+}
+
+double read_scalar(vd_grid* G, const double* dptr) {
+  double v = 0;
+  ck(hipMemcpyAsync(&G->hst->nrm2, dptr, sizeof(double), hipMemcpyDeviceToHost, G->st));
+  ck(hipStreamSynchronize(G->st));
+  v = G->hst->nrm2;
+  if (G->prof.on) G->prof.flush();
+  return v;
+}
+
+// ----------------------------------------------------------- solver core
+
+struct SolveCfg {
+  int solver, restart, max_iter;
+  double rtol;
+  OpParams op;  // kind, rho0, nu, precond
+};
+
+struct SolveOut {
+  int status = VD_OK;
+  int iters = 0;
+  double relres = 0;
+};
+
+template <typename R>
+struct Krylov {
+  vd_grid* G;
+  int prec;  // 64 or 32
+  const Geom& g;
+  SolveCfg cfg;
+  const void* coef;
+  const void* tw;
+  OpWork work{};
+
+  Krylov(vd_grid* G_, int prec_, const SolveCfg& c)
+      : G(G_), prec(prec_), g(G_->g), cfg(c) {
+    const bool helm = cfg.op.kind == OP_HELMHOLTZ;
+    if (prec == 64) {
+      coef = helm ? (const void*)G->rho : (const void*)G->a64;
+      tw = G->tw64;
+    } else {
+      coef = helm ? (const void*)G->rho32 : (const void*)G->a32;
+      tw = G->tw32;
+    }
+    if (g.nz > 1) {
+      work.t[0] = buf(G, prec, B_T0);
+      if (!helm) work.t[1] = buf(G, prec, B_T1);
+      if (!helm && g.ny > 1) work.t[2] = buf(G, prec, B_T2);
+    }
+  }
+
+  void apply(const void* v, void* y, bool with_prec) {
+    OpParams p = cfg.op;
+    p.precond = with_prec ? cfg.op.precond : 0;
+    p.in_scale = nullptr;
+    op_apply<R>(g, p, v, y, work, coef, tw, G->st, &G->prof);
+  }
+
+  // ||b - A x|| into r (and G->dst->nrm2); returns the norm
+  double true_resid(const void* b, const void* x, void* r) {
+    void* tmp = buf(G, prec, B_TMP);
+    apply(x, tmp, false);
+    sub_norm<R>(g, b, tmp, r, G->partial, &G->dst->nrm2, G->st);
+    return std::sqrt(std::fmax(read_scalar(G, &G->dst->nrm2), 0.0));
+  }
+
+  SolveOut run(const void* b, void* x, double bnorm) {
+    ck(hipMemsetAsync(&G->dst->bad, 0, sizeof(int), G->st));
+    switch (cfg.solver) {
+      case VD_CG: return cg(b, x, bnorm);
+      case VD_RMR: return rmr(b, x, bnorm);
+      default: return gmres(b, x, bnorm);
+    }
+  }
+
+  SolveOut gmres(const void* b, void* x, double bnorm) {
+    SolveOut o;
+    const int m = cfg.restart;
+    std::vector<void*> V(m + 1);
+    for (int i = 0; i <= m; ++i) V[i] = buf(G, prec, B_V0 + i);
+    void* tmp = buf(G, prec, B_TMP);
+    double beta = true_resid(b, x, V[0]);
+    while (true) {
+      o.relres = beta / bnorm;
+      if (!(beta == beta)) { o.status = VD_EBREAKDOWN; return o; }
+      if (o.relres <= cfg.rtol) { o.status = VD_OK; return o; }
+      if (o.iters >= cfg.max_iter) { o.status = VD_NOT_CONVERGED; return o; }
+      scale<R>(g, V[0], nullptr, 1.0 / beta, G->st);
+      gmres_init(G->dst, beta, m, G->st);
+      int k = 0;
+      for (int j = 0; j < m; ++j) {
+        apply(V[j], V[j + 1], true);
+        o.iters++;
+        VecPtrs P{};
+        for (int i = 0; i <= j; ++i) P.p[i] = V[i];
+        mdot<R>(g, V[j + 1], P, j + 1, false, G->partial, G->dst->red2, G->st);
+        mupdate<R>(g, V[j + 1], P, j + 1, G->dst->red2, true, G->partial, G->dst->red, G->st);
+        mupdate<R>(g, V[j + 1], P, j + 1, G->dst->red, false, G->partial, &G->dst->nrm2, G->st);
+        gmres_givens(G->dst, j, G->st);
+        scale<R>(g, V[j + 1], &G->dst->inv_h, 1.0, G->st);
+        sync_state(G);
+        k = j + 1;
+        if (G->hst->bad) { o.status = VD_EBREAKDOWN; return o; }
+        if (G->hst->resid / bnorm <= cfg.rtol || o.iters >= cfg.max_iter) break;
+      }
+      gmres_backsolve(G->dst, k, G->st);
+      VecPtrs P{};
+      for (int i = 0; i < k; ++i) P.p[i] = V[i];
+      lincomb<R>(g, tmp, P, k, G->dst->y, G->st);
+      OpParams pp = cfg.op;
+      precond_axpy<R>(g, pp, x, tmp, nullptr, 1.0, G->st);
+      beta = true_resid(b, x, V[0]);
+    }
+  }
+
+  SolveOut cg(const void* b, void* x, double bnorm) {
+    SolveOut o;
+    void* r = buf(G, prec, B_R);
+    void* p = buf(G, prec, B_P);
+    void* q = buf(G, prec, B_Q);
+    double rn = true_resid(b, x, r);
+    while (true) {
+      o.relres = rn / bnorm;
+      if (!(rn == rn)) { o.status = VD_EBREAKDOWN; return o; }
+      if (o.relres <= cfg.rtol) { o.status = VD_OK; return o; }
+      if (o.iters >= cfg.max_iter) { o.status = VD_NOT_CONVERGED; return o; }
+      // p = M^-1 r, rz = (r, M^-1 r)
+      OpParams op = cfg.op;
+      dot_rMr<R>(g, op, r, G->partial, G->dst->red, G->st);
+      cg_beta(G->dst, G->st);  // sets rz = red[0] (beta unused here)
+      if (op.precond) precond_apply<R>(g, op, r, p, G->st);
+      else ck(hipMemcpyAsync(p, r, G->nspec * elem_bytes(prec), hipMemcpyDeviceToDevice, G->st));
+      while (o.iters < cfg.max_iter) {
+        apply(p, q, false);
+        o.iters++;
+        VecPtrs P{};
+        P.p[0] = p;
+        mdot<R>(g, q, P, 1, false, G->partial, G->dst->red, G->st);
+        cg_alpha(G->dst, G->st);
+        cg_xr<R>(g, x, r, p, q, G->dst, G->partial, &G->dst->nrm2, G->st);
+        sync_state(G);
+        if (G->hst->bad) { o.status = VD_EBREAKDOWN; return o; }
+        if (std::sqrt(std::fmax(G->hst->nrm2, 0.0)) / bnorm <= cfg.rtol) break;
+        dot_rMr<R>(g, op, r, G->partial, G->dst->red, G->st);
+        cg_beta(G->dst, G->st);
+        cg_p<R>(g, op, p, r, G->dst, G->st);
+      }
+      rn = true_resid(b, x, r);
+    }
+  }
+
+  SolveOut rmr(const void* b, void* x, double bnorm) {
+    SolveOut o;
+    void* r = buf(G, prec, B_R);
+    void* w = buf(G, prec, B_W);
+    double rn = true_resid(b, x, r);
+    while (true) {
+      o.relres = rn / bnorm;
+      if (!(rn == rn)) { o.status = VD_EBREAKDOWN; return o; }
+      if (o.relres <= cfg.rtol) { o.status = VD_OK; return o; }
+      if (o.iters >= cfg.max_iter) { o.status = VD_NOT_CONVERGED; return o; }
+      while (o.iters < cfg.max_iter) {
+        apply(r, w, true);  // w = A M^-1 r
+        o.iters++;
+        VecPtrs P{};
+        P.p[0] = r;
+        mdot<R>(g, w, P, 1, true, G->partial, G->dst->red, G->st);
+        rmr_alpha(G->dst, G->st);
+        precond_axpy<R>(g, cfg.op, x, r, &G->dst->alpha, 1.0, G->st);
+        axpy_norm<R>(g, r, w, &G->dst->alpha, -1.0, G->partial, &G->dst->nrm2, G->st);
+        sync_state(G);
+        if (G->hst->bad) { o.status = VD_EBREAKDOWN; return o; }
+        if (std::sqrt(std::fmax(G->hst->nrm2, 0.0)) / bnorm <= cfg.rtol) break;
+      }
+      rn = true_resid(b, x, r);
+    }
+  }
+};
+
+// Solve A x = b in spectral space (b, x FP64 buffers of the grid).
+SolveOut solve_spectral(vd_grid* G, const vd_solve_opts& o, const OpParams& op, void* b64, void* x64,
+                        double bnorm, int* refinements) {
+  SolveCfg cfg{o.solver, o.restart, o.max_iter, o.rtol, op};
+  *refinements = 0;
+  if (bnorm == 0.0) {
+    ck(hipMemsetAsync(x64, 0, G->nspec * 16, G->st));
+    SolveOut s;
+    return s;
+  }
+  if (o.precision == VD_FP64) {
+    Krylov<double> K(G, 64, cfg);
+    return K.run(b64, x64, bnorm);
+  }
+  // FP32 inner solves inside FP64 iterative refinement
+  Krylov<double> K64(G, 64, cfg);
+  SolveCfg c32 = cfg;
+  c32.rtol = o.inner_rtol;
+  Krylov<float> K32(G, 32, c32);
+  void* r64 = buf(G, 64, B_R);
+  void* r32 = buf(G, 32, B_B);
+  void* d32 = buf(G, 32, B_X);
+  SolveOut out;
+  double rn = K64.true_resid(b64, x64, r64);
+  while (true) {
+    out.relres = rn / bnorm;
+    if (!(rn == rn)) { out.status = VD_EBREAKDOWN; return out; }
+    if (out.relres <= o.rtol) { out.status = VD_OK; return out; }
+    if (*refinements >= o.max_outer || out.iters >= o.max_iter) { out.status = VD_NOT_CONVERGED; return out; }
+    cast_d2f(G->g, r64, r32, 1.0 / rn, G->st);
+    ck(hipMemsetAsync(d32, 0, G->nspec * 8, G->st));
+    K32.cfg.max_iter = o.max_iter - out.iters;
+    SolveOut in = K32.run(r32, d32, 1.0);
+    out.iters += in.iters;
+    (*refinements)++;
+    if (in.status == VD_EBREAKDOWN) { out.status = VD_EBREAKDOWN; return out; }
+    axpy_f2d(G->g, d32, x64, rn, G->st);
+    rn = K64.true_resid(b64, x64, r64);
+  }
+}
+
+vd_status guard(vd_grid* G, vd_status (*fn)(vd_grid*, void*), void* ctx) {
+  try {
+    return fn(G, ctx);
+  } catch (const DevErr&) {
+    return VD_EDEVICE;
+  } catch (const std::bad_alloc&) {
+    hipGetLastError();
+    return VD_ENOMEM;
+  } catch (...) {
+    return VD_EDEVICE;
+  }
+}
+
+double host_norm_of(vd_grid* G, const void* spec64) {
+  VecPtrs P{};
+  mdot<double>(G->g, spec64, P, 0, true, G->partial, &G->dst->nrm2, G->st);
+  return std::sqrt(std::fmax(read_scalar(G, &G->dst->nrm2), 0.0));
+}
+
+bool opts_ok(const vd_solve_opts& o) {
+  if (o.solver < 0 || o.solver > 2) return false;
+  if (o.restart < 1 || o.restart > kMaxRestart) return false;
+  if (!(o.rtol > 0.0) || o.max_iter < 0) return false;
+  if (o.precision != VD_FP64 && o.precision != VD_FP32_REFINE) return false;
+  if (o.precision == VD_FP32_REFINE && (!(o.inner_rtol > 0.0) || o.inner_rtol >= 1.0 || o.max_outer < 1))
+    return false;
+  return true;
+}
+
+}  // namespace
+
+// ================================================================ C ABI
+
+extern "C" {
+
+void vd_default_opts(vd_solve_opts* o) {
+  if (!o) return;
+  o->solver = VD_GMRES;
+  o->restart = 30;
+  o->rtol = 1e-10;
+  o->max_iter = 2000;
+  o->precond = 1;
+  o->precision = VD_FP64;
+  o->inner_rtol = 1e-5;
+  o->max_outer = 10;
+  o->rho0 = NAN;
+  o->use_x0 = 0;
+}
+
+const char* vd_status_string(vd_status s) {
+  switch (s) {
+    case VD_OK: return "ok";
+    case VD_NOT_CONVERGED: return "not converged";
+    case VD_EINVAL: return "invalid argument";
+    case VD_ENOMEM: return "out of device memory";
+    case VD_EDOMAIN: return "density not strictly positive and finite";
+    case VD_EBREAKDOWN: return "Krylov breakdown (non-finite scalar)";
+    case VD_EDEVICE: return "HIP runtime error";
+    case VD_ETOOBIG: return "request larger than the budget";
+    case VD_ENOTSUP: return "not supported";
+  }
+  return "unknown status";
+}
+
+vd_status vd_grid_create(vd_grid** out, const vd_grid_desc* d, hipStream_t stream) {
+  if (!out) return VD_EINVAL;
+  *out = nullptr;
+  vd_status s = check_desc(d);
+  if (s != VD_OK) return s;
+  vd_grid* G = new (std::nothrow) vd_grid();
+  if (!G) return VD_ENOMEM;
+  G->ndim = d->ndim;
+  for (int i = 0; i < d->ndim; ++i) {
+    G->n[i] = d->n[i];
+    G->len[i] = d->length[i];
+  }
+  G->g = make_geom(d);
+  G->st = stream;
+  G->nreal = (size_t)G->g.nx * G->g.ny * G->g.nz;
+  G->nspec = (size_t)G->g.M * G->g.ny * G->g.nz;
+  try {
+    fill_twiddles(G);
+    ck(hipMalloc(&G->partial, nred_partial() * sizeof(double)));
+    ck(hipMalloc(&G->dsmall, 64 * sizeof(double)));
+    ck(hipMalloc(&G->dst, sizeof(DevState)));
+    ck(hipHostMalloc(&G->hst, sizeof(DevState)));
+    ck(hipMemset(G->dst, 0, sizeof(DevState)));
+    std::memset(G->hst, 0, sizeof(DevState));
+  } catch (...) {
+    vd_grid_destroy(G);
+    return VD_ENOMEM;
+  }
+  *out = G;
+  return VD_OK;
+}
+
+vd_status vd_grid_destroy(vd_grid* G) {
+  if (!G) return VD_EINVAL;
+  if (G->st) hipStreamSynchronize(G->st);
+  else hipDeviceSynchronize();
+  G->prof.release();
+  for (auto& kv : G->bufs) hipFree(kv.second);
+  hipFree(G->tw64);
+  hipFree(G->tw32);
+  hipFree(G->rho);
+  hipFree(G->a64);
+  hipFree(G->a32);
+  hipFree(G->rho32);
+  hipFree(G->partial);
+  hipFree(G->dsmall);
+  hipFree(G->dst);
+  if (G->hst) hipHostFree(G->hst);
+  delete G;
+  return VD_OK;
+}
+
+static vd_status set_density_impl(vd_grid* G, void* ctx) {
+  const double* rho = (const double*)ctx;
+  if (!G->rho) {
+    ck(hipMalloc(&G->rho, G->nreal * sizeof(double)));
+    ck(hipMalloc(&G->a64, G->nreal * sizeof(double)));
+    ck(hipMalloc(&G->a32, G->nreal * sizeof(float)));
+    ck(hipMalloc(&G->rho32, G->nreal * sizeof(float)));
+  }
+  ck(hipMemcpyAsync(G->rho, rho, G->nreal * sizeof(double), hipMemcpyDeviceToDevice, G->st));
+  density_setup(G->rho, G->nreal, G->a64, G->a32, G->rho32, G->partial, G->dsmall, G->st);
+  double h[4];
+  ck(hipMemcpyAsync(h, G->dsmall, 4 * sizeof(double), hipMemcpyDeviceToHost, G->st));
+  ck(hipStreamSynchronize(G->st));
+  if (h[3] != 0.0) {
+    G->has_rho = false;
+    return VD_EDOMAIN;
+  }
+  G->rho_mean = h[0] / (double)G->nreal;
+  G->rho_min = h[1];
+  G->rho_max = h[2];
+  G->has_rho = true;
+  return VD_OK;
+}
+
+vd_status vd_set_density(vd_grid* G, const double* rho) {
+  if (!G || !rho) return VD_EINVAL;
+  return guard(G, set_density_impl, (void*)rho);
+}
+
+struct ApplyCtx {
+  int kind, precision, is_prec;
+  double nu, rho0;
+  const double* x;
+  double* y;
+};
+
+static vd_status apply_impl(vd_grid* G, void* c) {
+  ApplyCtx* a = (ApplyCtx*)c;
+  void* s0 = buf(G, 64, B_B);
+  void* s1 = buf(G, 64, B_X);
+  fwd_transform(G->g, a->x, s0, nullptr, G->tw64, G->st);
+  OpParams p{};
+  p.kind = a->kind;
+  p.rho0 = std::isnan(a->rho0) ? G->rho_mean : a->rho0;
+  p.nu = a->nu;
+  p.precond = a->is_prec;
+  SolveCfg cfg{VD_GMRES, 1, 1, 1.0, p};
+  if (a->precision == VD_FP64) {
+    if (a->is_prec) precond_apply<double>(G->g, p, s0, s1, G->st);
+    else {
+      Krylov<double> K(G, 64, cfg);
+      K.apply(s0, s1, false);
+    }
+  } else {
+    void* f0 = buf(G, 32, B_B);
+    void* f1 = buf(G, 32, B_X);
+    cast_d2f(G->g, s0, f0, 1.0, G->st);
+    if (a->is_prec) precond_apply<float>(G->g, p, f0, f1, G->st);
+    else {
+      Krylov<float> K(G, 32, cfg);
+      K.apply(f0, f1, false);
+    }
+    cast_f2d(G->g, f1, s1, G->st);
+  }
+  inv_transform(G->g, s1, a->y, buf(G, 64, B_TMP), G->tw64, G->st);
+  ck(hipStreamSynchronize(G->st));
+  ck(hipGetLastError());
+  return VD_OK;
+}
+
+vd_status vd_apply_operator(vd_grid* G, int kind, int precision, double nu, const double* x, double* y) {
+  if (!G || !x || !y) return VD_EINVAL;
+  if (kind != VD_OP_PRESSURE && kind != VD_OP_HELMHOLTZ) return VD_EINVAL;
+  if (precision != VD_FP64 && precision != VD_FP32_REFINE) return VD_EINVAL;
+  if (!G->has_rho) return VD_EINVAL;
+  if (!(nu >= 0.0)) return VD_EINVAL;
+  ApplyCtx c{kind, precision, 0, nu, NAN, x, y};
+  return guard(G, apply_impl, &c);
+}
+
+vd_status vd_apply_precond(vd_grid* G, int kind, int precision, double nu, double rho0, const double* r,
+                           double* z) {
+  if (!G || !r || !z) return VD_EINVAL;
+  if (kind != VD_OP_PRESSURE && kind != VD_OP_HELMHOLTZ) return VD_EINVAL;
+  if (precision != VD_FP64 && precision != VD_FP32_REFINE) return VD_EINVAL;
+  if (std::isnan(rho0) && !G->has_rho) return VD_EINVAL;
+  if (!std::isnan(rho0) && !(rho0 > 0.0)) return VD_EINVAL;
+  if (!(nu >= 0.0)) return VD_EINVAL;
+  ApplyCtx c{kind, precision, 1, nu, rho0, r, z};
+  return guard(G, apply_impl, &c);
+}
+
+struct SolveCtx {
+  int kind;
+  double nu;
+  int ncomp;
+  const double* f;
+  double* x;
+  vd_solve_opts o;
+  vd_solve_info info;
+};
+
+static vd_status solve_impl(vd_grid* G, void* c) {
+  SolveCtx* s = (SolveCtx*)c;
+  auto t0 = std::chrono::steady_clock::now();
+  OpParams op{};
+  op.kind = s->kind;
+  op.rho0 = std::isnan(s->o.rho0) ? G->rho_mean : s->o.rho0;
+  op.nu = s->nu;
+  op.precond = s->o.precond ? 1 : 0;
+  void* b64 = buf(G, 64, B_B);
+  void* x64 = buf(G, 64, B_X);
+  vd_status worst = VD_OK;
+  s->info = vd_solve_info{};
+  for (int comp = 0; comp < s->ncomp; ++comp) {
+    const double* f = s->f + (size_t)comp * G->nreal;
+    double* x = s->x + (size_t)comp * G->nreal;
+    fwd_transform(G->g, f, b64, nullptr, G->tw64, G->st);
+    if (s->kind == VD_OP_PRESSURE) {
+      project_range(G->g, b64, G->dsmall, G->st);
+      scale<double>(G->g, b64, nullptr, -1.0, G->st);  // A = -L_rho, b = -f
+      s->info.rhs_null_norm = std::fmax(s->info.rhs_null_norm, read_scalar(G, G->dsmall));
+    }
+    if (s->o.use_x0) {
+      fwd_transform(G->g, x, x64, nullptr, G->tw64, G->st);
+      if (s->kind == VD_OP_PRESSURE) project_range(G->g, x64, G->dsmall + 1, G->st);
+    } else {
+      ck(hipMemsetAsync(x64, 0, G->nspec * 16, G->st));
+    }
+    double bnorm = host_norm_of(G, b64);
+    int refin = 0;
+    SolveOut so = solve_spectral(G, s->o, op, b64, x64, bnorm, &refin);
+    inv_transform(G->g, x64, x, buf(G, 64, B_TMP), G->tw64, G->st);
+    ck(hipStreamSynchronize(G->st));
+    ck(hipGetLastError());
+    s->info.iterations += so.iters;
+    s->info.refinements += refin;
+    s->info.rel_residual = std::fmax(s->info.rel_residual, so.relres);
+    if (so.status < 0) worst = (vd_status)so.status;
+    else if (so.status == VD_NOT_CONVERGED && worst == VD_OK) worst = VD_NOT_CONVERGED;
+    if (so.status < 0) break;
+  }
+  s->info.status = worst;
+  s->info.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return worst;
+}
+
+static vd_status solve_common(vd_grid* G, int kind, double nu, int ncomp, const double* f, double* x,
+                              const vd_solve_opts* opts, vd_solve_info* info) {
+  if (!G || !f || !x || ncomp < 1) return VD_EINVAL;
+  if (!G->has_rho) return VD_EINVAL;
+  SolveCtx c{};
+  c.kind = kind;
+  c.nu = nu;
+  c.ncomp = ncomp;
+  c.f = f;
+  c.x = x;
+  if (opts) c.o = *opts;
+  else vd_default_opts(&c.o);
+  if (!opts_ok(c.o)) return VD_EINVAL;
+  if (!std::isnan(c.o.rho0) && !(c.o.rho0 > 0.0)) return VD_EINVAL;
+  vd_status s = guard(G, solve_impl, &c);
+  c.info.status = s;
+  if (info) *info = c.info;
+  return s;
+}
+
+vd_status vd_solve_pressure(vd_grid* G, const double* f, double* p, const vd_solve_opts* opts, vd_solve_info* info) {
+  return solve_common(G, VD_OP_PRESSURE, 0.0, 1, f, p, opts, info);
+}
+
+vd_status vd_solve_helmholtz(vd_grid* G, double dt_nu, int ncomp, const double* g, double* u,
+                             const vd_solve_opts* opts, vd_solve_info* info) {
+  if (!(dt_nu >= 0.0) || !std::isfinite(dt_nu)) return VD_EINVAL;
+  return solve_common(G, VD_OP_HELMHOLTZ, dt_nu, ncomp, g, u, opts, info);
+}
+
+size_t vd_workspace_bytes(const vd_grid_desc* d, const vd_solve_opts* opts) {
+  if (check_desc(d) != VD_OK) return 0;
+  vd_solve_opts o;
+  if (opts) o = *opts;
+  else vd_default_opts(&o);
+  Geom g = make_geom(d);
+  const size_t nreal = (size_t)g.nx * g.ny * g.nz, nspec = (size_t)g.M * g.ny * g.nz;
+  size_t vecs;  // Krylov vectors of the method (work precision)
+  if (o.solver == VD_GMRES) vecs = (size_t)o.restart + 2;
+  else if (o.solver == VD_CG) vecs = 4;
+  else vecs = 3;
+  const size_t opwork = g.nz > 1 ? 3 : 0;
+  size_t bytes = 0;
+  bytes += nreal * (8 + 8 + 4 + 4);                 // rho, 1/rho, FP32 copies
+  bytes += nspec * 16 * 3;                          // b, x, tmp (FP64)
+  if (o.precision == VD_FP64) {
+    bytes += nspec * 16 * (vecs + opwork);
+  } else {
+    bytes += nspec * 16 * (1 + opwork);             // FP64 residual + FP64 operator work
+    bytes += nspec * 8 * (vecs + opwork + 2);       // FP32 basis, work, inner b and x
+  }
+  bytes += 2 * kTwEntries * (16 + 8) + nred_partial() * 8 + sizeof(DevState) + 512;
+  return bytes;
+}
+
+vd_status vd_profile_enable(vd_grid* G, int on) {
+  if (!G) return VD_EINVAL;
+  G->prof.flush();
+  G->prof.on = on != 0;
+  return VD_OK;
+}
+
+vd_status vd_profile_read(vd_grid* G, double* ms, long long* count, int nclass) {
+  if (!G || nclass < 0) return VD_EINVAL;
+  if (G->st) hipStreamSynchronize(G->st);
+  G->prof.flush();
+  for (int c = 0; c < nclass && c < Prof::kClasses; ++c) {
+    if (ms) ms[c] = G->prof.ms[c];
+    if (count) count[c] = G->prof.cnt[c];
+  }
+  for (int c = 0; c < Prof::kClasses; ++c) {
+    G->prof.ms[c] = 0;
+    G->prof.cnt[c] = 0;
+  }
+  return VD_OK;
+}
+
+}  // extern "C"

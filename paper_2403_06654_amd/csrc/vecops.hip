@@ -1,0 +1,578 @@
+// Krylov vector algebra and scalar recurrences (gfx950).
+//
+// Vector kernels stream packed spectral fields with grid-stride loops over a
+// fixed number of blocks; reductions accumulate in FP64 whatever the vector
+// precision, reduce within the block in a fixed tree (wave shuffles, then
+// LDS across the four waves) and finish in a single-block kernel that adds
+// the per-block partials in block order.
+#include <cmath>
+#include <cstdio>
+#include "spectral.hpp"
+#include "vecops.hpp"
+
+namespace vd {
+
+constexpr int kRedStride = kMaxVec + 2;
+
+size_t nred_partial() { return (size_t)kRedBlocks * kRedStride; }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Reduce acc[0..K) across a 256-thread block; thread 0 writes partial[0..K).
+template <int K>
+__device__ __forceinline__ void block_store(const double* acc, int k_used, double* partial) {
+  __shared__ double sh[4][K > 0 ? K : 1];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    if (i < k_used) {
+      double v = wave_sum(acc[i]);
+      if (lane == 0) sh[w][i] = v;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < k_used) {
+    int i = threadIdx.x;
+    partial[i] = ((sh[0][i] + sh[1][i]) + sh[2][i]) + sh[3][i];
+  }
+}
+
+__device__ __forceinline__ double spec_w(size_t e, int M) { return (e % M) == 0 ? 1.0 : 2.0; }
+
+__global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ partial, int nblk, int K, double scale,
+                                                double* __restrict__ out) {
+  __shared__ double sh[4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int i = 0; i < K; ++i) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 256) v += partial[(size_t)b * kRedStride + i];
+    v = wave_sum(v);
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) out[i] = (((sh[0] + sh[1]) + sh[2]) + sh[3]) * scale;
+    __syncthreads();
+  }
+}
+
+static void reduce(const double* partial, int K, double scale, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, partial, kRedBlocks, K, scale, out);
+}
+
+static size_t nspec(const Geom& g) { return (size_t)g.nz * g.ny * g.M; }
+
+// ------------------------------------------------------------ multi-dot
+
+template <typename R, int NV>
+__global__ __launch_bounds__(256) void k_mdot(const C2<R>* __restrict__ x, VecPtrs V, int nv, int want_norm,
+                                              size_t n, int M, double* __restrict__ partial) {
+  double acc[NV + 1];
+#pragma unroll
+  for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+    C2<R> xv = ldg(x + e);
+    const double w = spec_w(e, M);
+    const double xr = xv.x, xi = xv.y;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      if (i < nv) {
+        C2<R> v = ldg((const C2<R>*)V.p[i] + e);
+        acc[i] += w * ((double)v.x * xr + (double)v.y * xi);
+      }
+    }
+    if (want_norm) acc[NV] += w * (xr * xr + xi * xi);
+  }
+  double out[NV + 1];
+#pragma unroll
+  for (int i = 0; i <= NV; ++i) out[i] = acc[i];
+  // move the norm next to the used dots
+#pragma unroll
+  for (int i = 0; i < NV; ++i)
+    if (i == nv) out[i] = acc[NV];
+  block_store<NV + 1>(out, nv + (want_norm ? 1 : 0), partial + (size_t)blockIdx.x * kRedStride);
+}
+
+template <typename R>
+void mdot(const Geom& g, const void* x, const VecPtrs& V, int nv, bool want_norm, double* partial, double* out,
+          hipStream_t s) {
+  size_t n = nspec(g);
+  dim3 gr(kRedBlocks), bl(256);
+  const int wn = want_norm ? 1 : 0;
+  if (nv <= 1)
+    hipLaunchKernelGGL((k_mdot<R, 1>), gr, bl, 0, s, (const C2<R>*)x, V, nv, wn, n, g.M, partial);
+  else if (nv <= 2)
+    hipLaunchKernelGGL((k_mdot<R, 2>), gr, bl, 0, s, (const C2<R>*)x, V, nv, wn, n, g.M, partial);
+  else if (nv <= 4)
+    hipLaunchKernelGGL((k_mdot<R, 4>), gr, bl, 0, s, (const C2<R>*)x, V, nv, wn, n, g.M, partial);
+  else if (nv <= 8)
+    hipLaunchKernelGGL((k_mdot<R, 8>), gr, bl, 0, s, (const C2<R>*)x, V, nv, wn, n, g.M, partial);
+  else if (nv <= 16)
+    hipLaunchKernelGGL((k_mdot<R, 16>), gr, bl, 0, s, (const C2<R>*)x, V, nv, wn, n, g.M, partial);
+  else
+    hipLaunchKernelGGL((k_mdot<R, kMaxVec>), gr, bl, 0, s, (const C2<R>*)x, V, nv, wn, n, g.M, partial);
+  reduce(partial, nv + wn, g.ntot_inv, out, s);
+}
+
+// --------------------------------------------------------- multi-update
+
+template <typename R, int NV>
+__global__ __launch_bounds__(256) void k_mupdate(C2<R>* __restrict__ x, VecPtrs V, int nv,
+                                                 const double* __restrict__ coef, int want_dots, size_t n, int M,
+                                                 double* __restrict__ partial) {
+  double c[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) c[i] = i < nv ? coef[i] : 0.0;
+  double acc[NV + 1];
+#pragma unroll
+  for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+    C2<R> xv = ldg(x + e);
+    double xr = xv.x, xi = xv.y;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      if (i < nv) {
+        C2<R> v = ldg((const C2<R>*)V.p[i] + e);
+        xr -= c[i] * (double)v.x;
+        xi -= c[i] * (double)v.y;
+      }
+    }
+    C2<R> nx{R(xr), R(xi)};
+    stg(x + e, nx);
+    const double w = spec_w(e, M);
+    const double yr = nx.x, yi = nx.y;
+    if (want_dots) {
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        if (i < nv) {
+          C2<R> v = ldg((const C2<R>*)V.p[i] + e);
+          acc[i] += w * ((double)v.x * yr + (double)v.y * yi);
+        }
+      }
+    }
+    acc[NV] += w * (yr * yr + yi * yi);
+  }
+  double out[NV + 1];
+  const int k = want_dots ? nv : 0;
+#pragma unroll
+  for (int i = 0; i <= NV; ++i) out[i] = acc[i];
+#pragma unroll
+  for (int i = 0; i <= NV; ++i)
+    if (i == k) out[i] = acc[NV];
+  block_store<NV + 1>(out, k + 1, partial + (size_t)blockIdx.x * kRedStride);
+}
+
+template <typename R>
+void mupdate(const Geom& g, void* x, const VecPtrs& V, int nv, const double* coef, bool want_dots, double* partial,
+             double* out, hipStream_t s) {
+  size_t n = nspec(g);
+  dim3 gr(kRedBlocks), bl(256);
+  const int wd = want_dots ? 1 : 0;
+  if (nv <= 1)
+    hipLaunchKernelGGL((k_mupdate<R, 1>), gr, bl, 0, s, (C2<R>*)x, V, nv, coef, wd, n, g.M, partial);
+  else if (nv <= 2)
+    hipLaunchKernelGGL((k_mupdate<R, 2>), gr, bl, 0, s, (C2<R>*)x, V, nv, coef, wd, n, g.M, partial);
+  else if (nv <= 4)
+    hipLaunchKernelGGL((k_mupdate<R, 4>), gr, bl, 0, s, (C2<R>*)x, V, nv, coef, wd, n, g.M, partial);
+  else if (nv <= 8)
+    hipLaunchKernelGGL((k_mupdate<R, 8>), gr, bl, 0, s, (C2<R>*)x, V, nv, coef, wd, n, g.M, partial);
+  else if (nv <= 16)
+    hipLaunchKernelGGL((k_mupdate<R, 16>), gr, bl, 0, s, (C2<R>*)x, V, nv, coef, wd, n, g.M, partial);
+  else
+    hipLaunchKernelGGL((k_mupdate<R, kMaxVec>), gr, bl, 0, s, (C2<R>*)x, V, nv, coef, wd, n, g.M, partial);
+  reduce(partial, (want_dots ? nv : 0) + 1, g.ntot_inv, out, s);
+}
+
+// ------------------------------------------------------------- lincomb
+
+template <typename R, int NV>
+__global__ __launch_bounds__(256) void k_lincomb(C2<R>* __restrict__ z, VecPtrs V, int nv,
+                                                 const double* __restrict__ coef, size_t n) {
+  double c[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) c[i] = i < nv ? coef[i] : 0.0;
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+    double zr = 0.0, zi = 0.0;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      if (i < nv) {
+        C2<R> v = ldg((const C2<R>*)V.p[i] + e);
+        zr += c[i] * (double)v.x;
+        zi += c[i] * (double)v.y;
+      }
+    }
+    stg(z + e, C2<R>{R(zr), R(zi)});
+  }
+}
+
+template <typename R>
+void lincomb(const Geom& g, void* z, const VecPtrs& V, int nv, const double* coef, hipStream_t s) {
+  size_t n = nspec(g);
+  dim3 gr(kRedBlocks * 2), bl(256);
+  if (nv <= 4)
+    hipLaunchKernelGGL((k_lincomb<R, 4>), gr, bl, 0, s, (C2<R>*)z, V, nv, coef, n);
+  else if (nv <= 16)
+    hipLaunchKernelGGL((k_lincomb<R, 16>), gr, bl, 0, s, (C2<R>*)z, V, nv, coef, n);
+  else
+    hipLaunchKernelGGL((k_lincomb<R, kMaxVec>), gr, bl, 0, s, (C2<R>*)z, V, nv, coef, n);
+}
+
+// ---------------------------------------------------------- elementwise
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_scale(C2<R>* __restrict__ v, const double* __restrict__ sd, double sh,
+                                               size_t n) {
+  const R s = R((sd ? *sd : 1.0) * sh);
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256)
+    stg(v + e, cscale(ldg(v + e), s));
+}
+template <typename R>
+void scale(const Geom& g, void* v, const double* s_dev, double s_host, hipStream_t s) {
+  hipLaunchKernelGGL((k_scale<R>), dim3(kRedBlocks * 2), dim3(256), 0, s, (C2<R>*)v, s_dev, s_host, nspec(g));
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_sub_norm(const C2<R>* __restrict__ b, const C2<R>* __restrict__ q,
+                                                  C2<R>* __restrict__ r, size_t n, int M,
+                                                  double* __restrict__ partial) {
+  double acc = 0.0;
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+    C2<R> bv = ldg(b + e), qv = ldg(q + e);
+    C2<R> rv = bv - qv;
+    stg(r + e, rv);
+    acc += spec_w(e, M) * ((double)rv.x * rv.x + (double)rv.y * rv.y);
+  }
+  block_store<1>(&acc, 1, partial + (size_t)blockIdx.x * kRedStride);
+}
+template <typename R>
+void sub_norm(const Geom& g, const void* b, const void* q, void* r, double* partial, double* out, hipStream_t s) {
+  hipLaunchKernelGGL((k_sub_norm<R>), dim3(kRedBlocks), dim3(256), 0, s, (const C2<R>*)b, (const C2<R>*)q,
+                     (C2<R>*)r, nspec(g), g.M, partial);
+  reduce(partial, 1, g.ntot_inv, out, s);
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_precond_axpy(C2<R>* __restrict__ x, const C2<R>* __restrict__ z, Geom g,
+                                                      int kind, double rho0, double nu, const double* ad, double ah,
+                                                      size_t n) {
+  const double a = (ad ? *ad : 1.0) * ah;
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+    C2<R> mz = precond_at<R>(z, e, g, kind, rho0, nu);
+    C2<R> xv = ldg(x + e);
+    stg(x + e, C2<R>{R(xv.x + a * mz.x), R(xv.y + a * mz.y)});
+  }
+}
+template <typename R>
+void precond_axpy(const Geom& g, const OpParams& p, void* x, const void* z, const double* a_dev, double a_host,
+                  hipStream_t s) {
+  hipLaunchKernelGGL((k_precond_axpy<R>), dim3(kRedBlocks * 2), dim3(256), 0, s, (C2<R>*)x, (const C2<R>*)z, g,
+                     p.precond ? p.kind : -1, p.rho0, p.nu, a_dev, a_host, nspec(g));
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_dot_rMr(const C2<R>* __restrict__ r, Geom g, int kind, double rho0,
+                                                 double nu, size_t n, double* __restrict__ partial) {
+  double acc = 0.0;
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+    C2<R> rv = ldg(r + e), mz = precond_at<R>(r, e, g, kind, rho0, nu);
+    acc += spec_w(e, g.M) * ((double)rv.x * mz.x + (double)rv.y * mz.y);
+  }
+  block_store<1>(&acc, 1, partial + (size_t)blockIdx.x * kRedStride);
+}
+template <typename R>
+void dot_rMr(const Geom& g, const OpParams& p, const void* r, double* partial, double* out, hipStream_t s) {
+  hipLaunchKernelGGL((k_dot_rMr<R>), dim3(kRedBlocks), dim3(256), 0, s, (const C2<R>*)r, g,
+                     p.precond ? p.kind : -1, p.rho0, p.nu, nspec(g), partial);
+  reduce(partial, 1, g.ntot_inv, out, s);
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_cg_xr(C2<R>* __restrict__ x, C2<R>* __restrict__ r,
+                                               const C2<R>* __restrict__ p, const C2<R>* __restrict__ q,
+                                               const DevState* __restrict__ st, size_t n, int M,
+                                               double* __restrict__ partial) {
+  const double a = st->alpha;
+  double acc = 0.0;
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+    C2<R> xv = ldg(x + e), rv = ldg(r + e), pv = ldg(p + e), qv = ldg(q + e);
+    stg(x + e, C2<R>{R(xv.x + a * pv.x), R(xv.y + a * pv.y)});
+    C2<R> nr{R(rv.x - a * qv.x), R(rv.y - a * qv.y)};
+    stg(r + e, nr);
+    acc += spec_w(e, M) * ((double)nr.x * nr.x + (double)nr.y * nr.y);
+  }
+  block_store<1>(&acc, 1, partial + (size_t)blockIdx.x * kRedStride);
+}
+template <typename R>
+void cg_xr(const Geom& g, void* x, void* r, const void* p, const void* q, const DevState* st, double* partial,
+           double* out, hipStream_t s) {
+  hipLaunchKernelGGL((k_cg_xr<R>), dim3(kRedBlocks), dim3(256), 0, s, (C2<R>*)x, (C2<R>*)r, (const C2<R>*)p,
+                     (const C2<R>*)q, st, nspec(g), g.M, partial);
+  reduce(partial, 1, g.ntot_inv, out, s);
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_cg_p(C2<R>* __restrict__ p, const C2<R>* __restrict__ r, Geom g, int kind,
+                                              double rho0, double nu, const DevState* __restrict__ st, size_t n) {
+  const double b = st->beta;
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+    C2<R> mz = precond_at<R>(r, e, g, kind, rho0, nu);
+    C2<R> pv = ldg(p + e);
+    stg(p + e, C2<R>{R(mz.x + b * pv.x), R(mz.y + b * pv.y)});
+  }
+}
+template <typename R>
+void cg_p(const Geom& g, const OpParams& op, void* p, const void* r, const DevState* st, hipStream_t s) {
+  hipLaunchKernelGGL((k_cg_p<R>), dim3(kRedBlocks * 2), dim3(256), 0, s, (C2<R>*)p, (const C2<R>*)r, g,
+                     op.precond ? op.kind : -1, op.rho0, op.nu, st, nspec(g));
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_axpy_norm(C2<R>* __restrict__ r, const C2<R>* __restrict__ w,
+                                                   const double* __restrict__ ad, double sign, size_t n, int M,
+                                                   double* __restrict__ partial) {
+  const double a = *ad * sign;
+  double acc = 0.0;
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+    C2<R> rv = ldg(r + e), wv = ldg(w + e);
+    C2<R> nr{R(rv.x + a * wv.x), R(rv.y + a * wv.y)};
+    stg(r + e, nr);
+    acc += spec_w(e, M) * ((double)nr.x * nr.x + (double)nr.y * nr.y);
+  }
+  block_store<1>(&acc, 1, partial + (size_t)blockIdx.x * kRedStride);
+}
+template <typename R>
+void axpy_norm(const Geom& g, void* r, const void* w, const double* a_dev, double sign, double* partial, double* out,
+               hipStream_t s) {
+  hipLaunchKernelGGL((k_axpy_norm<R>), dim3(kRedBlocks), dim3(256), 0, s, (C2<R>*)r, (const C2<R>*)w, a_dev, sign,
+                     nspec(g), g.M, partial);
+  reduce(partial, 1, g.ntot_inv, out, s);
+}
+
+// ---------------------------------------------------------------- casts
+
+__global__ __launch_bounds__(256) void k_cast_d2f(const C2<double>* __restrict__ a, C2<float>* __restrict__ b,
+                                                  double s, size_t n) {
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+    C2<double> v = ldg(a + e);
+    stg(b + e, C2<float>{float(v.x * s), float(v.y * s)});
+  }
+}
+__global__ __launch_bounds__(256) void k_axpy_f2d(const C2<float>* __restrict__ a, C2<double>* __restrict__ b,
+                                                  double s, size_t n) {
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+    C2<float> v = ldg(a + e);
+    C2<double> w = ldg(b + e);
+    stg(b + e, C2<double>{w.x + s * (double)v.x, w.y + s * (double)v.y});
+  }
+}
+__global__ __launch_bounds__(256) void k_cast_f2d(const C2<float>* __restrict__ a, C2<double>* __restrict__ b,
+                                                  size_t n) {
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+    C2<float> v = ldg(a + e);
+    stg(b + e, C2<double>{(double)v.x, (double)v.y});
+  }
+}
+void cast_d2f(const Geom& g, const void* src, void* dst, double s, hipStream_t st) {
+  hipLaunchKernelGGL(k_cast_d2f, dim3(kRedBlocks * 2), dim3(256), 0, st, (const C2<double>*)src, (C2<float>*)dst, s,
+                     nspec(g));
+}
+void axpy_f2d(const Geom& g, const void* src, void* dst, double s, hipStream_t st) {
+  hipLaunchKernelGGL(k_axpy_f2d, dim3(kRedBlocks * 2), dim3(256), 0, st, (const C2<float>*)src, (C2<double>*)dst, s,
+                     nspec(g));
+}
+void cast_f2d(const Geom& g, const void* src, void* dst, hipStream_t st) {
+  hipLaunchKernelGGL(k_cast_f2d, dim3(kRedBlocks * 2), dim3(256), 0, st, (const C2<float>*)src, (C2<double>*)dst,
+                     nspec(g));
+}
+
+// ---------------------------------------------------------- range projection
+
+__global__ void k_project(C2<double>* __restrict__ s, Geom g, double* removed) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double acc = 0.0;
+  const int nkz = g.nz > 1 ? 2 : 1, nky = g.ny > 1 ? 2 : 1;
+  for (int a = 0; a < nkz; ++a)
+    for (int b = 0; b < nky; ++b) {
+      size_t kz = a ? g.nz / 2 : 0, ky = b ? g.ny / 2 : 0;
+      size_t e = (kz * g.ny + ky) * g.M;
+      C2<double> v = s[e];
+      acc += v.x * v.x + v.y * v.y;
+      s[e] = C2<double>{0.0, 0.0};
+    }
+  *removed = sqrt(acc * g.ntot_inv);
+}
+void project_range(const Geom& g, void* spec, double* removed, hipStream_t st) {
+  hipLaunchKernelGGL(k_project, dim3(1), dim3(64), 0, st, (C2<double>*)spec, g, removed);
+}
+
+// ------------------------------------------------------- scalar kernels
+
+__device__ __forceinline__ int ldh() { return kMaxRestart + 1; }
+
+__global__ void k_gmres_init(DevState* st, double beta, int m) {
+  if (threadIdx.x != 0) return;
+  for (int i = 0; i < (kMaxRestart + 1) * kMaxRestart; ++i) st->H[i] = 0.0;
+  for (int i = 0; i <= m && i <= kMaxRestart; ++i) st->g[i] = 0.0;
+  st->g[0] = beta;
+  st->resid = beta;
+  st->bad = 0;
+}
+
+// Column j of the Hessenberg matrix: h (first Gram-Schmidt pass, red2) plus
+// the correction of the second pass (red); subdiagonal = norm after both.
+__global__ void k_gmres_givens(DevState* st, int j) {
+  if (threadIdx.x != 0) return;
+  double* H = st->H;
+  const int ld = ldh();
+  for (int i = 0; i <= j; ++i) H[i + j * ld] = st->red2[i] + st->red[i];
+  const double hn = sqrt(fmax(st->nrm2, 0.0));
+  for (int i = 0; i < j; ++i) {
+    double a = H[i + j * ld], b = H[i + 1 + j * ld];
+    H[i + j * ld] = st->cs[i] * a + st->sn[i] * b;
+    H[i + 1 + j * ld] = -st->sn[i] * a + st->cs[i] * b;
+  }
+  const double a = H[j + j * ld];
+  const double rr = hypot(a, hn);
+  double c = 1.0, s = 0.0;
+  if (rr > 0.0) {
+    c = a / rr;
+    s = hn / rr;
+  }
+  st->cs[j] = c;
+  st->sn[j] = s;
+  H[j + j * ld] = rr;
+  H[j + 1 + j * ld] = 0.0;
+  st->g[j + 1] = -s * st->g[j];
+  st->g[j] = c * st->g[j];
+  st->resid = fabs(st->g[j + 1]);
+  st->inv_h = hn > 0.0 ? 1.0 / hn : 0.0;
+  if (!isfinite(rr) || !isfinite(st->g[j + 1])) st->bad = 1;
+}
+
+__global__ void k_gmres_backsolve(DevState* st, int k) {
+  if (threadIdx.x != 0) return;
+  const int ld = ldh();
+  for (int i = k - 1; i >= 0; --i) {
+    double s = st->g[i];
+    for (int l = i + 1; l < k; ++l) s -= st->H[i + l * ld] * st->y[l];
+    const double d = st->H[i + i * ld];
+    st->y[i] = d != 0.0 ? s / d : 0.0;
+  }
+}
+
+__global__ void k_cg_alpha(DevState* st) {
+  if (threadIdx.x) return;
+  const double pq = st->red[0];
+  st->alpha = pq != 0.0 ? st->rz / pq : 0.0;
+  if (!isfinite(st->alpha) || pq <= 0.0) st->bad = 1;
+}
+__global__ void k_cg_beta(DevState* st) {
+  if (threadIdx.x) return;
+  const double rzn = st->red[0];
+  st->beta = st->rz != 0.0 ? rzn / st->rz : 0.0;
+  st->rz = rzn;
+  if (!isfinite(st->beta)) st->bad = 1;
+}
+__global__ void k_rmr_alpha(DevState* st) {
+  if (threadIdx.x) return;
+  const double ww = st->red[1];
+  st->alpha = ww > 0.0 ? st->red[0] / ww : 0.0;
+  if (!isfinite(st->alpha)) st->bad = 1;
+}
+
+void gmres_init(DevState* st, double beta, int m, hipStream_t s) {
+  hipLaunchKernelGGL(k_gmres_init, dim3(1), dim3(64), 0, s, st, beta, m);
+}
+void gmres_givens(DevState* st, int j, hipStream_t s) { hipLaunchKernelGGL(k_gmres_givens, dim3(1), dim3(64), 0, s, st, j); }
+void gmres_backsolve(DevState* st, int k, hipStream_t s) {
+  hipLaunchKernelGGL(k_gmres_backsolve, dim3(1), dim3(64), 0, s, st, k);
+}
+void cg_alpha(DevState* st, hipStream_t s) { hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(64), 0, s, st); }
+void cg_beta(DevState* st, hipStream_t s) { hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(64), 0, s, st); }
+void rmr_alpha(DevState* st, hipStream_t s) { hipLaunchKernelGGL(k_rmr_alpha, dim3(1), dim3(64), 0, s, st); }
+
+// --------------------------------------------------------- density set-up
+
+__global__ __launch_bounds__(256) void k_density(const double* __restrict__ rho, size_t n, double* __restrict__ a64,
+                                                 float* __restrict__ a32, float* __restrict__ r32,
+                                                 double* __restrict__ partial) {
+  double sum = 0.0, mn = INFINITY, mx = -INFINITY, bad = 0.0;
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+    double r = rho[e];
+    if (!(r > 0.0) || !isfinite(r)) bad += 1.0;
+    sum += r;
+    mn = fmin(mn, r);
+    mx = fmax(mx, r);
+    double a = 1.0 / r;
+    a64[e] = a;
+    a32[e] = (float)a;
+    r32[e] = (float)r;
+  }
+  __shared__ double sh[4][4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int o = 32; o > 0; o >>= 1) {
+    sum += __shfl_xor(sum, o, 64);
+    mn = fmin(mn, __shfl_xor(mn, o, 64));
+    mx = fmax(mx, __shfl_xor(mx, o, 64));
+    bad += __shfl_xor(bad, o, 64);
+  }
+  if (lane == 0) {
+    sh[w][0] = sum;
+    sh[w][1] = mn;
+    sh[w][2] = mx;
+    sh[w][3] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double* p = partial + (size_t)blockIdx.x * kRedStride;
+    p[0] = ((sh[0][0] + sh[1][0]) + sh[2][0]) + sh[3][0];
+    p[1] = fmin(fmin(sh[0][1], sh[1][1]), fmin(sh[2][1], sh[3][1]));
+    p[2] = fmax(fmax(sh[0][2], sh[1][2]), fmax(sh[2][2], sh[3][2]));
+    p[3] = ((sh[0][3] + sh[1][3]) + sh[2][3]) + sh[3][3];
+  }
+}
+__global__ void k_density_fin(const double* __restrict__ partial, int nblk, double* out) {
+  if (threadIdx.x) return;
+  double sum = 0.0, mn = INFINITY, mx = -INFINITY, bad = 0.0;
+  for (int b = 0; b < nblk; ++b) {
+    const double* p = partial + (size_t)b * kRedStride;
+    sum += p[0];
+    mn = fmin(mn, p[1]);
+    mx = fmax(mx, p[2]);
+    bad += p[3];
+  }
+  out[0] = sum;
+  out[1] = mn;
+  out[2] = mx;
+  out[3] = bad;
+}
+void density_setup(const double* rho, size_t n, double* a64, float* a32, float* rho32, double* partial, double* out,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(k_density, dim3(kRedBlocks), dim3(256), 0, s, rho, n, a64, a32, rho32, partial);
+  hipLaunchKernelGGL(k_density_fin, dim3(1), dim3(64), 0, s, partial, kRedBlocks, out);
+}
+
+// ------------------------------------------------------- instantiations
+
+#define VD_INST(R)                                                                                             \
+  template void mdot<R>(const Geom&, const void*, const VecPtrs&, int, bool, double*, double*, hipStream_t);   \
+  template void mupdate<R>(const Geom&, void*, const VecPtrs&, int, const double*, bool, double*, double*,     \
+                           hipStream_t);                                                                       \
+  template void lincomb<R>(const Geom&, void*, const VecPtrs&, int, const double*, hipStream_t);               \
+  template void scale<R>(const Geom&, void*, const double*, double, hipStream_t);                              \
+  template void sub_norm<R>(const Geom&, const void*, const void*, void*, double*, double*, hipStream_t);      \
+  template void precond_axpy<R>(const Geom&, const OpParams&, void*, const void*, const double*, double,       \
+                                hipStream_t);                                                                  \
+  template void dot_rMr<R>(const Geom&, const OpParams&, const void*, double*, double*, hipStream_t);          \
+  template void cg_xr<R>(const Geom&, void*, void*, const void*, const void*, const DevState*, double*,       \
+                         double*, hipStream_t);                                                                \
+  template void cg_p<R>(const Geom&, const OpParams&, void*, const void*, const DevState*, hipStream_t);       \
+  template void axpy_norm<R>(const Geom&, void*, const void*, const double*, double, double*, double*,         \
+                             hipStream_t);
+
+VD_INST(double)
+VD_INST(float)
+
+}  // namespace vd

@@ -1,0 +1,111 @@
+// Krylov vector algebra on packed spectral fields (host interface).
+//
+// Inner products are the Euclidean products of the physical grid values,
+// evaluated from the packed half-spectrum by Parseval's identity: weight 1
+// on the kx = 0 slot (which holds kx = 0 and kx = nx/2), 2 elsewhere,
+// overall 1 / N.  Every reduction is two-stage with a fixed block count and
+// a fixed summation order, so results are bitwise reproducible and do not
+// depend on what else runs on the device.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include "passes.hpp"
+
+namespace vd {
+
+constexpr int kMaxVec = 34;       // vectors per multi-dot / multi-update
+constexpr int kRedBlocks = 512;   // partial sums per reduction
+
+struct VecPtrs {
+  const void* p[kMaxVec];
+};
+
+// Solver scalars kept on the device (FP64 regardless of vector precision).
+constexpr int kMaxRestart = 32;
+struct DevState {
+  double H[(kMaxRestart + 1) * kMaxRestart];  // column-major, ld = kMaxRestart + 1
+  double cs[kMaxRestart], sn[kMaxRestart], g[kMaxRestart + 1], y[kMaxRestart];
+  double red[kMaxVec + 2];   // outputs of the last reduction
+  double red2[kMaxVec + 2];  // outputs of the previous reduction
+  double inv_h;              // scale of the newest basis vector
+  double alpha, beta, rz, rz_new;
+  // mirrored to the host after each step
+  double resid;              // estimated (GMRES) or recursive residual norm
+  double nrm2;               // last computed squared norm
+  int bad;                   // non-finite scalar seen
+  int pad;
+};
+
+// partial[b][i] = sum_e w_e Re(conj(V_i[e]) x[e]) (i < nv), plus |x|^2 at
+// index nv when want_norm.  Then reduce into st->red (times 1/N).
+template <typename R>
+void mdot(const Geom& g, const void* x, const VecPtrs& V, int nv, bool want_norm, double* partial,
+          double* out, hipStream_t s);
+
+// x -= sum_i c_i V_i with c read from `coef` (device); then (optionally)
+// dots of V_i with the updated x and its squared norm, reduced into `out`.
+template <typename R>
+void mupdate(const Geom& g, void* x, const VecPtrs& V, int nv, const double* coef, bool want_dots,
+             double* partial, double* out, hipStream_t s);
+
+// z = sum_i c_i V_i
+template <typename R>
+void lincomb(const Geom& g, void* z, const VecPtrs& V, int nv, const double* coef, hipStream_t s);
+
+// v *= (*s_dev) * s_host
+template <typename R>
+void scale(const Geom& g, void* v, const double* s_dev, double s_host, hipStream_t s);
+
+// r = b - q, and |r|^2 reduced into out[0]
+template <typename R>
+void sub_norm(const Geom& g, const void* b, const void* q, void* r, double* partial, double* out,
+              hipStream_t s);
+
+// x += a M^-1 z   (a = (*a_dev) * a_host; M^-1 diagonal, Helmholtz kx = 0 mirrored)
+template <typename R>
+void precond_axpy(const Geom& g, const OpParams& p, void* x, const void* z, const double* a_dev,
+                  double a_host, hipStream_t s);
+
+// (r, M^-1 r) reduced into out[0]
+template <typename R>
+void dot_rMr(const Geom& g, const OpParams& p, const void* r, double* partial, double* out,
+             hipStream_t s);
+
+// CG: x += alpha p; r -= alpha q; |r|^2 -> out[0]   (alpha = st->alpha)
+template <typename R>
+void cg_xr(const Geom& g, void* x, void* r, const void* p, const void* q, const DevState* st,
+           double* partial, double* out, hipStream_t s);
+// CG: p = M^-1 r + beta p   (beta = st->beta)
+template <typename R>
+void cg_p(const Geom& g, const OpParams& op, void* p, const void* r, const DevState* st, hipStream_t s);
+// RMR: r -= alpha w; |r|^2 -> out[0]
+template <typename R>
+void axpy_norm(const Geom& g, void* r, const void* w, const double* a_dev, double sign, double* partial,
+               double* out, hipStream_t s);
+
+// precision casts between spectral vectors: dst(float) = src(double) * s
+void cast_d2f(const Geom& g, const void* src, void* dst, double s, hipStream_t st);
+// dst(double) += src(float) * s
+void axpy_f2d(const Geom& g, const void* src, void* dst, double s, hipStream_t st);
+void cast_f2d(const Geom& g, const void* src, void* dst, hipStream_t st);
+
+// Zero the 2^D nullspace slots of a packed pressure spectrum; write the
+// removed Euclidean norm (physical units) to *removed.
+void project_range(const Geom& g, void* spec, double* removed, hipStream_t st);
+
+// Scalar kernels (one thread) of the Krylov methods.
+void gmres_init(DevState* st, double beta, int m, hipStream_t s);
+void gmres_givens(DevState* st, int j, hipStream_t s);   // uses red (h), red2 (c) and nrm2
+void gmres_backsolve(DevState* st, int k, hipStream_t s);
+void cg_alpha(DevState* st, hipStream_t s);   // alpha = rz / red[0]
+void cg_beta(DevState* st, hipStream_t s);    // beta = red[0] / rz; rz = red[0]
+void rmr_alpha(DevState* st, hipStream_t s);  // alpha = red[0] / red[1]
+
+// Density set-up: a = 1/rho and copies, min/max/sum reductions.
+void density_setup(const double* rho, size_t n, double* a64, float* a32, float* rho32, double* partial,
+                   double* out /* [sum, min, max, nonfinite_or_nonpositive] */, hipStream_t s);
+
+size_t nred_partial();  // doubles needed for `partial`
+
+}  // namespace vd

@@ -1,0 +1,96 @@
+"""C-ABI library checks that need no GPU: the built library loads, exports
+every function include/vdsolve.h declares, and its host-only entry points
+(defaults, sizing, status strings, argument validation) behave."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+from paper_2403_06654_amd import api
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "vdsolve.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(vd_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = api.lib()
+    names = declared_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(api._SIGS), "binding and header disagree"
+
+
+def test_defaults():
+    o = api.vd_solve_opts()
+    api.lib().vd_default_opts(ctypes.byref(o))
+    assert o.solver == api.VD_GMRES and o.restart == 30 and o.rtol == 1e-10
+    assert o.precond == 1 and o.precision == api.VD_FP64 and math.isnan(o.rho0)
+    assert o.max_iter == 2000 and o.inner_rtol == 1e-5 and o.max_outer == 10
+
+
+def test_status_strings():
+    for s in range(-7, 2):
+        assert api.vd_status_string(s)
+    assert api.vd_status_string(0) == "ok"
+
+
+def test_workspace_bytes():
+    wb = api.workspace_bytes
+    c3 = wb((256, 256, 256))
+    n = 256 ** 3
+    # GMRES(30): 32 FP64 spectral vectors + operator work + b, x, tmp + coefficients
+    assert c3 > 32 * n * 8 and c3 < 45 * n * 8
+    assert wb((256, 256, 256), precision="fp32_refine") < c3
+    assert wb((256, 256, 256), solver="cg") < c3
+    assert wb((512, 512, 512)) > 7 * c3
+    assert wb((1024, 1024)) > wb((128, 128)) * 50
+    # invalid descriptors
+    assert wb((100, 100)) == 0
+    assert wb((8,)) == 0
+    assert wb((2048,)) == 0
+    d = api.make_desc((64, 64))
+    d.length[0] = -1.0
+    assert api.lib().vd_workspace_bytes(ctypes.byref(d), None) == 0
+
+
+def test_grid_create_rejects_bad_descriptors_without_touching_the_device():
+    h = ctypes.c_void_p()
+    for shape in [(100,), (8, 8), (4096,)]:
+        d = api.make_desc(shape)
+        assert api.lib().vd_grid_create(ctypes.byref(h), ctypes.byref(d), None) == -1
+    d = api.make_desc((64,))
+    d.ndim = 4
+    assert api.lib().vd_grid_create(ctypes.byref(h), ctypes.byref(d), None) == -1
+    d = api.make_desc((64,))
+    d.basis[0] = 1
+    assert api.lib().vd_grid_create(ctypes.byref(h), ctypes.byref(d), None) == -7
+    assert api.lib().vd_grid_create(None, ctypes.byref(d), None) == -1
+
+
+def test_null_handles_are_rejected():
+    L = api.lib()
+    assert L.vd_grid_destroy(None) == -1
+    assert L.vd_set_density(None, None) == -1
+    assert L.vd_apply_operator(None, 0, 0, 0.0, None, None) == -1
+    assert L.vd_solve_pressure(None, None, None, None, None) == -1
+    assert L.vd_solve_helmholtz(None, 1e-3, 1, None, None, None, None) == -1
+    assert L.vd_profile_enable(None, 1) == -1
+
+
+def test_build_flags_and_product_path_independent_of_oracle():
+    # the product package never imports the oracle
+    pkg = os.path.join(ROOT, "paper_2403_06654_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".cpp", ".hpp", ".h")):
+                txt = open(os.path.join(dirpath, fn)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt, fn

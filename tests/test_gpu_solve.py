@@ -1,0 +1,210 @@
+"""GPU solves checked by the oracle: the returned field is re-evaluated with
+the oracle's FP64 operator and must have a true relative residual
+||b - A x||_2 / ||b||_2 <= 1e-10 (the solver's own stopping test), and it
+must agree with the oracle's direct or closed-form solution to within
+tol * kappa(M^-1 A) (kappa <= rho_max / rho_min for the preconditioned
+systems).  Iteration counts of different but correct Krylov
+implementations may differ by rounding, so counts are checked as bounds."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import direct, krylov, operators
+from paper_2403_06654_amd import workloads
+from tests.gpu_util import rel2, smooth_density, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+TOL = 1e-10
+
+
+def oracle_relres_pressure(p, f, rho, L=None):
+    b, _ = operators.project_range(-f, operators.nullspace_basis(f.shape))
+    return rel2(operators.apply_pressure(p, rho, L), b)
+
+
+def oracle_relres_helm(u, g, rho, nu, L=None):
+    return rel2(operators.apply_helmholtz(u, rho, nu, L), g)
+
+
+@pytest.mark.parametrize("solver", ["gmres", "cg", "rmr"])
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_c1_preconditioned(solver, seed):
+    from paper_2403_06654_amd.api import Grid
+    print(f"case C1 solver={solver} seed={seed}", flush=True)
+    x, rho, f, pex = np.loadtxt(os.path.join(GOLD, f"c1_closed_form_seed{seed}.txt")).T
+    g = Grid((256,))
+    g.set_density(to_dev(rho))
+    p, info = g.solve_pressure(to_dev(f), solver=solver)
+    p = to_host(p)
+    assert info["status"] == 0 and info["rel_residual"] <= TOL
+    assert oracle_relres_pressure(p, f, rho) <= TOL * 1.01
+    assert rel2(p, pex) <= TOL * 3.0 * 3.0
+    assert info["iterations"] <= {"gmres": 22, "cg": 22, "rmr": 40}[solver]
+    assert abs(p.sum()) < 1e-9 * np.abs(p).sum()
+    g.close()
+
+
+@pytest.mark.parametrize("solver,max_iter,expect", [("gmres", 20000, 0), ("cg", 20000, 0), ("rmr", 20000, 1)])
+def test_c1_unpreconditioned(solver, max_iter, expect):
+    from paper_2403_06654_amd.api import Grid
+    print(f"case C1 unpreconditioned solver={solver}", flush=True)
+    inp = workloads.c1_inputs(seed=0)
+    g = Grid((256,))
+    g.set_density(to_dev(inp["rho"]))
+    p, info = g.solve_pressure(to_dev(inp["f"]), solver=solver, precond=False, max_iter=max_iter)
+    assert info["status"] == expect
+    if expect == 0:
+        assert oracle_relres_pressure(to_host(p), inp["f"], inp["rho"]) <= TOL * 1.01
+    else:   # RMR without the preconditioner stagnates (kappa ~ 5e4)
+        assert info["iterations"] == max_iter and info["rel_residual"] > TOL
+    g.close()
+
+
+CASES3 = [((32, 32, 32), 3.0), ((16, 32, 64), 5.0), ((64, 64, 64), 0.5)]
+
+
+@pytest.mark.parametrize("shape,rj", CASES3)
+@pytest.mark.parametrize("solver", ["gmres", "cg", "rmr"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_3d_pressure(shape, rj, solver, precision):
+    from paper_2403_06654_amd.api import Grid
+    print(f"case 3D pressure shape={shape} rj={rj} {solver} {precision}", flush=True)
+    z = 2 * np.pi * np.arange(shape[0]) / shape[0]
+    y = 2 * np.pi * np.arange(shape[1]) / shape[1]
+    rp = np.sqrt((y[None, :] - np.pi) ** 2 + (z[:, None] - np.pi) ** 2)
+    plane = 1.0 + 0.5 * (rj - 1.0) * (1.0 - np.tanh((rp - 0.5) / 0.2))
+    rho = np.ascontiguousarray(np.broadcast_to(plane[:, :, None], shape))
+    f = workloads.band_limited(shape, min(shape) // 4, seed=7, keep_mean=True)  # mean removed by projection
+    g = Grid(shape)
+    g.set_density(to_dev(rho))
+    p, info = g.solve_pressure(to_dev(f), solver=solver, precision=precision)
+    p = to_host(p)
+    assert info["status"] == 0, info
+    assert oracle_relres_pressure(p, f, rho) <= TOL * 1.01
+    assert info["rhs_null_norm"] == pytest.approx(abs(f.mean()) * np.sqrt(f.size), rel=1e-9)
+    if precision == "fp32_refine":
+        assert info["refinements"] >= 2
+    ref = krylov.gmres(lambda u: operators.apply_pressure(u, rho), operators.project_range(
+        -f, operators.nullspace_basis(shape))[0], lambda r: operators.precond_pressure(r, rho.mean()),
+        rtol=1e-13)["x"]
+    kappa = max(rho.max() / rho.mean(), rho.mean() / rho.min()) * 2
+    assert rel2(p, ref) <= TOL * kappa * 2
+    g.close()
+
+
+@pytest.mark.parametrize("shape", [(32, 32, 32), (64, 128)])
+@pytest.mark.parametrize("solver", ["gmres", "cg", "rmr"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_helmholtz_solve(shape, solver, precision):
+    from paper_2403_06654_amd.api import Grid
+    print(f"case Helmholtz shape={shape} {solver} {precision}", flush=True)
+    rho = smooth_density(shape, 11, 0.5, 5.0)
+    nu = 1e-3
+    gfield = np.stack([workloads.band_limited(shape, min(shape) // 4, seed=s, keep_mean=True) for s in range(3)])
+    g = Grid(shape)
+    g.set_density(to_dev(rho))
+    u, info = g.solve_helmholtz(to_dev(gfield), nu, solver=solver, precision=precision)
+    u = to_host(u)
+    assert info["status"] == 0, info
+    for c in range(3):
+        assert oracle_relres_helm(u[c], gfield[c], rho, nu) <= TOL * 1.01
+    g.close()
+
+
+def test_constant_density_one_iteration():
+    from paper_2403_06654_amd.api import Grid
+    shape = (32, 32, 32)
+    g = Grid(shape)
+    g.set_density(to_dev(np.full(shape, 1.7)))
+    f = workloads.band_limited(shape, 8, seed=1)
+    for solver in ("gmres", "cg", "rmr"):
+        for prec in ("fp64", "fp32_refine"):
+            p, info = g.solve_pressure(to_dev(f), solver=solver, precision=prec)
+            assert info["status"] == 0
+            if prec == "fp64":
+                assert info["iterations"] == 1, (solver, info)
+            else:   # one FP32 iteration per refinement step
+                assert info["iterations"] == info["refinements"], (solver, info)
+            u, info = g.solve_helmholtz(to_dev(f), 1e-3, solver=solver, precision=prec)
+            if prec == "fp64":
+                assert info["iterations"] == 1, (solver, info)
+    g.close()
+
+
+def test_edge_cases():
+    from paper_2403_06654_amd.api import Grid, VdError
+    import torch
+    shape = (16, 16)
+    g = Grid(shape)
+    rho = smooth_density(shape, 3, 1.0, 3.0)
+    # non-positive and non-finite density are rejected
+    bad = rho.copy()
+    bad[3, 4] = 0.0
+    with pytest.raises(VdError) as e:
+        g.set_density(to_dev(bad))
+    assert e.value.status == -3
+    bad[3, 4] = np.nan
+    with pytest.raises(VdError):
+        g.set_density(to_dev(bad))
+    with pytest.raises(VdError):   # no density set yet
+        g.solve_pressure(to_dev(np.ones(shape)))
+    g.set_density(to_dev(rho))
+    # zero right-hand side: zero solution, no iterations
+    p, info = g.solve_pressure(to_dev(np.zeros(shape)))
+    assert info["status"] == 0 and info["iterations"] == 0 and float(p.abs().max()) == 0.0
+    # right-hand side entirely in the nullspace
+    c = np.ones(shape) * 2.0 + (-1.0) ** np.arange(16)[None, :]
+    p, info = g.solve_pressure(to_dev(c))
+    assert info["iterations"] == 0 and info["rhs_null_norm"] == pytest.approx(np.linalg.norm(c), rel=1e-12)
+    # iteration cap reports NOT_CONVERGED with the best iterate
+    f = workloads.band_limited(shape, 4, seed=2)
+    p, info = g.solve_pressure(to_dev(f), max_iter=1)
+    assert info["status"] == 1 and info["iterations"] == 1 and info["rel_residual"] > TOL
+    # warm start from the converged solution needs no iteration
+    p, info = g.solve_pressure(to_dev(f))
+    p2, info2 = g.solve_pressure(to_dev(f), p=p.clone(), use_x0=True)
+    assert info2["iterations"] == 0 and info2["status"] == 0
+    # invalid options
+    with pytest.raises(VdError):
+        g.solve_pressure(to_dev(f), restart=40)
+    with pytest.raises(VdError):
+        g.solve_pressure(to_dev(f), rtol=0.0)
+    with pytest.raises(VdError):
+        g.solve_helmholtz(to_dev(f), -1.0)
+    with pytest.raises(TypeError):
+        g.solve_pressure(torch.ones(shape, dtype=torch.float32, device="cuda"))
+    g.close()
+
+
+def test_results_bitwise_reproducible():
+    from paper_2403_06654_amd.api import Grid
+    shape = (32, 32, 32)
+    rho = workloads.jet_density(32, 3.0)
+    f = workloads.band_limited(shape, 8, seed=4)
+    outs = []
+    for _ in range(2):
+        g = Grid(shape)
+        g.set_density(to_dev(rho))
+        p, info = g.solve_pressure(to_dev(f))
+        outs.append((to_host(p), info["iterations"]))
+        g.close()
+    assert outs[0][1] == outs[1][1]
+    assert np.array_equal(outs[0][0], outs[1][0])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_c3_full_size(precision):
+    """256^3, rj = 3: GMRES(30) to 1e-10; true residual by the oracle."""
+    from paper_2403_06654_amd.api import Grid
+    print(f"case C3 256^3 {precision}", flush=True)
+    inp = workloads.c3_inputs(rj=3.0, n=256, seed=0)
+    g = Grid((256, 256, 256))
+    g.set_density(to_dev(inp["rho"]))
+    p, info = g.solve_pressure(to_dev(inp["f"]), precision=precision)
+    p = to_host(p)
+    print(info, flush=True)
+    assert info["status"] == 0
+    assert oracle_relres_pressure(p, inp["f"], inp["rho"]) <= TOL * 1.01
+    g.close()
