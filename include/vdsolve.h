@@ -140,11 +140,12 @@ vd_status vd_solve_helmholtz(vd_grid* grid, double dt_nu, int ncomp, const doubl
  * serving admission test uses it).  Returns 0 for an invalid descriptor. */
 size_t vd_workspace_bytes(const vd_grid_desc* desc, const vd_solve_opts* opts);
 
-/* Time spent in each kernel class during the solves since the last reset,
- * measured with HIP events on the grid's stream when enabled.  Classes:
- * 0 z-first pass, 1 y-inverse pass, 2 x pass, 3 y-forward pass, 4 z-last
- * pass, 5 Krylov vector kernels.  ms[c] = total milliseconds, count[c] =
- * launches.  Enabling adds an event pair per timed launch. */
+/* Time spent in each operator pass since the last read, measured with HIP
+ * events on the grid's stream while enabled.  Classes 0..4: the pressure
+ * operator's z-first, y-inverse, x, y-forward and z-last passes; 5..9: the
+ * same passes of the Helmholtz operator.  ms[c] = total milliseconds,
+ * count[c] = launches, for c < nclass (<= 10).  Reading resets the totals.
+ * Enabling adds an event pair per timed launch. */
 vd_status vd_profile_enable(vd_grid* grid, int on);
 vd_status vd_profile_read(vd_grid* grid, double* ms, long long* count, int nclass);
 

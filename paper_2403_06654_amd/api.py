@@ -218,7 +218,7 @@ class Grid:
     def profile_enable(self, on=True):
         _check(lib().vd_profile_enable(self._h, 1 if on else 0), "vd_profile_enable", False)
 
-    def profile_read(self, nclass=6):
+    def profile_read(self, nclass=10):
         ms = (ctypes.c_double * nclass)()
         cnt = (ctypes.c_longlong * nclass)()
         _check(lib().vd_profile_read(self._h, ms, cnt, nclass), "vd_profile_read", False)

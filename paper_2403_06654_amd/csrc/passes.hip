@@ -554,7 +554,7 @@ void op_apply(const Geom& g, const OpParams& p, const void* v, void* y, const Op
       r.out[0] = y;
       r.coef = coef;
       r.cscale = g.ntot_inv;
-      VD_T0(2) launch_row<R, ROW_H1>(g.M, r, twtab, st); VD_T1()
+      VD_T0(7) launch_row<R, ROW_H1>(g.M, r, twtab, st); VD_T1()
       return;
     }
     void* t0 = w.t[0];
@@ -563,7 +563,7 @@ void op_apply(const Geom& g, const OpParams& p, const void* v, void* y, const Op
     a.inner = (int)zin;
     a.in[0] = v;
     a.out[0] = t0;
-    VD_T0(0) launch_col<R, COL_H_FIRST>(g.nz, a, twtab, st); VD_T1()
+    VD_T0(5) launch_col<R, COL_H_FIRST>(g.nz, a, twtab, st); VD_T1()
     if (g.ny > 1) {
       ColArgs b = col_args(g, nullptr);
       b.outer = g.nz;
@@ -571,14 +571,14 @@ void op_apply(const Geom& g, const OpParams& p, const void* v, void* y, const Op
       b.nf = 1;
       b.in[0] = t0;
       b.out[0] = t0;
-      VD_T0(1) launch_col<R, COL_FFT_INV>(g.ny, b, twtab, st); VD_T1()
+      VD_T0(6) launch_col<R, COL_FFT_INV>(g.ny, b, twtab, st); VD_T1()
     }
     RowArgs r = row_args(g, &p);
     r.in[0] = t0;
     r.out[0] = t0;
     r.coef = coef;
     r.cscale = g.ntot_inv;
-    VD_T0(2) launch_row<R, ROW_H>(g.M, r, twtab, st); VD_T1()
+    VD_T0(7) launch_row<R, ROW_H>(g.M, r, twtab, st); VD_T1()
     if (g.ny > 1) {
       ColArgs b = col_args(g, nullptr);
       b.outer = g.nz;
@@ -586,7 +586,7 @@ void op_apply(const Geom& g, const OpParams& p, const void* v, void* y, const Op
       b.nf = 1;
       b.in[0] = t0;
       b.out[0] = t0;
-      VD_T0(3) launch_col<R, COL_FFT_FWD>(g.ny, b, twtab, st); VD_T1()
+      VD_T0(8) launch_col<R, COL_FFT_FWD>(g.ny, b, twtab, st); VD_T1()
     }
     ColArgs d = col_args(g, &p);
     d.outer = 1;
@@ -594,7 +594,7 @@ void op_apply(const Geom& g, const OpParams& p, const void* v, void* y, const Op
     d.in[0] = t0;
     d.in[1] = v;
     d.out[0] = y;
-    VD_T0(4) launch_col<R, COL_H_LAST>(g.nz, d, twtab, st); VD_T1()
+    VD_T0(9) launch_col<R, COL_H_LAST>(g.nz, d, twtab, st); VD_T1()
   }
 #undef VD_T0
 #undef VD_T1

@@ -35,9 +35,11 @@ struct OpWork {
 };
 
 // Optional per-launch timing of the pass kernels with HIP events on the
-// launch stream.  Classes: 0 z-first, 1 y-inverse, 2 x, 3 y-forward, 4 z-last.
+// launch stream.  Classes: 0 z-first, 1 y-inverse, 2 x, 3 y-forward,
+// 4 z-last of the pressure operator; 5..9 the same passes of the
+// Helmholtz operator.
 struct Prof {
-  static constexpr int kClasses = 8;
+  static constexpr int kClasses = 10;
   bool on = false;
   struct Pair { int cls; hipEvent_t a, b; };
   std::vector<Pair> pending;

@@ -42,7 +42,7 @@ def band_limited(shape, band, seed, keep_mean=False, tag=0):
         coef[(0,) * len(shape)] = 0.0
     else:
         coef[(0,) * len(shape)] = rng.standard_normal() * np.sqrt(2.0)
-    u = np.fft.irfftn(coef, s=shape)
+    u = np.fft.irfftn(coef, s=shape, axes=tuple(range(len(shape))))
     rms = np.sqrt(np.mean(u * u))
     return np.ascontiguousarray(u / rms)
 
