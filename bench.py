@@ -1,0 +1,231 @@
+"""Throughput of the preconditioned variable-density Krylov solves on one MI355X.
+
+Workload (one "step"): at 256^3 (triply periodic, [0, 2 pi)^3) with the
+jet-like density rho = 1 + (rj-1)/2 (1 - tanh((r_perp - 0.5)/0.05)), rj
+cycling over {0.5, 3, 5} from step to step, solve
+  * the pressure equation L_rho p = f            (GMRES(30), rtol 1e-10),
+  * the 3-component velocity system rho u - dt nu Lap u = g, dt nu = 1e-3
+                                                 (GMRES(30), rtol 1e-10),
+both preconditioned by the constant-density inverse.  Inputs are seeded
+synthetic fields already resident in HBM.  The timed leg runs in plain FP64
+(the headline `value`) and again with FP32 operator/preconditioner inside
+FP64 iterative refinement at equal 1e-10 accuracy.
+
+Prints one JSON line.  `value` = Krylov iterations per second (operator
+applications inside the Krylov loops, summed over all solves of the FP64
+leg) divided by the leg's wall time.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N = 256
+RJS = (0.5, 3.0, 5.0)
+DT_NU = 1e-3
+PEAK_HBM_GBS = 8000.0
+# Fields moved per launch of each pass class (pressure 0-4, Helmholtz 5-9);
+# a field is one spectral or physical vector: N^3 / 2 complex = N^3 reals.
+PASS_FIELDS = [3, 5, 7, 5, 3, 2, 2, 3, 2, 3]
+PASS_NAMES = ["pressure z-first (k_col COL_P_FIRST)", "pressure y-inverse (k_col COL_P_MIDINV)",
+              "pressure x pass (k_row ROW_P)", "pressure y-forward (k_col COL_P_MIDFWD)",
+              "pressure z-last (k_col COL_P_LAST)", "helmholtz z-first (k_col COL_H_FIRST)",
+              "helmholtz y-inverse (k_col COL_FFT_INV)", "helmholtz x pass (k_row ROW_H)",
+              "helmholtz y-forward (k_col COL_FFT_FWD)", "helmholtz z-last (k_col COL_H_LAST)"]
+
+
+def pct(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * q / 100.0
+    lo, hi = math.floor(k), math.ceil(k)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def run_leg(grid, rho_dev, f_dev, g_dev, precision, steps, warmup, torch, profile=False):
+    lat_p, lat_u, iters, refin, worst = [], [], 0, 0, 0.0
+    p = torch.zeros_like(f_dev)
+    u = torch.zeros_like(g_dev)
+
+    def step(i):
+        nonlocal iters, refin, worst
+        grid.set_density(rho_dev[i % len(rho_dev)])
+        t0 = time.perf_counter()
+        _, ip = grid.solve_pressure(f_dev, p=p, precision=precision)
+        t1 = time.perf_counter()
+        _, iu = grid.solve_helmholtz(g_dev, DT_NU, u=u, precision=precision)
+        t2 = time.perf_counter()
+        for info in (ip, iu):
+            if info["status"] != 0:
+                raise RuntimeError(f"solve did not converge: {info}")
+        return (t1 - t0, t2 - t1, ip, iu)
+
+    for i in range(warmup):
+        step(i)
+    torch.cuda.synchronize()
+    if profile:
+        grid.profile_read()      # reset
+        grid.profile_enable(True)
+    t_start = time.perf_counter()
+    for i in range(steps):
+        tp, tu, ip, iu = step(i)
+        lat_p.append(tp * 1e3)
+        lat_u.append(tu * 1e3)
+        iters += ip["iterations"] + iu["iterations"]
+        refin += ip["refinements"] + iu["refinements"]
+        worst = max(worst, ip["rel_residual"], iu["rel_residual"])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    prof = None
+    if profile:
+        prof = grid.profile_read()
+        grid.profile_enable(False)
+    solves = steps * 4   # 1 pressure + 3 velocity components per step
+    return {
+        "elapsed_s": elapsed, "iters": iters, "iters_per_s": iters / elapsed, "solves_per_s": solves / elapsed,
+        "pressure_p50_ms": pct(lat_p, 50), "pressure_p99_ms": pct(lat_p, 99),
+        "velocity_p50_ms": pct(lat_u, 50), "velocity_p99_ms": pct(lat_u, 99),
+        "iters_per_step": iters / steps, "refinements_per_step": refin / steps,
+        "max_true_rel_residual": worst, "ms_per_step": elapsed * 1e3 / steps,
+    }, prof
+
+
+def roofline(prof, field_bytes):
+    ms, cnt = prof
+    best = max(range(len(ms)), key=lambda c: ms[c])
+    avg_ms = ms[best] / max(cnt[best], 1)
+    bytes_per_launch = PASS_FIELDS[best] * field_bytes
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    passes = {}
+    for c in range(len(ms)):
+        if cnt[c]:
+            a = ms[c] / cnt[c]
+            passes[PASS_NAMES[c]] = {"avg_us": round(a * 1e3, 2), "launches": cnt[c],
+                                     "GB_s": round(PASS_FIELDS[c] * field_bytes / (a * 1e-3) / 1e9, 1)}
+    # whole pressure operator application (5 passes, 23 field transfers)
+    op_ms = sum(ms[c] / cnt[c] for c in range(5) if cnt[c])
+    op = {"avg_ms": round(op_ms, 4), "fields": 23,
+          "GB_s": round(23 * field_bytes / (op_ms * 1e-3) / 1e9, 1) if op_ms else None}
+    return best, {
+        "bound": "hbm", "kernel": PASS_NAMES[best], "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+        "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+        "bytes_per_launch": bytes_per_launch, "avg_launch_us": round(avg_ms * 1e3, 2),
+    }, passes, op
+
+
+def traffic_from_profiles(best_name):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_counters.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, "paper_2403_06654_amd", "csrc", "passes.hip")
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if rec.get("passes_hip_sha256_16") != h:
+        return None
+    return rec.get("per_launch_bytes", {}).get(best_name)
+
+
+def cpu_baseline(inp):
+    """The oracle as it stands, on the host: GMRES on the same 256^3 pressure
+    problem (rj = 3), stopped after a fixed number of iterations."""
+    import numpy as np
+    from oracle import krylov, operators
+    rho, f = inp["rho"], inp["f"]
+    b, _ = operators.project_range(-f, operators.nullspace_basis(f.shape))
+    k = 2
+    t0 = time.perf_counter()
+    res = krylov.gmres(lambda u: operators.apply_pressure(u, rho), b,
+                       lambda r: operators.precond_pressure(r, rho.mean()), max_iter=k)
+    dt = time.perf_counter() - t0
+    return {"value": round(res["iterations"] / dt, 4), "unit": "Krylov iters/s", "cores": 1, "kind": "oracle",
+            "sample": (f"oracle.krylov.gmres(restart 30) on the 256^3 pressure problem (rj=3), stopped after "
+                       f"{res['iterations']} iterations; {dt:.1f} s wall including its initial and final "
+                       f"true-residual applications; NumPy FFTs run on one thread")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=6)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              f"(the multi-GPU design is described but not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2403_06654_amd import workloads
+    from paper_2403_06654_amd.api import Grid
+
+    print(f"bench: generating 256^3 inputs", file=sys.stderr, flush=True)
+    dens = {rj: workloads.jet_density(N, rj) for rj in RJS}
+    inp = workloads.c3_inputs(rj=3.0, n=N, seed=0, with_g=True)
+    rho_dev = [torch.from_numpy(dens[rj]).cuda() for rj in RJS]
+    f_dev = torch.from_numpy(inp["f"]).cuda()
+    g_dev = torch.from_numpy(inp["g"]).cuda()
+    grid = Grid((N, N, N))
+    field_bytes = (N * N * (N // 2)) * 16
+
+    print(f"bench: FP64 leg ({args.warmup} warmup + {args.steps} timed steps)", file=sys.stderr, flush=True)
+    r64, prof = run_leg(grid, rho_dev, f_dev, g_dev, "fp64", args.steps, args.warmup, torch, profile=True)
+    best, roof, passes, op = roofline(prof, field_bytes)
+    roof["traffic"] = traffic_from_profiles(roof["kernel"])
+    r32 = None
+    if not args.no_fp32:
+        print(f"bench: FP32+refine leg", file=sys.stderr, flush=True)
+        r32, _ = run_leg(grid, rho_dev, f_dev, g_dev, "fp32_refine", args.steps, args.warmup, torch)
+    grid.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("bench: oracle CPU baseline sample", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(inp)
+
+    out = {
+        "metric": "Krylov iters/s and solves/s at 256^3 (FP64 vs FP32+refine); p50/p99 solve latency",
+        "value": round(r64["iters_per_s"], 2),
+        "unit": "Krylov iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r64["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": ("256^3 triply periodic jet-like density, rj cycling {0.5,3,5}; per step one "
+                                "pressure solve L_rho p = f and one 3-component velocity solve rho u - 1e-3 Lap u "
+                                "= g; GMRES(30), constant-density preconditioner, rtol 1e-10"),
+                   "grid": [N, N, N], "solver": "gmres", "restart": 30, "rtol": 1e-10},
+        "solves_per_s": round(r64["solves_per_s"], 3),
+        "pressure_p50_ms": round(r64["pressure_p50_ms"], 3),
+        "pressure_p99_ms": round(r64["pressure_p99_ms"], 3),
+        "velocity_p50_ms": round(r64["velocity_p50_ms"], 3),
+        "velocity_p99_ms": round(r64["velocity_p99_ms"], 3),
+        "fp64": {k: (round(v, 6) if isinstance(v, float) else v) for k, v in r64.items()},
+        "fp32_refine": ({k: (round(v, 6) if isinstance(v, float) else v) for k, v in r32.items()}
+                        if r32 else None),
+        "roofline": roof,
+        "operator_apply": op,
+        "passes": passes,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()
