@@ -50,12 +50,12 @@ def pct(xs, q):
 
 
 def run_leg(grid, rho_dev, f_dev, g_dev, precision, steps, warmup, torch, profile=False):
-    lat_p, lat_u, iters, refin, worst = [], [], 0, 0, 0.0
+    lat_p, lat_u, iters, refin, worst, reorth = [], [], 0, 0, 0.0, 0
     p = torch.zeros_like(f_dev)
     u = torch.zeros_like(g_dev)
 
     def step(i):
-        nonlocal iters, refin, worst
+        nonlocal iters, refin, worst, reorth
         grid.set_density(rho_dev[i % len(rho_dev)])
         t0 = time.perf_counter()
         _, ip = grid.solve_pressure(f_dev, p=p, precision=precision)
@@ -80,6 +80,7 @@ def run_leg(grid, rho_dev, f_dev, g_dev, precision, steps, warmup, torch, profil
         lat_u.append(tu * 1e3)
         iters += ip["iterations"] + iu["iterations"]
         refin += ip["refinements"] + iu["refinements"]
+        reorth += ip["gs_second_passes"] + iu["gs_second_passes"]
         worst = max(worst, ip["rel_residual"], iu["rel_residual"])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
@@ -94,6 +95,7 @@ def run_leg(grid, rho_dev, f_dev, g_dev, precision, steps, warmup, torch, profil
         "velocity_p50_ms": pct(lat_u, 50), "velocity_p99_ms": pct(lat_u, 99),
         "iters_per_step": iters / steps, "refinements_per_step": refin / steps,
         "max_true_rel_residual": worst, "ms_per_step": elapsed * 1e3 / steps,
+        "gs_second_passes_per_step": reorth / steps,
     }, prof
 
 
@@ -216,8 +218,8 @@ def main():
         "pressure_p99_ms": round(r64["pressure_p99_ms"], 3),
         "velocity_p50_ms": round(r64["velocity_p50_ms"], 3),
         "velocity_p99_ms": round(r64["velocity_p99_ms"], 3),
-        "fp64": {k: (round(v, 6) if isinstance(v, float) else v) for k, v in r64.items()},
-        "fp32_refine": ({k: (round(v, 6) if isinstance(v, float) else v) for k, v in r32.items()}
+        "fp64": {k: (float(f"{v:.6g}") if isinstance(v, float) else v) for k, v in r64.items()},
+        "fp32_refine": ({k: (float(f"{v:.6g}") if isinstance(v, float) else v) for k, v in r32.items()}
                         if r32 else None),
         "roofline": roof,
         "operator_apply": op,

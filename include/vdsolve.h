@@ -85,6 +85,7 @@ typedef struct {
   double rel_residual;   /* true FP64 ||b - A x|| / ||b|| at exit (max over components) */
   double rhs_null_norm;  /* pressure: norm of the removed nullspace part of f */
   double seconds;        /* wall time of the solve on the host clock */
+  int gs_second_passes;  /* GMRES: steps whose Gram-Schmidt needed a second pass */
 } vd_solve_info;
 
 typedef struct vd_grid vd_grid;

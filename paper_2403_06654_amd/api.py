@@ -35,7 +35,7 @@ class vd_solve_opts(ctypes.Structure):
 class vd_solve_info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("iterations", ctypes.c_int), ("refinements", ctypes.c_int),
                 ("rel_residual", ctypes.c_double), ("rhs_null_norm", ctypes.c_double),
-                ("seconds", ctypes.c_double)]
+                ("seconds", ctypes.c_double), ("gs_second_passes", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

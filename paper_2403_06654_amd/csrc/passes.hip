@@ -39,9 +39,12 @@ struct ColCfg {
   static constexpr int NT = 256;
 };
 
-template <int L>
+template <int L, typename R>
 struct RowCfg {
-  static constexpr int E = L >= 16 ? 16 : L;
+  // FP64 rows use 8 points per thread: the x pass keeps a field's inverse
+  // and forward transforms plus the half-length pre/post-processing live at
+  // once, and 16 FP64 points per thread would cap occupancy at one wave/SIMD
+  static constexpr int E = L >= 16 ? (sizeof(R) == 8 ? 8 : 16) : L;
   static constexpr int T = L / E;
   static constexpr int RW = 256 / T;  // rows per block
   static constexpr int LP = row_pitch<L>();
@@ -242,22 +245,28 @@ struct RowArgs {
 };
 
 template <int L, typename R, int MODE>
-__global__ __launch_bounds__(256) void k_row(RowArgs a, const C2<R>* __restrict__ twtab) {
-  using Cf = RowCfg<L>;
+__global__ __launch_bounds__(MODE == ROW_P ? 768 : 256) void k_row(RowArgs a, const C2<R>* __restrict__ twtab) {
+  using Cf = RowCfg<L, R>;
   constexpr int E = Cf::E, T = Cf::T, RW = Cf::RW, LP = Cf::LP;
   using S = Sched<L, E>;
   constexpr int RI1 = S::template last_radix<false>();   // inverse output pattern
   constexpr int RF0 = S::template first_radix<true>();   // forward input pattern (== RI1)
   static_assert(RI1 == RF0, "pattern mismatch");
-  __shared__ C2<R> lds_all[RW * LP];
+  constexpr int NG = MODE == ROW_P ? 3 : 1;  // thread groups (fields) per block
+  __shared__ C2<R> lds_all[NG * RW * LP];
   const C2<R>* tw = twtab + L;       // length-L table
   const C2<R>* twN = twtab + 2 * L;  // length-2L table, first L entries used
 
-  const int tid = threadIdx.x;
+  // A block is nf groups of 256 threads, one field per group, over the
+  // same RW rows: the fields of the pressure pass share each coefficient
+  // row through the CU's L1 instead of re-reading it from HBM, and each
+  // thread keeps only one field's transforms live.
+  const int fsel = threadIdx.x / 256;
+  const int tid = threadIdx.x % 256;
   const int t = tid % T, rr = tid / T;
   const int row = blockIdx.x * RW + rr;
   const bool ok = row < a.nrows;
-  LdsRow<R> lds{lds_all + rr * LP};
+  LdsRow<R> lds{lds_all + (fsel * RW + rr) * LP};
   const R sx = R(a.g.sx);
   C2<R> reg[E];
 
@@ -373,21 +382,16 @@ __global__ __launch_bounds__(256) void k_row(RowArgs a, const C2<R>* __restrict_
   } else {
     const C2<R>* coef = (const C2<R>*)a.coef;
     const R cs = R(a.cscale);
-    C2<R> cf[E];
+    const int f = fsel;
+    inverse_row((const C2<R>*)a.in[f], f);
 #pragma unroll
     for (int s = 0; s < E; ++s) {
       int m = pat_index<L, E, RI1>(t, s);
       C2<R> q = ok ? ldg(coef + (size_t)row * L + m) : C2<R>{R(0), R(0)};
-      cf[s] = C2<R>{q.x * cs, q.y * cs};
+      reg[s] = C2<R>{reg[s].x * (q.x * cs), reg[s].y * (q.y * cs)};
     }
-    const int nf = (MODE == ROW_P) ? a.nf : 1;
-    for (int f = 0; f < nf; ++f) {
-      inverse_row((const C2<R>*)a.in[f], f);
-#pragma unroll
-      for (int s = 0; s < E; ++s) reg[s] = C2<R>{reg[s].x * cf[s].x, reg[s].y * cf[s].y};
-      fft_line<L, E, -1, true>(reg, lds, tw, t);
-      forward_post(f, (C2<R>*)a.out[f], (const C2<R>*)a.in[0]);
-    }
+    fft_line<L, E, -1, true>(reg, lds, tw, t);
+    forward_post(f, (C2<R>*)a.out[f], (const C2<R>*)a.in[0]);
   }
 }
 
@@ -442,8 +446,9 @@ static void launch_col(int L, const ColArgs& a, const void* tw, hipStream_t st) 
 
 template <typename R, int MODE, int L>
 static void launch_row_L(const RowArgs& a, const void* tw, hipStream_t st) {
-  dim3 grid((a.nrows + RowCfg<L>::RW - 1) / RowCfg<L>::RW);
-  hipLaunchKernelGGL((k_row<L, R, MODE>), grid, dim3(256), 0, st, a, (const C2<R>*)tw);
+  dim3 grid((a.nrows + RowCfg<L, R>::RW - 1) / RowCfg<L, R>::RW);
+  const int nf = (MODE == ROW_P) ? a.nf : 1;
+  hipLaunchKernelGGL((k_row<L, R, MODE>), grid, dim3(256 * nf), 0, st, a, (const C2<R>*)tw);
 }
 
 template <typename R, int MODE>

@@ -22,6 +22,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstddef>
 #include <cstring>
 #include <map>
 #include <new>
@@ -182,7 +183,10 @@ void fill_twiddles(vd_grid* G) {
 }
 
 void sync_state(vd_grid* G) {
-  ck(hipMemcpyAsync(G->hst, G->dst, sizeof(DevState), hipMemcpyDeviceToHost, G->st));
+  // only the tail (resid, nrm2, bad) is read on the host
+  const size_t off = offsetof(DevState, resid);
+  ck(hipMemcpyAsync((char*)G->hst + off, (const char*)G->dst + off, sizeof(DevState) - off,
+                    hipMemcpyDeviceToHost, G->st));
   ck(hipStreamSynchronize(G->st));
   if (G->prof.on) G->prof.flush();
 }
@@ -208,6 +212,7 @@ struct SolveOut {
   int status = VD_OK;
   int iters = 0;
   double relres = 0;
+  int reorth = 0;
 };
 
 template <typename R>
@@ -237,10 +242,10 @@ struct Krylov {
     }
   }
 
-  void apply(const void* v, void* y, bool with_prec) {
+  void apply(const void* v, void* y, bool with_prec, const double* in_scale = nullptr) {
     OpParams p = cfg.op;
     p.precond = with_prec ? cfg.op.precond : 0;
-    p.in_scale = nullptr;
+    p.in_scale = in_scale;
     op_apply<R>(g, p, v, y, work, coef, tw, G->st, &G->prof);
   }
 
@@ -261,7 +266,22 @@ struct Krylov {
     }
   }
 
+  int read_nreorth() {
+    int v = 0;
+    ck(hipMemcpyAsync(&G->hst->nreorth, &G->dst->nreorth, sizeof(int), hipMemcpyDeviceToHost, G->st));
+    ck(hipStreamSynchronize(G->st));
+    v = G->hst->nreorth;
+    return v;
+  }
+
   SolveOut gmres(const void* b, void* x, double bnorm) {
+    const int r0 = read_nreorth();
+    SolveOut o = gmres_core(b, x, bnorm);
+    o.reorth = read_nreorth() - r0;
+    return o;
+  }
+
+  SolveOut gmres_core(const void* b, void* x, double bnorm) {
     SolveOut o;
     const int m = cfg.restart;
     std::vector<void*> V(m + 1);
@@ -273,19 +293,15 @@ struct Krylov {
       if (!(beta == beta)) { o.status = VD_EBREAKDOWN; return o; }
       if (o.relres <= cfg.rtol) { o.status = VD_OK; return o; }
       if (o.iters >= cfg.max_iter) { o.status = VD_NOT_CONVERGED; return o; }
-      scale<R>(g, V[0], nullptr, 1.0 / beta, G->st);
-      gmres_init(G->dst, beta, m, G->st);
+      gmres_init(G->dst, beta, m, G->st);  // v_0 = V[0] / beta via the scale vs[0]
       int k = 0;
       for (int j = 0; j < m; ++j) {
-        apply(V[j], V[j + 1], true);
+        apply(V[j], V[j + 1], true, &G->dst->vs[j]);
         o.iters++;
         VecPtrs P{};
         for (int i = 0; i <= j; ++i) P.p[i] = V[i];
-        mdot<R>(g, V[j + 1], P, j + 1, false, G->partial, G->dst->red2, G->st);
-        mupdate<R>(g, V[j + 1], P, j + 1, G->dst->red2, true, G->partial, G->dst->red, G->st);
-        mupdate<R>(g, V[j + 1], P, j + 1, G->dst->red, false, G->partial, &G->dst->nrm2, G->st);
+        gs_orthogonalize<R>(g, V[j + 1], P, j + 1, G->dst, G->partial, G->st);
         gmres_givens(G->dst, j, G->st);
-        scale<R>(g, V[j + 1], &G->dst->inv_h, 1.0, G->st);
         sync_state(G);
         k = j + 1;
         if (G->hst->bad) { o.status = VD_EBREAKDOWN; return o; }
@@ -294,7 +310,7 @@ struct Krylov {
       gmres_backsolve(G->dst, k, G->st);
       VecPtrs P{};
       for (int i = 0; i < k; ++i) P.p[i] = V[i];
-      lincomb<R>(g, tmp, P, k, G->dst->y, G->st);
+      lincomb<R>(g, tmp, P, k, G->dst->coef, G->st);
       OpParams pp = cfg.op;
       precond_axpy<R>(g, pp, x, tmp, nullptr, 1.0, G->st);
       beta = true_resid(b, x, V[0]);
@@ -399,6 +415,7 @@ SolveOut solve_spectral(vd_grid* G, const vd_solve_opts& o, const OpParams& op, 
     K32.cfg.max_iter = o.max_iter - out.iters;
     SolveOut in = K32.run(r32, d32, 1.0);
     out.iters += in.iters;
+    out.reorth += in.reorth;
     (*refinements)++;
     if (in.status == VD_EBREAKDOWN) { out.status = VD_EBREAKDOWN; return out; }
     axpy_f2d(G->g, d32, x64, rn, G->st);
@@ -659,6 +676,7 @@ static vd_status solve_impl(vd_grid* G, void* c) {
     ck(hipGetLastError());
     s->info.iterations += so.iters;
     s->info.refinements += refin;
+    s->info.gs_second_passes += so.reorth;
     s->info.rel_residual = std::fmax(s->info.rel_residual, so.relres);
     if (so.status < 0) worst = (vd_status)so.status;
     else if (so.status == VD_NOT_CONVERGED && worst == VD_OK) worst = VD_NOT_CONVERGED;

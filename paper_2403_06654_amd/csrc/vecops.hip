@@ -43,23 +43,21 @@ __device__ __forceinline__ void block_store(const double* acc, int k_used, doubl
 
 __device__ __forceinline__ double spec_w(size_t e, int M) { return (e % M) == 0 ? 1.0 : 2.0; }
 
-__global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ partial, int nblk, int K, double scale,
-                                                double* __restrict__ out) {
-  __shared__ double sh[4];
+// One wave per output value; lanes stride over the block partials in a
+// fixed order, then a fixed shuffle tree.  No block-wide barrier.
+__global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ partial, int nblk, int K, double scale,
+                                                 double* __restrict__ out) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int i = 0; i < K; ++i) {
+  for (int i = w; i < K; i += 16) {
     double v = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += 256) v += partial[(size_t)b * kRedStride + i];
+    for (int b = lane; b < nblk; b += 64) v += partial[(size_t)b * kRedStride + i];
     v = wave_sum(v);
-    if (lane == 0) sh[w] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) out[i] = (((sh[0] + sh[1]) + sh[2]) + sh[3]) * scale;
-    __syncthreads();
+    if (lane == 0) out[i] = v * scale;
   }
 }
 
 static void reduce(const double* partial, int K, double scale, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, partial, kRedBlocks, K, scale, out);
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, partial, kRedBlocks, K, scale, out);
 }
 
 static size_t nspec(const Geom& g) { return (size_t)g.nz * g.ny * g.M; }
@@ -111,6 +109,8 @@ void mdot(const Geom& g, const void* x, const VecPtrs& V, int nv, bool want_norm
     hipLaunchKernelGGL((k_mdot<R, 8>), gr, bl, 0, s, (const C2<R>*)x, V, nv, wn, n, g.M, partial);
   else if (nv <= 16)
     hipLaunchKernelGGL((k_mdot<R, 16>), gr, bl, 0, s, (const C2<R>*)x, V, nv, wn, n, g.M, partial);
+  else if (nv <= 24)
+    hipLaunchKernelGGL((k_mdot<R, 24>), gr, bl, 0, s, (const C2<R>*)x, V, nv, wn, n, g.M, partial);
   else
     hipLaunchKernelGGL((k_mdot<R, kMaxVec>), gr, bl, 0, s, (const C2<R>*)x, V, nv, wn, n, g.M, partial);
   reduce(partial, nv + wn, g.ntot_inv, out, s);
@@ -183,6 +183,127 @@ void mupdate(const Geom& g, void* x, const VecPtrs& V, int nv, const double* coe
   else
     hipLaunchKernelGGL((k_mupdate<R, kMaxVec>), gr, bl, 0, s, (C2<R>*)x, V, nv, coef, wd, n, g.M, partial);
   reduce(partial, (want_dots ? nv : 0) + 1, g.ntot_inv, out, s);
+}
+
+// ------------------------------------------------ Gram-Schmidt (GMRES)
+//
+// Basis vectors are stored unnormalised with a scale vs[i] (v_i = vs[i] *
+// V_i); every consumer folds the scale into its coefficients, and the
+// operator takes it as an input scale, so no pass is spent on normalising.
+// One Arnoldi step (w = A M^-1 v_j, nv = j + 1):
+//   pass 1  k_mdot:      raw_i = (V_i, w)                         h_i = vs_i raw_i
+//   pass 2  k_gs_update: w' = w - sum_i h_i v_i, and in the same pass the
+//                        dots c_i = (v_i, w') and ||w'||^2
+//   check   c measures the orthogonality actually lost by classical
+//           Gram-Schmidt; if max|c_i| <= 1e-12 ||w'|| the step is done
+//           (H[:, j] = h, H[j+1, j] = ||w'||), else
+//   pass 3  w'' = w' - sum_i c_i v_i  (H[:, j] = h + c,
+//           ||w''||^2 = ||w'||^2 - |c|^2, accurate because |c| << ||w'||).
+// Pass 3 exits at once when not needed, so the common step costs two
+// passes over the basis.
+constexpr double kOrthTol = 1e-12;
+
+__global__ void k_gs_prep(DevState* st, int nv) {
+  if (threadIdx.x) return;
+  for (int i = 0; i < nv; ++i) {
+    const double h = st->vs[i] * st->red2[i];
+    st->hcol[i] = h;
+    st->coef[i] = h * st->vs[i];
+  }
+}
+
+__global__ void k_gs_check(DevState* st, int nv) {
+  if (threadIdx.x) return;
+  const double n2 = st->red[nv];
+  double cmax = 0.0, c2 = 0.0;
+  for (int i = 0; i < nv; ++i) {
+    const double c = st->vs[i] * st->red[i];
+    st->ccol[i] = c;
+    st->coef[i] = c * st->vs[i];
+    cmax = fmax(cmax, fabs(c));
+    c2 += c * c;
+  }
+  if (n2 > 0.0 && cmax <= kOrthTol * sqrt(n2)) {
+    st->reorth = 0;
+    st->hn = sqrt(n2);
+  } else {
+    st->reorth = 1;
+    const double h2 = n2 - c2;
+    st->hn = h2 > 0.0 ? sqrt(h2) : 0.0;
+    st->nreorth += 1;
+  }
+  st->vs[nv] = st->hn > 0.0 ? 1.0 / st->hn : 0.0;
+}
+
+template <typename R, int NV>
+__global__ __launch_bounds__(256) void k_gs_update(C2<R>* __restrict__ x, VecPtrs V, int nv,
+                                                   const DevState* __restrict__ st, int second, size_t n, int M,
+                                                   double* __restrict__ partial) {
+  if (second && !st->reorth) return;
+  double c[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) c[i] = i < nv ? st->coef[i] : 0.0;
+  double acc[NV + 1];
+#pragma unroll
+  for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+    C2<R> vv[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+      if (i < nv) vv[i] = ldg((const C2<R>*)V.p[i] + e);
+    C2<R> xv = ldg(x + e);
+    double xr = xv.x, xi = xv.y;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      if (i < nv) {
+        xr -= c[i] * (double)vv[i].x;
+        xi -= c[i] * (double)vv[i].y;
+      }
+    }
+    C2<R> nx{R(xr), R(xi)};
+    stg(x + e, nx);
+    if (!second) {
+      const double w = spec_w(e, M);
+      const double yr = nx.x, yi = nx.y;
+#pragma unroll
+      for (int i = 0; i < NV; ++i)
+        if (i < nv) acc[i] += w * ((double)vv[i].x * yr + (double)vv[i].y * yi);
+      acc[NV] += w * (yr * yr + yi * yi);
+    }
+  }
+  if (second) return;
+  double out[NV + 1];
+#pragma unroll
+  for (int i = 0; i <= NV; ++i) out[i] = acc[i];
+#pragma unroll
+  for (int i = 0; i <= NV; ++i)
+    if (i == nv) out[i] = acc[NV];
+  block_store<NV + 1>(out, nv + 1, partial + (size_t)blockIdx.x * kRedStride);
+}
+
+template <typename R, int NV>
+static void launch_gs(const Geom& g, void* x, const VecPtrs& V, int nv, const DevState* st, int second,
+                      double* partial, hipStream_t s) {
+  hipLaunchKernelGGL((k_gs_update<R, NV>), dim3(kRedBlocks), dim3(256), 0, s, (C2<R>*)x, V, nv, st, second,
+                     nspec(g), g.M, partial);
+}
+
+template <typename R>
+void gs_orthogonalize(const Geom& g, void* w, const VecPtrs& V, int nv, DevState* st, double* partial,
+                      hipStream_t s) {
+  mdot<R>(g, w, V, nv, false, partial, st->red2, s);
+  hipLaunchKernelGGL(k_gs_prep, dim3(1), dim3(64), 0, s, st, nv);
+  for (int second = 0; second < 2; ++second) {
+    if (nv <= 4) launch_gs<R, 4>(g, w, V, nv, st, second, partial, s);
+    else if (nv <= 8) launch_gs<R, 8>(g, w, V, nv, st, second, partial, s);
+    else if (nv <= 16) launch_gs<R, 16>(g, w, V, nv, st, second, partial, s);
+    else if (nv <= 24) launch_gs<R, 24>(g, w, V, nv, st, second, partial, s);
+    else launch_gs<R, kMaxVec>(g, w, V, nv, st, second, partial, s);
+    if (!second) {
+      reduce(partial, nv + 1, g.ntot_inv, st->red, s);
+      hipLaunchKernelGGL(k_gs_check, dim3(1), dim3(64), 0, s, st, nv);
+    }
+  }
 }
 
 // ------------------------------------------------------------- lincomb
@@ -418,16 +539,19 @@ __global__ void k_gmres_init(DevState* st, double beta, int m) {
   st->g[0] = beta;
   st->resid = beta;
   st->bad = 0;
+  st->reorth = 0;
+  for (int i = 0; i <= kMaxRestart; ++i) st->vs[i] = 0.0;
+  st->vs[0] = 1.0 / beta;
 }
 
-// Column j of the Hessenberg matrix: h (first Gram-Schmidt pass, red2) plus
-// the correction of the second pass (red); subdiagonal = norm after both.
+// Column j of the Hessenberg matrix: the Gram-Schmidt coefficients h (plus
+// the second-pass corrections c when that pass ran); subdiagonal ||w||.
 __global__ void k_gmres_givens(DevState* st, int j) {
   if (threadIdx.x != 0) return;
   double* H = st->H;
   const int ld = ldh();
-  for (int i = 0; i <= j; ++i) H[i + j * ld] = st->red2[i] + st->red[i];
-  const double hn = sqrt(fmax(st->nrm2, 0.0));
+  for (int i = 0; i <= j; ++i) H[i + j * ld] = st->hcol[i] + (st->reorth ? st->ccol[i] : 0.0);
+  const double hn = st->hn;
   for (int i = 0; i < j; ++i) {
     double a = H[i + j * ld], b = H[i + 1 + j * ld];
     H[i + j * ld] = st->cs[i] * a + st->sn[i] * b;
@@ -447,7 +571,6 @@ __global__ void k_gmres_givens(DevState* st, int j) {
   st->g[j + 1] = -s * st->g[j];
   st->g[j] = c * st->g[j];
   st->resid = fabs(st->g[j + 1]);
-  st->inv_h = hn > 0.0 ? 1.0 / hn : 0.0;
   if (!isfinite(rr) || !isfinite(st->g[j + 1])) st->bad = 1;
 }
 
@@ -460,6 +583,7 @@ __global__ void k_gmres_backsolve(DevState* st, int k) {
     const double d = st->H[i + i * ld];
     st->y[i] = d != 0.0 ? s / d : 0.0;
   }
+  for (int i = 0; i < k; ++i) st->coef[i] = st->y[i] * st->vs[i];  // stored basis is unnormalised
 }
 
 __global__ void k_cg_alpha(DevState* st) {
@@ -562,6 +686,7 @@ void density_setup(const double* rho, size_t n, double* a64, float* a32, float* 
                            hipStream_t);                                                                       \
   template void lincomb<R>(const Geom&, void*, const VecPtrs&, int, const double*, hipStream_t);               \
   template void scale<R>(const Geom&, void*, const double*, double, hipStream_t);                              \
+  template void gs_orthogonalize<R>(const Geom&, void*, const VecPtrs&, int, DevState*, double*, hipStream_t); \
   template void sub_norm<R>(const Geom&, const void*, const void*, void*, double*, double*, hipStream_t);      \
   template void precond_axpy<R>(const Geom&, const OpParams&, void*, const void*, const double*, double,       \
                                 hipStream_t);                                                                  \

@@ -15,7 +15,7 @@
 namespace vd {
 
 constexpr int kMaxVec = 34;       // vectors per multi-dot / multi-update
-constexpr int kRedBlocks = 512;   // partial sums per reduction
+constexpr int kRedBlocks = 1024;  // partial sums per reduction (4 blocks per CU)
 
 struct VecPtrs {
   const void* p[kMaxVec];
@@ -28,7 +28,11 @@ struct DevState {
   double cs[kMaxRestart], sn[kMaxRestart], g[kMaxRestart + 1], y[kMaxRestart];
   double red[kMaxVec + 2];   // outputs of the last reduction
   double red2[kMaxVec + 2];  // outputs of the previous reduction
-  double inv_h;              // scale of the newest basis vector
+  double vs[kMaxRestart + 1];     // scale of each stored (unnormalised) basis vector
+  double hcol[kMaxVec], ccol[kMaxVec], coef[kMaxVec];  // Gram-Schmidt coefficients
+  double hn;                 // norm of the newest orthogonalised vector
+  int reorth;                // second Gram-Schmidt pass ran for this step
+  int nreorth;               // second passes since the grid was created
   double alpha, beta, rz, rz_new;
   // mirrored to the host after each step
   double resid;              // estimated (GMRES) or recursive residual norm
@@ -48,6 +52,15 @@ void mdot(const Geom& g, const void* x, const VecPtrs& V, int nv, bool want_norm
 template <typename R>
 void mupdate(const Geom& g, void* x, const VecPtrs& V, int nv, const double* coef, bool want_dots,
              double* partial, double* out, hipStream_t s);
+
+// GMRES step: orthogonalise w against the stored basis V_0..V_{nv-1}
+// (v_i = vs[i] V_i) in place; classical Gram-Schmidt with a measured
+// orthogonality check and a conditional second pass.  Leaves the
+// Hessenberg column in st->hcol (+ st->ccol), ||w|| in st->hn and
+// vs[nv] = 1 / ||w||.
+template <typename R>
+void gs_orthogonalize(const Geom& g, void* w, const VecPtrs& V, int nv, DevState* st, double* partial,
+                      hipStream_t s);
 
 // z = sum_i c_i V_i
 template <typename R>
@@ -97,7 +110,7 @@ void project_range(const Geom& g, void* spec, double* removed, hipStream_t st);
 // Scalar kernels (one thread) of the Krylov methods.
 void gmres_init(DevState* st, double beta, int m, hipStream_t s);
 void gmres_givens(DevState* st, int j, hipStream_t s);   // uses red (h), red2 (c) and nrm2
-void gmres_backsolve(DevState* st, int k, hipStream_t s);
+void gmres_backsolve(DevState* st, int k, hipStream_t s);  // y, and coef = y * vs
 void cg_alpha(DevState* st, hipStream_t s);   // alpha = rz / red[0]
 void cg_beta(DevState* st, hipStream_t s);    // beta = red[0] / rz; rz = red[0]
 void rmr_alpha(DevState* st, hipStream_t s);  // alpha = red[0] / red[1]
