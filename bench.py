@@ -154,6 +154,100 @@ def cpu_baseline(inp):
                        f"true-residual applications; NumPy FFTs run on one thread")}
 
 
+def bench_serving(args):
+    """Serving stream of 2D periodic pressure solves (FP32+FP64-refine, rtol
+    1e-10): closed-loop saturation throughput, then Poisson arrivals at 0.8x
+    and 0.5x of it with p50/p99 arrival-to-completion latency; plain FP64
+    single-slot solving of the same requests as the reference mode."""
+    import numpy as np
+    import torch
+    from paper_2403_06654_amd import workloads
+    from paper_2403_06654_amd.api import Server
+
+    nreq = args.requests
+    reqs = workloads.serving_requests(count=nreq)
+    print(f"bench: serving pool for {nreq} requests", file=sys.stderr, flush=True)
+    pool = workloads.serving_pool(pool=8)
+    S_dev = {n: [torch.from_numpy(S).cuda() for S, _ in v] for n, v in pool.items()}
+    f_dev = {n: [torch.from_numpy(f).cuda() for _, f in v] for n, v in pool.items()}
+    # densities of every request (1 + (r-1)/2 S, the workload's formula) prepared in HBM up front
+    rho = [1.0 + 0.5 * (r["r"] - 1.0) * S_dev[r["n"]][r["seed"] % 8] for r in reqs]
+    xs = [torch.zeros_like(f_dev[r["n"]][0]) for r in reqs]
+    torch.cuda.synchronize()
+    budget = 64 << 30
+
+    def submit(srv, i, prec="fp32_refine"):
+        r = reqs[i]
+        return srv.submit((r["n"], r["n"]), rho=rho[i], f=f_dev[r["n"]][r["seed"] % 8], x=xs[i],
+                          precision=prec, user_tag=i)
+
+    def closed(srv, idx, prec):
+        t0 = time.perf_counter()
+        for i in idx:
+            submit(srv, i, prec)
+        got = []
+        while len(got) < len(idx):
+            got += srv.wait(timeout=5.0)
+        return time.perf_counter() - t0, got
+
+    srv = Server(budget, max_slots=args.slots)
+    closed(srv, list(range(min(16, nreq))), "fp32_refine")            # warm-up: grids of every size
+    print("bench: closed loop", file=sys.stderr, flush=True)
+    wall, got = closed(srv, list(range(nreq)), "fp32_refine")
+    bad = [g for g in got if g["status"] != 0]
+    if bad:
+        raise RuntimeError(f"{len(bad)} serving requests failed, e.g. {bad[0]}")
+    sat = nreq / wall
+    lat_closed = [g["t_done"] - g["t_arrive"] for g in got]
+    iters = sum(g["iterations"] for g in got)
+    open_runs = {}
+    for frac in (0.8, 0.5):
+        qps = frac * sat
+        arr = workloads.poisson_arrivals(nreq, qps)
+        print(f"bench: open loop at {frac} x saturation ({qps:.0f} req/s)", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        got = []
+        for i in range(nreq):
+            while True:
+                dt = arr[i] - (time.perf_counter() - t0)
+                if dt <= 0:
+                    break
+                got += srv.poll()
+                time.sleep(min(dt, 0.0005))
+            submit(srv, i)
+        while len(got) < nreq:
+            got += srv.wait(timeout=5.0)
+        el = time.perf_counter() - t0
+        lat = [1e3 * (g["t_done"] - g["t_arrive"]) for g in got]
+        open_runs[str(frac)] = {"qps_offered": round(qps, 1), "solves_per_s": round(nreq / el, 1),
+                                "p50_ms": round(pct(lat, 50), 3), "p99_ms": round(pct(lat, 99), 3)}
+    st = srv.stats()
+    srv.close()
+    # reference mode: plain FP64, one solve at a time, same requests (first 512)
+    nref = min(512, nreq)
+    srv1 = Server(budget, max_slots=1)
+    closed(srv1, list(range(min(16, nref))), "fp64")
+    wall1, got1 = closed(srv1, list(range(nref)), "fp64")
+    srv1.close()
+    out = {
+        "metric": "serving: solves/s at saturation and p50/p99 latency under Poisson arrivals (2D periodic, "
+                  "mixed 128^2..1024^2, density ratio 1.5..10, FP32+FP64-refine, rtol 1e-10)",
+        "value": round(sat, 2), "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"{nreq} serving requests, grids uniform in {{128,256,512,1024}}^2, "
+                               f"r log-uniform [1.5,10], tanh slab with 8-mode interface, GMRES(30)",
+                   "slots": args.slots, "hbm_budget_GB": budget / 2 ** 30},
+        "closed_loop": {"solves_per_s": round(sat, 2), "krylov_iters_per_s": round(iters / wall, 1),
+                        "p50_ms": round(1e3 * pct(lat_closed, 50), 3), "p99_ms": round(1e3 * pct(lat_closed, 99), 3)},
+        "open_loop": open_runs,
+        "reference_fp64_single_slot": {"requests": nref, "solves_per_s": round(nref / wall1, 2)},
+        "speedup_vs_fp64_single_slot": round(sat / (nref / wall1), 2),
+        "server": {"peak_busy_slots": st["peak_busy_slots"], "hbm_peak_GB": round(st["hbm_peak"] / 2 ** 30, 3),
+                   "grids": st["grids"]},
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -161,11 +255,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--workload", choices=["c3", "serving"], default="c3")
+    ap.add_argument("--requests", type=int, default=4096)
+    ap.add_argument("--slots", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU; --gpus {args.gpus} is not supported "
               f"(the multi-GPU design is described but not built)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "serving":
+        bench_serving(args)
+        return
 
     import numpy as np
     import torch

@@ -138,7 +138,8 @@ vd_status vd_solve_helmholtz(vd_grid* grid, double dt_nu, int ncomp, const doubl
                              const vd_solve_opts* opts, vd_solve_info* info);
 
 /* Device bytes the grid plus one solve with these options needs (the
- * serving admission test uses it).  Returns 0 for an invalid descriptor. */
+ * serving admission test uses it).  Returns 0 for an invalid descriptor or
+ * invalid options; opts == NULL means defaults. */
 size_t vd_workspace_bytes(const vd_grid_desc* desc, const vd_solve_opts* opts);
 
 /* Time spent in each operator pass since the last read, measured with HIP
@@ -151,6 +152,62 @@ vd_status vd_profile_enable(vd_grid* grid, int on);
 vd_status vd_profile_read(vd_grid* grid, double* ms, long long* count, int nclass);
 
 const char* vd_status_string(vd_status s);
+
+/* ------------------------------------------------------------------------
+ * Continuous-batching solve server.  Not in the paper: a serving front end
+ * for many independent solves of the kinds above (different grid sizes and
+ * densities).  Requests are queued FIFO and admitted as soon as a worker
+ * slot is free and their HBM footprint (vd_workspace_bytes) fits the budget
+ * next to the grids already held; admitted requests run concurrently, each
+ * on its own stream, with their Krylov state resident on the device.  A
+ * result does not depend on what else is running (fixed launch
+ * configurations and reduction orders).
+ * ---------------------------------------------------------------------- */
+typedef struct vd_server vd_server;
+
+typedef struct {
+  vd_grid_desc desc;   /* grid of this request */
+  int kind;            /* VD_OP_PRESSURE or VD_OP_HELMHOLTZ */
+  double dt_nu;        /* Helmholtz coefficient */
+  int ncomp;           /* Helmholtz components (0 or 1 = one) */
+  const double* rho;   /* device density, caller-owned until its result is returned */
+  const double* f;     /* device right-hand side (ready before submit) */
+  double* x;           /* device output (initial guess if opts.use_x0) */
+  vd_solve_opts opts;
+  unsigned long long user_tag;
+} vd_request;
+
+typedef struct {
+  unsigned long long ticket, user_tag;
+  int status, iterations, refinements, slot;
+  double rel_residual;
+  double t_arrive, t_start, t_done; /* seconds since the server was created */
+} vd_result;
+
+typedef struct {
+  long long queued, in_flight;
+  int busy_slots, grids;
+  size_t hbm_used, hbm_peak;
+  int peak_busy_slots;
+} vd_server_stats_t;
+
+/* Start a server with an HBM budget (bytes) and max_slots concurrent solves
+ * (1..64).  Errors: VD_EINVAL, VD_ENOMEM. */
+vd_status vd_server_create(vd_server** out, size_t hbm_budget, int max_slots);
+/* Same scheduler without device work (each request "runs" for the given
+ * seconds and returns VD_ENOTSUP): lets the admission policy be tested on a
+ * machine without a GPU. */
+vd_status vd_server_create_dry(vd_server** out, size_t hbm_budget, int max_slots, double seconds_per_request);
+/* Queue a request; never blocks.  VD_ETOOBIG if its footprint exceeds the
+ * whole budget, VD_EINVAL for a bad descriptor/options/pointers. */
+vd_status vd_server_submit(vd_server* s, const vd_request* req, unsigned long long* ticket);
+/* Move up to cap finished results into out (non-blocking); *n = count. */
+vd_status vd_server_poll(vd_server* s, vd_result* out, int cap, int* n);
+/* As poll, but first waits up to timeout_s for a result (or until idle). */
+vd_status vd_server_wait(vd_server* s, vd_result* out, int cap, int* n, double timeout_s);
+vd_status vd_server_stats(vd_server* s, vd_server_stats_t* st);
+/* Finish running requests, drop queued ones, release everything. */
+vd_status vd_server_destroy(vd_server* s);
 
 #ifdef __cplusplus
 }

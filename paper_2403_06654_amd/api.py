@@ -47,6 +47,28 @@ class VdError(RuntimeError):
         super().__init__(f"{where}: {vd_status_string(status)} ({status})")
 
 
+class vd_request(ctypes.Structure):
+    _fields_ = [("desc", vd_grid_desc), ("kind", ctypes.c_int), ("dt_nu", ctypes.c_double),
+                ("ncomp", ctypes.c_int), ("rho", ctypes.c_void_p), ("f", ctypes.c_void_p),
+                ("x", ctypes.c_void_p), ("opts", vd_solve_opts), ("user_tag", ctypes.c_ulonglong)]
+
+
+class vd_result(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_ulonglong), ("user_tag", ctypes.c_ulonglong), ("status", ctypes.c_int),
+                ("iterations", ctypes.c_int), ("refinements", ctypes.c_int), ("slot", ctypes.c_int),
+                ("rel_residual", ctypes.c_double), ("t_arrive", ctypes.c_double), ("t_start", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class vd_server_stats_t(ctypes.Structure):
+    _fields_ = [("queued", ctypes.c_longlong), ("in_flight", ctypes.c_longlong), ("busy_slots", ctypes.c_int),
+                ("grids", ctypes.c_int), ("hbm_used", ctypes.c_size_t), ("hbm_peak", ctypes.c_size_t),
+                ("peak_busy_slots", ctypes.c_int)]
+
+
 _LIB = None
 _P = ctypes.c_void_p
 _D = ctypes.c_double
@@ -66,6 +88,13 @@ _SIGS = {
     "vd_profile_enable": (_I, [_P, _I]),
     "vd_profile_read": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_longlong), _I]),
     "vd_status_string": (ctypes.c_char_p, [_I]),
+    "vd_server_create": (_I, [ctypes.POINTER(_P), ctypes.c_size_t, _I]),
+    "vd_server_create_dry": (_I, [ctypes.POINTER(_P), ctypes.c_size_t, _I, _D]),
+    "vd_server_submit": (_I, [_P, ctypes.POINTER(vd_request), ctypes.POINTER(ctypes.c_ulonglong)]),
+    "vd_server_poll": (_I, [_P, ctypes.POINTER(vd_result), _I, ctypes.POINTER(_I)]),
+    "vd_server_wait": (_I, [_P, ctypes.POINTER(vd_result), _I, ctypes.POINTER(_I), _D]),
+    "vd_server_stats": (_I, [_P, ctypes.POINTER(vd_server_stats_t)]),
+    "vd_server_destroy": (_I, [_P]),
 }
 
 
@@ -223,3 +252,68 @@ class Grid:
         cnt = (ctypes.c_longlong * nclass)()
         _check(lib().vd_profile_read(self._h, ms, cnt, nclass), "vd_profile_read", False)
         return list(ms), list(cnt)
+
+
+class Server:
+    """Continuous-batching solve server (vd_server_*)."""
+
+    def __init__(self, hbm_budget, max_slots=8, dry_seconds=None):
+        h = ctypes.c_void_p()
+        if dry_seconds is None:
+            st = lib().vd_server_create(ctypes.byref(h), int(hbm_budget), int(max_slots))
+        else:
+            st = lib().vd_server_create_dry(ctypes.byref(h), int(hbm_budget), int(max_slots), float(dry_seconds))
+        _check(st, "vd_server_create", False)
+        self._h = h
+        self._keep = {}   # ticket -> tensors the server reads or writes
+
+    def submit(self, shape, rho=None, f=None, x=None, lengths=None, kind="pressure", dt_nu=0.0, ncomp=1,
+               user_tag=0, **opts):
+        r = vd_request()
+        r.desc = make_desc(shape, lengths)
+        r.kind = VD_OP_PRESSURE if kind == "pressure" else VD_OP_HELMHOLTZ
+        r.dt_nu = float(dt_nu)
+        r.ncomp = int(ncomp)
+        r.rho = rho.data_ptr() if rho is not None else None
+        r.f = f.data_ptr() if f is not None else None
+        r.x = x.data_ptr() if x is not None else None
+        r.opts = make_opts(**opts)
+        r.user_tag = int(user_tag)
+        t = ctypes.c_ulonglong()
+        _check(lib().vd_server_submit(self._h, ctypes.byref(r), ctypes.byref(t)), "vd_server_submit", False)
+        self._keep[t.value] = (rho, f, x)
+        return t.value
+
+    def _collect(self, fn, cap, *extra):
+        buf = (vd_result * cap)()
+        n = ctypes.c_int()
+        _check(fn(self._h, buf, cap, ctypes.byref(n), *extra), "vd_server_poll", False)
+        out = []
+        for i in range(n.value):
+            d = buf[i].as_dict()
+            self._keep.pop(d["ticket"], None)
+            out.append(d)
+        return out
+
+    def poll(self, cap=256):
+        return self._collect(lib().vd_server_poll, cap)
+
+    def wait(self, timeout=1.0, cap=256):
+        return self._collect(lib().vd_server_wait, cap, float(timeout))
+
+    def stats(self):
+        st = vd_server_stats_t()
+        _check(lib().vd_server_stats(self._h, ctypes.byref(st)), "vd_server_stats", False)
+        return {k: getattr(st, k) for k, _ in st._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().vd_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -195,13 +195,16 @@ void mupdate(const Geom& g, void* x, const VecPtrs& V, int nv, const double* coe
 //   pass 2  k_gs_update: w' = w - sum_i h_i v_i, and in the same pass the
 //                        dots c_i = (v_i, w') and ||w'||^2
 //   check   c measures the orthogonality actually lost by classical
-//           Gram-Schmidt; if max|c_i| <= 1e-12 ||w'|| the step is done
+//           Gram-Schmidt; if max|c_i| <= tol ||w'|| the step is done
 //           (H[:, j] = h, H[j+1, j] = ||w'||), else
 //   pass 3  w'' = w' - sum_i c_i v_i  (H[:, j] = h + c,
 //           ||w''||^2 = ||w'||^2 - |c|^2, accurate because |c| << ||w'||).
 // Pass 3 exits at once when not needed, so the common step costs two
-// passes over the basis.
-constexpr double kOrthTol = 1e-12;
+// passes over the basis.  tol = 1e-12 for FP64 vectors (100x below the 1e-10
+// target); 1e-8 for FP32 vectors, whose own rounding already limits the
+// inner solves to ~1e-6.
+template <typename R>
+constexpr double orth_tol() { return sizeof(R) == 8 ? 1e-12 : 1e-8; }
 
 __global__ void k_gs_prep(DevState* st, int nv) {
   if (threadIdx.x) return;
@@ -212,7 +215,7 @@ __global__ void k_gs_prep(DevState* st, int nv) {
   }
 }
 
-__global__ void k_gs_check(DevState* st, int nv) {
+__global__ void k_gs_check(DevState* st, int nv, double tol) {
   if (threadIdx.x) return;
   const double n2 = st->red[nv];
   double cmax = 0.0, c2 = 0.0;
@@ -223,7 +226,7 @@ __global__ void k_gs_check(DevState* st, int nv) {
     cmax = fmax(cmax, fabs(c));
     c2 += c * c;
   }
-  if (n2 > 0.0 && cmax <= kOrthTol * sqrt(n2)) {
+  if (n2 > 0.0 && cmax <= tol * sqrt(n2)) {
     st->reorth = 0;
     st->hn = sqrt(n2);
   } else {
@@ -301,7 +304,7 @@ void gs_orthogonalize(const Geom& g, void* w, const VecPtrs& V, int nv, DevState
     else launch_gs<R, kMaxVec>(g, w, V, nv, st, second, partial, s);
     if (!second) {
       reduce(partial, nv + 1, g.ntot_inv, st->red, s);
-      hipLaunchKernelGGL(k_gs_check, dim3(1), dim3(64), 0, s, st, nv);
+      hipLaunchKernelGGL(k_gs_check, dim3(1), dim3(64), 0, s, st, nv, orth_tol<R>());
     }
   }
 }

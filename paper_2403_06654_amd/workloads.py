@@ -131,6 +131,29 @@ def serving_inputs(req):
             "lengths": (TWO_PI, TWO_PI)}
 
 
+def slab_shape_2d(n, seed, width=0.05, modes=8, amp=0.1):
+    """S(x, y) = tanh((y-pi/2-eta)/w) - tanh((y-3pi/2-eta)/w), so that the
+    serving density of ratio r is 1 + (r-1)/2 S."""
+    y = grid_1d(n)[:, None]
+    eta = interface_perturbation(n, modes, amp, seed, tag=4)[None, :]
+    return np.ascontiguousarray(np.tanh((y - np.pi / 2 - eta) / width)
+                                - np.tanh((y - 3 * np.pi / 2 - eta) / width))
+
+
+def serving_pool(sizes=(128, 256, 512, 1024), pool=8, seed=2024):
+    """Per grid size, `pool` interface shapes and right-hand sides; request
+    i uses entry (seed_i mod pool) with its own density ratio."""
+    out = {}
+    for n in sizes:
+        out[n] = [(slab_shape_2d(n, seed + 97 * k), band_limited((n, n), 32, seed + 97 * k, tag=6))
+                  for k in range(pool)]
+    return out
+
+
+def serving_density(shape_field, r):
+    return 1.0 + 0.5 * (r - 1.0) * shape_field
+
+
 def poisson_arrivals(count, qps, seed=2024):
     rng = _rng(seed, 7)
     return np.cumsum(rng.exponential(1.0 / qps, size=count))

@@ -1,0 +1,106 @@
+"""Host-side scheduling of the solve server, exercised without a GPU through
+the scheduler's dry-run mode (no device work; each request occupies its
+slot for a fixed time): FIFO admission, admission by HBM footprint,
+rejection of requests larger than the budget, the slot limit, and release
+of idle grids of other shapes under budget pressure."""
+import time
+
+import pytest
+
+from paper_2403_06654_amd import api
+
+
+def _drain(srv, count, timeout=30.0):
+    out = []
+    t_end = time.time() + timeout
+    while len(out) < count and time.time() < t_end:
+        out += srv.wait(timeout=0.5)
+    assert len(out) == count, (len(out), count)
+    return sorted(out, key=lambda r: r["ticket"])
+
+
+def test_fifo_order_single_slot():
+    srv = api.Server(hbm_budget=1 << 40, max_slots=1, dry_seconds=0.01)
+    tickets = [srv.submit((128, 128), user_tag=i, precision="fp32_refine") for i in range(8)]
+    res = _drain(srv, 8)
+    assert [r["ticket"] for r in res] == tickets
+    starts = [r["t_start"] for r in res]
+    assert starts == sorted(starts)
+    for a, b in zip(res, res[1:]):
+        assert b["t_start"] >= a["t_done"] - 1e-6
+    assert all(r["status"] == -7 for r in res)      # dry run: nothing solved
+    srv.close()
+
+
+def test_admission_by_footprint_and_head_of_line():
+    big = api.workspace_bytes((1024, 1024), precision="fp32_refine")
+    small = api.workspace_bytes((128, 128), precision="fp32_refine")
+    assert big > 40 * small
+    srv = api.Server(hbm_budget=big + small // 2, max_slots=8, dry_seconds=0.05)
+    t1 = srv.submit((1024, 1024), precision="fp32_refine")
+    t2 = srv.submit((1024, 1024), precision="fp32_refine")   # same shape: reuses the grid after t1
+    t3 = srv.submit((128, 128), precision="fp32_refine")     # does not fit next to the big grid
+    res = {r["ticket"]: r for r in _drain(srv, 3)}
+    assert res[t2]["t_start"] >= res[t1]["t_done"] - 1e-6
+    assert res[t3]["t_start"] >= res[t2]["t_start"] - 1e-6     # FIFO: no overtaking
+    st = srv.stats()
+    assert st["hbm_peak"] <= big + small // 2
+    srv.close()
+
+
+def test_too_big_is_rejected():
+    small = api.workspace_bytes((128, 128))
+    srv = api.Server(hbm_budget=small, max_slots=2, dry_seconds=0.0)
+    with pytest.raises(api.VdError) as e:
+        srv.submit((256, 256))
+    assert e.value.status == -6
+    srv.submit((128, 128))
+    _drain(srv, 1)
+    srv.close()
+
+
+def test_slot_limit_and_overlap():
+    srv = api.Server(hbm_budget=1 << 40, max_slots=4, dry_seconds=0.05)
+    t0 = time.time()
+    for i in range(16):
+        srv.submit((128, 128) if i % 2 else (256, 256))
+    res = _drain(srv, 16)
+    wall = time.time() - t0
+    st = srv.stats()
+    assert st["peak_busy_slots"] == 4
+    assert wall < 16 * 0.05 * 0.6                   # requests overlapped
+    # never more than 4 running at any instant
+    events = sorted([(r["t_start"], 1) for r in res] + [(r["t_done"], -1) for r in res])
+    run = peak = 0
+    for _, d in events:
+        run += d
+        peak = max(peak, run)
+    assert peak <= 4
+    srv.close()
+
+
+def test_idle_grids_released_under_pressure():
+    a = api.workspace_bytes((512, 512))
+    b = api.workspace_bytes((256, 256))
+    srv = api.Server(hbm_budget=a + b // 2, max_slots=2, dry_seconds=0.0)
+    srv.submit((512, 512))
+    _drain(srv, 1)
+    assert srv.stats()["grids"] == 1
+    srv.submit((256, 256))                           # needs the 512^2 grid released
+    _drain(srv, 1)
+    st = srv.stats()
+    assert st["grids"] == 1 and st["hbm_used"] == b
+    srv.close()
+
+
+def test_invalid_requests():
+    srv = api.Server(hbm_budget=1 << 30, max_slots=1, dry_seconds=0.0)
+    with pytest.raises(api.VdError):
+        srv.submit((100, 100))
+    with pytest.raises(api.VdError):
+        srv.submit((128, 128), restart=99)
+    srv.close()
+    with pytest.raises(api.VdError):
+        api.Server(hbm_budget=0, max_slots=1, dry_seconds=0.0)
+    with pytest.raises(api.VdError):
+        api.Server(hbm_budget=1 << 30, max_slots=0, dry_seconds=0.0)
