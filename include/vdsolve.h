@@ -142,14 +142,17 @@ vd_status vd_solve_helmholtz(vd_grid* grid, double dt_nu, int ncomp, const doubl
  * invalid options; opts == NULL means defaults. */
 size_t vd_workspace_bytes(const vd_grid_desc* desc, const vd_solve_opts* opts);
 
-/* Time spent in each operator pass since the last read, measured with HIP
+/* Time spent in each hot kernel since the last read, measured with HIP
  * events on the grid's stream while enabled.  Classes 0..4: the pressure
  * operator's z-first, y-inverse, x, y-forward and z-last passes; 5..9: the
- * same passes of the Helmholtz operator.  ms[c] = total milliseconds,
- * count[c] = launches, for c < nclass (<= 10).  Reading resets the totals.
- * Enabling adds an event pair per timed launch. */
+ * same passes of the Helmholtz operator; 10: the GMRES Gram-Schmidt dot
+ * pass; 11: the GMRES Gram-Schmidt update pass.  ms[c] = total
+ * milliseconds, count[c] = launches, bytes[c] = algorithmic bytes those
+ * launches read and wrote (3D grids), for c < nclass (<= 12); any output
+ * pointer may be NULL.  Reading resets the totals.  Enabling adds an event
+ * pair per timed launch. */
 vd_status vd_profile_enable(vd_grid* grid, int on);
-vd_status vd_profile_read(vd_grid* grid, double* ms, long long* count, int nclass);
+vd_status vd_profile_read(vd_grid* grid, double* ms, long long* count, double* bytes, int nclass);
 
 const char* vd_status_string(vd_status s);
 

@@ -86,7 +86,7 @@ _SIGS = {
                                 ctypes.POINTER(vd_solve_info)]),
     "vd_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(vd_grid_desc), ctypes.POINTER(vd_solve_opts)]),
     "vd_profile_enable": (_I, [_P, _I]),
-    "vd_profile_read": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_longlong), _I]),
+    "vd_profile_read": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(_D), _I]),
     "vd_status_string": (ctypes.c_char_p, [_I]),
     "vd_server_create": (_I, [ctypes.POINTER(_P), ctypes.c_size_t, _I]),
     "vd_server_create_dry": (_I, [ctypes.POINTER(_P), ctypes.c_size_t, _I, _D]),
@@ -247,11 +247,12 @@ class Grid:
     def profile_enable(self, on=True):
         _check(lib().vd_profile_enable(self._h, 1 if on else 0), "vd_profile_enable", False)
 
-    def profile_read(self, nclass=10):
+    def profile_read(self, nclass=12):
         ms = (ctypes.c_double * nclass)()
         cnt = (ctypes.c_longlong * nclass)()
-        _check(lib().vd_profile_read(self._h, ms, cnt, nclass), "vd_profile_read", False)
-        return list(ms), list(cnt)
+        nb = (ctypes.c_double * nclass)()
+        _check(lib().vd_profile_read(self._h, ms, cnt, nb, nclass), "vd_profile_read", False)
+        return list(ms), list(cnt), list(nb)
 
 
 class Server:

@@ -489,12 +489,16 @@ static RowArgs row_args(const Geom& g, const OpParams* p) {
   return a;
 }
 
+// Fields each pass reads plus writes (3D): pressure P1..P5, Helmholtz P1..P5.
+constexpr double kPassFields[10] = {3, 5, 7, 5, 3, 2, 2, 3, 2, 3};
+
 template <typename R>
 void op_apply(const Geom& g, const OpParams& p, const void* v, void* y, const OpWork& w, const void* coef,
               const void* twtab, hipStream_t st, Prof* prof) {
   const bool pr = prof && prof->on;
+  const double fb = (double)g.nz * g.ny * g.M * sizeof(C2<R>);  // one field
 #define VD_T0(c) \
-  if (pr) prof->begin(c, st);
+  if (pr) prof->begin(c, st, kPassFields[c] * fb);
 #define VD_T1() \
   if (pr) prof->end(st);
   const size_t zin = (size_t)g.ny * g.M;  // inner size of the z pass

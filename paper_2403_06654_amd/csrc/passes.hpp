@@ -34,21 +34,25 @@ struct OpWork {
   void* t[6];
 };
 
-// Optional per-launch timing of the pass kernels with HIP events on the
-// launch stream.  Classes: 0 z-first, 1 y-inverse, 2 x, 3 y-forward,
-// 4 z-last of the pressure operator; 5..9 the same passes of the
-// Helmholtz operator.
+// Optional per-launch timing of the hot kernels with HIP events on the
+// launch stream, with the algorithmic bytes each launch moves.  Classes:
+// 0 z-first, 1 y-inverse, 2 x, 3 y-forward, 4 z-last of the pressure
+// operator; 5..9 the same passes of the Helmholtz operator; 10 the
+// Gram-Schmidt dot pass (k_mdot), 11 the Gram-Schmidt update pass
+// (k_gs_update).
 struct Prof {
-  static constexpr int kClasses = 10;
+  static constexpr int kClasses = 12;
   bool on = false;
-  struct Pair { int cls; hipEvent_t a, b; };
+  struct Pair { int cls; double bytes; hipEvent_t a, b; };
   std::vector<Pair> pending;
   std::vector<hipEvent_t> spare;
   double ms[kClasses] = {0};
+  double bytes[kClasses] = {0};
   long long cnt[kClasses] = {0};
   int cur = -1;
+  double cur_bytes = 0;
   hipEvent_t cur_a = nullptr;
-  void begin(int cls, hipStream_t s);
+  void begin(int cls, hipStream_t s, double nbytes = 0);
   void end(hipStream_t s);
   void flush();  // accumulate completed pairs (call after a stream sync)
   void release();

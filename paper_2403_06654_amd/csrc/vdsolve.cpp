@@ -37,7 +37,7 @@ using namespace vd;
 
 // ------------------------------------------------------------ profiling
 
-void Prof::begin(int cls, hipStream_t s) {
+void Prof::begin(int cls, hipStream_t s, double nbytes) {
   hipEvent_t a;
   if (!spare.empty()) {
     a = spare.back();
@@ -47,6 +47,7 @@ void Prof::begin(int cls, hipStream_t s) {
   }
   hipEventRecord(a, s);
   cur = cls;
+  cur_bytes = nbytes;
   cur_a = a;
 }
 void Prof::end(hipStream_t s) {
@@ -58,13 +59,14 @@ void Prof::end(hipStream_t s) {
     hipEventCreate(&b);
   }
   hipEventRecord(b, s);
-  pending.push_back(Pair{cur, cur_a, b});
+  pending.push_back(Pair{cur, cur_bytes, cur_a, b});
 }
 void Prof::flush() {
   for (auto& p : pending) {
     float ms_ = 0.f;
     if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms_, p.a, p.b) == hipSuccess) {
       ms[p.cls] += ms_;
+      bytes[p.cls] += p.bytes;
       cnt[p.cls] += 1;
     }
     spare.push_back(p.a);
@@ -319,7 +321,7 @@ struct Krylov {
         o.iters++;
         VecPtrs P{};
         for (int i = 0; i <= j; ++i) P.p[i] = V[i];
-        gs_orthogonalize<R>(g, V[j + 1], P, j + 1, G->dst, G->partial, G->st);
+        gs_orthogonalize<R>(g, V[j + 1], P, j + 1, G->dst, G->partial, G->st, &G->prof);
         gmres_givens(G->dst, j, G->st);
         sync_state(G);
         k = j + 1;
@@ -787,17 +789,19 @@ vd_status vd_profile_enable(vd_grid* G, int on) {
   return VD_OK;
 }
 
-vd_status vd_profile_read(vd_grid* G, double* ms, long long* count, int nclass) {
+vd_status vd_profile_read(vd_grid* G, double* ms, long long* count, double* bytes, int nclass) {
   if (!G || nclass < 0) return VD_EINVAL;
-  if (G->st) hipStreamSynchronize(G->st);
+  if (G->st) (void)hipStreamSynchronize(G->st);
   G->prof.flush();
   for (int c = 0; c < nclass && c < Prof::kClasses; ++c) {
     if (ms) ms[c] = G->prof.ms[c];
     if (count) count[c] = G->prof.cnt[c];
+    if (bytes) bytes[c] = G->prof.bytes[c];
   }
   for (int c = 0; c < Prof::kClasses; ++c) {
     G->prof.ms[c] = 0;
     G->prof.cnt[c] = 0;
+    G->prof.bytes[c] = 0;
   }
   return VD_OK;
 }

@@ -95,7 +95,7 @@ __global__ __launch_bounds__(256) void k_mdot(const C2<R>* __restrict__ x, VecPt
 
 template <typename R>
 void mdot(const Geom& g, const void* x, const VecPtrs& V, int nv, bool want_norm, double* partial, double* out,
-          hipStream_t s) {
+          hipStream_t s, Prof* prof) {
   size_t n = nspec(g);
   dim3 gr(kRedBlocks), bl(256);
   const int wn = want_norm ? 1 : 0;
@@ -113,6 +113,7 @@ void mdot(const Geom& g, const void* x, const VecPtrs& V, int nv, bool want_norm
     hipLaunchKernelGGL((k_mdot<R, 24>), gr, bl, 0, s, (const C2<R>*)x, V, nv, wn, n, g.M, partial);
   else
     hipLaunchKernelGGL((k_mdot<R, kMaxVec>), gr, bl, 0, s, (const C2<R>*)x, V, nv, wn, n, g.M, partial);
+  if (prof) prof->end(s);
   reduce(partial, nv + wn, g.ntot_inv, out, s);
 }
 
@@ -240,9 +241,8 @@ __global__ void k_gs_check(DevState* st, int nv, double tol) {
 
 template <typename R, int NV>
 __global__ __launch_bounds__(256) void k_gs_update(C2<R>* __restrict__ x, VecPtrs V, int nv,
-                                                   const DevState* __restrict__ st, int second, size_t n, int M,
+                                                   const DevState* __restrict__ st, size_t n, int M,
                                                    double* __restrict__ partial) {
-  if (second && !st->reorth) return;
   double c[NV];
 #pragma unroll
   for (int i = 0; i < NV; ++i) c[i] = i < nv ? st->coef[i] : 0.0;
@@ -265,16 +265,13 @@ __global__ __launch_bounds__(256) void k_gs_update(C2<R>* __restrict__ x, VecPtr
     }
     C2<R> nx{R(xr), R(xi)};
     stg(x + e, nx);
-    if (!second) {
-      const double w = spec_w(e, M);
-      const double yr = nx.x, yi = nx.y;
+    const double w = spec_w(e, M);
+    const double yr = nx.x, yi = nx.y;
 #pragma unroll
-      for (int i = 0; i < NV; ++i)
-        if (i < nv) acc[i] += w * ((double)vv[i].x * yr + (double)vv[i].y * yi);
-      acc[NV] += w * (yr * yr + yi * yi);
-    }
+    for (int i = 0; i < NV; ++i)
+      if (i < nv) acc[i] += w * ((double)vv[i].x * yr + (double)vv[i].y * yi);
+    acc[NV] += w * (yr * yr + yi * yi);
   }
-  if (second) return;
   double out[NV + 1];
 #pragma unroll
   for (int i = 0; i <= NV; ++i) out[i] = acc[i];
@@ -284,24 +281,55 @@ __global__ __launch_bounds__(256) void k_gs_update(C2<R>* __restrict__ x, VecPtr
   block_store<NV + 1>(out, nv + 1, partial + (size_t)blockIdx.x * kRedStride);
 }
 
+// The second pass is its own kernel symbol so that profiles separate it.
+template <typename R, int NV>
+__global__ __launch_bounds__(256) void k_gs_reorth(C2<R>* __restrict__ x, VecPtrs V, int nv,
+                                                   const DevState* __restrict__ st, size_t n) {
+  if (!st->reorth) return;
+  double c[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) c[i] = i < nv ? st->coef[i] : 0.0;
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+    C2<R> xv = ldg(x + e);
+    double xr = xv.x, xi = xv.y;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      if (i < nv) {
+        C2<R> v = ldg((const C2<R>*)V.p[i] + e);
+        xr -= c[i] * (double)v.x;
+        xi -= c[i] * (double)v.y;
+      }
+    }
+    stg(x + e, C2<R>{R(xr), R(xi)});
+  }
+}
+
 template <typename R, int NV>
 static void launch_gs(const Geom& g, void* x, const VecPtrs& V, int nv, const DevState* st, int second,
                       double* partial, hipStream_t s) {
-  hipLaunchKernelGGL((k_gs_update<R, NV>), dim3(kRedBlocks), dim3(256), 0, s, (C2<R>*)x, V, nv, st, second,
-                     nspec(g), g.M, partial);
+  if (second)
+    hipLaunchKernelGGL((k_gs_reorth<R, NV>), dim3(kRedBlocks), dim3(256), 0, s, (C2<R>*)x, V, nv, st, nspec(g));
+  else
+    hipLaunchKernelGGL((k_gs_update<R, NV>), dim3(kRedBlocks), dim3(256), 0, s, (C2<R>*)x, V, nv, st, nspec(g),
+                       g.M, partial);
 }
 
 template <typename R>
 void gs_orthogonalize(const Geom& g, void* w, const VecPtrs& V, int nv, DevState* st, double* partial,
-                      hipStream_t s) {
-  mdot<R>(g, w, V, nv, false, partial, st->red2, s);
+                      hipStream_t s, Prof* prof) {
+  const bool pr = prof && prof->on;
+  const double fb = (double)nspec(g) * sizeof(C2<R>);
+  if (pr) prof->begin(10, s, (nv + 1) * fb);
+  mdot<R>(g, w, V, nv, false, partial, st->red2, s, pr ? prof : nullptr);
   hipLaunchKernelGGL(k_gs_prep, dim3(1), dim3(64), 0, s, st, nv);
   for (int second = 0; second < 2; ++second) {
+    if (pr && !second) prof->begin(11, s, (nv + 2) * fb);
     if (nv <= 4) launch_gs<R, 4>(g, w, V, nv, st, second, partial, s);
     else if (nv <= 8) launch_gs<R, 8>(g, w, V, nv, st, second, partial, s);
     else if (nv <= 16) launch_gs<R, 16>(g, w, V, nv, st, second, partial, s);
     else if (nv <= 24) launch_gs<R, 24>(g, w, V, nv, st, second, partial, s);
     else launch_gs<R, kMaxVec>(g, w, V, nv, st, second, partial, s);
+    if (pr && !second) prof->end(s);
     if (!second) {
       reduce(partial, nv + 1, g.ntot_inv, st->red, s);
       hipLaunchKernelGGL(k_gs_check, dim3(1), dim3(64), 0, s, st, nv, orth_tol<R>());
@@ -684,12 +712,14 @@ void density_setup(const double* rho, size_t n, double* a64, float* a32, float* 
 // ------------------------------------------------------- instantiations
 
 #define VD_INST(R)                                                                                             \
-  template void mdot<R>(const Geom&, const void*, const VecPtrs&, int, bool, double*, double*, hipStream_t);   \
+  template void mdot<R>(const Geom&, const void*, const VecPtrs&, int, bool, double*, double*, hipStream_t,    \
+                        Prof*);                                                                                \
   template void mupdate<R>(const Geom&, void*, const VecPtrs&, int, const double*, bool, double*, double*,     \
                            hipStream_t);                                                                       \
   template void lincomb<R>(const Geom&, void*, const VecPtrs&, int, const double*, hipStream_t);               \
   template void scale<R>(const Geom&, void*, const double*, double, hipStream_t);                              \
-  template void gs_orthogonalize<R>(const Geom&, void*, const VecPtrs&, int, DevState*, double*, hipStream_t); \
+  template void gs_orthogonalize<R>(const Geom&, void*, const VecPtrs&, int, DevState*, double*, hipStream_t,  \
+                                    Prof*);                                                                    \
   template void sub_norm<R>(const Geom&, const void*, const void*, void*, double*, double*, hipStream_t);      \
   template void precond_axpy<R>(const Geom&, const OpParams&, void*, const void*, const double*, double,       \
                                 hipStream_t);                                                                  \

@@ -45,7 +45,7 @@ struct DevState {
 // index nv when want_norm.  Then reduce into st->red (times 1/N).
 template <typename R>
 void mdot(const Geom& g, const void* x, const VecPtrs& V, int nv, bool want_norm, double* partial,
-          double* out, hipStream_t s);
+          double* out, hipStream_t s, Prof* prof = nullptr);
 
 // x -= sum_i c_i V_i with c read from `coef` (device); then (optionally)
 // dots of V_i with the updated x and its squared norm, reduced into `out`.
@@ -60,7 +60,7 @@ void mupdate(const Geom& g, void* x, const VecPtrs& V, int nv, const double* coe
 // vs[nv] = 1 / ||w||.
 template <typename R>
 void gs_orthogonalize(const Geom& g, void* w, const VecPtrs& V, int nv, DevState* st, double* partial,
-                      hipStream_t s);
+                      hipStream_t s, Prof* prof = nullptr);
 
 // z = sum_i c_i V_i
 template <typename R>
