@@ -9,10 +9,13 @@ second-derivative symbol keeps the Nyquist index.
 
 Chebyshev axes use Gauss-Lobatto points z_j = cos(pi j / M), j = 0..M, and
 the collocation differentiation matrix D^1 of Sec. 3.1 (eq. VDINSE.Vrho is
-written with these matrices).  Clenshaw-Curtis weights give the quadrature
-used by the weak (G-NI) form of the wall-bounded pressure operator.
+written with these matrices).  The weak form of the wall-bounded pressure
+operator integrates with Legendre-Gauss-Lobatto quadrature (exact to degree
+2M - 1), reached from the Chebyshev nodal values by polynomial interpolation.
+Clenshaw-Curtis weights are kept for the pins.
 """
 import numpy as np
+from numpy.polynomial import legendre as _leg
 
 
 def fourier_index(n):
@@ -83,3 +86,40 @@ def clenshaw_curtis_weights(m):
             v = v - 2.0 * np.cos(2 * k * theta[inner]) / (4 * k * k - 1)
     w[inner] = 2.0 * v / m
     return w
+
+
+def lgl_points_weights(m):
+    """Legendre-Gauss-Lobatto nodes (descending, +1 .. -1) and weights on
+    [-1, 1]: +-1 and the roots of P_m', weights 2 / (m (m+1) P_m(x)^2).
+    Roots from the Legendre companion matrix, polished by Newton steps."""
+    c = np.zeros(m + 1)
+    c[m] = 1.0
+    dc = _leg.legder(c)
+    x = np.sort(np.real(_leg.legroots(dc)))
+    d2 = _leg.legder(dc)
+    for _ in range(3):
+        x = x - _leg.legval(x, dc) / _leg.legval(x, d2)
+    x = np.concatenate([[-1.0], x, [1.0]])[::-1].copy()
+    w = 2.0 / (m * (m + 1) * _leg.legval(x, c) ** 2)
+    return x, w
+
+
+def cheb_interp_matrix(m, x_to):
+    """Matrix of polynomial interpolation from the m+1 Chebyshev-Gauss-Lobatto
+    nodes to the points x_to (barycentric formula with the closed-form
+    weights (-1)^j delta_j, delta_0 = delta_m = 1/2)."""
+    z = cheb_points(m)
+    bw = (-1.0) ** np.arange(m + 1)
+    bw[0] *= 0.5
+    bw[m] *= 0.5
+    x_to = np.asarray(x_to, dtype=float)
+    P = np.zeros((len(x_to), m + 1))
+    for i, xi in enumerate(x_to):
+        d = xi - z
+        hit = np.nonzero(d == 0.0)[0]
+        if len(hit):
+            P[i, hit[0]] = 1.0
+            continue
+        t = bw / d
+        P[i] = t / t.sum()
+    return P

@@ -159,9 +159,19 @@ def project_range(b, basis):
 # ------------------------------------------- Fourier (x) x Chebyshev (z)
 
 class FourierChebyshev2D:
-    """x periodic (nx Fourier points on [0, lx)), z on m+1 GL points.
+    """x periodic (nx Fourier points on [0, lx)), z on m+1 Chebyshev-Gauss-
+    Lobatto points with Neumann walls.  Field shape (m + 1, nx), row 0 is
+    z = +1.
 
-    Field shape (m + 1, nx): z is the slow axis, row 0 is z = +1.
+    Weak (Galerkin with numerical integration) form of L_rho p = f: for
+    every nodal test function v,  int a grad p . grad v = -int f v, the
+    boundary term vanishing by the natural Neumann condition.  Integrals in
+    z use Legendre-Gauss-Lobatto quadrature on m+1 nodes (exact to degree
+    2m - 1), reached by interpolation I from the Chebyshev nodes; x is
+    Fourier with the uniform rule h_x.  With G = I D_z and W = h_x w_LGL:
+        A u = I^T D_x^T (W a_L D_x I u) + G^T (W a_L G u),  b = -I^T (W I f),
+    a_L = 1 / (I rho).  A is symmetric positive semi-definite with
+    nullspace {1, (-1)^i in x} x {1 in z}.
     """
 
     def __init__(self, nx, m, lx=2.0):
@@ -170,29 +180,32 @@ class FourierChebyshev2D:
         self.z = grids.cheb_points(m)
         self.x = lx * np.arange(nx) / nx
         self.Dz = grids.cheb_diff_matrix(m)
-        self.wz = grids.clenshaw_curtis_weights(m)
-        self.W = self.hx * self.wz[:, None] * np.ones((1, nx))
+        self.zl, self.wl = grids.lgl_points_weights(m)
+        self.I = grids.cheb_interp_matrix(m, self.zl)
+        self.G = self.I @ self.Dz
+        self.W = self.hx * self.wl[:, None] * np.ones((1, nx))
 
     def dx(self, u):
         return deriv(u, 1, self.lx)
 
-    def dz(self, u):
-        return self.Dz @ u
-
     def dxT(self, u):
         return -deriv(u, 1, self.lx)  # D_x is real skew-symmetric
 
-    def dzT(self, u):
-        return self.Dz.T @ u
+    def a_lgl(self, rho):
+        return 1.0 / (self.I @ rho)
+
+    def gz(self, u):
+        return self.G @ u
+
+    def gzT(self, q):
+        return self.G.T @ q
 
     def apply_pressure(self, u, rho):
-        """A u = D_x^T (W a D_x u) + D_z^T (W a D_z u), a = 1/rho."""
-        wa = self.W / rho
-        return self.dxT(wa * self.dx(u)) + self.dzT(wa * self.dz(u))
+        wa = self.W * self.a_lgl(rho)
+        return self.I.T @ self.dxT(wa * self.dx(self.I @ u)) + self.gzT(wa * self.gz(u))
 
     def rhs(self, f):
-        """b = -W f (weak form of L_rho p = f with natural Neumann walls)."""
-        return -self.W * f
+        return -(self.I.T @ (self.W * (self.I @ f)))
 
     def nullspace_basis(self):
         ones_z = np.ones(self.m + 1)
@@ -202,21 +215,19 @@ class FourierChebyshev2D:
         return [np.multiply.outer(ones_z, v) for v in vs]
 
     def precond_pressure(self, r, rho0):
-        """Pseudo-inverse of A at rho = rho0, per x wavenumber.
-
-        A_0(kx) = (h_x / rho0) (k'_x^2 W_z + D_z^T W_z D_z); solved by LU where
-        k'_x != 0 and by the pseudo-inverse (constant-in-z nullspace) where
-        k'_x = 0.
-        """
+        """Pseudo-inverse of A at rho = rho0, per x wavenumber:
+        A_0(kx) = (h_x / rho0) (k'_x^2 M_z + S_z), M_z = I^T diag(w) I,
+        S_z = G^T diag(w) G; LU where k'_x != 0, pseudo-inverse (constant-in-z
+        nullspace) where k'_x = 0."""
         rh = np.fft.fft(r, axis=1)
         kp = grids.fourier_kprime(self.nx, self.lx)
-        Wz = np.diag(self.wz)
-        Sz = self.Dz.T @ Wz @ self.Dz
+        Mz = self.I.T @ np.diag(self.wl) @ self.I
+        Sz = self.G.T @ np.diag(self.wl) @ self.G
         out = np.zeros_like(rh)
         for j in range(self.nx):
-            mat = (self.hx / rho0) * (kp[j] ** 2 * Wz + Sz)
+            mat = (self.hx / rho0) * (kp[j] ** 2 * Mz + Sz)
             if kp[j] != 0.0:
                 out[:, j] = np.linalg.solve(mat, rh[:, j])
             else:
-                out[:, j] = np.linalg.pinv(mat) @ rh[:, j]
+                out[:, j] = np.linalg.pinv(mat, hermitian=True) @ rh[:, j]
         return np.real(np.fft.ifft(out, axis=1))

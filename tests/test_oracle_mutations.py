@@ -49,7 +49,7 @@ def test_preconditioner_without_rho0_is_caught(monkeypatch):
 
 
 def test_untransposed_chebyshev_operand_is_caught(monkeypatch):
-    monkeypatch.setattr(operators.FourierChebyshev2D, "dzT", lambda self, u: -(self.Dz @ u))
+    monkeypatch.setattr(operators.FourierChebyshev2D, "gzT", lambda self, q: self.G @ q)
     _fails(to.test_fourier_chebyshev_operator)
 
 
