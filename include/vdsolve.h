@@ -21,6 +21,14 @@
  *   - Grids are Fourier (periodic) on every axis; n[0] = nx is the
  *     contiguous axis.  Physical fields are real FP64 arrays in C order
  *     [nz][ny][nx] (2D: [ny][nx]; 1D: [nx]) with x_j = j L / n.
+ *   - Exception: a 2D grid may have basis[1] = VD_CHEB_GL, a wall-normal
+ *     axis on the n[1] Chebyshev-Gauss-Lobatto points z_j = cos(pi j /
+ *     (n[1]-1)) of [-1, 1] (row 0 is z = +1; length[1] is ignored) with
+ *     Neumann walls (Sec. 3, C-F-F decomposition).  Its pressure system is
+ *     the Galerkin weak form (Legendre-Gauss-Lobatto quadrature of the
+ *     interpolant): A p = b with b = -I^T W I f, A symmetric positive
+ *     semi-definite; residuals are measured on that system.  Helmholtz
+ *     solves are not available on such grids.
  *   - Every field pointer is DEVICE memory, owned by the caller, valid for
  *     the duration of the call.  The library keeps no pointer to it.
  *   - Work is enqueued on the stream given at grid creation; each call
@@ -52,7 +60,7 @@ typedef enum {
   VD_ENOTSUP = -7     /* valid but not implemented */
 } vd_status;
 
-typedef enum { VD_FOURIER = 0 } vd_basis;
+typedef enum { VD_FOURIER = 0, VD_CHEB_GL = 1 } vd_basis;
 typedef enum { VD_GMRES = 0, VD_CG = 1, VD_RMR = 2 } vd_solver;
 typedef enum { VD_FP64 = 0, VD_FP32_REFINE = 1 } vd_precision;
 typedef enum { VD_OP_PRESSURE = 0, VD_OP_HELMHOLTZ = 1 } vd_op_kind;
@@ -60,8 +68,8 @@ typedef enum { VD_OP_PRESSURE = 0, VD_OP_HELMHOLTZ = 1 } vd_op_kind;
 typedef struct {
   int ndim;         /* 1, 2 or 3 */
   int n[3];         /* points per axis, n[0] = nx (contiguous): powers of two,
-                       16 <= n <= 1024; unused axes ignored */
-  int basis[3];     /* VD_FOURIER on every used axis */
+                       16 <= n <= 1024 (Fourier); 9..513 (Chebyshev) */
+  int basis[3];     /* VD_FOURIER, or VD_CHEB_GL on axis 1 of a 2D grid */
   double length[3]; /* period of each axis (> 0) */
 } vd_grid_desc;
 
@@ -155,6 +163,14 @@ vd_status vd_profile_enable(vd_grid* grid, int on);
 vd_status vd_profile_read(vd_grid* grid, double* ms, long long* count, double* bytes, int nclass);
 
 const char* vd_status_string(vd_status s);
+
+/* C = A B for row-major device matrices A [M][K], B [K][N], C [M][N] in FP64
+ * (precision VD_FP64) or FP32 (VD_FP32_REFINE): the MFMA contraction the
+ * Chebyshev direction uses (its differentiation, interpolation and
+ * eigenbasis products, Sec. 3 C-F-F).  Runs on `stream` and returns after
+ * completion. */
+vd_status vd_dense_matmul(int precision, const void* A, const void* B, void* C, int M, int N, int K,
+                          hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * Continuous-batching solve server.  Not in the paper: a serving front end

@@ -88,6 +88,7 @@ _SIGS = {
     "vd_profile_enable": (_I, [_P, _I]),
     "vd_profile_read": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(_D), _I]),
     "vd_status_string": (ctypes.c_char_p, [_I]),
+    "vd_dense_matmul": (_I, [_I, _P, _P, _P, _I, _I, _I, _P]),
     "vd_server_create": (_I, [ctypes.POINTER(_P), ctypes.c_size_t, _I]),
     "vd_server_create_dry": (_I, [ctypes.POINTER(_P), ctypes.c_size_t, _I, _D]),
     "vd_server_submit": (_I, [_P, ctypes.POINTER(vd_request), ctypes.POINTER(ctypes.c_ulonglong)]),
@@ -117,8 +118,10 @@ def vd_status_string(s):
     return lib().vd_status_string(int(s)).decode()
 
 
-def make_desc(shape, lengths=None):
-    """Descriptor for a Fourier grid of C-order ``shape`` (x last)."""
+def make_desc(shape, lengths=None, cheb=False):
+    """Descriptor of a grid of C-order ``shape`` (x last).  Fourier on every
+    axis, or with ``cheb`` a 2D grid (nz, nx) whose first axis holds the nz
+    Chebyshev-Gauss-Lobatto points of [-1, 1] (row 0 at z = +1)."""
     nd = len(shape)
     if lengths is None:
         lengths = (2 * math.pi,) * nd
@@ -128,7 +131,25 @@ def make_desc(shape, lengths=None):
         d.n[i] = int(shape[nd - 1 - i])
         d.length[i] = float(lengths[nd - 1 - i])
         d.basis[i] = 0
+    if cheb:
+        if nd != 2:
+            raise ValueError("a Chebyshev axis needs a 2D grid (nz, nx)")
+        d.basis[1] = 1
+        d.length[1] = 2.0
     return d
+
+
+def dense_matmul(A, B, precision="fp64"):
+    """C = A @ B on the device with the library's MFMA contraction."""
+    import torch
+    M, K = A.shape
+    K2, N = B.shape
+    assert K == K2 and A.is_contiguous() and B.is_contiguous() and A.dtype == B.dtype
+    C = torch.empty((M, N), dtype=A.dtype, device=A.device)
+    st = torch.cuda.current_stream().cuda_stream
+    _check(lib().vd_dense_matmul(PRECISIONS[precision], A.data_ptr(), B.data_ptr(), C.data_ptr(), M, N, K, st),
+           "vd_dense_matmul", False)
+    return C
 
 
 def make_opts(solver="gmres", restart=30, rtol=1e-10, max_iter=2000, precond=True, precision="fp64",
@@ -148,8 +169,8 @@ def make_opts(solver="gmres", restart=30, rtol=1e-10, max_iter=2000, precond=Tru
     return o
 
 
-def workspace_bytes(shape, lengths=None, **opts):
-    d = make_desc(shape, lengths)
+def workspace_bytes(shape, lengths=None, cheb=False, **opts):
+    d = make_desc(shape, lengths, cheb)
     o = make_opts(**opts)
     return int(lib().vd_workspace_bytes(ctypes.byref(d), ctypes.byref(o)))
 
@@ -172,12 +193,12 @@ def _dev_f64(t, shape, what):
 class Grid:
     """A periodic grid with its device resources (vd_grid_create)."""
 
-    def __init__(self, shape, lengths=None, stream=None):
+    def __init__(self, shape, lengths=None, stream=None, cheb=False):
         import torch
         self.shape = tuple(int(s) for s in shape)
         self.lengths = lengths
         self._stream = stream if stream is not None else torch.cuda.current_stream()
-        d = make_desc(self.shape, lengths)
+        d = make_desc(self.shape, lengths, cheb)
         h = ctypes.c_void_p()
         _check(lib().vd_grid_create(ctypes.byref(h), ctypes.byref(d), ctypes.c_void_p(self._stream.cuda_stream)),
                "vd_grid_create", False)
@@ -269,9 +290,9 @@ class Server:
         self._keep = {}   # ticket -> tensors the server reads or writes
 
     def submit(self, shape, rho=None, f=None, x=None, lengths=None, kind="pressure", dt_nu=0.0, ncomp=1,
-               user_tag=0, **opts):
+               user_tag=0, cheb=False, **opts):
         r = vd_request()
-        r.desc = make_desc(shape, lengths)
+        r.desc = make_desc(shape, lengths, cheb)
         r.kind = VD_OP_PRESSURE if kind == "pressure" else VD_OP_HELMHOLTZ
         r.dt_nu = float(dt_nu)
         r.ncomp = int(ncomp)

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libvdsolve.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["passes.hip", "vecops.hip", "vdsolve.cpp", "vdserve.cpp"]
+SOURCES = ["passes.hip", "vecops.hip", "gemm.hip", "cheb.cpp", "vdsolve.cpp", "vdserve.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

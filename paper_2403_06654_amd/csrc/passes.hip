@@ -623,6 +623,7 @@ void fwd_transform(const Geom& g, const double* phys, void* spec, void* work, co
   r.in[0] = phys;
   r.out[0] = spec;
   launch_row<double, ROW_R2C>(g.M, r, twtab, st);
+  if (g.cheb) return;  // z is physical (Chebyshev nodes): x transform only
   if (g.ny > 1) {
     ColArgs b = col_args(g, nullptr);
     b.outer = g.nz;
@@ -646,7 +647,7 @@ void fwd_transform(const Geom& g, const double* phys, void* spec, void* work, co
 void inv_transform(const Geom& g, const void* spec, double* phys, void* work, const void* twtab,
                    hipStream_t st) {
   const void* cur = spec;
-  if (g.nz > 1) {
+  if (g.nz > 1 && !g.cheb) {
     ColArgs b = col_args(g, nullptr);
     b.outer = 1;
     b.inner = g.ny * g.M;
@@ -672,6 +673,24 @@ void inv_transform(const Geom& g, const void* spec, double* phys, void* work, co
   r.cscale = g.ntot_inv;
   launch_row<double, ROW_C2R>(g.M, r, twtab, st);
 }
+
+template <typename R>
+void row_pass_p2(const Geom& g, void* f0, void* f1, const void* coef, const void* twtab, hipStream_t st, Prof* prof) {
+  RowArgs r = row_args(g, nullptr);
+  r.nf = 2;
+  r.in[0] = f0;
+  r.in[1] = f1;
+  r.out[0] = f0;
+  r.out[1] = f1;
+  r.coef = coef;
+  r.cscale = g.ntot_inv;
+  const bool pr = prof && prof->on;
+  if (pr) prof->begin(2, st, 5.0 * g.nz * g.ny * g.M * sizeof(C2<R>));
+  launch_row<R, ROW_P>(g.M, r, twtab, st);
+  if (pr) prof->end(st);
+}
+template void row_pass_p2<double>(const Geom&, void*, void*, const void*, const void*, hipStream_t, Prof*);
+template void row_pass_p2<float>(const Geom&, void*, void*, const void*, const void*, hipStream_t, Prof*);
 
 template void op_apply<double>(const Geom&, const OpParams&, const void*, void*, const OpWork&, const void*,
                                const void*, hipStream_t, Prof*);

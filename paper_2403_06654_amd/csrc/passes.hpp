@@ -15,7 +15,8 @@ namespace vd {
 struct Geom {
   int nx, ny, nz, M;
   double sx, sy, sz;    // 2 pi / L_d
-  double ntot_inv;      // 1 / (nx ny nz)
+  double ntot_inv;      // 1 / (number of transformed points): 1/(nx ny nz), or 1/nx when cheb
+  int cheb;             // z is a Chebyshev-Gauss-Lobatto axis (2D, ny = 1): x transforms only
 };
 
 enum OpKind { OP_PRESSURE = 0, OP_HELMHOLTZ = 1 };

@@ -30,6 +30,8 @@
 #include <vector>
 
 #include "../../include/vdsolve.h"
+#include "cheb.hpp"
+#include "cheb_ops.hpp"
 #include "passes.hpp"
 #include "vecops.hpp"
 
@@ -103,6 +105,12 @@ struct vd_grid {
   DevState* hst = nullptr;    // pinned host mirror
   std::map<int, void*> bufs;  // spectral vectors by (precision, role)
   Prof prof;
+  // Chebyshev wall-normal direction (g.cheb)
+  ChebDev cd;
+  double* rhoL = nullptr;     // density interpolated to the LGL levels
+  double* c2coef64 = nullptr; // h_x w_LGL / rho_L
+  float* c2coef32 = nullptr;
+  int* dbad = nullptr;
 };
 
 namespace {
@@ -119,21 +127,32 @@ inline void ck(hipError_t e) {
 
 size_t elem_bytes(int prec) { return prec == 32 ? 8 : 16; }
 
+// Spectral work vector of the given precision and role (allocated on first
+// use, kept until the grid is destroyed).  Role B_T1 holds two fields on
+// Chebyshev grids (the stacked interpolated values and z-derivatives).
 void* buf(vd_grid* G, int prec, int role) {
   int key = prec * 1000 + role;
   auto it = G->bufs.find(key);
   if (it != G->bufs.end()) return it->second;
   void* p = nullptr;
-  if (hipMalloc(&p, G->nspec * elem_bytes(prec)) != hipSuccess) throw std::bad_alloc();
+  const size_t mult = (G->g.cheb && role == B_T1) ? 2 : 1;
+  if (hipMalloc(&p, mult * G->nspec * elem_bytes(prec)) != hipSuccess) throw std::bad_alloc();
   G->bufs[key] = p;
   return p;
 }
 
 bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
 
+bool is_cheb(const vd_grid_desc* d) { return d->ndim == 2 && d->basis[1] == VD_CHEB_GL; }
+
 vd_status check_desc(const vd_grid_desc* d) {
   if (!d || d->ndim < 1 || d->ndim > 3) return VD_EINVAL;
   for (int i = 0; i < d->ndim; ++i) {
+    if (d->basis[i] == VD_CHEB_GL) {
+      if (d->ndim != 2 || i != 1) return VD_ENOTSUP;  // only the wall-normal axis of a 2D grid
+      if (d->n[i] < 9 || d->n[i] > 513) return VD_EINVAL;
+      continue;
+    }
     if (d->basis[i] != VD_FOURIER) return VD_ENOTSUP;
     if (!pow2_in(d->n[i], 16, 1024)) return VD_EINVAL;
     if (!(d->length[i] > 0.0) || !std::isfinite(d->length[i])) return VD_EINVAL;
@@ -152,7 +171,7 @@ Geom make_geom(const vd_grid_desc* d) {
     g.sy = g.sz = 0;
   } else if (d->ndim == 2) {  // (ny', nx) stored as nz = ny', ny = 1
     g.nz = d->n[1];
-    g.sz = tp / d->length[1];
+    g.sz = is_cheb(d) ? 0.0 : tp / d->length[1];
     g.ny = 1;
     g.sy = 0;
   } else {
@@ -161,7 +180,8 @@ Geom make_geom(const vd_grid_desc* d) {
     g.nz = d->n[2];
     g.sz = tp / d->length[2];
   }
-  g.ntot_inv = 1.0 / ((double)g.nx * g.ny * g.nz);
+  g.cheb = is_cheb(d) ? 1 : 0;
+  g.ntot_inv = g.cheb ? 1.0 / g.nx : 1.0 / ((double)g.nx * g.ny * g.nz);
   return g;
 }
 
@@ -244,7 +264,11 @@ struct Krylov {
       coef = helm ? (const void*)G->rho32 : (const void*)G->a32;
       tw = G->tw32;
     }
-    if (g.nz > 1) {
+    if (g.cheb) {
+      coef = prec == 64 ? (const void*)G->c2coef64 : (const void*)G->c2coef32;
+      work.t[0] = buf(G, prec, B_T0);
+      work.t[1] = buf(G, prec, B_T1);
+    } else if (g.nz > 1) {
       work.t[0] = buf(G, prec, B_T0);
       if (!helm) work.t[1] = buf(G, prec, B_T1);
       if (!helm && g.ny > 1) work.t[2] = buf(G, prec, B_T2);
@@ -255,7 +279,28 @@ struct Krylov {
     OpParams p = cfg.op;
     p.precond = with_prec ? cfg.op.precond : 0;
     p.in_scale = in_scale;
-    op_apply<R>(g, p, v, y, work, coef, tw, G->st, &G->prof);
+    if (g.cheb) c2_apply<R>(g, G->cd, p, v, y, work.t[0], work.t[1], coef, tw, G->st, &G->prof);
+    else op_apply<R>(g, p, v, y, work, coef, tw, G->st, &G->prof);
+  }
+
+  // The constant-density inverse is diagonal on Fourier grids (applied on
+  // the fly inside the vector kernels) and two dense contractions on
+  // Chebyshev grids (materialised into B_Z first).
+  bool dense_prec() const { return g.cheb && cfg.op.precond; }
+  const void* materialise_prec(const void* r) {
+    void* z = buf(G, prec, B_Z);
+    c2_precond<R>(g, G->cd, cfg.op.rho0, r, z, buf(G, prec, B_T0), G->st);
+    return z;
+  }
+  OpParams ident() const {
+    OpParams q = cfg.op;
+    q.precond = 0;
+    return q;
+  }
+  // x += a M^-1 z
+  void prec_axpy(void* x, const void* z, const double* a_dev) {
+    if (dense_prec()) precond_axpy<R>(g, ident(), x, materialise_prec(z), a_dev, 1.0, G->st);
+    else precond_axpy<R>(g, cfg.op, x, z, a_dev, 1.0, G->st);
   }
 
   // ||b - A x|| into r (and G->dst->nrm2); returns the norm
@@ -332,8 +377,7 @@ struct Krylov {
       VecPtrs P{};
       for (int i = 0; i < k; ++i) P.p[i] = V[i];
       lincomb<R>(g, tmp, P, k, G->dst->coef, G->st);
-      OpParams pp = cfg.op;
-      precond_axpy<R>(g, pp, x, tmp, nullptr, 1.0, G->st);
+      prec_axpy(x, tmp, nullptr);
       ++cycles;
       if (cfg.inner && (G->hst->resid / bnorm <= cfg.rtol || cycles >= kInnerCycles || o.iters >= cfg.max_iter)) {
         o.relres = G->hst->resid / bnorm;  // estimate
@@ -342,6 +386,26 @@ struct Krylov {
       }
       beta = true_resid(b, x, V[0]);
     }
+  }
+
+  // rz = (r, M^-1 r); then p = M^-1 r (restart) or p = M^-1 r + beta p
+  void rz_and_p(const void* r, void* p, bool restart) {
+    if (dense_prec()) {
+      const void* z = materialise_prec(r);
+      VecPtrs P{};
+      P.p[0] = r;
+      mdot<R>(g, z, P, 1, false, G->partial, G->dst->red, G->st);
+      cg_beta(G->dst, G->st);
+      if (restart) ck(hipMemcpyAsync(p, z, G->nspec * elem_bytes(prec), hipMemcpyDeviceToDevice, G->st));
+      else cg_p<R>(g, ident(), p, z, G->dst, G->st);
+      return;
+    }
+    OpParams op = cfg.op;
+    dot_rMr<R>(g, op, r, G->partial, G->dst->red, G->st);
+    cg_beta(G->dst, G->st);  // rz = red[0]
+    if (!restart) cg_p<R>(g, op, p, r, G->dst, G->st);
+    else if (op.precond) precond_apply<R>(g, op, r, p, G->st);
+    else ck(hipMemcpyAsync(p, r, G->nspec * elem_bytes(prec), hipMemcpyDeviceToDevice, G->st));
   }
 
   SolveOut cg(const void* b, void* x, double bnorm) {
@@ -356,11 +420,7 @@ struct Krylov {
       if (o.relres <= cfg.rtol) { o.status = VD_OK; return o; }
       if (o.iters >= cfg.max_iter) { o.status = VD_NOT_CONVERGED; return o; }
       // p = M^-1 r, rz = (r, M^-1 r)
-      OpParams op = cfg.op;
-      dot_rMr<R>(g, op, r, G->partial, G->dst->red, G->st);
-      cg_beta(G->dst, G->st);  // sets rz = red[0] (beta unused here)
-      if (op.precond) precond_apply<R>(g, op, r, p, G->st);
-      else ck(hipMemcpyAsync(p, r, G->nspec * elem_bytes(prec), hipMemcpyDeviceToDevice, G->st));
+      rz_and_p(r, p, true);
       while (o.iters < cfg.max_iter) {
         apply(p, q, false);
         o.iters++;
@@ -373,9 +433,7 @@ struct Krylov {
         if (G->hst->bad) { o.status = VD_EBREAKDOWN; return o; }
         if (std::sqrt(std::fmax(G->hst->nrm2, 0.0)) / bnorm <= cfg.rtol) break;
         if (cfg.inner && o.iters >= cfg.max_iter) break;
-        dot_rMr<R>(g, op, r, G->partial, G->dst->red, G->st);
-        cg_beta(G->dst, G->st);
-        cg_p<R>(g, op, p, r, G->dst, G->st);
+        rz_and_p(r, p, false);
       }
       if (cfg.inner) {
         o.relres = std::sqrt(std::fmax(G->hst->nrm2, 0.0)) / bnorm;
@@ -403,7 +461,7 @@ struct Krylov {
         P.p[0] = r;
         mdot<R>(g, w, P, 1, true, G->partial, G->dst->red, G->st);
         rmr_alpha(G->dst, G->st);
-        precond_axpy<R>(g, cfg.op, x, r, &G->dst->alpha, 1.0, G->st);
+        prec_axpy(x, r, &G->dst->alpha);
         axpy_norm<R>(g, r, w, &G->dst->alpha, -1.0, G->partial, &G->dst->nrm2, G->st);
         sync_state(G);
         if (G->hst->bad) { o.status = VD_EBREAKDOWN; return o; }
@@ -491,6 +549,63 @@ bool opts_ok(const vd_solve_opts& o) {
   return true;
 }
 
+// Build the dense z matrices of a Chebyshev grid on the host and upload
+// them (FP64 and FP32).
+bool upload_cheb(vd_grid* G, const vd_grid_desc* d) {
+  ChebSetup cs;
+  if (!cheb_setup(d->n[1], &cs)) return false;
+  const int n = cs.nz;
+  const double hx = d->length[0] / d->n[0];
+  auto at = [n](const std::vector<double>& m, int i, int j) { return m[(size_t)i * n + j]; };
+  std::vector<std::vector<double>> M(CH_NMAT);
+  M[CH_VT].resize((size_t)n * n);
+  M[CH_V] = cs.V;
+  M[CH_I] = cs.I;
+  M[CH_PRE].resize((size_t)2 * n * n);
+  M[CH_PRE_V].assign((size_t)2 * n * n, 0.0);
+  M[CH_POST].resize((size_t)2 * n * n);
+  M[CH_RHS].assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      M[CH_VT][(size_t)i * n + j] = at(cs.V, j, i);
+      M[CH_PRE][(size_t)i * n + j] = at(cs.I, i, j);
+      M[CH_PRE][(size_t)(n + i) * n + j] = at(cs.G, i, j);
+      M[CH_POST][(size_t)i * 2 * n + j] = -at(cs.I, j, i);
+      M[CH_POST][(size_t)i * 2 * n + n + j] = at(cs.G, j, i);
+    }
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < n; ++k) {
+      const double vi = at(cs.I, i, k), vg = at(cs.G, i, k);
+      for (int j = 0; j < n; ++j) {
+        M[CH_PRE_V][(size_t)i * n + j] += vi * at(cs.V, k, j);
+        M[CH_PRE_V][(size_t)(n + i) * n + j] += vg * at(cs.V, k, j);
+      }
+    }
+  for (int l = 0; l < n; ++l) {  // -I^T diag(h_x w) I
+    const double wv = hx * cs.wl[l];
+    for (int i = 0; i < n; ++i) {
+      const double a = -wv * at(cs.I, l, i);
+      if (a == 0.0) continue;
+      for (int j = 0; j < n; ++j) M[CH_RHS][(size_t)i * n + j] += a * at(cs.I, l, j);
+    }
+  }
+  for (int m = 0; m < CH_NMAT; ++m) {
+    const size_t cnt = M[m].size();
+    std::vector<float> f(cnt);
+    for (size_t i = 0; i < cnt; ++i) f[i] = (float)M[m][i];
+    ck(hipMalloc(&G->cd.m64[m], cnt * sizeof(double)));
+    ck(hipMalloc(&G->cd.m32[m], cnt * sizeof(float)));
+    ck(hipMemcpy(G->cd.m64[m], M[m].data(), cnt * sizeof(double), hipMemcpyHostToDevice));
+    ck(hipMemcpy(G->cd.m32[m], f.data(), cnt * sizeof(float), hipMemcpyHostToDevice));
+  }
+  ck(hipMalloc(&G->cd.lam, n * sizeof(double)));
+  ck(hipMemcpy(G->cd.lam, cs.lam.data(), n * sizeof(double), hipMemcpyHostToDevice));
+  ck(hipMalloc(&G->cd.wl, n * sizeof(double)));
+  ck(hipMemcpy(G->cd.wl, cs.wl.data(), n * sizeof(double), hipMemcpyHostToDevice));
+  G->cd.hx = hx;
+  return true;
+}
+
 }  // namespace
 
 // ================================================================ C ABI
@@ -543,6 +658,12 @@ vd_status vd_grid_create(vd_grid** out, const vd_grid_desc* d, hipStream_t strea
   G->nreal = (size_t)G->g.nx * G->g.ny * G->g.nz;
   G->nspec = (size_t)G->g.M * G->g.ny * G->g.nz;
   try {
+    if (G->g.cheb) {
+      if (!upload_cheb(G, d)) {
+        vd_grid_destroy(G);
+        return VD_EDEVICE;
+      }
+    }
     fill_twiddles(G);
     ck(hipMalloc(&G->partial, nred_partial() * sizeof(double)));
     ck(hipMalloc(&G->dsmall, 64 * sizeof(double)));
@@ -572,6 +693,16 @@ vd_status vd_grid_destroy(vd_grid* G) {
   hipFree(G->rho32);
   hipFree(G->partial);
   hipFree(G->dsmall);
+  for (int m = 0; m < CH_NMAT; ++m) {
+    hipFree(G->cd.m64[m]);
+    hipFree(G->cd.m32[m]);
+  }
+  hipFree(G->cd.lam);
+  hipFree(G->cd.wl);
+  hipFree(G->rhoL);
+  hipFree(G->c2coef64);
+  hipFree(G->c2coef32);
+  hipFree(G->dbad);
   hipFree(G->dst);
   if (G->hst) hipHostFree(G->hst);
   delete G;
@@ -598,6 +729,23 @@ static vd_status set_density_impl(vd_grid* G, void* ctx) {
   G->rho_mean = h[0] / (double)G->nreal;
   G->rho_min = h[1];
   G->rho_max = h[2];
+  if (G->g.cheb) {
+    if (!G->rhoL) {
+      ck(hipMalloc(&G->rhoL, G->nreal * sizeof(double)));
+      ck(hipMalloc(&G->c2coef64, G->nreal * sizeof(double)));
+      ck(hipMalloc(&G->c2coef32, G->nreal * sizeof(float)));
+      ck(hipMalloc(&G->dbad, sizeof(int)));
+    }
+    ck(hipMemsetAsync(G->dbad, 0, sizeof(int), G->st));
+    c2_density(G->g, G->cd, G->rho, G->rhoL, G->c2coef64, G->c2coef32, G->dbad, G->st);
+    int bad = 0;
+    ck(hipMemcpyAsync(&bad, G->dbad, sizeof(int), hipMemcpyDeviceToHost, G->st));
+    ck(hipStreamSynchronize(G->st));
+    if (bad) {  // the interpolated density must stay positive too
+      G->has_rho = false;
+      return VD_EDOMAIN;
+    }
+  }
   G->has_rho = true;
   return VD_OK;
 }
@@ -625,8 +773,10 @@ static vd_status apply_impl(vd_grid* G, void* c) {
   p.nu = a->nu;
   p.precond = a->is_prec;
   SolveCfg cfg{VD_GMRES, 1, 1, 1.0, p};
+  if (G->g.cheb && a->kind != VD_OP_PRESSURE) return VD_ENOTSUP;
   if (a->precision == VD_FP64) {
-    if (a->is_prec) precond_apply<double>(G->g, p, s0, s1, G->st);
+    if (a->is_prec && G->g.cheb) c2_precond<double>(G->g, G->cd, p.rho0, s0, s1, buf(G, 64, B_T0), G->st);
+    else if (a->is_prec) precond_apply<double>(G->g, p, s0, s1, G->st);
     else {
       Krylov<double> K(G, 64, cfg);
       K.apply(s0, s1, false);
@@ -635,7 +785,8 @@ static vd_status apply_impl(vd_grid* G, void* c) {
     void* f0 = buf(G, 32, B_B);
     void* f1 = buf(G, 32, B_X);
     cast_d2f(G->g, s0, f0, 1.0, G->st);
-    if (a->is_prec) precond_apply<float>(G->g, p, f0, f1, G->st);
+    if (a->is_prec && G->g.cheb) c2_precond<float>(G->g, G->cd, p.rho0, f0, f1, buf(G, 32, B_T0), G->st);
+    else if (a->is_prec) precond_apply<float>(G->g, p, f0, f1, G->st);
     else {
       Krylov<float> K(G, 32, cfg);
       K.apply(f0, f1, false);
@@ -695,21 +846,33 @@ static vd_status solve_impl(vd_grid* G, void* c) {
   for (int comp = 0; comp < s->ncomp; ++comp) {
     const double* f = s->f + (size_t)comp * G->nreal;
     double* x = s->x + (size_t)comp * G->nreal;
-    fwd_transform(G->g, f, b64, nullptr, G->tw64, G->st);
-    if (s->kind == VD_OP_PRESSURE) {
+    if (G->g.cheb) {  // weak form: b = -I^T W I f, nullspace constant in z
+      void* tmp = buf(G, 64, B_TMP);
+      fwd_transform(G->g, f, tmp, nullptr, G->tw64, G->st);
+      c2_rhs(G->g, G->cd, tmp, b64, G->st);
+      c2_project(G->g, b64, G->dsmall, G->st);
+      s->info.rhs_null_norm = std::fmax(s->info.rhs_null_norm, read_scalar(G, G->dsmall));
+    } else {
+      fwd_transform(G->g, f, b64, nullptr, G->tw64, G->st);
+    }
+    if (s->kind == VD_OP_PRESSURE && !G->g.cheb) {
       project_range(G->g, b64, G->dsmall, G->st);
       scale<double>(G->g, b64, nullptr, -1.0, G->st);  // A = -L_rho, b = -f
       s->info.rhs_null_norm = std::fmax(s->info.rhs_null_norm, read_scalar(G, G->dsmall));
     }
     if (s->o.use_x0) {
       fwd_transform(G->g, x, x64, nullptr, G->tw64, G->st);
-      if (s->kind == VD_OP_PRESSURE) project_range(G->g, x64, G->dsmall + 1, G->st);
+      if (G->g.cheb) c2_project(G->g, x64, G->dsmall + 1, G->st);
+      else if (s->kind == VD_OP_PRESSURE) project_range(G->g, x64, G->dsmall + 1, G->st);
     } else {
       ck(hipMemsetAsync(x64, 0, G->nspec * 16, G->st));
     }
     double bnorm = host_norm_of(G, b64);
     int refin = 0;
     SolveOut so = solve_spectral(G, s->o, op, b64, x64, bnorm, &refin);
+    // the Chebyshev preconditioner's pseudo-inverse is not Euclidean-orthogonal
+    // to the nullspace: return the representative orthogonal to it
+    if (G->g.cheb) c2_project(G->g, x64, G->dsmall + 1, G->st);
     inv_transform(G->g, x64, x, buf(G, 64, B_TMP), G->tw64, G->st);
     ck(hipStreamSynchronize(G->st));
     ck(hipGetLastError());
@@ -753,6 +916,7 @@ vd_status vd_solve_pressure(vd_grid* G, const double* f, double* p, const vd_sol
 vd_status vd_solve_helmholtz(vd_grid* G, double dt_nu, int ncomp, const double* g, double* u,
                              const vd_solve_opts* opts, vd_solve_info* info) {
   if (!(dt_nu >= 0.0) || !std::isfinite(dt_nu)) return VD_EINVAL;
+  if (G && G->g.cheb) return VD_ENOTSUP;
   return solve_common(G, VD_OP_HELMHOLTZ, dt_nu, ncomp, g, u, opts, info);
 }
 
@@ -779,6 +943,12 @@ size_t vd_workspace_bytes(const vd_grid_desc* d, const vd_solve_opts* opts) {
     bytes += nspec * 8 * (vecs + opwork + 2);       // FP32 basis, work, inner b and x
   }
   bytes += 2 * kTwEntries * (16 + 8) + nred_partial() * 8 + sizeof(DevState) + 512;
+  if (g.cheb) {
+    const size_t nz = (size_t)g.nz;
+    bytes += 12 * nz * nz * 12;                  // dense z matrices (FP64 + FP32)
+    bytes += nreal * (8 + 8 + 4);                // rho_L and the x-pass coefficient
+    bytes += nspec * 16 * 2;                     // preconditioner and second work field
+  }
   return bytes;
 }
 
