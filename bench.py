@@ -306,6 +306,51 @@ def bench_c5(args):
     print(json.dumps(res))
 
 
+def bench_c2(args):
+    """512 (Fourier x) x 257 (Chebyshev z, Neumann walls) pressure solves of
+    the Rayleigh-Taylor-like configuration: PCG and GMRES(30) to 1e-10 in FP64
+    and FP32+refine; per-kernel times come from rocprofv3 (the dense
+    contractions are not event-timed)."""
+    import torch
+    from paper_2403_06654_amd import workloads
+    from paper_2403_06654_amd.api import Grid
+    inp = workloads.c2_inputs(nx=512, m=256, r=3.0, seed=0)
+    rho = torch.from_numpy(inp["rho"]).cuda()
+    f = torch.from_numpy(inp["f"]).cuda()
+    grid = Grid((257, 512), lengths=(2.0, 2.0), cheb=True)
+    grid.set_density(rho)
+    out = {}
+    for solver in ("cg", "gmres"):
+        for prec in ("fp64", "fp32_refine"):
+            p = torch.zeros_like(f)
+            for _ in range(args.warmup):
+                grid.solve_pressure(f, p=p, solver=solver, precision=prec)
+            torch.cuda.synchronize()
+            lat, iters = [], 0
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                t1 = time.perf_counter()
+                _, info = grid.solve_pressure(f, p=p, solver=solver, precision=prec)
+                lat.append(1e3 * (time.perf_counter() - t1))
+                if info["status"] != 0:
+                    raise RuntimeError(f"C2 solve failed: {info}")
+                iters += info["iterations"]
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            out[f"{solver}_{prec}"] = {"iters_per_s": round(iters / el, 1), "solves_per_s": round(args.steps / el, 2),
+                                       "iters_per_solve": iters / args.steps, "p50_ms": round(pct(lat, 50), 3),
+                                       "p99_ms": round(pct(lat, 99), 3), "rel_residual": info["rel_residual"]}
+    grid.close()
+    res = {"metric": "Krylov iters/s and solves/s, 512 x 257 Fourier-Chebyshev pressure (PCG and GMRES(30))",
+           "value": out["gmres_fp64"]["iters_per_s"], "unit": "Krylov iters/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "x periodic 512 Fourier points on [0,2), z 257 Chebyshev-Gauss-Lobatto points "
+                                  "with Neumann walls, rho = 1 + (1 + tanh((z - eta(x))/0.02)), 16-mode eta of "
+                                  "amplitude 0.05, rtol 1e-10"},
+           "results": out}
+    print(json.dumps(res))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -313,7 +358,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--workload", choices=["c3", "serving", "c5"], default="c3")
+    ap.add_argument("--workload", choices=["c3", "serving", "c5", "c2"], default="c3")
     ap.add_argument("--requests", type=int, default=4096)
     ap.add_argument("--slots", type=int, default=8)
     args = ap.parse_args()
@@ -326,6 +371,9 @@ def main():
         return
     if args.workload == "c5":
         bench_c5(args)
+        return
+    if args.workload == "c2":
+        bench_c2(args)
         return
 
     import numpy as np
