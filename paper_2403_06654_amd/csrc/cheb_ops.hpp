@@ -6,7 +6,8 @@
 
 namespace vd {
 
-// Dense z matrices kept on the device (FP64 and FP32 copies), row-major.
+// Dense z matrices kept on the device (FP64 and FP32 copies), stored
+// transposed ([K][M] for a matrix applied as C[M][N] = A[M][K] B[K][N]).
 enum ChebMat {
   CH_VT = 0,    // V^T                          [nz][nz]
   CH_PRE_V,     // [I V ; G V]                  [2 nz][nz]

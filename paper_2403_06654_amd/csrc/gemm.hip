@@ -54,11 +54,17 @@ struct EpiArgs {
   double sx;               // 2 pi / L_x
 };
 
-template <typename R>
-__global__ __launch_bounds__(64) void k_gemm(const R* __restrict__ A, int lda, const R* __restrict__ B, int ldb,
-                                             R* __restrict__ C, int ldc, int M, int N, int K, EpiArgs e) {
+// One 256-thread block per 32 x 32 tile of C; the 4 waves split K (wave w
+// takes the k-steps w, w+4, w+8, ...) so each wave's dependent chain of
+// loads and MFMAs is a quarter of K, and the partial tiles are summed through
+// LDS before the epilogue.  AT: A is stored transposed ([K][M]), so a load of
+// 16 consecutive rows is one contiguous run.
+template <typename R, bool AT>
+__global__ __launch_bounds__(256) void k_gemm(const R* __restrict__ A, int lda, const R* __restrict__ B, int ldb,
+                                              R* __restrict__ C, int ldc, int M, int N, int K, EpiArgs e) {
   using MF = Mfma<R>;
-  const int lane = threadIdx.x;
+  __shared__ double part[4][32 * 33];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
   const int li = lane & 15, lk = lane >> 4;
   typename MF::V acc[2][2];
@@ -68,12 +74,15 @@ __global__ __launch_bounds__(64) void k_gemm(const R* __restrict__ A, int lda, c
     for (int b = 0; b < 2; ++b) acc[a][b] = typename MF::V{0, 0, 0, 0};
   const int ra0 = r0 + li, ra1 = r0 + 16 + li;
   const int cb0 = c0 + li, cb1 = c0 + 16 + li;
+  auto ld_a = [&](int row, int k) -> R {
+    if (row >= M || k >= K) return R(0);
+    return AT ? A[(size_t)k * lda + row] : A[(size_t)row * lda + k];
+  };
 #pragma unroll 4
-  for (int k0 = 0; k0 < K; k0 += 4) {
+  for (int k0 = 4 * w; k0 < K; k0 += 16) {
     const int k = k0 + lk;
+    const R a0 = ld_a(ra0, k), a1 = ld_a(ra1, k);
     const bool kin = k < K;
-    const R a0 = (kin && ra0 < M) ? A[(size_t)ra0 * lda + k] : R(0);
-    const R a1 = (kin && ra1 < M) ? A[(size_t)ra1 * lda + k] : R(0);
     const R b0 = (kin && cb0 < N) ? B[(size_t)k * ldb + cb0] : R(0);
     const R b1 = (kin && cb1 < N) ? B[(size_t)k * ldb + cb1] : R(0);
     acc[0][0] = MF::mac(a0, b0, acc[0][0]);
@@ -81,32 +90,35 @@ __global__ __launch_bounds__(64) void k_gemm(const R* __restrict__ A, int lda, c
     acc[1][0] = MF::mac(a1, b0, acc[1][0]);
     acc[1][1] = MF::mac(a1, b1, acc[1][1]);
   }
-  const double al = (e.alpha_dev ? *e.alpha_dev : 1.0) * e.alpha;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = r0 + 16 * a + MF::row(lk, r);
-        const int col = c0 + 16 * b + li;
-        if (row >= M || col >= N) continue;
-        double v = (double)acc[a][b][r] * al;
-        if (e.kind == 1) {
-          const int kx = col >> 1;
-          const double kp = kx * e.sx;  // slot 0: k' = 0 for both halves
-          if (kx == 0 && row == 0) v = 0.0;
-          else v *= e.scale / (kp * kp + e.lam[row]);
-        }
-        C[(size_t)row * ldc + col] = R(v);
-      }
+      for (int r = 0; r < 4; ++r) part[w][(16 * a + MF::row(lk, r)) * 33 + 16 * b + li] = (double)acc[a][b][r];
+  __syncthreads();
+  const double al = (e.alpha_dev ? *e.alpha_dev : 1.0) * e.alpha;
+  for (int idx = threadIdx.x; idx < 1024; idx += 256) {
+    const int tr = idx >> 5, tc = idx & 31;
+    const int row = r0 + tr, col = c0 + tc;
+    if (row >= M || col >= N) continue;
+    const int o = tr * 33 + tc;
+    double v = ((part[0][o] + part[1][o]) + part[2][o] + part[3][o]) * al;
+    if (e.kind == 1) {
+      const int kx = col >> 1;
+      const double kp = kx * e.sx;  // slot 0: k' = 0 for both halves
+      if (kx == 0 && row == 0) v = 0.0;
+      else v *= e.scale / (kp * kp + e.lam[row]);
+    }
+    C[(size_t)row * ldc + col] = R(v);
+  }
 }
 
-template <typename R>
+template <typename R, bool AT = true>
 static void gemm(const R* A, int lda, const R* B, int ldb, R* C, int ldc, int M, int N, int K, const EpiArgs& e,
                  hipStream_t s) {
   dim3 grid((N + 31) / 32, (M + 31) / 32);
-  hipLaunchKernelGGL((k_gemm<R>), grid, dim3(64), 0, s, A, lda, B, ldb, C, ldc, M, N, K, e);
+  hipLaunchKernelGGL((k_gemm<R, AT>), grid, dim3(256), 0, s, A, lda, B, ldb, C, ldc, M, N, K, e);
 }
 
 static EpiArgs plain(double alpha = 1.0, const double* alpha_dev = nullptr) {
@@ -119,7 +131,7 @@ static EpiArgs plain(double alpha = 1.0, const double* alpha_dev = nullptr) {
 
 template <typename R>
 void gemm_plain(const void* A, const void* B, void* C, int M, int N, int K, hipStream_t s) {
-  gemm<R>((const R*)A, K, (const R*)B, N, (R*)C, N, M, N, K, plain(), s);
+  gemm<R, false>((const R*)A, K, (const R*)B, N, (R*)C, N, M, N, K, plain(), s);
 }
 
 // ------------------------------------------------------------ C2 operator
@@ -150,14 +162,14 @@ void c2_apply(const Geom& g, const ChebDev& cd, const OpParams& p, const void* v
     e.lam = cd.lam;
     e.scale = p.rho0 / cd.hx;
     e.sx = g.sx;
-    gemm<R>(mat<R>(cd, CH_VT), nz, (const R*)v, n, (R*)wY, n, nz, n, nz, e, st);      // diag * V^T v
-    gemm<R>(mat<R>(cd, CH_PRE_V), nz, (const R*)wY, n, T, n, 2 * nz, n, nz, plain(), st);  // [I V; G V]
+    gemm<R>(mat<R>(cd, CH_VT), nz, (const R*)v, n, (R*)wY, n, nz, n, nz, e, st);              // diag * V^T v
+    gemm<R>(mat<R>(cd, CH_PRE_V), 2 * nz, (const R*)wY, n, T, n, 2 * nz, n, nz, plain(), st);  // [I V; G V]
   } else {
-    gemm<R>(mat<R>(cd, CH_PRE), nz, (const R*)v, n, T, n, 2 * nz, n, nz, plain(1.0, p.in_scale), st);  // [I; G]
+    gemm<R>(mat<R>(cd, CH_PRE), 2 * nz, (const R*)v, n, T, n, 2 * nz, n, nz, plain(1.0, p.in_scale), st);  // [I; G]
   }
   // x pass over the 2 nz rows: field 0 (I u) gets i k'_x in and out, field 1 (G u) plain
   row_pass_p2<R>(g, T, T + fs, coef, twtab, st, prof);
-  gemm<R>(mat<R>(cd, CH_POST), 2 * nz, T, n, (R*)y, n, nz, n, 2 * nz, plain(), st);  // [-I^T | G^T]
+  gemm<R>(mat<R>(cd, CH_POST), nz, T, n, (R*)y, n, nz, n, 2 * nz, plain(), st);  // [-I^T | G^T]
 }
 
 template <typename R>

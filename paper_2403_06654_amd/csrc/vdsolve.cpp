@@ -589,8 +589,15 @@ bool upload_cheb(vd_grid* G, const vd_grid_desc* d) {
       for (int j = 0; j < n; ++j) M[CH_RHS][(size_t)i * n + j] += a * at(cs.I, l, j);
     }
   }
-  for (int m = 0; m < CH_NMAT; ++m) {
+  // rows of each matrix as applied (C = A B): CH_PRE and CH_PRE_V have 2n
+  const int rows[CH_NMAT] = {n, 2 * n, 2 * n, n, n, n, n};
+  for (int m = 0; m < CH_NMAT; ++m) {  // upload transposed: [K][M]
     const size_t cnt = M[m].size();
+    const int R = rows[m], Kc = (int)(cnt / R);
+    std::vector<double> t(cnt);
+    for (int i = 0; i < R; ++i)
+      for (int k = 0; k < Kc; ++k) t[(size_t)k * R + i] = M[m][(size_t)i * Kc + k];
+    M[m].swap(t);
     std::vector<float> f(cnt);
     for (size_t i = 0; i < cnt; ++i) f[i] = (float)M[m][i];
     ck(hipMalloc(&G->cd.m64[m], cnt * sizeof(double)));

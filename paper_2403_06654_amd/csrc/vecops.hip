@@ -16,6 +16,15 @@ constexpr int kRedStride = kMaxVec + 2;
 
 size_t nred_partial() { return (size_t)kRedBlocks * kRedStride; }
 
+// Blocks of the streaming and reduction kernels: 4 per CU for large fields,
+// fewer for small ones (at least 1024 elements per block) so that small
+// problems do not pay for empty blocks and long partial reductions.  A pure
+// function of the field size: results stay bitwise reproducible.
+static int nblk(size_t n) {
+  size_t b = (n + 1023) / 1024;
+  return (int)(b < 1 ? 1 : (b > (size_t)kRedBlocks ? kRedBlocks : b));
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -56,8 +65,8 @@ __global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ part
   }
 }
 
-static void reduce(const double* partial, int K, double scale, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, partial, kRedBlocks, K, scale, out);
+static void reduce(const double* partial, int nb, int K, double scale, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, partial, nb, K, scale, out);
 }
 
 static size_t nspec(const Geom& g) { return (size_t)g.nz * g.ny * g.M; }
@@ -97,7 +106,7 @@ template <typename R>
 void mdot(const Geom& g, const void* x, const VecPtrs& V, int nv, bool want_norm, double* partial, double* out,
           hipStream_t s, Prof* prof) {
   size_t n = nspec(g);
-  dim3 gr(kRedBlocks), bl(256);
+  dim3 gr(nblk(n)), bl(256);
   const int wn = want_norm ? 1 : 0;
   if (nv <= 1)
     hipLaunchKernelGGL((k_mdot<R, 1>), gr, bl, 0, s, (const C2<R>*)x, V, nv, wn, n, g.M, partial);
@@ -114,7 +123,7 @@ void mdot(const Geom& g, const void* x, const VecPtrs& V, int nv, bool want_norm
   else
     hipLaunchKernelGGL((k_mdot<R, kMaxVec>), gr, bl, 0, s, (const C2<R>*)x, V, nv, wn, n, g.M, partial);
   if (prof) prof->end(s);
-  reduce(partial, nv + wn, g.ntot_inv, out, s);
+  reduce(partial, nblk(nspec(g)), nv + wn, g.ntot_inv, out, s);
 }
 
 // --------------------------------------------------------- multi-update
@@ -169,7 +178,7 @@ template <typename R>
 void mupdate(const Geom& g, void* x, const VecPtrs& V, int nv, const double* coef, bool want_dots, double* partial,
              double* out, hipStream_t s) {
   size_t n = nspec(g);
-  dim3 gr(kRedBlocks), bl(256);
+  dim3 gr(nblk(n)), bl(256);
   const int wd = want_dots ? 1 : 0;
   if (nv <= 1)
     hipLaunchKernelGGL((k_mupdate<R, 1>), gr, bl, 0, s, (C2<R>*)x, V, nv, coef, wd, n, g.M, partial);
@@ -183,7 +192,7 @@ void mupdate(const Geom& g, void* x, const VecPtrs& V, int nv, const double* coe
     hipLaunchKernelGGL((k_mupdate<R, 16>), gr, bl, 0, s, (C2<R>*)x, V, nv, coef, wd, n, g.M, partial);
   else
     hipLaunchKernelGGL((k_mupdate<R, kMaxVec>), gr, bl, 0, s, (C2<R>*)x, V, nv, coef, wd, n, g.M, partial);
-  reduce(partial, (want_dots ? nv : 0) + 1, g.ntot_inv, out, s);
+  reduce(partial, nblk(nspec(g)), (want_dots ? nv : 0) + 1, g.ntot_inv, out, s);
 }
 
 // ------------------------------------------------ Gram-Schmidt (GMRES)
@@ -308,9 +317,9 @@ template <typename R, int NV>
 static void launch_gs(const Geom& g, void* x, const VecPtrs& V, int nv, const DevState* st, int second,
                       double* partial, hipStream_t s) {
   if (second)
-    hipLaunchKernelGGL((k_gs_reorth<R, NV>), dim3(kRedBlocks), dim3(256), 0, s, (C2<R>*)x, V, nv, st, nspec(g));
+    hipLaunchKernelGGL((k_gs_reorth<R, NV>), dim3(nblk(nspec(g))), dim3(256), 0, s, (C2<R>*)x, V, nv, st, nspec(g));
   else
-    hipLaunchKernelGGL((k_gs_update<R, NV>), dim3(kRedBlocks), dim3(256), 0, s, (C2<R>*)x, V, nv, st, nspec(g),
+    hipLaunchKernelGGL((k_gs_update<R, NV>), dim3(nblk(nspec(g))), dim3(256), 0, s, (C2<R>*)x, V, nv, st, nspec(g),
                        g.M, partial);
 }
 
@@ -331,7 +340,7 @@ void gs_orthogonalize(const Geom& g, void* w, const VecPtrs& V, int nv, DevState
     else launch_gs<R, kMaxVec>(g, w, V, nv, st, second, partial, s);
     if (pr && !second) prof->end(s);
     if (!second) {
-      reduce(partial, nv + 1, g.ntot_inv, st->red, s);
+      reduce(partial, nblk(nspec(g)), nv + 1, g.ntot_inv, st->red, s);
       hipLaunchKernelGGL(k_gs_check, dim3(1), dim3(64), 0, s, st, nv, orth_tol<R>());
     }
   }
@@ -362,7 +371,7 @@ __global__ __launch_bounds__(256) void k_lincomb(C2<R>* __restrict__ z, VecPtrs 
 template <typename R>
 void lincomb(const Geom& g, void* z, const VecPtrs& V, int nv, const double* coef, hipStream_t s) {
   size_t n = nspec(g);
-  dim3 gr(kRedBlocks * 2), bl(256);
+  dim3 gr(nblk(n)), bl(256);
   if (nv <= 4)
     hipLaunchKernelGGL((k_lincomb<R, 4>), gr, bl, 0, s, (C2<R>*)z, V, nv, coef, n);
   else if (nv <= 16)
@@ -382,7 +391,7 @@ __global__ __launch_bounds__(256) void k_scale(C2<R>* __restrict__ v, const doub
 }
 template <typename R>
 void scale(const Geom& g, void* v, const double* s_dev, double s_host, hipStream_t s) {
-  hipLaunchKernelGGL((k_scale<R>), dim3(kRedBlocks * 2), dim3(256), 0, s, (C2<R>*)v, s_dev, s_host, nspec(g));
+  hipLaunchKernelGGL((k_scale<R>), dim3(nblk(nspec(g))), dim3(256), 0, s, (C2<R>*)v, s_dev, s_host, nspec(g));
 }
 
 template <typename R>
@@ -400,9 +409,9 @@ __global__ __launch_bounds__(256) void k_sub_norm(const C2<R>* __restrict__ b, c
 }
 template <typename R>
 void sub_norm(const Geom& g, const void* b, const void* q, void* r, double* partial, double* out, hipStream_t s) {
-  hipLaunchKernelGGL((k_sub_norm<R>), dim3(kRedBlocks), dim3(256), 0, s, (const C2<R>*)b, (const C2<R>*)q,
+  hipLaunchKernelGGL((k_sub_norm<R>), dim3(nblk(nspec(g))), dim3(256), 0, s, (const C2<R>*)b, (const C2<R>*)q,
                      (C2<R>*)r, nspec(g), g.M, partial);
-  reduce(partial, 1, g.ntot_inv, out, s);
+  reduce(partial, nblk(nspec(g)), 1, g.ntot_inv, out, s);
 }
 
 template <typename R>
@@ -419,7 +428,7 @@ __global__ __launch_bounds__(256) void k_precond_axpy(C2<R>* __restrict__ x, con
 template <typename R>
 void precond_axpy(const Geom& g, const OpParams& p, void* x, const void* z, const double* a_dev, double a_host,
                   hipStream_t s) {
-  hipLaunchKernelGGL((k_precond_axpy<R>), dim3(kRedBlocks * 2), dim3(256), 0, s, (C2<R>*)x, (const C2<R>*)z, g,
+  hipLaunchKernelGGL((k_precond_axpy<R>), dim3(nblk(nspec(g))), dim3(256), 0, s, (C2<R>*)x, (const C2<R>*)z, g,
                      p.precond ? p.kind : -1, p.rho0, p.nu, a_dev, a_host, nspec(g));
 }
 
@@ -435,9 +444,9 @@ __global__ __launch_bounds__(256) void k_dot_rMr(const C2<R>* __restrict__ r, Ge
 }
 template <typename R>
 void dot_rMr(const Geom& g, const OpParams& p, const void* r, double* partial, double* out, hipStream_t s) {
-  hipLaunchKernelGGL((k_dot_rMr<R>), dim3(kRedBlocks), dim3(256), 0, s, (const C2<R>*)r, g,
+  hipLaunchKernelGGL((k_dot_rMr<R>), dim3(nblk(nspec(g))), dim3(256), 0, s, (const C2<R>*)r, g,
                      p.precond ? p.kind : -1, p.rho0, p.nu, nspec(g), partial);
-  reduce(partial, 1, g.ntot_inv, out, s);
+  reduce(partial, nblk(nspec(g)), 1, g.ntot_inv, out, s);
 }
 
 template <typename R>
@@ -459,9 +468,9 @@ __global__ __launch_bounds__(256) void k_cg_xr(C2<R>* __restrict__ x, C2<R>* __r
 template <typename R>
 void cg_xr(const Geom& g, void* x, void* r, const void* p, const void* q, const DevState* st, double* partial,
            double* out, hipStream_t s) {
-  hipLaunchKernelGGL((k_cg_xr<R>), dim3(kRedBlocks), dim3(256), 0, s, (C2<R>*)x, (C2<R>*)r, (const C2<R>*)p,
+  hipLaunchKernelGGL((k_cg_xr<R>), dim3(nblk(nspec(g))), dim3(256), 0, s, (C2<R>*)x, (C2<R>*)r, (const C2<R>*)p,
                      (const C2<R>*)q, st, nspec(g), g.M, partial);
-  reduce(partial, 1, g.ntot_inv, out, s);
+  reduce(partial, nblk(nspec(g)), 1, g.ntot_inv, out, s);
 }
 
 template <typename R>
@@ -476,7 +485,7 @@ __global__ __launch_bounds__(256) void k_cg_p(C2<R>* __restrict__ p, const C2<R>
 }
 template <typename R>
 void cg_p(const Geom& g, const OpParams& op, void* p, const void* r, const DevState* st, hipStream_t s) {
-  hipLaunchKernelGGL((k_cg_p<R>), dim3(kRedBlocks * 2), dim3(256), 0, s, (C2<R>*)p, (const C2<R>*)r, g,
+  hipLaunchKernelGGL((k_cg_p<R>), dim3(nblk(nspec(g))), dim3(256), 0, s, (C2<R>*)p, (const C2<R>*)r, g,
                      op.precond ? op.kind : -1, op.rho0, op.nu, st, nspec(g));
 }
 
@@ -497,9 +506,9 @@ __global__ __launch_bounds__(256) void k_axpy_norm(C2<R>* __restrict__ r, const 
 template <typename R>
 void axpy_norm(const Geom& g, void* r, const void* w, const double* a_dev, double sign, double* partial, double* out,
                hipStream_t s) {
-  hipLaunchKernelGGL((k_axpy_norm<R>), dim3(kRedBlocks), dim3(256), 0, s, (C2<R>*)r, (const C2<R>*)w, a_dev, sign,
+  hipLaunchKernelGGL((k_axpy_norm<R>), dim3(nblk(nspec(g))), dim3(256), 0, s, (C2<R>*)r, (const C2<R>*)w, a_dev, sign,
                      nspec(g), g.M, partial);
-  reduce(partial, 1, g.ntot_inv, out, s);
+  reduce(partial, nblk(nspec(g)), 1, g.ntot_inv, out, s);
 }
 
 // ---------------------------------------------------------------- casts
@@ -527,15 +536,15 @@ __global__ __launch_bounds__(256) void k_cast_f2d(const C2<float>* __restrict__ 
   }
 }
 void cast_d2f(const Geom& g, const void* src, void* dst, double s, hipStream_t st) {
-  hipLaunchKernelGGL(k_cast_d2f, dim3(kRedBlocks * 2), dim3(256), 0, st, (const C2<double>*)src, (C2<float>*)dst, s,
+  hipLaunchKernelGGL(k_cast_d2f, dim3(nblk(nspec(g))), dim3(256), 0, st, (const C2<double>*)src, (C2<float>*)dst, s,
                      nspec(g));
 }
 void axpy_f2d(const Geom& g, const void* src, void* dst, double s, hipStream_t st) {
-  hipLaunchKernelGGL(k_axpy_f2d, dim3(kRedBlocks * 2), dim3(256), 0, st, (const C2<float>*)src, (C2<double>*)dst, s,
+  hipLaunchKernelGGL(k_axpy_f2d, dim3(nblk(nspec(g))), dim3(256), 0, st, (const C2<float>*)src, (C2<double>*)dst, s,
                      nspec(g));
 }
 void cast_f2d(const Geom& g, const void* src, void* dst, hipStream_t st) {
-  hipLaunchKernelGGL(k_cast_f2d, dim3(kRedBlocks * 2), dim3(256), 0, st, (const C2<float>*)src, (C2<double>*)dst,
+  hipLaunchKernelGGL(k_cast_f2d, dim3(nblk(nspec(g))), dim3(256), 0, st, (const C2<float>*)src, (C2<double>*)dst,
                      nspec(g));
 }
 
@@ -705,8 +714,8 @@ __global__ void k_density_fin(const double* __restrict__ partial, int nblk, doub
 }
 void density_setup(const double* rho, size_t n, double* a64, float* a32, float* rho32, double* partial, double* out,
                    hipStream_t s) {
-  hipLaunchKernelGGL(k_density, dim3(kRedBlocks), dim3(256), 0, s, rho, n, a64, a32, rho32, partial);
-  hipLaunchKernelGGL(k_density_fin, dim3(1), dim3(64), 0, s, partial, kRedBlocks, out);
+  hipLaunchKernelGGL(k_density, dim3(nblk(n)), dim3(256), 0, s, rho, n, a64, a32, rho32, partial);
+  hipLaunchKernelGGL(k_density_fin, dim3(1), dim3(64), 0, s, partial, nblk(n), out);
 }
 
 // ------------------------------------------------------- instantiations
