@@ -132,11 +132,21 @@ def traffic_from_profiles(best_name):
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = os.path.join(ROOT, "paper_2403_06654_amd", "csrc", "passes.hip")
-    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    if rec.get("passes_hip_sha256_16") != h:
+    if rec.get("csrc_sha256_16") != csrc_hash():
         return None
     return rec.get("per_launch_bytes", {}).get(best_name)
+
+
+def csrc_hash():
+    """Hash of the kernel sources, so that stored counter readings are only
+    used for the kernels they were taken on."""
+    d = os.path.join(ROOT, "paper_2403_06654_amd", "csrc")
+    h = hashlib.sha256()
+    for fn in sorted(os.listdir(d)):
+        if fn.endswith((".hip", ".hpp", ".cpp")):
+            h.update(fn.encode())
+            h.update(open(os.path.join(d, fn), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def cpu_baseline(inp):
@@ -351,6 +361,32 @@ def bench_c2(args):
     print(json.dumps(res))
 
 
+def bench_pmc(args):
+    """Short run for hardware-counter passes: one 1 GiB plain device copy
+    (calibration of the byte counters), then exactly the solve steps of the
+    default run's timed FP64 leg (same densities, same order, so the same
+    launches), without warm-up or timing."""
+    import torch
+    from paper_2403_06654_amd import workloads
+    from paper_2403_06654_amd.api import Grid
+    nbytes = 1 << 30
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)                      # calibration: reads and writes exactly 1 GiB
+    torch.cuda.synchronize()
+    del a, b
+    dens = {rj: workloads.jet_density(N, rj) for rj in RJS}
+    inp = workloads.c3_inputs(rj=3.0, n=N, seed=0, with_g=True)
+    rho_dev = [torch.from_numpy(dens[rj]).cuda() for rj in RJS]
+    f_dev = torch.from_numpy(inp["f"]).cuda()
+    g_dev = torch.from_numpy(inp["g"]).cuda()
+    grid = Grid((N, N, N))
+    r, _ = run_leg(grid, rho_dev, f_dev, g_dev, "fp64", args.steps, 0, torch)
+    grid.close()
+    print(json.dumps({"pmc_run": True, "copy_bytes": nbytes, "iters": r["iters"]}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -358,7 +394,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--workload", choices=["c3", "serving", "c5", "c2"], default="c3")
+    ap.add_argument("--workload", choices=["c3", "serving", "c5", "c2", "pmc"], default="c3")
     ap.add_argument("--requests", type=int, default=4096)
     ap.add_argument("--slots", type=int, default=8)
     args = ap.parse_args()
@@ -374,6 +410,9 @@ def main():
         return
     if args.workload == "c2":
         bench_c2(args)
+        return
+    if args.workload == "pmc":
+        bench_pmc(args)
         return
 
     import numpy as np

@@ -41,10 +41,11 @@ struct ColCfg {
 
 template <int L, typename R>
 struct RowCfg {
-  // FP64 rows use 8 points per thread: the x pass keeps a field's inverse
-  // and forward transforms plus the half-length pre/post-processing live at
-  // once, and 16 FP64 points per thread would cap occupancy at one wave/SIMD
-  static constexpr int E = L >= 16 ? (sizeof(R) == 8 ? 8 : 16) : L;
+  // FP64 rows (and long FP32 rows) use 8 points per thread: the x pass
+  // keeps a field's inverse and forward transforms plus the half-length
+  // pre/post-processing live at once, and 16 points per thread would cap
+  // occupancy at one wave/SIMD or spill
+  static constexpr int E = L >= 16 ? ((sizeof(R) == 8 || L >= 256) ? 8 : 16) : L;
   static constexpr int T = L / E;
   static constexpr int RW = 256 / T;  // rows per block
   static constexpr int LP = row_pitch<L>();
@@ -261,7 +262,9 @@ __global__ __launch_bounds__(MODE == ROW_P ? 768 : 256) void k_row(RowArgs a, co
   // same RW rows: the fields of the pressure pass share each coefficient
   // row through the CU's L1 instead of re-reading it from HBM, and each
   // thread keeps only one field's transforms live.
-  const int fsel = threadIdx.x / 256;
+  // field of this thread group; readfirstlane tells the compiler it is
+  // wave-uniform, so the field's pointers stay in scalar registers
+  const int fsel = __builtin_amdgcn_readfirstlane(threadIdx.x / 256);
   const int tid = threadIdx.x % 256;
   const int t = tid % T, rr = tid / T;
   const int row = blockIdx.x * RW + rr;

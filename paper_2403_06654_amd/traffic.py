@@ -1,0 +1,56 @@
+"""Turn two rocprofv3 --pmc runs of `bench.py --workload pmc` (FETCH_SIZE,
+then WRITE_SIZE) into calibrated HBM bytes per launch of the timed kernel
+classes, stored in profiles/traffic_counters.json for bench.py's roofline.
+
+    python -m paper_2403_06654_amd.traffic FETCH_DIR WRITE_DIR
+
+Calibration: the first device copy of the run moves exactly 1 GiB each way;
+the ratio of that to what each counter reports for it scales every other
+dispatch.  The result is keyed by a hash of the kernel sources so that it
+is ignored once the kernels change.
+"""
+import csv
+import glob
+import json
+import os
+import re
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+CLASS_PATTERNS = {
+    "gmres gram-schmidt update (k_gs_update)": r"^void vd::k_gs_update<double,",
+    "pressure x pass (k_row ROW_P)": r"^void vd::k_row<128, double, 2>",
+}
+
+
+def _rows(d):
+    path = glob.glob(os.path.join(d, "*counter_collection.csv"))[0]
+    return list(csv.DictReader(open(path)))
+
+
+def main(fetch_dir, write_dir):
+    from bench import csrc_hash  # noqa: E402
+    F, W = _rows(fetch_dir), _rows(write_dir)
+    copy_bytes = 1 << 30
+    cf = next(r for r in F if r["Kernel_Name"].startswith("__amd_rocclr_copyBuffer"))
+    cw = next(r for r in W if r["Kernel_Name"].startswith("__amd_rocclr_copyBuffer"))
+    kf = copy_bytes / (float(cf["Counter_Value"]) * 1024)
+    kw = copy_bytes / (float(cw["Counter_Value"]) * 1024)
+    out = {"csrc_sha256_16": csrc_hash(), "calibration": {"copy_bytes": copy_bytes, "fetch_factor": kf,
+                                                           "write_factor": kw},
+           "per_launch_bytes": {}, "launches": {}}
+    for name, pat in CLASS_PATTERNS.items():
+        fv = [float(r["Counter_Value"]) * 1024 * kf for r in F if re.match(pat, r["Kernel_Name"])]
+        wv = [float(r["Counter_Value"]) * 1024 * kw for r in W if re.match(pat, r["Kernel_Name"])]
+        if fv and len(fv) == len(wv):
+            out["per_launch_bytes"][name] = round((sum(fv) + sum(wv)) / len(fv))
+            out["launches"][name] = len(fv)
+    path = os.path.join(ROOT, "profiles", "traffic_counters.json")
+    json.dump(out, open(path, "w"), indent=1)
+    print(json.dumps(out, indent=1))
+
+
+if __name__ == "__main__":
+    main(sys.argv[1], sys.argv[2])
