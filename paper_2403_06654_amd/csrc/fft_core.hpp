@@ -178,12 +178,27 @@ __device__ __forceinline__ void stockham_butterflies(C2<R>* reg, const C2<R>* __
   }
 }
 
+// LDS synchronisation between the passes of a line.  Lines whose threads
+// all sit in one wavefront (row passes) need only a wave-level barrier with
+// wavefront-scope fences (LDS operations of one wave complete in order);
+// lines spread over several waves (column passes) need the block barrier.
+template <bool WAVE>
+__device__ __forceinline__ void lds_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 // Write the outputs of a pass (radix RP, stride NS) to LDS, then read the
 // inputs of the next pass (radix RN).  Leading barrier protects earlier reads.
-template <int L, int E, int RP, int NS, int RN, typename R, class V>
+template <int L, int E, int RP, int NS, int RN, bool WAVE, typename R, class V>
 __device__ __forceinline__ void stockham_exchange(C2<R>* reg, const V& lds, int t) {
   constexpr int T = L / E;
-  __syncthreads();
+  lds_sync<WAVE>();
 #pragma unroll
   for (int b = 0; b < E / RP; ++b) {
     const int j = t + T * b;
@@ -191,7 +206,7 @@ __device__ __forceinline__ void stockham_exchange(C2<R>* reg, const V& lds, int 
 #pragma unroll
     for (int r = 0; r < RP; ++r) lds.st(base + r * NS, reg[b * RP + r]);
   }
-  __syncthreads();
+  lds_sync<WAVE>();
 #pragma unroll
   for (int b = 0; b < E / RN; ++b) {
     const int j = t + T * b;
@@ -200,23 +215,24 @@ __device__ __forceinline__ void stockham_exchange(C2<R>* reg, const V& lds, int 
   }
 }
 
-template <int L, int E, int DIR, bool SF, int P, int NS, typename R, class V>
+template <int L, int E, int DIR, bool SF, int P, int NS, bool WAVE, typename R, class V>
 __device__ __forceinline__ void fft_passes(C2<R>* reg, const V& lds, const C2<R>* __restrict__ tw, int t) {
   using S = Sched<L, E>;
   constexpr int RP = S::template radix<SF>(P);
   stockham_butterflies<L, E, RP, NS, DIR, R>(reg, tw, t);
   if constexpr (P + 1 < S::npass) {
     constexpr int RN = S::template radix<SF>(P + 1);
-    stockham_exchange<L, E, RP, NS, RN, R>(reg, lds, t);
-    fft_passes<L, E, DIR, SF, P + 1, NS * RP, R>(reg, lds, tw, t);
+    stockham_exchange<L, E, RP, NS, RN, WAVE, R>(reg, lds, t);
+    fft_passes<L, E, DIR, SF, P + 1, NS * RP, WAVE, R>(reg, lds, tw, t);
   }
 }
 
 // Unnormalised FFT of one line (DIR = -1 forward, +1 inverse).  Input in
 // the pattern of the first radix, output in the pattern of the last radix.
-template <int L, int E, int DIR, bool SMALL_FIRST, typename R, class V>
+// WAVE: all T threads of the line are lanes of one wavefront.
+template <int L, int E, int DIR, bool SMALL_FIRST, bool WAVE = false, typename R, class V>
 __device__ __forceinline__ void fft_line(C2<R>* reg, const V& lds, const C2<R>* __restrict__ tw, int t) {
-  fft_passes<L, E, DIR, SMALL_FIRST, 0, 1, R>(reg, lds, tw, t);
+  fft_passes<L, E, DIR, SMALL_FIRST, 0, 1, WAVE, R>(reg, lds, tw, t);
 }
 
 }  // namespace vd

@@ -47,8 +47,15 @@ struct RowCfg {
   // occupancy at one wave/SIMD or spill
   static constexpr int E = L >= 16 ? ((sizeof(R) == 8 || L >= 256) ? 8 : 16) : L;
   static constexpr int T = L / E;
-  static constexpr int RW = 256 / T;  // rows per block
+  static_assert(T <= 64, "a row must fit one wavefront");
+  // One wavefront per field group: a row's T threads are adjacent lanes of
+  // one wavefront and each row owns its LDS slice, so the LDS exchanges need
+  // only wavefront-level ordering (no block barrier), and small blocks let
+  // the CU overlap the load, transform and store phases of several blocks.
+  static constexpr int NTG = 64;      // threads per field group (launch bounds of k_row)
+  static constexpr int RW = NTG / T;  // rows per block
   static constexpr int LP = row_pitch<L>();
+  static constexpr bool WAVE = true;
 };
 
 // ------------------------------------------------------ column kernels
@@ -246,9 +253,10 @@ struct RowArgs {
 };
 
 template <int L, typename R, int MODE>
-__global__ __launch_bounds__(MODE == ROW_P ? 768 : 256) void k_row(RowArgs a, const C2<R>* __restrict__ twtab) {
+__global__ __launch_bounds__(MODE == ROW_P ? 192 : 64) void k_row(RowArgs a, const C2<R>* __restrict__ twtab) {
   using Cf = RowCfg<L, R>;
   constexpr int E = Cf::E, T = Cf::T, RW = Cf::RW, LP = Cf::LP;
+  constexpr bool WV = Cf::WAVE;
   using S = Sched<L, E>;
   constexpr int RI1 = S::template last_radix<false>();   // inverse output pattern
   constexpr int RF0 = S::template first_radix<true>();   // forward input pattern (== RI1)
@@ -258,14 +266,14 @@ __global__ __launch_bounds__(MODE == ROW_P ? 768 : 256) void k_row(RowArgs a, co
   const C2<R>* tw = twtab + L;       // length-L table
   const C2<R>* twN = twtab + 2 * L;  // length-2L table, first L entries used
 
-  // A block is nf groups of 256 threads, one field per group, over the
+  // A block is nf groups of NTG threads, one field per group, over the
   // same RW rows: the fields of the pressure pass share each coefficient
   // row through the CU's L1 instead of re-reading it from HBM, and each
   // thread keeps only one field's transforms live.
   // field of this thread group; readfirstlane tells the compiler it is
   // wave-uniform, so the field's pointers stay in scalar registers
-  const int fsel = __builtin_amdgcn_readfirstlane(threadIdx.x / 256);
-  const int tid = threadIdx.x % 256;
+  const int fsel = __builtin_amdgcn_readfirstlane(threadIdx.x / Cf::NTG);
+  const int tid = threadIdx.x % Cf::NTG;
   const int t = tid % T, rr = tid / T;
   const int row = blockIdx.x * RW + rr;
   const bool ok = row < a.nrows;
@@ -293,14 +301,14 @@ __global__ __launch_bounds__(MODE == ROW_P ? 768 : 256) void k_row(RowArgs a, co
 
   auto inverse_row = [&](const C2<R>* __restrict__ src, int f) {
     // stage the packed row, build Z_k = E_k + i O_k for the half-length FFT
-    __syncthreads();
+    lds_sync<WV>();
 #pragma unroll
     for (int s = 0; s < E; ++s) {
       int k = t + s * T;
       C2<R> X = ok ? ldg(src + (size_t)row * L + k) : C2<R>{R(0), R(0)};
       lds.st(k, pre_mult(f, k, X));
     }
-    __syncthreads();
+    lds_sync<WV>();
     constexpr int RI0 = S::template first_radix<false>();
 #pragma unroll
     for (int s = 0; s < E; ++s) {
@@ -317,15 +325,15 @@ __global__ __launch_bounds__(MODE == ROW_P ? 768 : 256) void k_row(RowArgs a, co
       }
       reg[s] = Z;
     }
-    fft_line<L, E, +1, false>(reg, lds, tw, t);
+    fft_line<L, E, +1, false, WV>(reg, lds, tw, t);
   };
 
   auto forward_post = [&](int f, C2<R>* __restrict__ dst, const C2<R>* __restrict__ vsrc) {
     // reg holds Z_k for k = t + s T (forward output, radix E last)
-    __syncthreads();
+    lds_sync<WV>();
 #pragma unroll
     for (int s = 0; s < E; ++s) lds.st(t + s * T, reg[s]);
-    __syncthreads();
+    lds_sync<WV>();
 #pragma unroll
     for (int s = 0; s < E; ++s) {
       int k = t + s * T;
@@ -369,7 +377,7 @@ __global__ __launch_bounds__(MODE == ROW_P ? 768 : 256) void k_row(RowArgs a, co
       int m = pat_index<L, E, RF0>(t, s);
       reg[s] = ok ? ldg(src + (size_t)row * L + m) : C2<R>{R(0), R(0)};
     }
-    fft_line<L, E, -1, true>(reg, lds, tw, t);
+    fft_line<L, E, -1, true, WV>(reg, lds, tw, t);
     forward_post(0, (C2<R>*)a.out[0], nullptr);
   } else if constexpr (MODE == ROW_C2R) {
     inverse_row((const C2<R>*)a.in[0], 0);
@@ -393,7 +401,7 @@ __global__ __launch_bounds__(MODE == ROW_P ? 768 : 256) void k_row(RowArgs a, co
       C2<R> q = ok ? ldg(coef + (size_t)row * L + m) : C2<R>{R(0), R(0)};
       reg[s] = C2<R>{reg[s].x * (q.x * cs), reg[s].y * (q.y * cs)};
     }
-    fft_line<L, E, -1, true>(reg, lds, tw, t);
+    fft_line<L, E, -1, true, WV>(reg, lds, tw, t);
     forward_post(f, (C2<R>*)a.out[f], (const C2<R>*)a.in[0]);
   }
 }
@@ -451,7 +459,7 @@ template <typename R, int MODE, int L>
 static void launch_row_L(const RowArgs& a, const void* tw, hipStream_t st) {
   dim3 grid((a.nrows + RowCfg<L, R>::RW - 1) / RowCfg<L, R>::RW);
   const int nf = (MODE == ROW_P) ? a.nf : 1;
-  hipLaunchKernelGGL((k_row<L, R, MODE>), grid, dim3(256 * nf), 0, st, a, (const C2<R>*)tw);
+  hipLaunchKernelGGL((k_row<L, R, MODE>), grid, dim3(RowCfg<L, R>::NTG * nf), 0, st, a, (const C2<R>*)tw);
 }
 
 template <typename R, int MODE>

@@ -210,11 +210,21 @@ void mupdate(const Geom& g, void* x, const VecPtrs& V, int nv, const double* coe
 //   pass 3  w'' = w' - sum_i c_i v_i  (H[:, j] = h + c,
 //           ||w''||^2 = ||w'||^2 - |c|^2, accurate because |c| << ||w'||).
 // Pass 3 exits at once when not needed, so the common step costs two
-// passes over the basis.  tol = 1e-12 for FP64 vectors (100x below the 1e-10
-// target); 1e-8 for FP32 vectors, whose own rounding already limits the
-// inner solves to ~1e-6.
+// passes over the basis.
+//
+// Choice of tol: the Arnoldi relation A V_j = V_{j+1} H_j holds to rounding
+// whatever the orthogonality, so the computed least-squares residual
+// |beta e1 - H y| differs from the true one |V_{j+1}(beta e1 - H y)| only by
+// the factor |V_{j+1}| <= sqrt(1 + (j+1) delta), delta the largest cosine
+// between basis vectors.  Orthogonality must therefore stay far from 1
+// (else the basis degenerates and convergence stalls), not below the solve
+// tolerance.  tol = 1e-8 (FP64) keeps that factor within 2e-7 of 1 for 32
+// vectors; 1e-4 (FP32 inner solves, target 1e-5) within 0.2%.  A tighter
+// tol only makes the second pass fire whenever the operator is close to the
+// identity (velocity solves), where |w'| << |w| magnifies the rounding of the
+// first-pass dots.
 template <typename R>
-constexpr double orth_tol() { return sizeof(R) == 8 ? 1e-12 : 1e-8; }
+constexpr double orth_tol() { return sizeof(R) == 8 ? 1e-8 : 1e-4; }
 
 __global__ void k_gs_prep(DevState* st, int nv) {
   if (threadIdx.x) return;
