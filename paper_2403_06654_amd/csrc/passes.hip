@@ -413,9 +413,9 @@ __global__ __launch_bounds__(256) void k_precond(const C2<R>* __restrict__ r, C2
                                                  int kind, double rho0, double nu, size_t n) {
   size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
-  int kx = (int)(e % g.M);
-  size_t q = e / g.M;
-  int ky = (int)(q % g.ny), kz = (int)(q / g.ny);
+  const unsigned ue = (unsigned)e, q = ue / (unsigned)g.M;  // at most 2^29 slots
+  const int kx = (int)(ue - q * (unsigned)g.M);
+  const int ky = (int)(q % (unsigned)g.ny), kz = (int)(q / (unsigned)g.ny);
   C2<R> v = ldg(r + e);
   if (kind == OP_PRESSURE) {
     stg(z + e, cscale(v, mult_press<R>(kx, ky, kz, g, rho0)));

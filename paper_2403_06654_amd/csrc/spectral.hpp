@@ -69,9 +69,10 @@ __device__ __forceinline__ R in_scale_of(const double* p) {
 template <typename R>
 __device__ __forceinline__ C2<R> precond_at(const C2<R>* __restrict__ r, size_t e, const Geom& g, int kind,
                                             double rho0, double nu) {
-  int kx = (int)(e % g.M);
-  size_t q = e / g.M;
-  int ky = (int)(q % g.ny), kz = (int)(q / g.ny);
+  // 32-bit index arithmetic: a packed spectrum has at most 2^29 slots
+  const unsigned ue = (unsigned)e, q = ue / (unsigned)g.M;
+  const int kx = (int)(ue - q * (unsigned)g.M);
+  const int ky = (int)(q % (unsigned)g.ny), kz = (int)(q / (unsigned)g.ny);
   C2<R> v = ldg(r + e);
   if (kind < 0) return v;  // identity (no preconditioner)
   if (kind == OP_PRESSURE) return cscale(v, mult_press<R>(kx, ky, kz, g, rho0));

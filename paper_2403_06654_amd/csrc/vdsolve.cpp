@@ -366,8 +366,7 @@ struct Krylov {
         o.iters++;
         VecPtrs P{};
         for (int i = 0; i <= j; ++i) P.p[i] = V[i];
-        gs_orthogonalize<R>(g, V[j + 1], P, j + 1, G->dst, G->partial, G->st, &G->prof);
-        gmres_givens(G->dst, j, G->st);
+        gs_orthogonalize<R>(g, V[j + 1], P, j + 1, G->dst, G->partial, G->st, &G->prof);  // + Givens on column j
         sync_state(G);
         k = j + 1;
         if (G->hst->bad) { o.status = VD_EBREAKDOWN; return o; }

@@ -50,12 +50,14 @@ __device__ __forceinline__ void block_store(const double* acc, int k_used, doubl
   }
 }
 
-__device__ __forceinline__ double spec_w(size_t e, int M) { return (e % M) == 0 ? 1.0 : 2.0; }
+// M (half the x length) is a power of two for every grid (Fourier axes are
+// powers of two), so the kx = 0 test is a mask, not a 64-bit division
+__device__ __forceinline__ double spec_w(size_t e, int M) { return (e & (size_t)(M - 1)) == 0 ? 1.0 : 2.0; }
 
 // One wave per output value; lanes stride over the block partials in a
 // fixed order, then a fixed shuffle tree.  No block-wide barrier.
-__global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ partial, int nblk, int K, double scale,
-                                                 double* __restrict__ out) {
+__device__ __forceinline__ void reduce_values(const double* __restrict__ partial, int nblk, int K, double scale,
+                                              double* __restrict__ out) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int i = w; i < K; i += 16) {
     double v = 0.0;
@@ -63,6 +65,11 @@ __global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ part
     v = wave_sum(v);
     if (lane == 0) out[i] = v * scale;
   }
+}
+
+__global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ partial, int nblk, int K, double scale,
+                                                 double* __restrict__ out) {
+  reduce_values(partial, nblk, K, scale, out);
 }
 
 static void reduce(const double* partial, int nb, int K, double scale, double* out, hipStream_t s) {
@@ -102,9 +109,10 @@ __global__ __launch_bounds__(256) void k_mdot(const C2<R>* __restrict__ x, VecPt
   block_store<NV + 1>(out, nv + (want_norm ? 1 : 0), partial + (size_t)blockIdx.x * kRedStride);
 }
 
+// Block partials only (the caller reduces them).
 template <typename R>
-void mdot(const Geom& g, const void* x, const VecPtrs& V, int nv, bool want_norm, double* partial, double* out,
-          hipStream_t s, Prof* prof) {
+static void mdot_partials(const Geom& g, const void* x, const VecPtrs& V, int nv, bool want_norm, double* partial,
+                          hipStream_t s) {
   size_t n = nspec(g);
   dim3 gr(nblk(n)), bl(256);
   const int wn = want_norm ? 1 : 0;
@@ -122,8 +130,14 @@ void mdot(const Geom& g, const void* x, const VecPtrs& V, int nv, bool want_norm
     hipLaunchKernelGGL((k_mdot<R, 24>), gr, bl, 0, s, (const C2<R>*)x, V, nv, wn, n, g.M, partial);
   else
     hipLaunchKernelGGL((k_mdot<R, kMaxVec>), gr, bl, 0, s, (const C2<R>*)x, V, nv, wn, n, g.M, partial);
+}
+
+template <typename R>
+void mdot(const Geom& g, const void* x, const VecPtrs& V, int nv, bool want_norm, double* partial, double* out,
+          hipStream_t s, Prof* prof) {
+  mdot_partials<R>(g, x, V, nv, want_norm, partial, s);
   if (prof) prof->end(s);
-  reduce(partial, nblk(nspec(g)), nv + wn, g.ntot_inv, out, s);
+  reduce(partial, nblk(nspec(g)), nv + (want_norm ? 1 : 0), g.ntot_inv, out, s);
 }
 
 // --------------------------------------------------------- multi-update
@@ -226,7 +240,15 @@ void mupdate(const Geom& g, void* x, const VecPtrs& V, int nv, const double* coe
 template <typename R>
 constexpr double orth_tol() { return sizeof(R) == 8 ? 1e-8 : 1e-4; }
 
-__global__ void k_gs_prep(DevState* st, int nv) {
+// Givens step of GMRES on the new Hessenberg column j (after the check).
+__device__ void gmres_givens_col(DevState* st, int j);
+
+// The scalar steps below run in the block that finishes the cross-block
+// reduction of the pass before them (one launch instead of two).
+__global__ __launch_bounds__(1024) void k_gs_prep(DevState* st, int nv, const double* __restrict__ partial, int nb,
+                                                  double scale) {
+  reduce_values(partial, nb, nv, scale, st->red2);
+  __syncthreads();
   if (threadIdx.x) return;
   for (int i = 0; i < nv; ++i) {
     const double h = st->vs[i] * st->red2[i];
@@ -235,7 +257,10 @@ __global__ void k_gs_prep(DevState* st, int nv) {
   }
 }
 
-__global__ void k_gs_check(DevState* st, int nv, double tol) {
+__global__ __launch_bounds__(1024) void k_gs_check(DevState* st, int nv, double tol, const double* __restrict__ partial,
+                                                   int nb, double scale) {
+  reduce_values(partial, nb, nv + 1, scale, st->red);
+  __syncthreads();
   if (threadIdx.x) return;
   const double n2 = st->red[nv];
   double cmax = 0.0, c2 = 0.0;
@@ -256,6 +281,7 @@ __global__ void k_gs_check(DevState* st, int nv, double tol) {
     st->nreorth += 1;
   }
   st->vs[nv] = st->hn > 0.0 ? 1.0 / st->hn : 0.0;
+  gmres_givens_col(st, nv - 1);  // the second pass changes only w, not H
 }
 
 template <typename R, int NV>
@@ -339,8 +365,10 @@ void gs_orthogonalize(const Geom& g, void* w, const VecPtrs& V, int nv, DevState
   const bool pr = prof && prof->on;
   const double fb = (double)nspec(g) * sizeof(C2<R>);
   if (pr) prof->begin(10, s, (nv + 1) * fb);
-  mdot<R>(g, w, V, nv, false, partial, st->red2, s, pr ? prof : nullptr);
-  hipLaunchKernelGGL(k_gs_prep, dim3(1), dim3(64), 0, s, st, nv);
+  const int nb = nblk(nspec(g));
+  mdot_partials<R>(g, w, V, nv, false, partial, s);
+  if (pr) prof->end(s);
+  hipLaunchKernelGGL(k_gs_prep, dim3(1), dim3(1024), 0, s, st, nv, (const double*)partial, nb, g.ntot_inv);
   for (int second = 0; second < 2; ++second) {
     if (pr && !second) prof->begin(11, s, (nv + 2) * fb);
     if (nv <= 4) launch_gs<R, 4>(g, w, V, nv, st, second, partial, s);
@@ -349,10 +377,9 @@ void gs_orthogonalize(const Geom& g, void* w, const VecPtrs& V, int nv, DevState
     else if (nv <= 24) launch_gs<R, 24>(g, w, V, nv, st, second, partial, s);
     else launch_gs<R, kMaxVec>(g, w, V, nv, st, second, partial, s);
     if (pr && !second) prof->end(s);
-    if (!second) {
-      reduce(partial, nblk(nspec(g)), nv + 1, g.ntot_inv, st->red, s);
-      hipLaunchKernelGGL(k_gs_check, dim3(1), dim3(64), 0, s, st, nv, orth_tol<R>());
-    }
+    if (!second)
+      hipLaunchKernelGGL(k_gs_check, dim3(1), dim3(1024), 0, s, st, nv, orth_tol<R>(), (const double*)partial, nb,
+                         g.ntot_inv);
   }
 }
 
@@ -596,8 +623,7 @@ __global__ void k_gmres_init(DevState* st, double beta, int m) {
 
 // Column j of the Hessenberg matrix: the Gram-Schmidt coefficients h (plus
 // the second-pass corrections c when that pass ran); subdiagonal ||w||.
-__global__ void k_gmres_givens(DevState* st, int j) {
-  if (threadIdx.x != 0) return;
+__device__ void gmres_givens_col(DevState* st, int j) {
   double* H = st->H;
   const int ld = ldh();
   for (int i = 0; i <= j; ++i) H[i + j * ld] = st->hcol[i] + (st->reorth ? st->ccol[i] : 0.0);
@@ -659,7 +685,6 @@ __global__ void k_rmr_alpha(DevState* st) {
 void gmres_init(DevState* st, double beta, int m, hipStream_t s) {
   hipLaunchKernelGGL(k_gmres_init, dim3(1), dim3(64), 0, s, st, beta, m);
 }
-void gmres_givens(DevState* st, int j, hipStream_t s) { hipLaunchKernelGGL(k_gmres_givens, dim3(1), dim3(64), 0, s, st, j); }
 void gmres_backsolve(DevState* st, int k, hipStream_t s) {
   hipLaunchKernelGGL(k_gmres_backsolve, dim3(1), dim3(64), 0, s, st, k);
 }

@@ -57,7 +57,8 @@ void mupdate(const Geom& g, void* x, const VecPtrs& V, int nv, const double* coe
 // (v_i = vs[i] V_i) in place; classical Gram-Schmidt with a measured
 // orthogonality check and a conditional second pass.  Leaves the
 // Hessenberg column in st->hcol (+ st->ccol), ||w|| in st->hn and
-// vs[nv] = 1 / ||w||.
+// vs[nv] = 1 / ||w||, and applies the Givens rotations to column nv - 1
+// (st->resid = new residual estimate).
 template <typename R>
 void gs_orthogonalize(const Geom& g, void* w, const VecPtrs& V, int nv, DevState* st, double* partial,
                       hipStream_t s, Prof* prof = nullptr);
@@ -109,7 +110,6 @@ void project_range(const Geom& g, void* spec, double* removed, hipStream_t st);
 
 // Scalar kernels (one thread) of the Krylov methods.
 void gmres_init(DevState* st, double beta, int m, hipStream_t s);
-void gmres_givens(DevState* st, int j, hipStream_t s);   // uses red (h), red2 (c) and nrm2
 void gmres_backsolve(DevState* st, int k, hipStream_t s);  // y, and coef = y * vs
 void cg_alpha(DevState* st, hipStream_t s);   // alpha = rz / red[0]
 void cg_beta(DevState* st, hipStream_t s);    // beta = red[0] / rz; rz = red[0]
