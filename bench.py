@@ -140,10 +140,11 @@ def traffic_from_profiles(best_name):
 def csrc_hash():
     """Hash of the kernel sources, so that stored counter readings are only
     used for the kernels they were taken on."""
+    from paper_2403_06654_amd.build import SOURCES
     d = os.path.join(ROOT, "paper_2403_06654_amd", "csrc")
     h = hashlib.sha256()
     for fn in sorted(os.listdir(d)):
-        if fn.endswith((".hip", ".hpp", ".cpp")):
+        if fn in SOURCES or fn.endswith(".hpp"):  # the library's sources
             h.update(fn.encode())
             h.update(open(os.path.join(d, fn), "rb").read())
     return h.hexdigest()[:16]

@@ -9,6 +9,9 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libvdsolve.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["passes.hip", "vecops.hip", "gemm.hip", "cheb.cpp", "vdsolve.cpp", "vdserve.cpp"]
+# standalone stream-bandwidth ceiling probe (not part of the library)
+CEILING_SRC = "stream_ceiling.hip"
+CEILING_OUT = os.path.join(HERE, "stream_ceiling")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
@@ -39,6 +42,10 @@ def build(verbose=False):
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr[-4000:]}")
     os.replace(tmp, OUT)
+    cmd = [HIPCC, *FLAGS, "-x", "hip", os.path.join(CSRC, CEILING_SRC), "-o", CEILING_OUT]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {CEILING_SRC}:\n{r.stderr[-4000:]}")
     return OUT
 
 
