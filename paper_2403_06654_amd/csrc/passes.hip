@@ -31,9 +31,31 @@ namespace vd {
 
 // ------------------------------------------------------------ config
 
-template <int L>
+// Points per thread of a column line.  Measured on MI355X at 256^3 and 512^3
+// (FP64 passes, us per launch, E = 16 -> 8):
+//   L = 256: Helmholtz z-first 78 -> 62, z-last 99 -> 81, plain FFT 47 -> 44,
+//            pressure y-inverse 127 -> 122; but pressure z-last 76 -> 86 and
+//            y-forward 134 -> 135 (two transforms per thread, one more LDS
+//            exchange each);
+//   L = 512: every pass 40-70% slower (a 256-thread tile is then only 4
+//            columns wide, 64 B per row access).
+// E = 16 in FP64 needs ~256 VGPRs in the two-field modes and a 64 KB tile
+// (one or two waves per SIMD); E = 8 halves both.
+enum ColMode {
+  COL_FFT_FWD = 0,  // NF fields, forward
+  COL_FFT_INV,      // NF fields, inverse
+  COL_P_FIRST,      // v -> Fz^-1(M v), Fz^-1(i k'_z M v)
+  COL_P_MIDINV,     // T1, T1z -> Fy^-1 T1, Fy^-1(i k'_y T1), Fy^-1 T1z
+  COL_P_MIDFWD,     // Qx', Qy, Qz -> Fy Qx' + i k'_y Fy Qy, Fy Qz
+  COL_P_LAST,       // S, Qz2 -> -(Fz S + i k'_z Fz Qz2)
+  COL_H_FIRST,      // v -> Fz^-1(M v)
+  COL_H_LAST,       // Q2, v -> Fz Q2 + nu |k|^2 M v
+};
+
+template <int L, typename R, int MODE>
 struct ColCfg {
-  static constexpr int E = L >= 16 ? 16 : L;
+  static constexpr bool E8 = sizeof(R) == 8 && L < 512 && MODE != COL_P_LAST && MODE != COL_P_MIDFWD;
+  static constexpr int E = E8 ? (L >= 8 ? 8 : L) : (L >= 16 ? 16 : L);
   static constexpr int T = L / E;
   static constexpr int TC = 256 / T;  // columns per tile (256 threads)
   static constexpr int NT = 256;
@@ -48,28 +70,18 @@ struct RowCfg {
   static constexpr int E = L >= 16 ? ((sizeof(R) == 8 || L >= 256) ? 8 : 16) : L;
   static constexpr int T = L / E;
   static_assert(T <= 64, "a row must fit one wavefront");
-  // One wavefront per field group: a row's T threads are adjacent lanes of
-  // one wavefront and each row owns its LDS slice, so the LDS exchanges need
-  // only wavefront-level ordering (no block barrier), and small blocks let
-  // the CU overlap the load, transform and store phases of several blocks.
-  static constexpr int NTG = 64;      // threads per field group (launch bounds of k_row)
-  static constexpr int RW = NTG / T;  // rows per block
+  // A row's T threads are adjacent lanes of one wavefront and each row owns
+  // its LDS slice, so the LDS exchanges need only wavefront-level ordering
+  // (no block barrier).  Blocks are a few wavefronts (the CU overlaps the
+  // load, transform and store phases of several blocks); the block shares
+  // the twiddle tables, staged once in LDS.
+  static constexpr int RW = 64 / T;  // rows per wavefront
   static constexpr int LP = row_pitch<L>();
   static constexpr bool WAVE = true;
 };
 
 // ------------------------------------------------------ column kernels
 
-enum ColMode {
-  COL_FFT_FWD = 0,  // NF fields, forward
-  COL_FFT_INV,      // NF fields, inverse
-  COL_P_FIRST,      // v -> Fz^-1(M v), Fz^-1(i k'_z M v)
-  COL_P_MIDINV,     // T1, T1z -> Fy^-1 T1, Fy^-1(i k'_y T1), Fy^-1 T1z
-  COL_P_MIDFWD,     // Qx', Qy, Qz -> Fy Qx' + i k'_y Fy Qy, Fy Qz
-  COL_P_LAST,       // S, Qz2 -> -(Fz S + i k'_z Fz Qz2)
-  COL_H_FIRST,      // v -> Fz^-1(M v)
-  COL_H_LAST,       // Q2, v -> Fz Q2 + nu |k|^2 M v
-};
 
 struct ColArgs {
   const void* in[3];
@@ -105,14 +117,18 @@ __device__ __forceinline__ void col_store(const C2<R>* reg, C2<R>* p, size_t bas
 
 template <int L, typename R, int MODE>
 __global__ __launch_bounds__(256) void k_col(ColArgs a, const C2<R>* __restrict__ twtab) {
-  using Cf = ColCfg<L>;
+  using Cf = ColCfg<L, R, MODE>;
   constexpr int E = Cf::E, T = Cf::T, TC = Cf::TC;
   using S = Sched<L, E>;
   constexpr int R0 = S::template first_radix<false>();
   constexpr int R1 = S::template last_radix<false>();
   constexpr int LDSN = S::npass > 1 ? TC * L : 1;
   __shared__ C2<R> lds_raw[LDSN];
-  const C2<R>* tw = twtab + L;
+  // twiddle table staged in LDS (see k_row)
+  __shared__ C2<R> tw_lds[L];
+  for (int i = threadIdx.x; i < L; i += blockDim.x) tw_lds[i] = twtab[L + i];
+  __syncthreads();
+  const C2<R>* tw = tw_lds;
 
   const int tid = threadIdx.x;
   const int c = tid % TC, t = tid / TC;
@@ -252,8 +268,14 @@ struct RowArgs {
   const double* in_scale;
 };
 
+// Wavefronts per block: the pressure x pass runs its (up to three) fields as
+// one wavefront each over the same rows; the other modes run four
+// wavefronts over consecutive row groups.
+template <int MODE>
+constexpr int row_waves() { return MODE == ROW_P ? 3 : 4; }
+
 template <int L, typename R, int MODE>
-__global__ __launch_bounds__(MODE == ROW_P ? 192 : 64) void k_row(RowArgs a, const C2<R>* __restrict__ twtab) {
+__global__ __launch_bounds__(64 * row_waves<MODE>()) void k_row(RowArgs a, const C2<R>* __restrict__ twtab) {
   using Cf = RowCfg<L, R>;
   constexpr int E = Cf::E, T = Cf::T, RW = Cf::RW, LP = Cf::LP;
   constexpr bool WV = Cf::WAVE;
@@ -261,23 +283,30 @@ __global__ __launch_bounds__(MODE == ROW_P ? 192 : 64) void k_row(RowArgs a, con
   constexpr int RI1 = S::template last_radix<false>();   // inverse output pattern
   constexpr int RF0 = S::template first_radix<true>();   // forward input pattern (== RI1)
   static_assert(RI1 == RF0, "pattern mismatch");
-  constexpr int NG = MODE == ROW_P ? 3 : 1;  // thread groups (fields) per block
-  __shared__ C2<R> lds_all[NG * RW * LP];
-  const C2<R>* tw = twtab + L;       // length-L table
-  const C2<R>* twN = twtab + 2 * L;  // length-2L table, first L entries used
+  constexpr int NW = row_waves<MODE>();
+  constexpr int RB = MODE == ROW_P ? RW : NW * RW;  // rows per block
+  __shared__ C2<R> lds_all[NW * RW * LP];
+  // twiddle tables in LDS: a load in every butterfly pass from global memory
+  // (even an L1 hit) costs latency inside the transform and address registers
+  __shared__ C2<R> tw_lds[2 * L];
+  for (int i = threadIdx.x; i < 2 * L; i += blockDim.x) tw_lds[i] = twtab[L + i];
+  __syncthreads();
+  const C2<R>* tw = tw_lds;       // length-L table
+  const C2<R>* twN = tw_lds + L;  // length-2L table, first L entries used
 
-  // A block is nf groups of NTG threads, one field per group, over the
-  // same RW rows: the fields of the pressure pass share each coefficient
-  // row through the CU's L1 instead of re-reading it from HBM, and each
-  // thread keeps only one field's transforms live.
-  // field of this thread group; readfirstlane tells the compiler it is
-  // wave-uniform, so the field's pointers stay in scalar registers
-  const int fsel = __builtin_amdgcn_readfirstlane(threadIdx.x / Cf::NTG);
-  const int tid = threadIdx.x % Cf::NTG;
-  const int t = tid % T, rr = tid / T;
-  const int row = blockIdx.x * RW + rr;
+  // ROW_P: wavefront w handles field w of the block's rows, so the fields
+  // share each coefficient row through the CU's L1 instead of re-reading it
+  // from HBM, and each thread keeps only one field's transforms live.
+  // readfirstlane tells the compiler the wave index is wave-uniform, so the
+  // field's pointers stay in scalar registers.
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  const int lane = threadIdx.x % 64;
+  const int fsel = MODE == ROW_P ? wave : 0;
+  const int t = lane % T;
+  const int rr = (MODE == ROW_P ? 0 : wave * RW) + lane / T;  // row within the block
+  const int row = blockIdx.x * RB + rr;
   const bool ok = row < a.nrows;
-  LdsRow<R> lds{lds_all + (fsel * RW + rr) * LP};
+  LdsRow<R> lds{lds_all + (MODE == ROW_P ? fsel * RW + rr : rr) * LP};
   const R sx = R(a.g.sx);
   C2<R> reg[E];
 
@@ -436,7 +465,7 @@ __global__ __launch_bounds__(256) void k_precond(const C2<R>* __restrict__ r, C2
 template <typename R, int MODE, int L>
 static void launch_col_L(const ColArgs& a0, const void* tw, hipStream_t st) {
   ColArgs a = a0;
-  a.ntile = (a.inner + ColCfg<L>::TC - 1) / ColCfg<L>::TC;
+  a.ntile = (a.inner + ColCfg<L, R, MODE>::TC - 1) / ColCfg<L, R, MODE>::TC;
   dim3 grid(a.outer * a.ntile);
   hipLaunchKernelGGL((k_col<L, R, MODE>), grid, dim3(256), 0, st, a, (const C2<R>*)tw);
 }
@@ -457,9 +486,11 @@ static void launch_col(int L, const ColArgs& a, const void* tw, hipStream_t st) 
 
 template <typename R, int MODE, int L>
 static void launch_row_L(const RowArgs& a, const void* tw, hipStream_t st) {
-  dim3 grid((a.nrows + RowCfg<L, R>::RW - 1) / RowCfg<L, R>::RW);
-  const int nf = (MODE == ROW_P) ? a.nf : 1;
-  hipLaunchKernelGGL((k_row<L, R, MODE>), grid, dim3(RowCfg<L, R>::NTG * nf), 0, st, a, (const C2<R>*)tw);
+  constexpr int RW = RowCfg<L, R>::RW;
+  const int rb = MODE == ROW_P ? RW : row_waves<MODE>() * RW;
+  dim3 grid((a.nrows + rb - 1) / rb);
+  const int waves = MODE == ROW_P ? a.nf : row_waves<MODE>();  // ROW_P: one wavefront per field (<= 3)
+  hipLaunchKernelGGL((k_row<L, R, MODE>), grid, dim3(64 * waves), 0, st, a, (const C2<R>*)tw);
 }
 
 template <typename R, int MODE>
