@@ -116,8 +116,9 @@ def roofline(prof, field_bytes):
                                      "GB_s": round(nbytes[c] / (ms[c] * 1e-3) / 1e9, 1)}
     # whole pressure operator application (5 passes, 23 field transfers)
     op_ms = sum(ms[c] / cnt[c] for c in range(5) if cnt[c])
-    op = {"avg_ms": round(op_ms, 4), "fields": 23,
-          "GB_s": round(23 * field_bytes / (op_ms * 1e-3) / 1e9, 1) if op_ms else None}
+    op_gbs = 23 * field_bytes / (op_ms * 1e-3) / 1e9 if op_ms else None
+    op = {"avg_ms": round(op_ms, 4), "fields": 23, "GB_s": round(op_gbs, 1) if op_gbs else None,
+          "frac_of_hbm_peak": round(op_gbs / PEAK_HBM_GBS, 4) if op_gbs else None}
     return best, {
         "bound": "hbm", "kernel": PASS_NAMES[best], "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
         "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
