@@ -423,11 +423,28 @@ __global__ __launch_bounds__(64 * row_waves<MODE>()) void k_row(RowArgs a, const
     const C2<R>* coef = (const C2<R>*)a.coef;
     const R cs = R(a.cscale);
     const int f = fsel;
+    // pressure x pass: issue the coefficient row's loads before the inverse
+    // transform so that their latency hides behind it (measured: 215 -> 204
+    // us at 256^3 FP64; the single-field Helmholtz pass is faster without)
+    constexpr bool PREFETCH = MODE == ROW_P;
+    C2<R> qv[PREFETCH ? E : 1];
+    if constexpr (PREFETCH) {
+#pragma unroll
+      for (int s = 0; s < E; ++s) {
+        int m = pat_index<L, E, RI1>(t, s);
+        qv[s] = ok ? ldg(coef + (size_t)row * L + m) : C2<R>{R(0), R(0)};
+      }
+    }
     inverse_row((const C2<R>*)a.in[f], f);
 #pragma unroll
     for (int s = 0; s < E; ++s) {
-      int m = pat_index<L, E, RI1>(t, s);
-      C2<R> q = ok ? ldg(coef + (size_t)row * L + m) : C2<R>{R(0), R(0)};
+      C2<R> q;
+      if constexpr (PREFETCH) {
+        q = qv[s];
+      } else {
+        int m = pat_index<L, E, RI1>(t, s);
+        q = ok ? ldg(coef + (size_t)row * L + m) : C2<R>{R(0), R(0)};
+      }
       reg[s] = C2<R>{reg[s].x * (q.x * cs), reg[s].y * (q.y * cs)};
     }
     fft_line<L, E, -1, true, WV>(reg, lds, tw, t);
