@@ -31,7 +31,9 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Reduce acc[0..K) across a 256-thread block; thread 0 writes partial[0..K).
+// Reduce acc[0..K) across a 256-thread block; value i of block b goes to
+// partial[i * kRedBlocks + b] (callers pass partial + b), so that the final
+// reduction reads each value's block partials contiguously.
 template <int K>
 __device__ __forceinline__ void block_store(const double* acc, int k_used, double* partial) {
   __shared__ double sh[4][K > 0 ? K : 1];
@@ -46,7 +48,7 @@ __device__ __forceinline__ void block_store(const double* acc, int k_used, doubl
   __syncthreads();
   if (threadIdx.x < k_used) {
     int i = threadIdx.x;
-    partial[i] = ((sh[0][i] + sh[1][i]) + sh[2][i]) + sh[3][i];
+    partial[(size_t)i * kRedBlocks] = ((sh[0][i] + sh[1][i]) + sh[2][i]) + sh[3][i];
   }
 }
 
@@ -61,7 +63,7 @@ __device__ __forceinline__ void reduce_values(const double* __restrict__ partial
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int i = w; i < K; i += 16) {
     double v = 0.0;
-    for (int b = lane; b < nblk; b += 64) v += partial[(size_t)b * kRedStride + i];
+    for (int b = lane; b < nblk; b += 64) v += partial[(size_t)i * kRedBlocks + b];
     v = wave_sum(v);
     if (lane == 0) out[i] = v * scale;
   }
@@ -106,7 +108,7 @@ __global__ __launch_bounds__(256) void k_mdot(const C2<R>* __restrict__ x, VecPt
 #pragma unroll
   for (int i = 0; i < NV; ++i)
     if (i == nv) out[i] = acc[NV];
-  block_store<NV + 1>(out, nv + (want_norm ? 1 : 0), partial + (size_t)blockIdx.x * kRedStride);
+  block_store<NV + 1>(out, nv + (want_norm ? 1 : 0), partial + blockIdx.x);
 }
 
 // Block partials only (the caller reduces them).
@@ -185,7 +187,7 @@ __global__ __launch_bounds__(256) void k_mupdate(C2<R>* __restrict__ x, VecPtrs 
 #pragma unroll
   for (int i = 0; i <= NV; ++i)
     if (i == k) out[i] = acc[NV];
-  block_store<NV + 1>(out, k + 1, partial + (size_t)blockIdx.x * kRedStride);
+  block_store<NV + 1>(out, k + 1, partial + blockIdx.x);
 }
 
 template <typename R>
@@ -240,48 +242,95 @@ void mupdate(const Geom& g, void* x, const VecPtrs& V, int nv, const double* coe
 template <typename R>
 constexpr double orth_tol() { return sizeof(R) == 8 ? 1e-8 : 1e-4; }
 
-// Givens step of GMRES on the new Hessenberg column j (after the check).
-__device__ void gmres_givens_col(DevState* st, int j);
+// leading dimension of the column-major Hessenberg matrix
+__device__ __forceinline__ int ldh() { return kMaxRestart + 1; }
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
 
 // The scalar steps below run in the block that finishes the cross-block
-// reduction of the pass before them (one launch instead of two).
+// reduction of the pass before them (one launch instead of two).  Reduced
+// values stay in LDS; per-vector work runs one lane per basis vector
+// (nv <= kMaxVec < 64), so no thread walks the device state serially.
 __global__ __launch_bounds__(1024) void k_gs_prep(DevState* st, int nv, const double* __restrict__ partial, int nb,
                                                   double scale) {
-  reduce_values(partial, nb, nv, scale, st->red2);
+  __shared__ double val[kMaxVec + 2];
+  reduce_values(partial, nb, nv, scale, val);
   __syncthreads();
-  if (threadIdx.x) return;
-  for (int i = 0; i < nv; ++i) {
-    const double h = st->vs[i] * st->red2[i];
+  const int i = threadIdx.x;
+  if (i < nv) {
+    const double v = st->vs[i], h = v * val[i];
+    st->red2[i] = val[i];
     st->hcol[i] = h;
-    st->coef[i] = h * st->vs[i];
+    st->coef[i] = h * v;
   }
 }
 
+// Orthogonality check of the first pass, then the Givens rotations of GMRES
+// on the new Hessenberg column j = nv - 1 (the second pass, if any, changes
+// only w, not H).
 __global__ __launch_bounds__(1024) void k_gs_check(DevState* st, int nv, double tol, const double* __restrict__ partial,
                                                    int nb, double scale) {
-  reduce_values(partial, nb, nv + 1, scale, st->red);
+  __shared__ double val[kMaxVec + 2];
+  __shared__ double hc[kMaxVec + 1], csl[kMaxRestart], snl[kMaxRestart];
+  reduce_values(partial, nb, nv + 1, scale, val);
   __syncthreads();
-  if (threadIdx.x) return;
-  const double n2 = st->red[nv];
-  double cmax = 0.0, c2 = 0.0;
-  for (int i = 0; i < nv; ++i) {
-    const double c = st->vs[i] * st->red[i];
-    st->ccol[i] = c;
-    st->coef[i] = c * st->vs[i];
-    cmax = fmax(cmax, fabs(c));
-    c2 += c * c;
+  if (threadIdx.x >= 64) return;  // one wavefront from here on
+  const int lane = threadIdx.x, j = nv - 1;
+  double c = 0.0, h = 0.0, v = 0.0;
+  if (lane <= nv) st->red[lane] = val[lane];
+  if (lane < nv) {
+    v = st->vs[lane];
+    h = st->hcol[lane];
+    c = v * val[lane];
+    st->ccol[lane] = c;
+    st->coef[lane] = c * v;
   }
-  if (n2 > 0.0 && cmax <= tol * sqrt(n2)) {
-    st->reorth = 0;
-    st->hn = sqrt(n2);
-  } else {
-    st->reorth = 1;
-    const double h2 = n2 - c2;
-    st->hn = h2 > 0.0 ? sqrt(h2) : 0.0;
-    st->nreorth += 1;
+  if (lane < j) {
+    csl[lane] = st->cs[lane];
+    snl[lane] = st->sn[lane];
   }
-  st->vs[nv] = st->hn > 0.0 ? 1.0 / st->hn : 0.0;
-  gmres_givens_col(st, nv - 1);  // the second pass changes only w, not H
+  const double n2 = val[nv];
+  const double cmax = wave_max(fabs(c)), c2 = wave_sum(c * c);
+  const bool orth = n2 > 0.0 && cmax <= tol * sqrt(n2);
+  const double h2 = n2 - c2;
+  const double hn = orth ? sqrt(n2) : (h2 > 0.0 ? sqrt(h2) : 0.0);
+  if (lane < nv) hc[lane] = h + (orth ? 0.0 : c);  // Hessenberg column before rotation
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if (lane != 0) return;
+  st->reorth = orth ? 0 : 1;
+  if (!orth) st->nreorth += 1;
+  st->hn = hn;
+  st->vs[nv] = hn > 0.0 ? 1.0 / hn : 0.0;
+  // previous rotations, in order, then the new one
+  double* H = st->H;
+  const int ld = ldh();
+  double a = hc[0];
+  for (int i = 0; i < j; ++i) {
+    const double b = hc[i + 1];
+    H[i + j * ld] = csl[i] * a + snl[i] * b;
+    a = -snl[i] * a + csl[i] * b;
+  }
+  const double rr = hypot(a, hn);
+  double cr = 1.0, sr = 0.0;
+  if (rr > 0.0) {
+    cr = a / rr;
+    sr = hn / rr;
+  }
+  st->cs[j] = cr;
+  st->sn[j] = sr;
+  H[j + j * ld] = rr;
+  H[j + 1 + j * ld] = 0.0;
+  const double gj = st->g[j];
+  st->g[j + 1] = -sr * gj;
+  st->g[j] = cr * gj;
+  st->resid = fabs(sr * gj);
+  if (!isfinite(rr) || !isfinite(sr * gj)) st->bad = 1;
 }
 
 template <typename R, int NV>
@@ -323,7 +372,7 @@ __global__ __launch_bounds__(256) void k_gs_update(C2<R>* __restrict__ x, VecPtr
 #pragma unroll
   for (int i = 0; i <= NV; ++i)
     if (i == nv) out[i] = acc[NV];
-  block_store<NV + 1>(out, nv + 1, partial + (size_t)blockIdx.x * kRedStride);
+  block_store<NV + 1>(out, nv + 1, partial + blockIdx.x);
 }
 
 // The second pass is its own kernel symbol so that profiles separate it.
@@ -442,7 +491,7 @@ __global__ __launch_bounds__(256) void k_sub_norm(const C2<R>* __restrict__ b, c
     stg(r + e, rv);
     acc += spec_w(e, M) * ((double)rv.x * rv.x + (double)rv.y * rv.y);
   }
-  block_store<1>(&acc, 1, partial + (size_t)blockIdx.x * kRedStride);
+  block_store<1>(&acc, 1, partial + blockIdx.x);
 }
 template <typename R>
 void sub_norm(const Geom& g, const void* b, const void* q, void* r, double* partial, double* out, hipStream_t s) {
@@ -477,7 +526,7 @@ __global__ __launch_bounds__(256) void k_dot_rMr(const C2<R>* __restrict__ r, Ge
     C2<R> rv = ldg(r + e), mz = precond_at<R>(r, e, g, kind, rho0, nu);
     acc += spec_w(e, g.M) * ((double)rv.x * mz.x + (double)rv.y * mz.y);
   }
-  block_store<1>(&acc, 1, partial + (size_t)blockIdx.x * kRedStride);
+  block_store<1>(&acc, 1, partial + blockIdx.x);
 }
 template <typename R>
 void dot_rMr(const Geom& g, const OpParams& p, const void* r, double* partial, double* out, hipStream_t s) {
@@ -500,7 +549,7 @@ __global__ __launch_bounds__(256) void k_cg_xr(C2<R>* __restrict__ x, C2<R>* __r
     stg(r + e, nr);
     acc += spec_w(e, M) * ((double)nr.x * nr.x + (double)nr.y * nr.y);
   }
-  block_store<1>(&acc, 1, partial + (size_t)blockIdx.x * kRedStride);
+  block_store<1>(&acc, 1, partial + blockIdx.x);
 }
 template <typename R>
 void cg_xr(const Geom& g, void* x, void* r, const void* p, const void* q, const DevState* st, double* partial,
@@ -538,7 +587,7 @@ __global__ __launch_bounds__(256) void k_axpy_norm(C2<R>* __restrict__ r, const 
     stg(r + e, nr);
     acc += spec_w(e, M) * ((double)nr.x * nr.x + (double)nr.y * nr.y);
   }
-  block_store<1>(&acc, 1, partial + (size_t)blockIdx.x * kRedStride);
+  block_store<1>(&acc, 1, partial + blockIdx.x);
 }
 template <typename R>
 void axpy_norm(const Geom& g, void* r, const void* w, const double* a_dev, double sign, double* partial, double* out,
@@ -607,8 +656,6 @@ void project_range(const Geom& g, void* spec, double* removed, hipStream_t st) {
 
 // ------------------------------------------------------- scalar kernels
 
-__device__ __forceinline__ int ldh() { return kMaxRestart + 1; }
-
 __global__ void k_gmres_init(DevState* st, double beta, int m) {
   if (threadIdx.x != 0) return;
   for (int i = 0; i < (kMaxRestart + 1) * kMaxRestart; ++i) st->H[i] = 0.0;
@@ -623,33 +670,6 @@ __global__ void k_gmres_init(DevState* st, double beta, int m) {
 
 // Column j of the Hessenberg matrix: the Gram-Schmidt coefficients h (plus
 // the second-pass corrections c when that pass ran); subdiagonal ||w||.
-__device__ void gmres_givens_col(DevState* st, int j) {
-  double* H = st->H;
-  const int ld = ldh();
-  for (int i = 0; i <= j; ++i) H[i + j * ld] = st->hcol[i] + (st->reorth ? st->ccol[i] : 0.0);
-  const double hn = st->hn;
-  for (int i = 0; i < j; ++i) {
-    double a = H[i + j * ld], b = H[i + 1 + j * ld];
-    H[i + j * ld] = st->cs[i] * a + st->sn[i] * b;
-    H[i + 1 + j * ld] = -st->sn[i] * a + st->cs[i] * b;
-  }
-  const double a = H[j + j * ld];
-  const double rr = hypot(a, hn);
-  double c = 1.0, s = 0.0;
-  if (rr > 0.0) {
-    c = a / rr;
-    s = hn / rr;
-  }
-  st->cs[j] = c;
-  st->sn[j] = s;
-  H[j + j * ld] = rr;
-  H[j + 1 + j * ld] = 0.0;
-  st->g[j + 1] = -s * st->g[j];
-  st->g[j] = c * st->g[j];
-  st->resid = fabs(st->g[j + 1]);
-  if (!isfinite(rr) || !isfinite(st->g[j + 1])) st->bad = 1;
-}
-
 __global__ void k_gmres_backsolve(DevState* st, int k) {
   if (threadIdx.x != 0) return;
   const int ld = ldh();
