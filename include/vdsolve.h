@@ -157,9 +157,10 @@ size_t vd_workspace_bytes(const vd_grid_desc* desc, const vd_solve_opts* opts);
  * pass; 11: the GMRES Gram-Schmidt update pass.  ms[c] = total
  * milliseconds, count[c] = launches, bytes[c] = algorithmic bytes those
  * launches read and wrote (3D grids), for c < nclass (<= 12); any output
- * pointer may be NULL.  Reading resets the totals.  Enabling adds an event
- * pair per timed launch. */
-vd_status vd_profile_enable(vd_grid* grid, int on);
+ * pointer may be NULL.  Reading resets the totals.  `classes` is a bit mask
+ * of the classes to time (bit c = class c; -1 times all, 0 disables); each
+ * timed launch adds an event pair on the grid's stream. */
+vd_status vd_profile_enable(vd_grid* grid, int classes);
 vd_status vd_profile_read(vd_grid* grid, double* ms, long long* count, double* bytes, int nclass);
 
 const char* vd_status_string(vd_status s);

@@ -266,7 +266,9 @@ class Grid:
         return u, info.as_dict()
 
     def profile_enable(self, on=True):
-        _check(lib().vd_profile_enable(self._h, 1 if on else 0), "vd_profile_enable", False)
+        """on: True (every kernel class), False, or a bit mask of classes."""
+        mask = -1 if on is True else (0 if on is False else int(on))
+        _check(lib().vd_profile_enable(self._h, mask), "vd_profile_enable", False)
 
     def profile_read(self, nclass=12):
         ms = (ctypes.c_double * nclass)()

@@ -44,6 +44,7 @@ struct OpWork {
 struct Prof {
   static constexpr int kClasses = 12;
   bool on = false;
+  unsigned mask = 0;  // classes timed while on (bit c = class c)
   struct Pair { int cls; double bytes; hipEvent_t a, b; };
   std::vector<Pair> pending;
   std::vector<hipEvent_t> spare;

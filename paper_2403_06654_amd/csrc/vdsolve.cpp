@@ -40,6 +40,10 @@ using namespace vd;
 // ------------------------------------------------------------ profiling
 
 void Prof::begin(int cls, hipStream_t s, double nbytes) {
+  if (!((mask >> cls) & 1u)) {  // class not selected: no events
+    cur = -1;
+    return;
+  }
   hipEvent_t a;
   if (!spare.empty()) {
     a = spare.back();
@@ -53,6 +57,7 @@ void Prof::begin(int cls, hipStream_t s, double nbytes) {
   cur_a = a;
 }
 void Prof::end(hipStream_t s) {
+  if (cur < 0) return;
   hipEvent_t b;
   if (!spare.empty()) {
     b = spare.back();
@@ -62,6 +67,7 @@ void Prof::end(hipStream_t s) {
   }
   hipEventRecord(b, s);
   pending.push_back(Pair{cur, cur_bytes, cur_a, b});
+  cur = -1;
 }
 void Prof::flush() {
   for (auto& p : pending) {
@@ -958,10 +964,11 @@ size_t vd_workspace_bytes(const vd_grid_desc* d, const vd_solve_opts* opts) {
   return bytes;
 }
 
-vd_status vd_profile_enable(vd_grid* G, int on) {
+vd_status vd_profile_enable(vd_grid* G, int classes) {
   if (!G) return VD_EINVAL;
   G->prof.flush();
-  G->prof.on = on != 0;
+  G->prof.mask = (unsigned)classes & ((1u << Prof::kClasses) - 1u);
+  G->prof.on = G->prof.mask != 0;
   return VD_OK;
 }
 

@@ -47,12 +47,6 @@ template <typename R>
 void mdot(const Geom& g, const void* x, const VecPtrs& V, int nv, bool want_norm, double* partial,
           double* out, hipStream_t s, Prof* prof = nullptr);
 
-// x -= sum_i c_i V_i with c read from `coef` (device); then (optionally)
-// dots of V_i with the updated x and its squared norm, reduced into `out`.
-template <typename R>
-void mupdate(const Geom& g, void* x, const VecPtrs& V, int nv, const double* coef, bool want_dots,
-             double* partial, double* out, hipStream_t s);
-
 // GMRES step: orthogonalise w against the stored basis V_0..V_{nv-1}
 // (v_i = vs[i] V_i) in place; classical Gram-Schmidt with a measured
 // orthogonality check and a conditional second pass.  Leaves the
