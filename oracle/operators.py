@@ -24,11 +24,12 @@ of the same operator with rho replaced by the constant rho0 -- diagonal in
 Fourier space; the pressure one is the pseudo-inverse (zero on the
 nullspace modes).
 
+Modified pressure (eq. VDINSE.Krho): see the K_rho section below.
+
 Wall-bounded 2D pressure (x periodic, z Chebyshev with Neumann walls) is
-the symmetric weak form
-    A u = D_x^T (W a D_x u) + D_z^T (W a D_z u),   b = -W f,
-with W = h_x w_j (Clenshaw-Curtis weights); its constant-density inverse is
-built per x wavenumber by dense linear algebra.
+the symmetric weak form of FourierChebyshev2D (Legendre-Gauss-Lobatto
+quadrature of the Chebyshev nodal interpolant); its constant-density
+inverse is built per x wavenumber by dense linear algebra.
 """
 import numpy as np
 
@@ -154,6 +155,70 @@ def project_range(b, basis):
     for e in basis:
         out = out - (np.vdot(e, b) / np.vdot(e, e)) * e
     return out, float(np.linalg.norm(b - out))
+
+
+# ------------------------------------------ modified pressure (K_rho form)
+#
+# Sec. 4.2, eq. VDINSE.Krho: with Phi = phi / sqrt(rho) the pressure equation
+# L_rho phi = f becomes the modified Helmholtz equation
+#     K_rho Phi = Lap Phi + c Phi = sqrt(rho) f,
+#     c = Lap(rho) / (2 rho) - (3/4) |grad rho|^2 / rho^2,
+# preconditioned by the pseudo-inverse of the Laplacian (the inverse of K_rho
+# at constant density).  Expanding Lap(rho^-1/2) shows c = -Lap(psi) / psi
+# with psi = rho^-1/2; evaluated in that form with the spectral Laplacian,
+# psi is an exact null vector of the discrete K_rho (continuum: phi constant
+# <=> Phi proportional to psi), so the singular system keeps its structure.
+# The solver works with A_K = -K_rho (symmetric) and b = -sqrt(rho) f,
+# projected onto psi's orthogonal complement (the range of A_K).
+
+
+def k_coefficient(rho, lengths=None):
+    """c(x) of eq. VDINSE.Krho as -Lap(psi) / psi, psi = rho^-1/2."""
+    psi = rho ** -0.5
+    return -laplacian(psi, lengths) / psi
+
+
+def k_coefficient_literal(rho, lengths=None):
+    """c(x) term by term as printed in eq. VDINSE.Krho (spectral derivatives)."""
+    lengths = _axis_len(rho.shape, lengths)
+    g2 = sum(deriv(rho, d, lengths[d]) ** 2 for d in range(rho.ndim))
+    return laplacian(rho, lengths) / (2.0 * rho) - 0.75 * g2 / rho ** 2
+
+
+def K_rho(u, c, lengths=None):
+    """The paper's modified pressure operator  Lap u + c u."""
+    return laplacian(u, lengths) + c * u
+
+
+def apply_pressure_k(u, c, lengths=None):
+    """A_K u = -K_rho u."""
+    return -K_rho(u, c, lengths)
+
+
+def precond_pressure_k(r, lengths=None):
+    """Pseudo-inverse of -Lap (the inverse of A_K at constant density):
+    r_hat / |k|^2 (Nyquist kept), zero on the constant mode."""
+    lengths = _axis_len(r.shape, lengths)
+    ksq = np.zeros(r.shape)
+    for d, (n, ln) in enumerate(zip(r.shape, lengths)):
+        shp = [1] * r.ndim
+        shp[d] = n
+        ksq = ksq + grids.fourier_k(n, ln).reshape(shp) ** 2
+    sym = np.zeros_like(ksq)
+    sym[ksq > 0] = 1.0 / ksq[ksq > 0]
+    return np.real(np.fft.ifftn(sym * np.fft.fftn(r)))
+
+
+def pressure_k_rhs(f, rho):
+    """b = -sqrt(rho) f projected onto the range of A_K (orthogonal to psi);
+    returns (b, norm of the removed component)."""
+    return project_range(-np.sqrt(rho) * f, [rho ** -0.5])
+
+
+def pressure_k_recover(Phi, rho):
+    """phi = sqrt(rho) Phi, returned in the gauge of the L_rho solve
+    (orthogonal to the nullspace of L_rho: zero mean, no checkerboard)."""
+    return project_range(np.sqrt(rho) * Phi, nullspace_basis(Phi.shape))[0]
 
 
 # ------------------------------------------- Fourier (x) x Chebyshev (z)

@@ -75,3 +75,31 @@ def test_rmr_wrong_step_is_caught(monkeypatch):
                 "rel_residual": np.linalg.norm(r) / np.linalg.norm(b)}
     monkeypatch.setitem(tk.SOLVERS, "rmr", bad_rmr)
     _fails(tk.test_solvers_match_dense_minnorm, (32,), "rmr")
+
+
+# ------------------------------------------------ modified pressure (K_rho)
+
+def test_k_coefficient_sign_error_is_caught(monkeypatch):
+    from tests import test_oracle_krho as tkr
+    orig = operators.laplacian
+    monkeypatch.setattr(operators, "k_coefficient",
+                        lambda rho, L=None: orig(rho ** -0.5, L) / rho ** -0.5)   # + instead of -
+    _fails(tkr.test_k_matches_dense_brute_force, (8, 12), (2 * np.pi, 3.0))
+    _fails(tkr.test_coefficient_is_the_papers_expression)
+
+
+def test_k_literal_coefficient_error_is_caught(monkeypatch):
+    from tests import test_oracle_krho as tkr
+    def wrong(rho, L=None):   # 3/4 replaced by 1/2
+        Ls = operators._axis_len(rho.shape, L)
+        g2 = sum(operators.deriv(rho, d, Ls[d]) ** 2 for d in range(rho.ndim))
+        return operators.laplacian(rho, Ls) / (2.0 * rho) - 0.5 * g2 / rho ** 2
+    monkeypatch.setattr(operators, "k_coefficient_literal", wrong)
+    _fails(tkr.test_coefficient_is_the_papers_expression)
+
+
+def test_k_recovery_without_sqrt_rho_is_caught(monkeypatch):
+    from tests import test_oracle_krho as tkr
+    monkeypatch.setattr(operators, "pressure_k_recover",
+                        lambda Phi, rho: operators.project_range(Phi, operators.nullspace_basis(Phi.shape))[0])
+    _fails(tkr.test_k_solution_is_the_l_solution)
