@@ -174,6 +174,31 @@ def csrc_hash():
     return h.hexdigest()[:16]
 
 
+def pressure_forms(grid, rho_dev, f_dev, torch):
+    """The paper's modified pressure form (Sec. 4.2, eq. VDINSE.Krho) beside
+    the direct one on the same 256^3 pressure problems (FP64 GMRES(30), rtol
+    1e-10, one solve per density after one untimed solve): iterations,
+    milliseconds per solve and the relative difference of the two answers."""
+    out = {}
+    for i, rj in enumerate(RJS):
+        grid.set_density(rho_dev[i])
+        rec = {}
+        sol = {}
+        for form in ("L", "K"):
+            grid.solve_pressure(f_dev, formulation=form)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            p, info = grid.solve_pressure(f_dev, formulation=form)
+            torch.cuda.synchronize()
+            rec[form] = {"iterations": info["iterations"], "ms": round(1e3 * (time.perf_counter() - t0), 2),
+                         "rel_residual": info["rel_residual"]}
+            sol[form] = p
+        rec["rel_difference"] = float(torch.linalg.vector_norm(sol["K"] - sol["L"]) /
+                                      torch.linalg.vector_norm(sol["L"]))
+        out[f"rj={rj}"] = rec
+    return out
+
+
 def cpu_baseline(inp):
     """The oracle as it stands, on the host: GMRES on the same 256^3 pressure
     problem (rj = 3), stopped after a fixed number of iterations."""
@@ -469,6 +494,8 @@ def main():
     if not args.no_fp32:
         print(f"bench: FP32+refine leg", file=sys.stderr, flush=True)
         r32, _ = run_leg(grid, rho_dev, f_dev, g_dev, "fp32_refine", args.steps, args.warmup, torch)
+    print("bench: pressure forms (L_rho vs K_rho)", file=sys.stderr, flush=True)
+    forms = pressure_forms(grid, rho_dev, f_dev, torch)
     grid.close()
 
     cpu = None
@@ -505,6 +532,7 @@ def main():
         "operator_apply": op,
         "passes": passes,
         "passes_timed_over": "the warm-up steps (every class event-timed); the timed steps time only the roofline class",
+        "pressure_forms": forms,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

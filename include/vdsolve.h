@@ -63,7 +63,10 @@ typedef enum {
 typedef enum { VD_FOURIER = 0, VD_CHEB_GL = 1 } vd_basis;
 typedef enum { VD_GMRES = 0, VD_CG = 1, VD_RMR = 2 } vd_solver;
 typedef enum { VD_FP64 = 0, VD_FP32_REFINE = 1 } vd_precision;
-typedef enum { VD_OP_PRESSURE = 0, VD_OP_HELMHOLTZ = 1 } vd_op_kind;
+typedef enum { VD_OP_PRESSURE = 0, VD_OP_HELMHOLTZ = 1, VD_OP_PRESSURE_K = 2 } vd_op_kind;
+/* Pressure formulation (Sec. 4.2): L_rho phi = f directly, or the modified
+ * form K_rho Phi = sqrt(rho) f with Phi = phi / sqrt(rho) (eq. VDINSE.Krho). */
+typedef enum { VD_FORM_L = 0, VD_FORM_K = 1 } vd_pressure_form;
 
 typedef struct {
   int ndim;         /* 1, 2 or 3 */
@@ -84,6 +87,7 @@ typedef struct {
   int max_outer;     /* FP32_REFINE: cap on refinement steps */
   double rho0;       /* preconditioner density; NaN = mean of rho */
   int use_x0;        /* 1: the output array holds the initial guess on entry */
+  int formulation;   /* pressure solves: vd_pressure_form (default VD_FORM_L) */
 } vd_solve_opts;
 
 typedef struct {
@@ -99,7 +103,8 @@ typedef struct {
 typedef struct vd_grid vd_grid;
 
 /* Fill opts with the defaults: GMRES(30), rtol 1e-10, max_iter 2000,
- * precond 1, FP64, inner_rtol 1e-5, max_outer 10, rho0 = NaN, use_x0 0. */
+ * precond 1, FP64, inner_rtol 1e-5, max_outer 10, rho0 = NaN, use_x0 0,
+ * formulation VD_FORM_L. */
 void vd_default_opts(vd_solve_opts* opts);
 
 /* Create a grid and its device resources on `stream` (0 = null stream).
@@ -116,14 +121,19 @@ vd_status vd_set_density(vd_grid* grid, const double* rho);
 
 /* y = A x for the operator `kind` (physical in, physical out, device FP64):
  * VD_OP_PRESSURE: A = -L_rho (symmetric positive semi-definite);
- * VD_OP_HELMHOLTZ: A = rho - dt_nu Lap.  precision VD_FP32_REFINE evaluates
- * the operator in FP32 (spectral vectors and coefficients rounded to FP32).
- * Used for per-kernel parity and timing. */
+ * VD_OP_HELMHOLTZ: A = rho - dt_nu Lap;
+ * VD_OP_PRESSURE_K: A = -K_rho = -Lap - c, c = Lap(rho)/(2 rho)
+ *   - 3/4 |grad rho|^2 / rho^2 (eq. VDINSE.Krho), evaluated as
+ *   c = -Lap(psi)/psi with psi = rho^-1/2 so that psi is an exact null vector
+ *   (Lap spectral, Nyquist kept; dt_nu ignored; Fourier grids only).
+ * precision VD_FP32_REFINE evaluates the operator in FP32 (spectral vectors
+ * and coefficients rounded to FP32).  Used for per-kernel parity and timing. */
 vd_status vd_apply_operator(vd_grid* grid, int kind, int precision, double dt_nu, const double* x, double* y);
 
 /* z = M^-1 r with M the constant-density operator at rho0 (NaN = mean rho):
  * pressure: the pseudo-inverse (zero on the nullspace); Helmholtz: the
- * inverse of rho0 - dt_nu Lap. */
+ * inverse of rho0 - dt_nu Lap; VD_OP_PRESSURE_K: the pseudo-inverse of -Lap
+ * (zero on the constant mode; rho0 and dt_nu ignored). */
 vd_status vd_apply_precond(vd_grid* grid, int kind, int precision, double dt_nu, double rho0, const double* r,
                            double* z);
 
@@ -134,7 +144,16 @@ vd_status vd_apply_precond(vd_grid* grid, int kind, int precision, double dt_nu,
  * are removed and their norm reported in info->rhs_null_norm); the
  * solution returned is the one orthogonal to that nullspace (zero mean).
  * The residual is measured in the Euclidean norm of grid values.
- * opts == NULL means defaults; info may be NULL. */
+ * With opts->formulation = VD_FORM_K (Fourier grids; Sec. 4.2) the solve
+ * runs on Phi = p / sqrt(rho): A = -K_rho, b = -sqrt(rho) f with its
+ * component along rho^-1/2 removed (that norm goes to rhs_null_norm), the
+ * preconditioner is the pseudo-inverse of -Lap, info->rel_residual is that
+ * system's; p = sqrt(rho) Phi is returned with zero mean (removing a
+ * constant from p removes a multiple of rho^-1/2, a null vector, from Phi);
+ * modulo the checkerboard modes, which L_rho does not see, it agrees with
+ * the direct form's solution up to discretisation error.
+ * opts == NULL means defaults; info may be NULL.  VD_ENOTSUP: VD_FORM_K on
+ * a Chebyshev grid. */
 vd_status vd_solve_pressure(vd_grid* grid, const double* f, double* p, const vd_solve_opts* opts,
                             vd_solve_info* info);
 

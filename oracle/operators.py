@@ -216,9 +216,12 @@ def pressure_k_rhs(f, rho):
 
 
 def pressure_k_recover(Phi, rho):
-    """phi = sqrt(rho) Phi, returned in the gauge of the L_rho solve
-    (orthogonal to the nullspace of L_rho: zero mean, no checkerboard)."""
-    return project_range(np.sqrt(rho) * Phi, nullspace_basis(Phi.shape))[0]
+    """phi = sqrt(rho) Phi with its mean removed (Sec. 4.2 gauge).  Removing
+    a constant from phi removes a multiple of psi from Phi, which K_rho
+    annihilates; the checkerboard modes (null for L_rho, not for K_rho) are
+    kept as the K_rho solution has them."""
+    phi = np.sqrt(rho) * Phi
+    return phi - phi.mean()
 
 
 # ------------------------------------------- Fourier (x) x Chebyshev (z)

@@ -15,7 +15,10 @@ LIB_PATH = os.path.join(HERE, "libvdsolve.so")
 VD_OK, VD_NOT_CONVERGED = 0, 1
 VD_GMRES, VD_CG, VD_RMR = 0, 1, 2
 VD_FP64, VD_FP32_REFINE = 0, 1
-VD_OP_PRESSURE, VD_OP_HELMHOLTZ = 0, 1
+VD_OP_PRESSURE, VD_OP_HELMHOLTZ, VD_OP_PRESSURE_K = 0, 1, 2
+VD_FORM_L, VD_FORM_K = 0, 1
+OP_KINDS = {"pressure": VD_OP_PRESSURE, "helmholtz": VD_OP_HELMHOLTZ, "pressure_k": VD_OP_PRESSURE_K}
+FORMULATIONS = {"L": VD_FORM_L, "K": VD_FORM_K}
 SOLVERS = {"gmres": VD_GMRES, "cg": VD_CG, "rmr": VD_RMR}
 PRECISIONS = {"fp64": VD_FP64, "fp32_refine": VD_FP32_REFINE, "fp32": VD_FP32_REFINE}
 
@@ -29,7 +32,7 @@ class vd_solve_opts(ctypes.Structure):
     _fields_ = [("solver", ctypes.c_int), ("restart", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("max_iter", ctypes.c_int), ("precond", ctypes.c_int), ("precision", ctypes.c_int),
                 ("inner_rtol", ctypes.c_double), ("max_outer", ctypes.c_int), ("rho0", ctypes.c_double),
-                ("use_x0", ctypes.c_int)]
+                ("use_x0", ctypes.c_int), ("formulation", ctypes.c_int)]
 
 
 class vd_solve_info(ctypes.Structure):
@@ -153,7 +156,7 @@ def dense_matmul(A, B, precision="fp64"):
 
 
 def make_opts(solver="gmres", restart=30, rtol=1e-10, max_iter=2000, precond=True, precision="fp64",
-              inner_rtol=1e-5, max_outer=10, rho0=float("nan"), use_x0=False):
+              inner_rtol=1e-5, max_outer=10, rho0=float("nan"), use_x0=False, formulation="L"):
     o = vd_solve_opts()
     lib().vd_default_opts(ctypes.byref(o))
     o.solver = SOLVERS[solver] if isinstance(solver, str) else int(solver)
@@ -166,6 +169,7 @@ def make_opts(solver="gmres", restart=30, rtol=1e-10, max_iter=2000, precond=Tru
     o.max_outer = int(max_outer)
     o.rho0 = float(rho0)
     o.use_x0 = 1 if use_x0 else 0
+    o.formulation = FORMULATIONS[formulation] if isinstance(formulation, str) else int(formulation)
     return o
 
 
@@ -227,7 +231,7 @@ class Grid:
     def apply_operator(self, kind, x, precision="fp64", nu=0.0, out=None):
         import torch
         y = out if out is not None else torch.empty_like(x)
-        k = VD_OP_PRESSURE if kind == "pressure" else VD_OP_HELMHOLTZ
+        k = OP_KINDS[kind]
         _check(lib().vd_apply_operator(self._h, k, PRECISIONS[precision], float(nu), _dev_f64(x, self.shape, "x"),
                                        _dev_f64(y, self.shape, "y")), "vd_apply_operator", False)
         return y
@@ -235,7 +239,7 @@ class Grid:
     def apply_precond(self, kind, r, precision="fp64", nu=0.0, rho0=float("nan"), out=None):
         import torch
         z = out if out is not None else torch.empty_like(r)
-        k = VD_OP_PRESSURE if kind == "pressure" else VD_OP_HELMHOLTZ
+        k = OP_KINDS[kind]
         _check(lib().vd_apply_precond(self._h, k, PRECISIONS[precision], float(nu), float(rho0),
                                       _dev_f64(r, self.shape, "r"), _dev_f64(z, self.shape, "z")),
                "vd_apply_precond", False)

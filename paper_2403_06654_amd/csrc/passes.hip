@@ -477,6 +477,35 @@ __global__ __launch_bounds__(256) void k_precond(const C2<R>* __restrict__ r, C2
   }
 }
 
+// ------------------------------------------------- spectral Laplacian
+
+// y = Lap x on a packed spectrum (symbol -|k|^2, Nyquist kept; the kx = 0
+// slot mixes with its mirror because its two halves differ).  Out of place.
+__global__ __launch_bounds__(256) void k_lap_packed(const C2<double>* __restrict__ x, C2<double>* __restrict__ y,
+                                                    Geom g, size_t n) {
+  size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const unsigned ue = (unsigned)e, q = ue / (unsigned)g.M;  // at most 2^29 slots
+  const int kx = (int)(ue - q * (unsigned)g.M);
+  const int ky = (int)(q % (unsigned)g.ny), kz = (int)(q / (unsigned)g.ny);
+  const double kyz = ksq_yz<double>(ky, kz, g);
+  const double kxp = (double)kx * g.sx, kn = (double)g.M * g.sx;
+  const C2<double> v = ldg(x + e);
+  if (kx == 0) {
+    const int kym = (g.ny - ky) % g.ny, kzm = (g.nz - kz) % g.nz;
+    const C2<double> pm = ldg(x + ((size_t)kzm * g.ny + kym) * g.M);
+    stg(y + e, diag_packed(v, pm, -kyz, -(kyz + kn * kn)));
+  } else {
+    stg(y + e, cscale(v, -(kyz + kxp * kxp)));
+  }
+}
+
+void lap_packed(const Geom& g, const void* x, void* y, hipStream_t st) {
+  const size_t n = (size_t)g.nz * g.ny * g.M;
+  hipLaunchKernelGGL(k_lap_packed, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (const C2<double>*)x,
+                     (C2<double>*)y, g, n);
+}
+
 // ------------------------------------------------------------ launchers
 
 template <typename R, int MODE, int L>

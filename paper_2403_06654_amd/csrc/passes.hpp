@@ -77,6 +77,9 @@ void fwd_transform(const Geom& g, const double* phys, void* spec, void* work, co
 void inv_transform(const Geom& g, const void* spec, double* phys, void* work, const void* twtab,
                    hipStream_t st);
 
+// y = Lap x on a packed FP64 spectrum (symbol -|k|^2, Nyquist kept); x != y.
+void lap_packed(const Geom& g, const void* x, void* y, hipStream_t st);
+
 // Twiddle tables: entries [L, 2L) hold exp(-2 pi i k / L) for L = 1..4096.
 constexpr int kTwEntries = 8192;
 

@@ -37,7 +37,9 @@ __device__ __forceinline__ C2<R> diag_packed(C2<R> P, C2<R> Pm, R g0, R gN) {
 }
 
 // Helmholtz preconditioner value g(k) = 1 / (rho0 + nu |k|^2) and the
-// operator's diagonal part nu |k|^2 g(k), for both halves of a slot.
+// operator's diagonal part nu |k|^2 g(k), for both halves of a slot.  With
+// rho0 = 0 (the modified pressure form, preconditioned by the Laplacian's
+// pseudo-inverse) the k = 0 mode gets g = 0.
 template <typename R>
 struct HelmMult {
   R g0, gN;  // for kx (slot) and, at slot 0, kx = nx/2
@@ -50,8 +52,9 @@ __device__ __forceinline__ HelmMult<R> mult_helm(int kx, int ky, int kz, const G
   kx2 *= kx2;
   R kn = R(g.M) * R(g.sx);
   R k0 = kyz + kx2, kN = kyz + kn * kn;
-  R g0 = R(1) / (R(rho0) + R(nu) * k0);
-  R gN = R(1) / (R(rho0) + R(nu) * kN);
+  const R d0 = R(rho0) + R(nu) * k0, dN = R(rho0) + R(nu) * kN;
+  R g0 = d0 > R(0) ? R(1) / d0 : R(0);
+  R gN = dN > R(0) ? R(1) / dN : R(0);
   if (times_nuk2) {
     g0 *= R(nu) * k0;
     gN *= R(nu) * kN;

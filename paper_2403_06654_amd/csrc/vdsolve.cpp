@@ -117,12 +117,18 @@ struct vd_grid {
   double* c2coef64 = nullptr; // h_x w_LGL / rho_L
   float* c2coef32 = nullptr;
   int* dbad = nullptr;
+  // modified pressure form (eq. VDINSE.Krho): kc = -c, FP64 and FP32, and
+  // the squared norm of psi = rho^-1/2 (its spectrum is buffer B_PSI)
+  double* kc64 = nullptr;
+  float* kc32 = nullptr;
+  bool kc_valid = false;
+  double psi2 = 0;
 };
 
 namespace {
 
 enum Role {
-  B_B = 0, B_X, B_R, B_TMP, B_T0, B_T1, B_T2, B_W, B_P, B_Q, B_Z, B_V0 = 32,
+  B_B = 0, B_X, B_R, B_TMP, B_T0, B_T1, B_T2, B_W, B_P, B_Q, B_Z, B_PSI, B_V0 = 32,
 };
 
 struct DevErr {};
@@ -231,10 +237,14 @@ double read_scalar(vd_grid* G, const double* dptr) {
 
 // ----------------------------------------------------------- solver core
 
+// Pointwise coefficient of the operator's x pass.
+enum CoefSel { COEF_INV_RHO = 0, COEF_RHO, COEF_KC };
+
 struct SolveCfg {
   int solver, restart, max_iter;
   double rtol;
   OpParams op;  // kind, rho0, nu, precond
+  int coef = -1;  // CoefSel; -1: from op.kind (1/rho for pressure, rho for Helmholtz)
   // Inner solve of iterative refinement: x starts at zero, the method stops
   // on its own residual estimate (GMRES: at most kInnerCycles cycles) and
   // never on an FP32 true residual, whose rounding floor can sit near the
@@ -263,11 +273,12 @@ struct Krylov {
   Krylov(vd_grid* G_, int prec_, const SolveCfg& c)
       : G(G_), prec(prec_), g(G_->g), cfg(c) {
     const bool helm = cfg.op.kind == OP_HELMHOLTZ;
+    const int sel = cfg.coef >= 0 ? cfg.coef : (helm ? COEF_RHO : COEF_INV_RHO);
     if (prec == 64) {
-      coef = helm ? (const void*)G->rho : (const void*)G->a64;
+      coef = sel == COEF_KC ? (const void*)G->kc64 : sel == COEF_RHO ? (const void*)G->rho : (const void*)G->a64;
       tw = G->tw64;
     } else {
-      coef = helm ? (const void*)G->rho32 : (const void*)G->a32;
+      coef = sel == COEF_KC ? (const void*)G->kc32 : sel == COEF_RHO ? (const void*)G->rho32 : (const void*)G->a32;
       tw = G->tw32;
     }
     if (g.cheb) {
@@ -483,9 +494,9 @@ struct Krylov {
 };
 
 // Solve A x = b in spectral space (b, x FP64 buffers of the grid).
-SolveOut solve_spectral(vd_grid* G, const vd_solve_opts& o, const OpParams& op, void* b64, void* x64,
+SolveOut solve_spectral(vd_grid* G, const vd_solve_opts& o, const OpParams& op, int coef, void* b64, void* x64,
                         double bnorm, int* refinements) {
-  SolveCfg cfg{o.solver, o.restart, o.max_iter, o.rtol, op};
+  SolveCfg cfg{o.solver, o.restart, o.max_iter, o.rtol, op, coef};
   *refinements = 0;
   if (bnorm == 0.0) {
     ck(hipMemsetAsync(x64, 0, G->nspec * 16, G->st));
@@ -544,6 +555,30 @@ double host_norm_of(vd_grid* G, const void* spec64) {
   return std::sqrt(std::fmax(read_scalar(G, &G->dst->nrm2), 0.0));
 }
 
+// The modified pressure form's pointwise coefficient, -c = Lap(psi)/psi with
+// psi = rho^-1/2 (spectral Laplacian, Nyquist kept): computed once per
+// density, with psi's spectrum and squared norm kept for the projection of
+// right-hand sides onto the operator's range.
+void ensure_kcoef(vd_grid* G) {
+  if (G->kc_valid) return;
+  if (!G->kc64) {
+    ck(hipMalloc(&G->kc64, G->nreal * sizeof(double)));
+    ck(hipMalloc(&G->kc32, G->nreal * sizeof(float)));
+  }
+  double* psi = (double*)buf(G, 64, B_TMP);
+  void* psih = buf(G, 64, B_PSI);
+  void* laph = buf(G, 64, B_T0);
+  double* lap = (double*)buf(G, 64, B_R);
+  rho_sqrt_mul(G->rho, nullptr, psi, true, 1.0, G->nreal, G->st);  // psi = rho^-1/2
+  fwd_transform(G->g, psi, psih, nullptr, G->tw64, G->st);
+  lap_packed(G->g, psih, laph, G->st);
+  inv_transform(G->g, laph, lap, buf(G, 64, B_TMP), G->tw64, G->st);
+  kcoef_finish(G->rho, lap, G->kc64, G->kc32, G->nreal, G->st);
+  const double pn = host_norm_of(G, psih);
+  G->psi2 = pn * pn;
+  G->kc_valid = true;
+}
+
 bool opts_ok(const vd_solve_opts& o) {
   if (o.solver < 0 || o.solver > 2) return false;
   if (o.restart < 1 || o.restart > kMaxRestart) return false;
@@ -551,6 +586,7 @@ bool opts_ok(const vd_solve_opts& o) {
   if (o.precision != VD_FP64 && o.precision != VD_FP32_REFINE) return false;
   if (o.precision == VD_FP32_REFINE && (!(o.inner_rtol > 0.0) || o.inner_rtol >= 1.0 || o.max_outer < 1))
     return false;
+  if (o.formulation != VD_FORM_L && o.formulation != VD_FORM_K) return false;
   return true;
 }
 
@@ -636,6 +672,7 @@ void vd_default_opts(vd_solve_opts* o) {
   o->max_outer = 10;
   o->rho0 = NAN;
   o->use_x0 = 0;
+  o->formulation = VD_FORM_L;
 }
 
 const char* vd_status_string(vd_status s) {
@@ -715,6 +752,8 @@ vd_status vd_grid_destroy(vd_grid* G) {
   hipFree(G->c2coef64);
   hipFree(G->c2coef32);
   hipFree(G->dbad);
+  hipFree(G->kc64);
+  hipFree(G->kc32);
   hipFree(G->dst);
   if (G->hst) hipHostFree(G->hst);
   delete G;
@@ -722,6 +761,7 @@ vd_status vd_grid_destroy(vd_grid* G) {
 }
 
 static vd_status set_density_impl(vd_grid* G, void* ctx) {
+  G->kc_valid = false;
   const double* rho = (const double*)ctx;
   if (!G->rho) {
     ck(hipMalloc(&G->rho, G->nreal * sizeof(double)));
@@ -779,13 +819,21 @@ static vd_status apply_impl(vd_grid* G, void* c) {
   void* s0 = buf(G, 64, B_B);
   void* s1 = buf(G, 64, B_X);
   fwd_transform(G->g, a->x, s0, nullptr, G->tw64, G->st);
+  if (G->g.cheb && a->kind != VD_OP_PRESSURE) return VD_ENOTSUP;
   OpParams p{};
   p.kind = a->kind;
   p.rho0 = std::isnan(a->rho0) ? G->rho_mean : a->rho0;
   p.nu = a->nu;
   p.precond = a->is_prec;
-  SolveCfg cfg{VD_GMRES, 1, 1, 1.0, p};
-  if (G->g.cheb && a->kind != VD_OP_PRESSURE) return VD_ENOTSUP;
+  int coef = -1;
+  if (a->kind == VD_OP_PRESSURE_K) {  // Helmholtz skeleton: -c in the x pass, |k|^2, pseudo-inverse of -Lap
+    if (!a->is_prec) ensure_kcoef(G);
+    p.kind = OP_HELMHOLTZ;
+    p.rho0 = 0.0;
+    p.nu = 1.0;
+    coef = COEF_KC;
+  }
+  SolveCfg cfg{VD_GMRES, 1, 1, 1.0, p, coef};
   if (a->precision == VD_FP64) {
     if (a->is_prec && G->g.cheb) c2_precond<double>(G->g, G->cd, p.rho0, s0, s1, buf(G, 64, B_T0), G->st);
     else if (a->is_prec) precond_apply<double>(G->g, p, s0, s1, G->st);
@@ -813,7 +861,7 @@ static vd_status apply_impl(vd_grid* G, void* c) {
 
 vd_status vd_apply_operator(vd_grid* G, int kind, int precision, double nu, const double* x, double* y) {
   if (!G || !x || !y) return VD_EINVAL;
-  if (kind != VD_OP_PRESSURE && kind != VD_OP_HELMHOLTZ) return VD_EINVAL;
+  if (kind != VD_OP_PRESSURE && kind != VD_OP_HELMHOLTZ && kind != VD_OP_PRESSURE_K) return VD_EINVAL;
   if (precision != VD_FP64 && precision != VD_FP32_REFINE) return VD_EINVAL;
   if (!G->has_rho) return VD_EINVAL;
   if (!(nu >= 0.0)) return VD_EINVAL;
@@ -824,7 +872,7 @@ vd_status vd_apply_operator(vd_grid* G, int kind, int precision, double nu, cons
 vd_status vd_apply_precond(vd_grid* G, int kind, int precision, double nu, double rho0, const double* r,
                            double* z) {
   if (!G || !r || !z) return VD_EINVAL;
-  if (kind != VD_OP_PRESSURE && kind != VD_OP_HELMHOLTZ) return VD_EINVAL;
+  if (kind != VD_OP_PRESSURE && kind != VD_OP_HELMHOLTZ && kind != VD_OP_PRESSURE_K) return VD_EINVAL;
   if (precision != VD_FP64 && precision != VD_FP32_REFINE) return VD_EINVAL;
   if (std::isnan(rho0) && !G->has_rho) return VD_EINVAL;
   if (!std::isnan(rho0) && !(rho0 > 0.0)) return VD_EINVAL;
@@ -843,6 +891,19 @@ struct SolveCtx {
   vd_solve_info info;
 };
 
+// Remove from the spectrum b its component along psi = rho^-1/2 (the null
+// vector of the modified pressure operator); returns the removed norm.
+double project_psi(vd_grid* G, void* b64) {
+  void* psih = buf(G, 64, B_PSI);
+  VecPtrs P{};
+  P.p[0] = psih;
+  mdot<double>(G->g, b64, P, 1, false, G->partial, G->dsmall + 2, G->st);
+  const double dot = read_scalar(G, G->dsmall + 2);
+  OpParams plain{};
+  precond_axpy<double>(G->g, plain, b64, psih, nullptr, -dot / G->psi2, G->st);
+  return std::fabs(dot) / std::sqrt(G->psi2);
+}
+
 static vd_status solve_impl(vd_grid* G, void* c) {
   SolveCtx* s = (SolveCtx*)c;
   auto t0 = std::chrono::steady_clock::now();
@@ -851,6 +912,19 @@ static vd_status solve_impl(vd_grid* G, void* c) {
   op.rho0 = std::isnan(s->o.rho0) ? G->rho_mean : s->o.rho0;
   op.nu = s->nu;
   op.precond = s->o.precond ? 1 : 0;
+  // Modified pressure form (Sec. 4.2, eq. VDINSE.Krho): unknown Phi =
+  // phi / sqrt(rho), A = -K_rho = -Lap - c on the Helmholtz skeleton (x-pass
+  // coefficient -c, diagonal |k|^2, preconditioner the pseudo-inverse of
+  // -Lap), b = -sqrt(rho) f projected onto the range (orthogonal to psi).
+  const bool kform = s->kind == VD_OP_PRESSURE && s->o.formulation == VD_FORM_K;
+  int coef = -1;
+  if (kform) {
+    ensure_kcoef(G);
+    op.kind = OP_HELMHOLTZ;
+    op.rho0 = 0.0;
+    op.nu = 1.0;
+    coef = COEF_KC;
+  }
   void* b64 = buf(G, 64, B_B);
   void* x64 = buf(G, 64, B_X);
   vd_status worst = VD_OK;
@@ -864,15 +938,24 @@ static vd_status solve_impl(vd_grid* G, void* c) {
       c2_rhs(G->g, G->cd, tmp, b64, G->st);
       c2_project(G->g, b64, G->dsmall, G->st);
       s->info.rhs_null_norm = std::fmax(s->info.rhs_null_norm, read_scalar(G, G->dsmall));
+    } else if (kform) {
+      double* t = (double*)buf(G, 64, B_TMP);
+      rho_sqrt_mul(G->rho, f, t, false, -1.0, G->nreal, G->st);
+      fwd_transform(G->g, t, b64, nullptr, G->tw64, G->st);
+      s->info.rhs_null_norm = std::fmax(s->info.rhs_null_norm, project_psi(G, b64));
     } else {
       fwd_transform(G->g, f, b64, nullptr, G->tw64, G->st);
     }
-    if (s->kind == VD_OP_PRESSURE && !G->g.cheb) {
+    if (s->kind == VD_OP_PRESSURE && !G->g.cheb && !kform) {
       project_range(G->g, b64, G->dsmall, G->st);
       scale<double>(G->g, b64, nullptr, -1.0, G->st);  // A = -L_rho, b = -f
       s->info.rhs_null_norm = std::fmax(s->info.rhs_null_norm, read_scalar(G, G->dsmall));
     }
-    if (s->o.use_x0) {
+    if (s->o.use_x0 && kform) {  // Phi_0 = phi_0 / sqrt(rho)
+      double* t = (double*)buf(G, 64, B_TMP);
+      rho_sqrt_mul(G->rho, x, t, true, 1.0, G->nreal, G->st);
+      fwd_transform(G->g, t, x64, nullptr, G->tw64, G->st);
+    } else if (s->o.use_x0) {
       fwd_transform(G->g, x, x64, nullptr, G->tw64, G->st);
       if (G->g.cheb) c2_project(G->g, x64, G->dsmall + 1, G->st);
       else if (s->kind == VD_OP_PRESSURE) project_range(G->g, x64, G->dsmall + 1, G->st);
@@ -881,11 +964,18 @@ static vd_status solve_impl(vd_grid* G, void* c) {
     }
     double bnorm = host_norm_of(G, b64);
     int refin = 0;
-    SolveOut so = solve_spectral(G, s->o, op, b64, x64, bnorm, &refin);
+    SolveOut so = solve_spectral(G, s->o, op, coef, b64, x64, bnorm, &refin);
     // the Chebyshev preconditioner's pseudo-inverse is not Euclidean-orthogonal
     // to the nullspace: return the representative orthogonal to it
     if (G->g.cheb) c2_project(G->g, x64, G->dsmall + 1, G->st);
     inv_transform(G->g, x64, x, buf(G, 64, B_TMP), G->tw64, G->st);
+    if (kform) {  // phi = sqrt(rho) Phi with its mean removed (a multiple of psi in Phi)
+      void* t = buf(G, 64, B_T0);
+      rho_sqrt_mul(G->rho, x, x, false, 1.0, G->nreal, G->st);
+      fwd_transform(G->g, x, t, nullptr, G->tw64, G->st);
+      zero_mean(G->g, t, G->dsmall + 1, G->st);
+      inv_transform(G->g, t, x, buf(G, 64, B_TMP), G->tw64, G->st);
+    }
     ck(hipStreamSynchronize(G->st));
     ck(hipGetLastError());
     s->info.iterations += so.iters;
@@ -915,6 +1005,7 @@ static vd_status solve_common(vd_grid* G, int kind, double nu, int ncomp, const 
   else vd_default_opts(&c.o);
   if (!opts_ok(c.o)) return VD_EINVAL;
   if (!std::isnan(c.o.rho0) && !(c.o.rho0 > 0.0)) return VD_EINVAL;
+  if (c.o.formulation == VD_FORM_K && G->g.cheb) return VD_ENOTSUP;
   vd_status s = guard(G, solve_impl, &c);
   c.info.status = s;
   if (info) *info = c.info;
@@ -955,6 +1046,7 @@ size_t vd_workspace_bytes(const vd_grid_desc* d, const vd_solve_opts* opts) {
     bytes += nspec * 8 * (vecs + opwork + 2);       // FP32 basis, work, inner b and x
   }
   bytes += 2 * kTwEntries * (16 + 8) + nred_partial() * 8 + sizeof(DevState) + 512;
+  if (o.formulation == VD_FORM_K) bytes += nreal * (8 + 4) + nspec * 16 * 2;  // -c, psi spectrum, Lap work
   if (g.cheb) {
     const size_t nz = (size_t)g.nz;
     bytes += 12 * nz * nz * 12;                  // dense z matrices (FP64 + FP32)

@@ -586,6 +586,17 @@ __global__ void k_project(C2<double>* __restrict__ s, Geom g, double* removed) {
     }
   *removed = sqrt(acc * g.ntot_inv);
 }
+// Zero the mean (the real part of the DC slot) of a packed FP64 spectrum.
+__global__ void k_zero_mean(C2<double>* s, Geom g, double* removed) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double dc = s[0].x;  // sum of the grid values (unnormalised transform)
+  s[0].x = 0.0;
+  if (removed) *removed = fabs(dc) * sqrt(g.ntot_inv);
+}
+void zero_mean(const Geom& g, void* spec, double* removed, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_mean, dim3(1), dim3(64), 0, st, (C2<double>*)spec, g, removed);
+}
+
 void project_range(const Geom& g, void* spec, double* removed, hipStream_t st) {
   hipLaunchKernelGGL(k_project, dim3(1), dim3(64), 0, st, (C2<double>*)spec, g, removed);
 }
@@ -707,6 +718,37 @@ void density_setup(const double* rho, size_t n, double* a64, float* a32, float* 
                    hipStream_t s) {
   hipLaunchKernelGGL(k_density, dim3(nblk(n)), dim3(256), 0, s, rho, n, a64, a32, rho32, partial);
   hipLaunchKernelGGL(k_density_fin, dim3(1), dim3(64), 0, s, partial, nblk(n), out);
+}
+
+// ----------------------------------------------- modified pressure form
+
+// out = sign * rho^(+-1/2) * in on physical grid values (the change of
+// unknown phi = sqrt(rho) Phi and the right-hand side sqrt(rho) f); in ==
+// nullptr stands for in = 1.
+__global__ __launch_bounds__(256) void k_rho_sqrt_mul(const double* __restrict__ rho, const double* __restrict__ in,
+                                                      double* __restrict__ out, int inverse, double sign, size_t n) {
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+    const double r = sqrt(rho[e]), v = in ? in[e] : 1.0;
+    out[e] = sign * (inverse ? v / r : v * r);
+  }
+}
+void rho_sqrt_mul(const double* rho, const double* in, double* out, bool inverse, double sign, size_t n,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(k_rho_sqrt_mul, dim3(nblk(n)), dim3(256), 0, s, rho, in, out, inverse ? 1 : 0, sign, n);
+}
+
+// kc = Lap(psi) / psi = -c with psi = rho^-1/2 (so Lap(psi) / psi =
+// Lap(psi) sqrt(rho)), in FP64 and FP32.
+__global__ __launch_bounds__(256) void k_kcoef(const double* __restrict__ rho, const double* __restrict__ lap_psi,
+                                               double* __restrict__ kc64, float* __restrict__ kc32, size_t n) {
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+    const double v = lap_psi[e] * sqrt(rho[e]);
+    kc64[e] = v;
+    kc32[e] = (float)v;
+  }
+}
+void kcoef_finish(const double* rho, const double* lap_psi, double* kc64, float* kc32, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_kcoef, dim3(nblk(n)), dim3(256), 0, s, rho, lap_psi, kc64, kc32, n);
 }
 
 // ------------------------------------------------------- instantiations

@@ -101,6 +101,8 @@ void cast_f2d(const Geom& g, const void* src, void* dst, hipStream_t st);
 // Zero the 2^D nullspace slots of a packed pressure spectrum; write the
 // removed Euclidean norm (physical units) to *removed.
 void project_range(const Geom& g, void* spec, double* removed, hipStream_t st);
+// Zero the mean (DC) of a packed FP64 spectrum; removed Euclidean norm to *removed.
+void zero_mean(const Geom& g, void* spec, double* removed, hipStream_t st);
 
 // Scalar kernels (one thread) of the Krylov methods.
 void gmres_init(DevState* st, double beta, int m, hipStream_t s);
@@ -112,6 +114,14 @@ void rmr_alpha(DevState* st, hipStream_t s);  // alpha = red[0] / red[1]
 // Density set-up: a = 1/rho and copies, min/max/sum reductions.
 void density_setup(const double* rho, size_t n, double* a64, float* a32, float* rho32, double* partial,
                    double* out /* [sum, min, max, nonfinite_or_nonpositive] */, hipStream_t s);
+
+// Modified pressure form (eq. VDINSE.Krho), physical FP64 grid values:
+// out = sign * in * sqrt(rho), or sign * in / sqrt(rho) if `inverse`
+// (in == nullptr: in = 1).
+void rho_sqrt_mul(const double* rho, const double* in, double* out, bool inverse, double sign, size_t n,
+                  hipStream_t s);
+// kc = Lap(rho^-1/2) sqrt(rho) = -c (FP64 and FP32 copies).
+void kcoef_finish(const double* rho, const double* lap_psi, double* kc64, float* kc32, size_t n, hipStream_t s);
 
 size_t nred_partial();  // doubles needed for `partial`
 

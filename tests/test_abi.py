@@ -35,6 +35,7 @@ def test_defaults():
     assert o.solver == api.VD_GMRES and o.restart == 30 and o.rtol == 1e-10
     assert o.precond == 1 and o.precision == api.VD_FP64 and math.isnan(o.rho0)
     assert o.max_iter == 2000 and o.inner_rtol == 1e-5 and o.max_outer == 10
+    assert o.use_x0 == 0 and o.formulation == api.VD_FORM_L
 
 
 def test_status_strings():
@@ -53,6 +54,9 @@ def test_workspace_bytes():
     assert wb((256, 256, 256), solver="cg") < c3
     assert wb((512, 512, 512)) > 7 * c3
     assert wb((1024, 1024)) > wb((128, 128)) * 50
+    # the modified pressure form keeps -c (FP64 + FP32) and two spectral fields more
+    assert wb((256, 256, 256), formulation="K") - c3 == n * (8 + 4) + 2 * n * 8
+    assert wb((64, 64), formulation=7) == 0
     # invalid descriptors
     assert wb((100, 100)) == 0
     assert wb((8,)) == 0

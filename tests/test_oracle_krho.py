@@ -109,7 +109,10 @@ def test_k_solution_is_the_l_solution():
     rK = krylov.gmres(lambda u: operators.apply_pressure_k(u, c), bK,
                       lambda r: operators.precond_pressure_k(r), rtol=1e-13)
     assert removed < 1e-13 * np.linalg.norm(bK)   # zero-mean f is compatible
-    phiL = operators.project_range(rL["x"], operators.nullspace_basis(f.shape))[0]
+    basis = operators.nullspace_basis(f.shape)
+    phiL = operators.project_range(rL["x"], basis)[0]
     phiK = operators.pressure_k_recover(rK["x"], rho)
-    assert np.linalg.norm(phiK - phiL) <= 1e-11 * np.linalg.norm(phiL)
+    assert abs(phiK.mean()) < 1e-15 * np.abs(phiK).max()
+    # equal modulo the checkerboard modes, which L_rho does not see
+    assert np.linalg.norm(operators.project_range(phiK, basis)[0] - phiL) <= 1e-11 * np.linalg.norm(phiL)
     assert rK["iterations"] < rL["iterations"]
