@@ -102,3 +102,29 @@ def test_k_recovery_without_sqrt_rho_is_caught(monkeypatch):
     from tests import test_oracle_krho as tkr
     monkeypatch.setattr(operators, "pressure_k_recover", lambda Phi, rho: Phi - Phi.mean())
     _fails(tkr.test_k_solution_is_the_l_solution)
+
+
+# ------------------------------------------------ 1D viscous operator
+
+def test_viscous_missing_density_curvature_is_caught(monkeypatch):
+    from oracle import viscous
+    from tests import test_oracle_viscous as tv
+    def wrong(rho, a, d1, d2):   # rho'' u term dropped
+        n = rho.size
+        A = np.eye(n) - (a / rho)[:, None] * (d2 + (d1 @ rho)[:, None] * d1)
+        return A, np.eye(n) - a * d2
+    monkeypatch.setattr(viscous, "visc_operator", wrong)
+    _fails(tv.test_fourier_operator_closed_form)
+    _fails(tv.test_chebyshev_operator_closed_form)
+
+
+def test_viscous_transposed_advection_term_is_caught(monkeypatch):
+    from oracle import viscous
+    from tests import test_oracle_viscous as tv
+    def wrong(rho, a, d1, d2):   # D1 diag(rho') instead of diag(rho') D1
+        n = rho.size
+        rp, rpp = d1 @ rho, d2 @ rho
+        A = np.eye(n) - (a / rho)[:, None] * (d2 + np.diag(rpp) + d1 * rp[None, :])
+        return A, np.eye(n) - a * d2
+    monkeypatch.setattr(viscous, "visc_operator", wrong)
+    _fails(tv.test_chebyshev_operator_closed_form)
