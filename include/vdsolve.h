@@ -193,6 +193,42 @@ vd_status vd_dense_matmul(int precision, const void* A, const void* B, void* C, 
                           hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * One-dimensional implicit viscous systems (Sec. 3.1): batches of
+ *     V_rho u = u - (a / rho)(D2 u + rho'' u + rho' D1 u) = b
+ * (eq. VDINSE.Vrho, a = dt / (2 Re), Sc = 1), right-preconditioned by the
+ * constant-density operator V = I - a D2 (eq. VDINSE.V), with rho' = D1 rho
+ * and rho'' = D2 rho.  Basis VD_CHEB_GL: n Chebyshev-Gauss-Lobatto points of
+ * [-1, 1] (descending), D1 the collocation matrix, D2 = D1 D1, no-slip walls
+ * u(+-1) = 0 (the interior rows are solved; b's wall values are ignored and
+ * u's are returned as 0).  Basis VD_FOURIER: n (even) periodic points of
+ * [0, length), D1 the spectral derivative with its Nyquist mode zeroed, D2
+ * with it kept.  One workgroup solves each system of a batch.
+ * ---------------------------------------------------------------------- */
+typedef struct vd_visc1d vd_visc1d;
+
+/* Build the matrices (long double on the host, FP64 on the device) for n
+ * points (Chebyshev 9..512; Fourier even, 16..512) and a > 0.  Errors:
+ * VD_EINVAL, VD_ENOMEM. */
+vd_status vd_visc1d_create(vd_visc1d** out, int basis, int n, double length, double a, hipStream_t stream);
+vd_status vd_visc1d_destroy(vd_visc1d* h);
+
+/* y = V_rho u (precond 0) or y = V^-1 u (precond 1) for `batch` systems;
+ * rho, u, y: device FP64 [batch][n].  VD_EDOMAIN if a density is not
+ * strictly positive and finite. */
+vd_status vd_visc1d_apply(vd_visc1d* h, int batch, const double* rho, const double* u, double* y, int precond);
+
+/* Solve the batch: rho, b: device FP64 [batch][n]; u: device output (initial
+ * guess if opts->use_x0).  opts: solver VD_GMRES (restart 1..128) or VD_RMR
+ * (VD_CG and VD_FP32_REFINE give VD_ENOTSUP), rtol on each system's true
+ * relative residual ||b - V_rho u|| / ||b|| over the unknowns, max_iter,
+ * precond.  Per-system iterations and relative residuals go to the host
+ * arrays when given; info gets the largest of each and the worst status.
+ * The Krylov workspace (batch (restart+1)(n + restart) doubles) is kept by
+ * the handle for later calls. */
+vd_status vd_visc1d_solve(vd_visc1d* h, int batch, const double* rho, const double* b, double* u,
+                          const vd_solve_opts* opts, int* iterations, double* rel_residual, vd_solve_info* info);
+
+/* ------------------------------------------------------------------------
  * Continuous-batching solve server.  Not in the paper: a serving front end
  * for many independent solves of the kinds above (different grid sizes and
  * densities).  Requests are queued FIFO and admitted as soon as a worker

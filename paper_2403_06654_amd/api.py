@@ -17,6 +17,7 @@ VD_GMRES, VD_CG, VD_RMR = 0, 1, 2
 VD_FP64, VD_FP32_REFINE = 0, 1
 VD_OP_PRESSURE, VD_OP_HELMHOLTZ, VD_OP_PRESSURE_K = 0, 1, 2
 VD_FORM_L, VD_FORM_K = 0, 1
+VD_FOURIER, VD_CHEB_GL = 0, 1
 OP_KINDS = {"pressure": VD_OP_PRESSURE, "helmholtz": VD_OP_HELMHOLTZ, "pressure_k": VD_OP_PRESSURE_K}
 FORMULATIONS = {"L": VD_FORM_L, "K": VD_FORM_K}
 SOLVERS = {"gmres": VD_GMRES, "cg": VD_CG, "rmr": VD_RMR}
@@ -92,6 +93,11 @@ _SIGS = {
     "vd_profile_read": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(_D), _I]),
     "vd_status_string": (ctypes.c_char_p, [_I]),
     "vd_dense_matmul": (_I, [_I, _P, _P, _P, _I, _I, _I, _P]),
+    "vd_visc1d_create": (_I, [ctypes.POINTER(_P), _I, _I, _D, _D, _P]),
+    "vd_visc1d_destroy": (_I, [_P]),
+    "vd_visc1d_apply": (_I, [_P, _I, _P, _P, _P, _I]),
+    "vd_visc1d_solve": (_I, [_P, _I, _P, _P, _P, ctypes.POINTER(vd_solve_opts), _P, _P,
+                             ctypes.POINTER(vd_solve_info)]),
     "vd_server_create": (_I, [ctypes.POINTER(_P), ctypes.c_size_t, _I]),
     "vd_server_create_dry": (_I, [ctypes.POINTER(_P), ctypes.c_size_t, _I, _D]),
     "vd_server_submit": (_I, [_P, ctypes.POINTER(vd_request), ctypes.POINTER(ctypes.c_ulonglong)]),
@@ -280,6 +286,65 @@ class Grid:
         nb = (ctypes.c_double * nclass)()
         _check(lib().vd_profile_read(self._h, ms, cnt, nb, nclass), "vd_profile_read", False)
         return list(ms), list(cnt), list(nb)
+
+
+class Visc1d:
+    """Batched 1D implicit viscous systems V_rho u = b (vd_visc1d_*)."""
+
+    def __init__(self, basis, n, a, length=2 * math.pi, stream=None):
+        import torch
+        self.n = int(n)
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        b = {"cheb": VD_CHEB_GL, "fourier": VD_FOURIER}[basis]
+        h = ctypes.c_void_p()
+        _check(lib().vd_visc1d_create(ctypes.byref(h), b, self.n, float(length), float(a),
+                                      ctypes.c_void_p(self._stream.cuda_stream)), "vd_visc1d_create", False)
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().vd_visc1d_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _batch(self, t, name):
+        if t.dtype != __import__("torch").float64 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name}: contiguous float64 CUDA tensor expected")
+        if t.shape[-1] != self.n:
+            raise ValueError(f"{name}: last dimension must be {self.n}")
+        return t.numel() // self.n
+
+    def apply(self, rho, u, precond=False, out=None):
+        import torch
+        y = out if out is not None else torch.empty_like(u)
+        nb = self._batch(u, "u")
+        if self._batch(rho, "rho") != nb:
+            raise ValueError("rho and u batch sizes differ")
+        _check(lib().vd_visc1d_apply(self._h, nb, rho.data_ptr(), u.data_ptr(), y.data_ptr(), 1 if precond else 0),
+               "vd_visc1d_apply", False)
+        return y
+
+    def solve(self, rho, b, u=None, **opts):
+        import numpy as np
+        import torch
+        if u is None:
+            u = torch.zeros_like(b)
+        nb = self._batch(b, "b")
+        if self._batch(rho, "rho") != nb or self._batch(u, "u") != nb:
+            raise ValueError("batch sizes differ")
+        o = make_opts(**opts)
+        it = np.zeros(nb, dtype=np.int32)
+        rr = np.zeros(nb, dtype=np.float64)
+        info = vd_solve_info()
+        st = lib().vd_visc1d_solve(self._h, nb, rho.data_ptr(), b.data_ptr(), u.data_ptr(), ctypes.byref(o),
+                                   it.ctypes.data, rr.ctypes.data, ctypes.byref(info))
+        _check(st, "vd_visc1d_solve")
+        return u, it, rr, info.as_dict()
 
 
 class Server:

@@ -8,7 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libvdsolve.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["passes.hip", "vecops.hip", "gemm.hip", "cheb.cpp", "vdsolve.cpp", "vdserve.cpp"]
+SOURCES = ["passes.hip", "vecops.hip", "gemm.hip", "cheb.cpp", "vdsolve.cpp", "vdserve.cpp", "visc1d.hip",
+           "visc1d_host.cpp"]
 # standalone stream-bandwidth ceiling probe (not part of the library)
 CEILING_SRC = "stream_ceiling.hip"
 CEILING_OUT = os.path.join(HERE, "stream_ceiling")
