@@ -162,12 +162,15 @@ def traffic_from_profiles(best_name):
 
 
 def csrc_hash():
-    """Hash of the kernel sources, so that stored counter readings are only
-    used for the kernels they were taken on."""
+    """Hash of the sources of the 3D solver kernels, so that stored counter
+    readings are only used for the kernels they were taken on (the batched
+    1D viscous solver's files are not part of that path)."""
     from paper_2403_06654_amd.build import SOURCES
     d = os.path.join(ROOT, "paper_2403_06654_amd", "csrc")
     h = hashlib.sha256()
     for fn in sorted(os.listdir(d)):
+        if fn.startswith("visc1d"):
+            continue
         if fn in SOURCES or fn.endswith(".hpp"):  # the library's sources
             h.update(fn.encode())
             h.update(open(os.path.join(d, fn), "rb").read())
@@ -442,6 +445,111 @@ def bench_pmc(args):
     print(json.dumps({"pmc_run": True, "copy_bytes": nbytes, "iters": r["iters"]}))
 
 
+VISC_FLOPS_PER_IT = 6   # x ni^2: V^-1 (ni x ni) and D1, D2 on the interior columns per iteration
+
+
+def bench_visc1d(args):
+    """Batched 1D viscous solves V_rho u = b (Sec. 3.1, Table 1 set-up: 257
+    Chebyshev points, s = 1000): RMR and GMRES run for exactly 5/10/20/40
+    iterations per system (rtol 1e-300, GMRES without restart), at batch 1
+    (latency of one system) and at a full batch (throughput); then both
+    methods to convergence at 1e-10 and a warm start from the converged
+    solution after a small change of b."""
+    import numpy as np
+    import torch
+    from paper_2403_06654_amd import workloads
+    from paper_2403_06654_amd.api import Visc1d
+    n, a, big = 257, 1e-3, args.batch
+    ni = n - 2
+    inp = workloads.visc1d_inputs(big, n=n, s=1000.0, seed=0)
+    rho = torch.from_numpy(inp["rho"]).cuda()
+    b = torch.from_numpy(inp["b"]).cuda()
+    h = Visc1d("cheb", n, a)
+    st = torch.cuda.current_stream()
+
+    def timed(nb, its, solver, reps):
+        u = torch.zeros((nb, n), dtype=torch.float64, device="cuda")
+        kw = dict(solver=solver, rtol=1e-300, max_iter=its, restart=max(its, 1))
+        h.solve(rho[:nb], b[:nb], u=u, **kw)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * reps)]
+        t0 = time.perf_counter()
+        for k in range(reps):
+            ev[2 * k].record(st)
+            _, it, _, _ = h.solve(rho[:nb], b[:nb], u=u, **kw)
+            ev[2 * k + 1].record(st)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / reps
+        dev = sum(ev[2 * k].elapsed_time(ev[2 * k + 1]) for k in range(reps)) / reps * 1e-3
+        assert int(it.min()) == its and int(it.max()) == its, (it.min(), it.max())
+        return wall, dev
+
+    table, roof = {}, None
+    for its in (5, 10, 20, 40):
+        row = {}
+        for solver in ("rmr", "gmres"):
+            w1, d1 = timed(1, its, solver, max(args.steps, 3))
+            wb, db = timed(big, its, solver, max(args.steps, 3))
+            row[solver] = {"one_system_ms": round(1e3 * w1, 3), "batch_ms": round(1e3 * wb, 3),
+                           "per_system_us": round(1e6 * db / big, 3),
+                           "system_iters_per_s": round(big * its / db, 1)}
+            if its == 40 and solver == "rmr":
+                fl = VISC_FLOPS_PER_IT * ni * ni * its * big
+                roof = {"bound": "alu", "achieved": round(fl / db / 1e12, 3), "peak": 78.6, "unit": "TFLOP/s",
+                        "frac": round(fl / db / 1e12 / 78.6, 4), "traffic": None,
+                        "kernel": "k_visc1d", "launch_ms": round(1e3 * db, 3)}
+        table[str(its)] = row
+    conv = {}
+    for solver in ("rmr", "gmres"):
+        u = torch.zeros_like(b)
+        t0 = time.perf_counter()
+        _, it, rr, info = h.solve(rho, b, u=u, solver=solver, rtol=1e-10, max_iter=2000, restart=128)
+        el = time.perf_counter() - t0
+        b2 = b * (1.0 + 1e-4 * torch.sin(torch.arange(n, device="cuda", dtype=torch.float64)))
+        t1 = time.perf_counter()
+        _, it2, rr2, info2 = h.solve(rho, b2, u=u, solver=solver, rtol=1e-10, max_iter=2000, restart=128,
+                                     use_x0=True)
+        el2 = time.perf_counter() - t1
+        conv[solver] = {"converged": int((np.asarray(rr) <= 1e-10).sum()), "of": big,
+                        "iters_median": float(np.median(it)), "iters_max": int(it.max()),
+                        "batch_ms": round(1e3 * el, 3),
+                        "warm_iters_median": float(np.median(it2)), "warm_iters_max": int(it2.max()),
+                        "warm_batch_ms": round(1e3 * el2, 3)}
+    h.close()
+    res = {"metric": "1D viscous solves: per-system time at fixed iteration counts (batched)",
+           "value": table["40"]["rmr"]["system_iters_per_s"], "unit": "system-iterations/s (RMR, 40 its)",
+           "n_gpus": 1, "steps": args.steps, "warmup": 1, "higher_is_better": True, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": f"{big} systems, 257 Chebyshev-Gauss-Lobatto points with no-slip walls, "
+                                  "a = 1e-3, top-hat rho with s = 1000, width 0.1, half-width uniform in [0.3, 0.5]"},
+           "paper_table_seconds_one_cpu_core": {"5": [5.6e-3, 1.0e-2], "10": [1.1e-2, 3.4e-2],
+                                                "20": [2.0e-2, 9.7e-2], "40": [4.2e-2, 2.2e-1]},
+           "roofline": roof, "fixed_iterations": table, "to_convergence": conv}
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = visc1d_cpu_baseline(inp, a)
+    print(json.dumps(res))
+
+
+def visc1d_cpu_baseline(inp, a):
+    """The oracle's RMR (dense V^-1 and differentiation matrices, NumPy on
+    one BLAS thread) for 40 iterations on a sample of the systems."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import krylov, viscous
+    n = inp["rho"].shape[1]
+    done, el = 0, 0.0
+    with threadpool_limits(1):
+        while done < 512 and el < 10.0:
+            A, V = viscous.cheb_system(inp["rho"][done], a)
+            Vi = np.linalg.inv(V)
+            t0 = time.perf_counter()
+            krylov.rmr(lambda u: A @ u, inp["b"][done, 1:n - 1], lambda r: Vi @ r, rtol=1e-300, max_iter=40)
+            el += time.perf_counter() - t0
+            done += 1
+    return {"value": round(done * 40 / el, 1), "unit": "system-iterations/s (RMR, 40 its)",
+            "cores": 1, "kind": "oracle",
+            "sample": f"oracle.krylov.rmr, {done} systems x 40 iterations, {el:.2f} s (assembly and inversion "
+                      f"of the dense matrices not timed), one BLAS thread"}
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -449,9 +557,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--workload", choices=["c3", "serving", "c5", "c2", "pmc"], default="c3")
+    ap.add_argument("--workload", choices=["c3", "serving", "c5", "c2", "pmc", "visc1d"], default="c3")
     ap.add_argument("--requests", type=int, default=4096)
     ap.add_argument("--slots", type=int, default=8)
+    ap.add_argument("--batch", type=int, default=8192)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -468,6 +577,9 @@ def main():
         return
     if args.workload == "pmc":
         bench_pmc(args)
+        return
+    if args.workload == "visc1d":
+        bench_visc1d(args)
         return
 
     import numpy as np

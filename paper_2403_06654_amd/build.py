@@ -9,7 +9,10 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libvdsolve.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["passes.hip", "vecops.hip", "gemm.hip", "cheb.cpp", "vdsolve.cpp", "vdserve.cpp", "visc1d.hip",
-           "visc1d_host.cpp"]
+           "visc1d_large.hip", "visc1d_host.cpp"]
+# per-source extra flags: the batched viscous kernels keep their MFMA
+# accumulators in VGPRs instead of copying them through AGPRs every k step
+EXTRA_FLAGS = {"visc1d.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 # standalone stream-bandwidth ceiling probe (not part of the library)
 CEILING_SRC = "stream_ceiling.hip"
 CEILING_OUT = os.path.join(HERE, "stream_ceiling")
@@ -23,7 +26,7 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
 
 def _compile(src):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, *EXTRA_FLAGS.get(src, []), "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr[-6000:]}")

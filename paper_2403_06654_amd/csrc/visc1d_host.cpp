@@ -13,13 +13,15 @@
 using LD = long double;
 
 struct vd_visc1d {
-  int basis = 0, np = 0, ni = 0, off = 0;
+  int basis = 0, np = 0, ni = 0, off = 0, tpw = 0, kt_full = 0;
   double a = 0;
   hipStream_t st = nullptr;
-  double* D1T = nullptr;
-  double* D2T = nullptr;
-  double* VinvT = nullptr;
-  double* work = nullptr;  // Krylov basis and Hessenberg matrices of a batch
+  double* D1I = nullptr;   // matrices in MFMA operand order (see visc1d.hpp)
+  double* D2I = nullptr;
+  double* VI = nullptr;
+  double* D1F = nullptr;
+  double* D2F = nullptr;
+  double* work = nullptr;  // per-group workspace of a batch
   size_t work_cap = 0;     // doubles
   int* iters = nullptr;
   double* relres = nullptr;
@@ -108,20 +110,28 @@ bool invert(int n, std::vector<LD> A, std::vector<LD>& inv) {
   return true;
 }
 
-// Upload a row-major LD matrix (rows [r0, r0+nr), cols [c0, c0+nc) of an
-// n-column matrix) as a column-major double matrix with leading dimension nr.
-bool upload_colmajor(const std::vector<LD>& M, int n, int r0, int c0, int nr, int nc, double** out) {
-  std::vector<double> t((size_t)nr * nc);
-  for (int j = 0; j < nc; ++j)
-    for (int i = 0; i < nr; ++i) t[(size_t)j * nr + i] = (double)M[(size_t)(r0 + i) * n + (c0 + j)];
+// Upload the block M(i, j) = src[(r0 + i) * n + c0 + j], i < nr, j < nc, of a
+// row-major n-column matrix in MFMA operand order with nrt row tiles and nkt
+// k tiles (zero outside the block).
+bool upload_tiles(const std::vector<LD>& src, int n, int r0, int c0, int nr, int nc, int nrt, int nkt, double** out) {
+  std::vector<double> t((size_t)nrt * nkt * 256, 0.0);
+  for (int R = 0; R < nrt; ++R)
+    for (int T = 0; T < nkt; ++T)
+      for (int l = 0; l < 64; ++l)
+        for (int q = 0; q < 4; ++q) {
+          const int i = 16 * R + (l & 15), j = 16 * T + 4 * q + (l >> 4);
+          if (i < nr && j < nc) t[(((size_t)R * nkt + T) * 64 + l) * 4 + q] = (double)src[(size_t)(r0 + i) * n + (c0 + j)];
+        }
   if (hipMalloc(out, t.size() * sizeof(double)) != hipSuccess) return false;
   return hipMemcpy(*out, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
 }
 
 void release(vd_visc1d* h) {
-  hipFree(h->D1T);
-  hipFree(h->D2T);
-  hipFree(h->VinvT);
+  hipFree(h->D1I);
+  hipFree(h->D2I);
+  hipFree(h->VI);
+  hipFree(h->D1F);
+  hipFree(h->D2F);
   hipFree(h->work);
   hipFree(h->iters);
   hipFree(h->relres);
@@ -175,8 +185,13 @@ vd_status vd_visc1d_create(vd_visc1d** out, int basis, int n, double length, dou
     release(h);
     return VD_EINVAL;
   }
-  if (!upload_colmajor(d1, n, 0, 0, n, n, &h->D1T) || !upload_colmajor(d2, n, 0, 0, n, n, &h->D2T) ||
-      !upload_colmajor(Vinv, ni, 0, 0, ni, ni, &h->VinvT)) {
+  h->tpw = vd::visc1d_tpw(ni);
+  h->kt_full = (n + 15) / 16;
+  const int rt = vd::visc1d_rows(h->tpw) / 16;
+  if (!upload_tiles(d1, n, off, off, ni, ni, rt, rt, &h->D1I) || !upload_tiles(d2, n, off, off, ni, ni, rt, rt, &h->D2I) ||
+      !upload_tiles(Vinv, ni, 0, 0, ni, ni, rt, rt, &h->VI) ||
+      !upload_tiles(d1, n, off, 0, ni, n, rt, h->kt_full, &h->D1F) ||
+      !upload_tiles(d2, n, off, 0, ni, n, rt, h->kt_full, &h->D2F)) {
     hipGetLastError();
     release(h);
     return VD_ENOMEM;
@@ -198,15 +213,34 @@ static vd::Visc1dArgs base_args(vd_visc1d* h, int batch, const double* rho, cons
   a.np = h->np;
   a.ni = h->ni;
   a.off = h->off;
+  a.batch = batch;
+  a.kt_full = h->kt_full;
   a.a = h->a;
-  a.D1T = h->D1T;
-  a.D2T = h->D2T;
-  a.VinvT = h->VinvT;
+  a.D1I = h->D1I;
+  a.D2I = h->D2I;
+  a.VI = h->VI;
+  a.D1F = h->D1F;
+  a.D2F = h->D2F;
   a.rho = rho;
   a.b = b;
   a.x = x;
-  (void)batch;
   return a;
+}
+
+// Workspace of a batch: per_group doubles for each group of systems.
+static bool ensure_work(vd_visc1d* h, int batch, size_t per_group) {
+  const size_t groups = ((size_t)batch + vd::kVisc1dGroup - 1) / vd::kVisc1dGroup;
+  const size_t need = groups * per_group;
+  if (need <= h->work_cap) return true;
+  hipFree(h->work);
+  h->work = nullptr;
+  h->work_cap = 0;
+  if (hipMalloc(&h->work, need * sizeof(double)) != hipSuccess) {
+    hipGetLastError();
+    return false;
+  }
+  h->work_cap = need;
+  return true;
 }
 
 static bool ensure_outputs(vd_visc1d* h, size_t batch) {
@@ -229,14 +263,21 @@ static bool ensure_outputs(vd_visc1d* h, size_t batch) {
 
 vd_status vd_visc1d_apply(vd_visc1d* h, int batch, const double* rho, const double* u, double* y, int precond) {
   if (!h || batch < 1 || !rho || !u || !y) return VD_EINVAL;
-  if (!ensure_outputs(h, (size_t)batch)) return VD_ENOMEM;
+  const int mode = precond ? vd::VISC1D_APPLY_PREC : vd::VISC1D_APPLY_OP;
+  const size_t per_group = vd::visc1d_work_doubles(h->tpw, mode, 0, 0);
+  if (!ensure_outputs(h, (size_t)batch) || !ensure_work(h, batch, per_group)) return VD_ENOMEM;
   vd::Visc1dArgs a = base_args(h, batch, rho, u, y);
-  a.mode = precond ? vd::VISC1D_APPLY_PREC : vd::VISC1D_APPLY_OP;
+  a.mode = mode;
   a.precond = precond ? 1 : 0;
+  a.work = h->work;
+  a.work_stride = per_group;
   a.iters = h->iters;
   a.relres = h->relres;
   a.status = h->status;
-  vd::visc1d_launch(a, batch, h->st);
+  if (vd::visc1d_launch(a, h->st) != hipSuccess) {
+    hipGetLastError();
+    return VD_EDEVICE;
+  }
   if (hipStreamSynchronize(h->st) != hipSuccess || hipGetLastError() != hipSuccess) return VD_EDEVICE;
   std::vector<int> st(batch);
   if (hipMemcpy(st.data(), h->status, batch * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return VD_EDEVICE;
@@ -256,32 +297,26 @@ vd_status vd_visc1d_solve(vd_visc1d* h, int batch, const double* rho, const doub
   if (o.solver != VD_GMRES && o.solver != VD_RMR) return VD_EINVAL;
   if (o.restart < 1 || o.restart > vd::kMaxVisc1dRestart || !(o.rtol > 0.0) || o.max_iter < 0) return VD_EINVAL;
   const int m = o.restart;
-  const size_t need = (size_t)batch * ((size_t)(m + 1) * h->ni + (size_t)(m + 1) * m);
-  if (need > h->work_cap) {
-    hipFree(h->work);
-    h->work = nullptr;
-    h->work_cap = 0;
-    if (hipMalloc(&h->work, need * sizeof(double)) != hipSuccess) {
-      hipGetLastError();
-      return VD_ENOMEM;
-    }
-    h->work_cap = need;
-  }
-  if (!ensure_outputs(h, (size_t)batch)) return VD_ENOMEM;
+  const int solver = o.solver == VD_RMR ? vd::VISC1D_RMR : vd::VISC1D_GMRES;
+  const size_t per_group = vd::visc1d_work_doubles(h->tpw, vd::VISC1D_SOLVE, solver, m);
+  if (!ensure_outputs(h, (size_t)batch) || !ensure_work(h, batch, per_group)) return VD_ENOMEM;
   vd::Visc1dArgs a = base_args(h, batch, rho, b, u);
   a.mode = vd::VISC1D_SOLVE;
-  a.solver = o.solver == VD_RMR ? vd::VISC1D_RMR : vd::VISC1D_GMRES;
+  a.solver = solver;
   a.restart = m;
   a.max_iter = o.max_iter;
   a.precond = o.precond ? 1 : 0;
   a.use_x0 = o.use_x0 ? 1 : 0;
   a.rtol = o.rtol;
-  a.basis = h->work;
-  a.H = h->work + (size_t)batch * (m + 1) * h->ni;
+  a.work = h->work;
+  a.work_stride = per_group;
   a.iters = h->iters;
   a.relres = h->relres;
   a.status = h->status;
-  vd::visc1d_launch(a, batch, h->st);
+  if (vd::visc1d_launch(a, h->st) != hipSuccess) {
+    hipGetLastError();
+    return VD_EDEVICE;
+  }
   std::vector<int> it(batch), st(batch);
   std::vector<double> rr(batch);
   if (hipMemcpyAsync(it.data(), h->iters, batch * sizeof(int), hipMemcpyDeviceToHost, h->st) != hipSuccess ||

@@ -215,3 +215,19 @@ def c2_inputs(nx=512, m=256, r=3.0, seed=0, lx=2.0, width=0.02):
         f += np.real(np.outer(T.T @ c, np.exp(1j * np.pi * mm * x)))
     f /= np.sqrt(np.mean(f * f))
     return {"rho": np.ascontiguousarray(rho), "f": np.ascontiguousarray(f), "lx": lx}
+
+
+# ------------------------------------ batched 1D viscous systems (Sec. 3.1)
+
+def visc1d_inputs(batch, n=257, s=1000.0, seed=0):
+    """A batch of 1D viscous systems on the n Chebyshev-Gauss-Lobatto points
+    (descending) of [-1, 1]: top-hat densities of eq. VDINSE.rho.hat with
+    ratio s, width 0.1 and half-width x0 uniform in [0.3, 0.5] per system,
+    right-hand sides standard normal with zero wall values.  Shapes (batch, n)."""
+    rng = _rng(seed, 11, batch, n)
+    x = cheb_gl(n - 1)
+    x0 = rng.uniform(0.3, 0.5, size=(batch, 1))
+    rho = 1.0 + 0.5 * (s - 1.0) * (np.tanh((x + x0) / 0.1) - np.tanh((x - x0) / 0.1))
+    b = rng.standard_normal((batch, n))
+    b[:, 0] = b[:, -1] = 0.0
+    return {"rho": np.ascontiguousarray(rho), "b": b, "x": x}
