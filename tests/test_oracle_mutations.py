@@ -128,3 +128,43 @@ def test_viscous_transposed_advection_term_is_caught(monkeypatch):
         return A, np.eye(n) - a * d2
     monkeypatch.setattr(viscous, "visc_operator", wrong)
     _fails(tv.test_chebyshev_operator_closed_form)
+
+
+# ------------------------------------------------ fractional-step scheme
+
+def test_first_order_advection_extrapolation_is_caught(monkeypatch):
+    from oracle import fractional_step as fs
+    from tests import test_oracle_fractional_step as tf
+    monkeypatch.setattr(fs, "AB2", (1.0, 0.0))
+    _fails(tf.test_second_order_in_time)
+
+
+def test_missing_pressure_update_correction_is_caught(monkeypatch):
+    from oracle import fractional_step as fs
+    from tests import test_oracle_fractional_step as tf
+    monkeypatch.setattr(fs, "divgrad_pinv", lambda f: 0.0 * f)
+    _fails(tf.test_pressure_update_reproduces_the_crank_nicolson_momentum_step)
+
+
+def test_wrong_crank_nicolson_weight_is_caught(monkeypatch):
+    from oracle import fractional_step as fs
+    from tests import test_oracle_fractional_step as tf
+    orig = fs.helmholtz_inv
+    monkeypatch.setattr(fs, "helmholtz_inv", lambda f, c: orig(f, 2.0 * c))
+    _fails(tf.test_second_order_in_time)
+
+
+def test_zeta_without_diffusion_velocity_terms_is_caught(monkeypatch):
+    from oracle import fractional_step as fs
+    from tests import test_oracle_fractional_step as tf
+    orig = fs.zeta
+    monkeypatch.setattr(fs, "zeta", lambda rho, u, re, sc: orig(rho, u, re, 1e30))
+    _fails(tf.test_zeta_closed_form)
+
+
+def test_wrong_sign_of_mass_source_is_caught(monkeypatch):
+    from oracle import fractional_step as fs
+    from tests import test_oracle_fractional_step as tf
+    orig = fs.forcing
+    monkeypatch.setattr(fs, "forcing", lambda n, t, s, re, sc: (orig(n, t, s, re, sc)[0], -orig(n, t, s, re, sc)[1]))
+    _fails(tf.test_second_order_in_time)
