@@ -202,7 +202,9 @@ vd_status vd_dense_matmul(int precision, const void* A, const void* B, void* C, 
  * u(+-1) = 0 (the interior rows are solved; b's wall values are ignored and
  * u's are returned as 0).  Basis VD_FOURIER: n (even) periodic points of
  * [0, length), D1 the spectral derivative with its Nyquist mode zeroed, D2
- * with it kept.  One workgroup solves each system of a batch.
+ * with it kept.  One workgroup solves each group of 16 systems of a batch
+ * in lockstep (the shared matrices applied to the group with FP64 MFMA);
+ * a system's result does not depend on the rest of the batch.
  * ---------------------------------------------------------------------- */
 typedef struct vd_visc1d vd_visc1d;
 
@@ -223,10 +225,71 @@ vd_status vd_visc1d_apply(vd_visc1d* h, int batch, const double* rho, const doub
  * relative residual ||b - V_rho u|| / ||b|| over the unknowns, max_iter,
  * precond.  Per-system iterations and relative residuals go to the host
  * arrays when given; info gets the largest of each and the worst status.
- * The Krylov workspace (batch (restart+1)(n + restart) doubles) is kept by
- * the handle for later calls. */
+ * The workspace (per group of 16 systems: 16 (5 + restart + 1) rows
+ * padded to 64 plus the Hessenberg and rotation arrays, GMRES; 80 rows,
+ * RMR) is kept by the handle for later calls. */
 vd_status vd_visc1d_solve(vd_visc1d* h, int batch, const double* rho, const double* b, double* u,
                           const vd_solve_opts* opts, int* iterations, double* rel_residual, vd_solve_info* info);
+
+/* ------------------------------------------------------------------------
+ * Fractional-step time integration of the variable-density incompressible
+ * Navier-Stokes equations (Sec. 2, eq. VDINSE) on the triply periodic box
+ * [0, 2 pi)^3 with n^3 points (n a power of two, 16..512).  One step:
+ * Adams-Bashforth advection terms (Euler on the first step after a state is
+ * set), Crank-Nicolson density (eq. VDINSE.num.mass.proj), rho^(n+1/2) the
+ * mean of the two densities, the implicit viscous system
+ * u* - dt/2 zeta(rho^(n+1/2), u*) = rhs (eq. VDINSE.num.momentum.proj, zeta
+ * of eq. VDINSE.zeta) by GMRES preconditioned with (I - dt/(2 Re) Lap)^-1
+ * (eq. VDINSE.V) from u^n, L_rho phi = div(u*) / dt by vd_solve_pressure
+ * warm-started from the previous phi (eq. VDINSE.Lrho.num), the projection
+ * u^(n+1) = u* - dt grad(phi) / rho^(n+1/2) (eq. VDINSE.num.proj) and the
+ * pressure update of eq. VDINSE.num.p.update (its Lap^-1 is the
+ * pseudo-inverse of div grad).  Derivatives are spectral (first derivatives
+ * with the Nyquist mode zeroed, the Laplacian with it kept).  With s > 0 the
+ * body force and mass source that make the Taylor-Green solution of
+ * eq. VDINSE.solexact (density ratio s) exact are added at t^(n+1/2).
+ * Fields: device FP64, velocity [3][n][n][n] (components along x, y, z),
+ * scalars [n][n][n], x contiguous.  All work runs on the handle's stream.
+ * ---------------------------------------------------------------------- */
+typedef struct vd_ns vd_ns;
+
+typedef struct {
+  double re, sc;      /* Reynolds and Schmidt numbers (> 0) */
+  double dt;          /* time step (> 0) */
+  double s;           /* > 0: manufactured forcing with density ratio s; 0: none */
+  double visc_rtol;   /* viscous solve: relative true residual (default 1e-12) */
+  double pres_rtol;   /* pressure solve: relative true residual (default 1e-12) */
+  int restart;        /* GMRES restart of both solves, 1..30 (default 30) */
+  int max_iter;       /* per solve (default 2000) */
+} vd_ns_params;
+
+typedef struct {
+  double t;                  /* time after the last step */
+  int steps;                 /* steps since the state was set */
+  int visc_iters, pres_iters;            /* Krylov iterations of the last step */
+  int visc_status, pres_status;          /* vd_status of the last step's solves */
+  double visc_rel_residual, pres_rel_residual;
+} vd_ns_info;
+
+void vd_ns_default_params(vd_ns_params* p);
+/* VD_EINVAL for bad sizes or parameters; VD_ENOMEM.  The handle holds about
+ * 40 + 3 (restart + 1) fields of n^3 doubles and a pressure grid. */
+vd_status vd_ns_create(vd_ns** out, int n, const vd_ns_params* prm, hipStream_t stream);
+vd_status vd_ns_destroy(vd_ns* h);
+/* Copy u^n, rho^n and p^(n-1/2) (device arrays) in and set the time; the
+ * advection history and the pressure warm start are reset. */
+vd_status vd_ns_set_state(vd_ns* h, const double* u, const double* rho, const double* p, double t);
+/* The state of eq. VDINSE.solexact at t = 0 with p^(-1/2) = p_e(-dt/2)
+ * (requires s > 0). */
+vd_status vd_ns_init_taylor_green(vd_ns* h);
+/* Advance nsteps steps; info (may be NULL) describes the last one.
+ * Returns the worse of the last step's solve statuses. */
+vd_status vd_ns_step(vd_ns* h, int nsteps, vd_ns_info* info);
+/* Copy the state out (device arrays; any may be NULL). */
+vd_status vd_ns_get_state(vd_ns* h, double* u, double* rho, double* p, double* t);
+/* err[0..3] = RMS over the grid of |u - u_e(t)|, p - p_e(t - dt/2),
+ * rho - rho_e(t) (eq. VDINSE.solexact) and div u (requires s > 0). */
+vd_status vd_ns_errors(vd_ns* h, double* err);
 
 /* ------------------------------------------------------------------------
  * Continuous-batching solve server.  Not in the paper: a serving front end

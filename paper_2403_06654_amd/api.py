@@ -73,6 +73,21 @@ class vd_server_stats_t(ctypes.Structure):
                 ("peak_busy_slots", ctypes.c_int)]
 
 
+class vd_ns_params(ctypes.Structure):
+    _fields_ = [("re", ctypes.c_double), ("sc", ctypes.c_double), ("dt", ctypes.c_double), ("s", ctypes.c_double),
+                ("visc_rtol", ctypes.c_double), ("pres_rtol", ctypes.c_double), ("restart", ctypes.c_int),
+                ("max_iter", ctypes.c_int)]
+
+
+class vd_ns_info(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("steps", ctypes.c_int), ("visc_iters", ctypes.c_int),
+                ("pres_iters", ctypes.c_int), ("visc_status", ctypes.c_int), ("pres_status", ctypes.c_int),
+                ("visc_rel_residual", ctypes.c_double), ("pres_rel_residual", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _LIB = None
 _P = ctypes.c_void_p
 _D = ctypes.c_double
@@ -98,6 +113,14 @@ _SIGS = {
     "vd_visc1d_apply": (_I, [_P, _I, _P, _P, _P, _I]),
     "vd_visc1d_solve": (_I, [_P, _I, _P, _P, _P, ctypes.POINTER(vd_solve_opts), _P, _P,
                              ctypes.POINTER(vd_solve_info)]),
+    "vd_ns_default_params": (None, [ctypes.POINTER(vd_ns_params)]),
+    "vd_ns_create": (_I, [ctypes.POINTER(_P), _I, ctypes.POINTER(vd_ns_params), _P]),
+    "vd_ns_destroy": (_I, [_P]),
+    "vd_ns_set_state": (_I, [_P, _P, _P, _P, _D]),
+    "vd_ns_init_taylor_green": (_I, [_P]),
+    "vd_ns_step": (_I, [_P, _I, ctypes.POINTER(vd_ns_info)]),
+    "vd_ns_get_state": (_I, [_P, _P, _P, _P, ctypes.POINTER(_D)]),
+    "vd_ns_errors": (_I, [_P, ctypes.POINTER(_D)]),
     "vd_server_create": (_I, [ctypes.POINTER(_P), ctypes.c_size_t, _I]),
     "vd_server_create_dry": (_I, [ctypes.POINTER(_P), ctypes.c_size_t, _I, _D]),
     "vd_server_submit": (_I, [_P, ctypes.POINTER(vd_request), ctypes.POINTER(ctypes.c_ulonglong)]),
@@ -345,6 +368,66 @@ class Visc1d:
                                    it.ctypes.data, rr.ctypes.data, ctypes.byref(info))
         _check(st, "vd_visc1d_solve")
         return u, it, rr, info.as_dict()
+
+
+class FractionalStep:
+    """Fractional-step time integration of the variable-density Navier-Stokes
+    equations on [0, 2 pi)^3 (vd_ns_*)."""
+
+    def __init__(self, n, re=1.0, sc=1.0, dt=0.01, s=0.0, visc_rtol=1e-12, pres_rtol=1e-12, restart=30,
+                 max_iter=2000, stream=None):
+        import torch
+        self.n = int(n)
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        prm = vd_ns_params()
+        lib().vd_ns_default_params(ctypes.byref(prm))
+        prm.re, prm.sc, prm.dt, prm.s = float(re), float(sc), float(dt), float(s)
+        prm.visc_rtol, prm.pres_rtol = float(visc_rtol), float(pres_rtol)
+        prm.restart, prm.max_iter = int(restart), int(max_iter)
+        h = ctypes.c_void_p()
+        _check(lib().vd_ns_create(ctypes.byref(h), self.n, ctypes.byref(prm),
+                                  ctypes.c_void_p(self._stream.cuda_stream)), "vd_ns_create", False)
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().vd_ns_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init_taylor_green(self):
+        _check(lib().vd_ns_init_taylor_green(self._h), "vd_ns_init_taylor_green", False)
+
+    def set_state(self, u, rho, p, t=0.0):
+        n = self.n
+        _check(lib().vd_ns_set_state(self._h, _dev_f64(u, (3, n, n, n), "u"), _dev_f64(rho, (n, n, n), "rho"),
+                                     _dev_f64(p, (n, n, n), "p"), float(t)), "vd_ns_set_state", False)
+
+    def step(self, nsteps=1):
+        info = vd_ns_info()
+        _check(lib().vd_ns_step(self._h, int(nsteps), ctypes.byref(info)), "vd_ns_step", False)
+        return info.as_dict()
+
+    def state(self):
+        import torch
+        n = self.n
+        u = torch.empty((3, n, n, n), dtype=torch.float64, device="cuda")
+        rho = torch.empty((n, n, n), dtype=torch.float64, device="cuda")
+        p = torch.empty((n, n, n), dtype=torch.float64, device="cuda")
+        t = ctypes.c_double()
+        _check(lib().vd_ns_get_state(self._h, ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(rho.data_ptr()),
+                                     ctypes.c_void_p(p.data_ptr()), ctypes.byref(t)), "vd_ns_get_state", False)
+        return u, rho, p, t.value
+
+    def errors(self):
+        e = (ctypes.c_double * 4)()
+        _check(lib().vd_ns_errors(self._h, e), "vd_ns_errors", False)
+        return {"u": e[0], "p": e[1], "rho": e[2], "div": e[3]}
 
 
 class Server:

@@ -125,6 +125,13 @@ struct vd_grid {
   double psi2 = 0;
 };
 
+namespace vd {
+
+const Geom& grid_geom(const vd_grid* G) { return G->g; }
+const void* grid_twiddles(const vd_grid* G) { return G->tw64; }
+
+}  // namespace vd
+
 namespace {
 
 enum Role {

@@ -98,3 +98,23 @@ def test_build_flags_and_product_path_independent_of_oracle():
             if fn.endswith((".py", ".hip", ".cpp", ".hpp", ".h")):
                 txt = open(os.path.join(dirpath, fn)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, fn
+
+
+def test_fractional_step_rejects_bad_parameters_without_touching_the_device():
+    L = api.lib()
+    h = ctypes.c_void_p()
+    prm = api.vd_ns_params()
+    L.vd_ns_default_params(ctypes.byref(prm))
+    assert (prm.re, prm.sc, prm.visc_rtol, prm.pres_rtol, prm.restart) == (1.0, 1.0, 1e-12, 1e-12, 30)
+    for n in (8, 48, 1024):
+        assert L.vd_ns_create(ctypes.byref(h), n, ctypes.byref(prm), None) == -1
+    for field, bad in (("dt", 0.0), ("re", -1.0), ("s", -2.0), ("restart", 31), ("visc_rtol", 0.0)):
+        p = api.vd_ns_params()
+        L.vd_ns_default_params(ctypes.byref(p))
+        setattr(p, field, bad)
+        assert L.vd_ns_create(ctypes.byref(h), 32, ctypes.byref(p), None) == -1, field
+    assert L.vd_ns_create(None, 32, None, None) == -1
+    assert L.vd_ns_destroy(None) == -1
+    assert L.vd_ns_step(None, 1, None) == -1
+    assert L.vd_ns_errors(None, None) == -1
+    assert L.vd_ns_init_taylor_green(None) == -1
