@@ -559,6 +559,96 @@ def visc1d_cpu_baseline(inp, a):
             "sample": f"oracle.krylov.rmr, {done} systems x 40 iterations, {el:.2f} s (assembly and inversion "
                       f"of the dense matrices not timed), one BLAS thread"}
 
+def bench_ns(args):
+    """Fractional-step steps of the variable-density Navier-Stokes equations
+    (Sec. 2) on the manufactured Taylor-Green solution (Sec. 5.1,
+    eq. VDINSE.solexact): 128^3, Re = Sc = 1, s = 10.  (a) dt = 0.01 (the
+    divergence-history set-up): time per step with warm-started solves,
+    Krylov iterations, ||div u|| after every step up to t = pi/4; (b) errors
+    at T = pi/4 for dt = T/8 .. T/64 and their orders (the temporal-error
+    set-up); (c) event-timed classes over profiled steps for the roofline of
+    the FFT transforms."""
+    import numpy as np
+    import torch
+    from paper_2403_06654_amd.api import FractionalStep
+    n, re, sc, s = args.ns_n, 1.0, 1.0, 10.0
+    T = np.pi / 4
+    ns = FractionalStep(n, re=re, sc=sc, dt=0.01, s=s)
+    ns.init_taylor_green()
+    print(f"bench: ns {n}^3 warm-up", file=sys.stderr, flush=True)
+    ns.step(args.warmup)
+    torch.cuda.synchronize()
+    its_v, its_p = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        info = ns.step(1)
+        its_v.append(info["visc_iters"])
+        its_p.append(info["pres_iters"])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms_step = 1e3 * el / args.steps
+    # (c) profiled steps
+    ns.profile_enable(True)
+    ns.step(args.steps)
+    prof = ns.profile_read()
+    ns.profile_enable(False)
+    tr = prof["transforms"]
+    ach = tr["bytes"] / (tr["ms"] * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": 8000.0, "unit": "GB/s", "frac": round(ach / 8000.0, 4),
+            "traffic": None, "kernel": "FFT transform passes (k_row R2C/C2R, k_col FFT_FWD/FFT_INV)",
+            "per_unit": f"48 n^3 bytes per 3D transform (3 passes reading and writing the field), n = {n}",
+            "launches": tr["count"], "avg_us_per_transform": round(1e3 * tr["ms"] / max(tr["count"], 1), 2)}
+    ns.close()
+    # (a) divergence history at dt = 0.01 up to t = pi/4
+    print("bench: ns divergence history", file=sys.stderr, flush=True)
+    ns = FractionalStep(n, re=re, sc=sc, dt=0.01, s=s)
+    ns.init_taylor_green()
+    divs = []
+    for _ in range(int(round(T / 0.01))):
+        ns.step(1)
+        divs.append(ns.errors()["div"])
+    ns.close()
+    # (b) temporal errors
+    errs = {}
+    for K in (8, 16, 32, 64):
+        print(f"bench: ns errors K={K}", file=sys.stderr, flush=True)
+        ns = FractionalStep(n, re=re, sc=sc, dt=T / K, s=s)
+        ns.init_taylor_green()
+        ns.step(K)
+        errs[K] = ns.errors()
+        ns.close()
+    Ks = sorted(errs)
+    orders = {key: [round(float(np.log2(errs[Ks[i]][key] / errs[Ks[i + 1]][key])), 3) for i in range(len(Ks) - 1)]
+              for key in ("u", "p", "rho")}
+    res = {"metric": f"fractional-step time steps/s, {n}^3 manufactured Taylor-Green (Re = Sc = 1, s = 10)",
+           "value": round(1e3 / ms_step, 3), "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": f"{n}^3 triply periodic box, eq. VDINSE.solexact forcing, Re = Sc = 1, s = 10, "
+                                  "dt = 0.01, solves to 1e-12 warm-started"},
+           "iterations_per_step": {"viscous_mean": float(np.mean(its_v)), "pressure_mean": float(np.mean(its_p)),
+                                   "viscous_max": int(max(its_v)), "pressure_max": int(max(its_p))},
+           "roofline": roof, "profile_classes": prof,
+           "divergence_rms": {"max": max(divs), "last": divs[-1], "steps": len(divs)},
+           "temporal_errors": {str(K): errs[K] for K in Ks}, "orders": orders}
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = ns_cpu_baseline(n)
+    print(json.dumps(res))
+
+
+def ns_cpu_baseline(n):
+    """One oracle step (NumPy FFTs, one BLAS thread) of the same problem."""
+    from threadpoolctl import threadpool_limits
+    from oracle import fractional_step as fs
+    st = fs.taylor_green_state(n, 10.0, 0.01)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        fs.step(st, 0.01, 1.0, 1.0, s=10.0)
+        el = time.perf_counter() - t0
+    return {"value": round(1.0 / el, 5), "unit": "steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle.fractional_step.step, 1 step at {n}^3 from the initial state, {el:.1f} s"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -566,10 +656,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--workload", choices=["c3", "serving", "c5", "c2", "pmc", "visc1d"], default="c3")
+    ap.add_argument("--workload", choices=["c3", "serving", "c5", "c2", "pmc", "visc1d", "ns"], default="c3")
     ap.add_argument("--requests", type=int, default=4096)
     ap.add_argument("--slots", type=int, default=8)
     ap.add_argument("--batch", type=int, default=8192)
+    ap.add_argument("--ns-n", type=int, default=128)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -589,6 +680,9 @@ def main():
         return
     if args.workload == "visc1d":
         bench_visc1d(args)
+        return
+    if args.workload == "ns":
+        bench_ns(args)
         return
 
     import numpy as np

@@ -290,6 +290,13 @@ vd_status vd_ns_get_state(vd_ns* h, double* u, double* rho, double* p, double* t
 /* err[0..3] = RMS over the grid of |u - u_e(t)|, p - p_e(t - dt/2),
  * rho - rho_e(t) (eq. VDINSE.solexact) and div u (requires s > 0). */
 vd_status vd_ns_errors(vd_ns* h, double* err);
+/* Optional timing of the handle's work with HIP events on its stream, by
+ * class: 0 the FFT transforms (algorithmic bytes 48 n^3 each: three passes
+ * reading and writing the field), 1 the pressure solves, 2 the viscous
+ * solve's inner products and updates.  Enabling resets the totals; reading
+ * returns milliseconds, launch counts and bytes per class. */
+vd_status vd_ns_profile_enable(vd_ns* h, int on);
+vd_status vd_ns_profile_read(vd_ns* h, double* ms, long long* count, double* bytes, int nclass);
 
 /* ------------------------------------------------------------------------
  * Continuous-batching solve server.  Not in the paper: a serving front end

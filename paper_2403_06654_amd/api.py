@@ -121,6 +121,8 @@ _SIGS = {
     "vd_ns_step": (_I, [_P, _I, ctypes.POINTER(vd_ns_info)]),
     "vd_ns_get_state": (_I, [_P, _P, _P, _P, ctypes.POINTER(_D)]),
     "vd_ns_errors": (_I, [_P, ctypes.POINTER(_D)]),
+    "vd_ns_profile_enable": (_I, [_P, _I]),
+    "vd_ns_profile_read": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(_D), _I]),
     "vd_server_create": (_I, [ctypes.POINTER(_P), ctypes.c_size_t, _I]),
     "vd_server_create_dry": (_I, [ctypes.POINTER(_P), ctypes.c_size_t, _I, _D]),
     "vd_server_submit": (_I, [_P, ctypes.POINTER(vd_request), ctypes.POINTER(ctypes.c_ulonglong)]),
@@ -428,6 +430,17 @@ class FractionalStep:
         e = (ctypes.c_double * 4)()
         _check(lib().vd_ns_errors(self._h, e), "vd_ns_errors", False)
         return {"u": e[0], "p": e[1], "rho": e[2], "div": e[3]}
+
+    def profile_enable(self, on=True):
+        _check(lib().vd_ns_profile_enable(self._h, 1 if on else 0), "vd_ns_profile_enable", False)
+
+    def profile_read(self):
+        ms = (ctypes.c_double * 3)()
+        cnt = (ctypes.c_longlong * 3)()
+        by = (ctypes.c_double * 3)()
+        _check(lib().vd_ns_profile_read(self._h, ms, cnt, by, 3), "vd_ns_profile_read", False)
+        names = ("transforms", "pressure_solves", "viscous_krylov_vector_ops")
+        return {names[c]: {"ms": ms[c], "count": cnt[c], "bytes": by[c]} for c in range(3)}
 
 
 class Server:

@@ -57,6 +57,18 @@ struct vd_ns {
   int nb = 0;
   std::vector<double> hpart;
   vd_ns_info last{};
+  // optional HIP-event timing by class: 0 FFT transforms, 1 pressure solves,
+  // 2 viscous Krylov inner products and updates
+  struct Pend {
+    int cls;
+    double bytes;
+    hipEvent_t a, b;
+  };
+  bool prof = false;
+  std::vector<Pend> pend;
+  std::vector<hipEvent_t> spare;
+  double pms[3] = {0, 0, 0}, pbytes[3] = {0, 0, 0};
+  long long pcnt[3] = {0, 0, 0};
 };
 
 namespace {
@@ -80,6 +92,11 @@ double* dalloc(vd_ns* h, size_t count) {
 }
 
 void release(vd_ns* h) {
+  for (auto& p : h->pend) {
+    hipEventDestroy(p.a);
+    hipEventDestroy(p.b);
+  }
+  for (hipEvent_t e : h->spare) hipEventDestroy(e);
   for (void* p : h->allocs) hipFree(p);
   if (h->grid) vd_grid_destroy(h->grid);
   delete h;
@@ -91,8 +108,54 @@ int hidx(int i, int j) {
   return t[i][j];
 }
 
-void fwd(vd_ns* h, const double* phys, void* spec) { fwd_transform(h->g, phys, spec, nullptr, h->tw, h->st); }
-void inv(vd_ns* h, const void* spec, double* phys) { inv_transform(h->g, spec, phys, h->swork, h->tw, h->st); }
+hipEvent_t ev(vd_ns* h) {
+  if (!h->spare.empty()) {
+    hipEvent_t e = h->spare.back();
+    h->spare.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  ck(hipEventCreate(&e));
+  return e;
+}
+
+// Bracket the work launched by fn with events when profiling.
+template <class F>
+void timed(vd_ns* h, int cls, double bytes, F fn) {
+  if (!h->prof) {
+    fn();
+    return;
+  }
+  vd_ns::Pend p{cls, bytes, ev(h), ev(h)};
+  ck(hipEventRecord(p.a, h->st));
+  fn();
+  ck(hipEventRecord(p.b, h->st));
+  h->pend.push_back(p);
+}
+
+void prof_flush(vd_ns* h) {
+  for (auto& p : h->pend) {
+    float ms = 0.f;
+    ck(hipEventElapsedTime(&ms, p.a, p.b));
+    h->pms[p.cls] += ms;
+    h->pbytes[p.cls] += p.bytes;
+    h->pcnt[p.cls] += 1;
+    h->spare.push_back(p.a);
+    h->spare.push_back(p.b);
+  }
+  h->pend.clear();
+}
+
+// One 3D transform is three passes (x rows, y and z columns), each reading
+// and writing the field once: 3 * 16 N algorithmic bytes.
+double transform_bytes(const vd_ns* h) { return 3.0 * 16.0 * (double)h->N; }
+
+void fwd(vd_ns* h, const double* phys, void* spec) {
+  timed(h, 0, transform_bytes(h), [&] { fwd_transform(h->g, phys, spec, nullptr, h->tw, h->st); });
+}
+void inv(vd_ns* h, const void* spec, double* phys) {
+  timed(h, 0, transform_bytes(h), [&] { inv_transform(h->g, spec, phys, h->swork, h->tw, h->st); });
+}
 
 void lin(vd_ns* h, double* out, size_t n, std::initializer_list<std::pair<double, const double*>> terms,
          std::initializer_list<std::pair<double, const double*>> dterms = {}, const double* den = nullptr,
@@ -223,7 +286,7 @@ void divgrad_pinv(vd_ns* h, const double* f, double* out) {
 
 // inner products of w with V_0..V_{nv-1} (stride between vectors), summed on the host
 void dots(vd_ns* h, const double* V, size_t stride, int nv, const double* w, size_t n, double* out) {
-  ns_dots(V, stride, nv, w, n, h->part, h->nb, h->st);
+  timed(h, 2, 8.0 * (double)n * (nv + 1), [&] { ns_dots(V, stride, nv, w, n, h->part, h->nb, h->st); });
   h->hpart.resize((size_t)nv * h->nb);
   ck(hipMemcpyAsync(h->hpart.data(), h->part, h->hpart.size() * sizeof(double), hipMemcpyDeviceToHost, h->st));
   ck(hipStreamSynchronize(h->st));
@@ -291,7 +354,7 @@ void solve_viscous(vd_ns* h, const double* b, double* x, int& iters, int& status
         dots(h, h->V, n3, j + 1, w, n3, c2.data());
         for (int i = 0; i <= j; ++i) cf[i] += c2[i];
         to_dev(h, c2.data(), j + 1);
-        ns_mupdate(h->V, n3, j + 1, h->dc, w, n3, 0, h->st);
+        timed(h, 2, 8.0 * (double)n3 * (j + 3), [&] { ns_mupdate(h->V, n3, j + 1, h->dc, w, n3, 0, h->st); });
       }
       const double hn = norm(h, w, n3);
       double hj = cf[0];
@@ -398,7 +461,8 @@ void step_once(vd_ns* h) {
   o.max_iter = h->prm.max_iter;
   o.use_x0 = 1;
   vd_solve_info pi{};
-  const vd_status ps = vd_solve_pressure(h->grid, h->sc1, h->phi, &o, &pi);
+  vd_status ps = VD_OK;
+  timed(h, 1, 0.0, [&] { ps = vd_solve_pressure(h->grid, h->sc1, h->phi, &o, &pi); });
   if (ps < 0 && ps != VD_NOT_CONVERGED) throw Err{ps};
   // 6. projection
   grad(h, h->phi, h->gp);
@@ -557,7 +621,13 @@ vd_status vd_ns_step(vd_ns* h, int nsteps, vd_ns_info* info) {
   if (!h || nsteps < 0) return VD_EINVAL;
   if (!h->have_state) return VD_EINVAL;
   try {
-    for (int k = 0; k < nsteps; ++k) step_once(h);
+    for (int k = 0; k < nsteps; ++k) {
+      step_once(h);
+      if (h->prof) {
+        ck(hipStreamSynchronize(h->st));
+        prof_flush(h);
+      }
+    }
     ck(hipStreamSynchronize(h->st));
     ck(hipGetLastError());
   } catch (const Err& e) {
@@ -601,6 +671,27 @@ vd_status vd_ns_errors(vd_ns* h, double* err) {
   } catch (const Err& e) {
     hipGetLastError();
     return e.s;
+  }
+  return VD_OK;
+}
+
+vd_status vd_ns_profile_enable(vd_ns* h, int on) {
+  if (!h) return VD_EINVAL;
+  h->prof = on != 0;
+  for (int c = 0; c < 3; ++c) {
+    h->pms[c] = 0;
+    h->pbytes[c] = 0;
+    h->pcnt[c] = 0;
+  }
+  return VD_OK;
+}
+
+vd_status vd_ns_profile_read(vd_ns* h, double* ms, long long* count, double* bytes, int nclass) {
+  if (!h || nclass < 0) return VD_EINVAL;
+  for (int c = 0; c < nclass && c < 3; ++c) {
+    if (ms) ms[c] = h->pms[c];
+    if (count) count[c] = h->pcnt[c];
+    if (bytes) bytes[c] = h->pbytes[c];
   }
   return VD_OK;
 }
