@@ -649,6 +649,40 @@ def ns_cpu_baseline(n):
             "sample": f"oracle.fractional_step.step, 1 step at {n}^3 from the initial state, {el:.1f} s"}
 
 
+def bench_kappa(args):
+    """Condition-number study (Sec. 3.1 Figs. 1-3 set-ups for V_rho, Sec. 4.2
+    Figs. 5-6 set-ups for L_rho and K_rho on periodic grids) with every
+    operator column computed by the library's GPU applications and kappa from
+    an SVD on the host; and iterations of the batched 1D viscous solver for
+    a in {1e-4, 1e-3, 1e-2} and s in {10, 100, 1000} (App. A set-up)."""
+    from paper_2403_06654_amd import conditioning as C
+    t0 = time.perf_counter()
+    out = {}
+    print("bench: kappa V_rho vs N", file=sys.stderr, flush=True)
+    out["visc_cheb_vs_N"] = {str(n): C.visc_kappa("cheb", n + 1, 1e-2, 2.0) for n in (16, 32, 64, 128, 256, 511)}
+    out["visc_fourier_vs_N"] = {str(n): C.visc_kappa("fourier", n, 1e-2, 2.0) for n in (16, 32, 64, 128, 256, 512)}
+    print("bench: kappa V_rho vs s, a", file=sys.stderr, flush=True)
+    out["visc_cheb_vs_s"] = {str(s): C.visc_kappa("cheb", 257, 1e-2, s)
+                             for s in (1.0, 2.0, 5.0, 10.0, 20.0, 50.0, 100.0, 200.0, 500.0, 1000.0)}
+    out["visc_cheb_vs_a"] = {str(a): C.visc_kappa("cheb", 257, a, 2.0) for a in (1e-4, 1e-3, 1e-2, 1e-1, 1.0)}
+    print("bench: kappa pressure", file=sys.stderr, flush=True)
+    out["pressure_fourier_vs_N"] = {str(n): C.pressure_kappa(n, 2.0) for n in (32, 64, 128, 256, 512)}
+    out["pressure_fourier_vs_s"] = {str(s): C.pressure_kappa(256, s)
+                                    for s in (0.1, 0.2, 0.5, 1.0, 2.0, 5.0, 10.0, 20.0, 50.0, 100.0)}
+    print("bench: viscous iterations", file=sys.stderr, flush=True)
+    out["visc_iterations"] = {f"{solver}_a{a:g}": C.viscous_iterations(257, a, (10.0, 100.0, 1000.0), solver)
+                              for solver in ("gmres", "rmr") for a in (1e-4, 1e-3, 1e-2)}
+    el = time.perf_counter() - t0
+    res = {"metric": "condition-number study wall time (GPU-assembled operators, host SVD)", "value": round(el, 2),
+           "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0, "higher_is_better": False, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "top-hat densities of eq. VDINSE.rho.hat (d = 0.1, x0 a fifth of the domain); "
+                                  "V_rho on Chebyshev (N+1 points, no-slip) and Fourier grids, a = dt/(2 Re); "
+                                  "L_rho and K_rho on periodic 1D grids"},
+           "kappa": out}
+    print(json.dumps(res))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -656,7 +690,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--workload", choices=["c3", "serving", "c5", "c2", "pmc", "visc1d", "ns"], default="c3")
+    ap.add_argument("--workload", choices=["c3", "serving", "c5", "c2", "pmc", "visc1d", "ns", "kappa"], default="c3")
     ap.add_argument("--requests", type=int, default=4096)
     ap.add_argument("--slots", type=int, default=8)
     ap.add_argument("--batch", type=int, default=8192)
@@ -683,6 +717,9 @@ def main():
         return
     if args.workload == "ns":
         bench_ns(args)
+        return
+    if args.workload == "kappa":
+        bench_kappa(args)
         return
 
     import numpy as np

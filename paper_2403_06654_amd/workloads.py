@@ -231,3 +231,9 @@ def visc1d_inputs(batch, n=257, s=1000.0, seed=0):
     b = rng.standard_normal((batch, n))
     b[:, 0] = b[:, -1] = 0.0
     return {"rho": np.ascontiguousarray(rho), "b": b, "x": x}
+
+
+def tophat(x, s, x0, d=0.1):
+    """Top-hat density of eq. VDINSE.rho.hat centred on 0:
+    1 + (s - 1)/2 [tanh((x + x0)/d) - tanh((x - x0)/d)]."""
+    return 1.0 + 0.5 * (s - 1.0) * (np.tanh((x + x0) / d) - np.tanh((x - x0) / d))

@@ -115,3 +115,21 @@ def test_convergence_statements():
     assert rmr["status"] == "not_converged"
     gm = krylov.gmres(lambda u: A @ u, b, lambda r: Vi @ r, restart=128, rtol=1e-10, max_iter=2000)
     assert gm["status"] == "converged"
+
+
+def test_conditioning_versus_density_ratio_and_viscosity():
+    """Sec. 3.1 (Figs. 2 and 3 set-ups, N = 256): the preconditioned
+    operators stay below O(10^2) for s up to 50 and for a up to 1, while
+    kappa(V_rho) and kappa(V) are O(10^4)-O(10^8)."""
+    def k(M):
+        s = np.linalg.svd(M, compute_uv=False)
+        return s[0] / s[-1]
+    for s in (2.0, 10.0, 50.0):
+        A, V = _cheb_case(256, s, 1e-2)
+        Vi = np.linalg.inv(V)
+        assert 1e4 < k(A) < 1e8 and 1e4 < k(V) < 1e8
+        assert k(Vi @ A) < 100 and k(A @ Vi) < 100
+    for a in (1e-4, 1e-2, 1.0):
+        A, V = _cheb_case(256, 2.0, a)
+        Vi = np.linalg.inv(V)
+        assert k(A) > 1e4 and k(Vi @ A) < 30 and k(A @ Vi) < 30
