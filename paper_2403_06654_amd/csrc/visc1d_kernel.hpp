@@ -188,28 +188,35 @@ __device__ __forceinline__ void gsum(double (&v)[NV], double* red, const Ln& l) 
   __syncthreads();
 }
 
-// w = V_rho z with z already in the operand buffer (and in registers).
+// w = V_rho z with z in the operand buffer.  D1 z and D2 z are two passes
+// over the buffer (one matrix each, fewer live registers than both at once);
+// z itself is read back from the buffer for the pointwise terms.
 template <int TPW>
-__device__ __forceinline__ void op_buf(const Visc1dArgs& a, const double* buf, const Vec<TPW>& z, Vec<TPW>& w,
-                                       const double* wca, const double* wrp, const double* wrpp, const Ln& l) {
-  Vec<TPW> acc[2];
-  const double* const M[2] = {a.D1I, a.D2I};
-  mv<TPW, 2>(M, Lay<TPW>::KT, buf, l, acc);
-  Vec<TPW> ca, rp, rpp;
-  vld(ca, wca, l);
-  vld(rp, wrp, l);
-  vld(rpp, wrpp, l);
+__device__ __forceinline__ void op_buf(const Visc1dArgs& a, const double* buf, Vec<TPW>& w, const double* wca,
+                                       const double* wrp, const double* wrpp, const Ln& l) {
+  Vec<TPW> d1[1], d2[1];
+  const double* const M1[1] = {a.D1I};
+  const double* const M2[1] = {a.D2I};
+  mv<TPW, 1>(M1, Lay<TPW>::KT, buf, l, d1);
+  mv<TPW, 1>(M2, Lay<TPW>::KT, buf, l, d2);
+  const v4d* zq = reinterpret_cast<const v4d*>(buf);
+  const v4d* caq = reinterpret_cast<const v4d*>(wca);
+  const v4d* rpq = reinterpret_cast<const v4d*>(wrp);
+  const v4d* rppq = reinterpret_cast<const v4d*>(wrpp);
 #pragma unroll
-  for (int t = 0; t < TPW; ++t)
+  for (int t = 0; t < TPW; ++t) {
+    const int i = vi4<TPW>(l, t);
+    const v4d z = zq[i], ca = caq[i], rp = rpq[i], rpp = rppq[i];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-      w.t[t][r] = z.t[t][r] - ca.t[t][r] * (acc[1].t[t][r] + rpp.t[t][r] * z.t[t][r] + rp.t[t][r] * acc[0].t[t][r]);
+      w.t[t][r] = z[r] - ca[r] * (d2[0].t[t][r] + rpp[r] * z[r] + rp[r] * d1[0].t[t][r]);
+  }
 }
 
 }  // namespace
 
 template <int TPW, int KIND>
-__global__ __launch_bounds__(kT) void k_visc1d(Visc1dArgs a) {
+__global__ __launch_bounds__(kT, (KIND == K_GMRES || TPW > 4) ? 1 : 2) void k_visc1d(Visc1dArgs a) {
   using L = Lay<TPW>;
   extern __shared__ __attribute__((aligned(32))) double lds[];
   const int m = KIND == K_GMRES ? a.restart : 0;
@@ -314,11 +321,11 @@ __global__ __launch_bounds__(kT) void k_visc1d(Visc1dArgs a) {
       Z = R;
     }
   };
-  // Wv = V_rho Z
+  // Wv = V_rho Z; Z stays in the operand buffer until the next product
   auto apply = [&](const Vec<TPW>& Z, Vec<TPW>& Wv) {
     vst(Z, buf, l);
     __syncthreads();
-    op_buf(a, buf, Z, Wv, wca, wrp, wrpp, l);
+    op_buf(a, buf, Wv, wca, wrp, wrpp, l);
     __syncthreads();
   };
   // R = b - V_rho X; returns ||R|| of this lane's system
@@ -363,8 +370,11 @@ __global__ __launch_bounds__(kT) void k_visc1d(Visc1dArgs a) {
     Vec<TPW> R;
 
     if constexpr (KIND == K_RMR) {
-      // z = M^-1 r; w = A z; alpha = (r, w) / (w, w); x += alpha z; r -= alpha w
+      // z = M^-1 r; w = A z; alpha = (r, w) / (w, w); x += alpha z; r -= alpha w.
+      // x lives in the workspace (read and written once per iteration) so that
+      // the registers hold two groups per CU.
       double rn = residual(X, R);
+      vst(X, wx, l);
       while (true) {
         if (!done) {
           rel = rn / bn;
@@ -386,9 +396,12 @@ __global__ __launch_bounds__(kT) void k_visc1d(Visc1dArgs a) {
         gsum<2>(s2, red, l);
         const double alpha = s2[1] > 0.0 ? s2[0] / s2[1] : 0.0;
         if (!done) {
+          // z is still in the operand buffer
+          v4d* xq = reinterpret_cast<v4d*>(wx);
+          const v4d* zq = reinterpret_cast<const v4d*>(buf);
 #pragma unroll
           for (int t = 0; t < TPW; ++t) {
-            X.t[t] += alpha * Z.t[t];
+            xq[vi4<TPW>(l, t)] += alpha * zq[vi4<TPW>(l, t)];
             R.t[t] -= alpha * Wv.t[t];
           }
           ++it;
@@ -399,14 +412,16 @@ __global__ __launch_bounds__(kT) void k_visc1d(Visc1dArgs a) {
         // the true residual now and then, against drift of the recurrence
         const bool need = !done && (rn / bn <= a.rtol || it % 50 == 0);
         if (__syncthreads_or(need)) {
-          Vec<TPW> R2;
-          const double rn2 = residual(X, R2);
+          Vec<TPW> R2, Xc;
+          vld(Xc, wx, l);
+          const double rn2 = residual(Xc, R2);
           if (need) {
             R = R2;
             rn = rn2;
           }
         }
       }
+      vld(X, wx, l);
       scatter(X);
     } else {
       // right-preconditioned GMRES(m), classical Gram-Schmidt applied twice
