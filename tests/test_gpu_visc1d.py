@@ -129,3 +129,58 @@ def test_edge_cases():
     with pytest.raises(VdError):
         h.apply(to_dev(bad), to_dev(b))
     h.close()
+
+
+def test_ragged_groups_restarts_and_mixed_outcomes():
+    """Batches that end inside a group of 16, GMRES cycles shorter than the
+    solve (restart 16), and a group whose systems stop at different
+    iterations or fail: every system gives the bits it gives alone and the
+    iteration count of the oracle's method."""
+    from paper_2403_06654_amd.api import Visc1d, VD_NOT_CONVERGED
+    n, a = 129, 1e-2
+    ratios = [1.5, 2.0, 3.0, 5.0, 8.0, 10.0] * 3   # 18 systems: groups of 16 and 2
+    _, rho, systems = _case("cheb", n, ratios, a)
+    b = np.random.default_rng(7).standard_normal(rho.shape)
+    h = Visc1d("cheb", n, a)
+    u, it, rr, info = h.solve(to_dev(rho), to_dev(b), solver="gmres", restart=16, max_iter=3000)
+    assert info["status"] == 0
+    u = to_host(u)
+    for k in (0, 5, 16, 17):
+        A, V = systems[k]
+        assert rel2(A @ u[k, 1:-1], b[k, 1:-1]) <= 1.01e-10
+        orc = krylov.gmres(lambda v: A @ v, b[k, 1:-1], lambda r: np.linalg.solve(V, r), rtol=1e-10,
+                           restart=16, max_iter=3000)
+        assert abs(int(it[k]) - orc["iterations"]) <= 2, (k, it[k], orc["iterations"])
+        u1, it1, _, _ = h.solve(to_dev(rho[k:k + 1]), to_dev(b[k:k + 1]), solver="gmres", restart=16, max_iter=3000)
+        assert np.array_equal(to_host(u1)[0], u[k]) and it1[0] == it[k]
+    # RMR: s = 100 fails at a = 1e-2 (Sec. 3.1) next to systems that converge
+    _, rho2, _ = _case("cheb", n, [2.0, 100.0, 5.0], a)
+    b2 = b[:3]
+    u2, it2, rr2, info2 = h.solve(to_dev(rho2), to_dev(b2), solver="rmr", max_iter=300)
+    assert info2["status"] == VD_NOT_CONVERGED
+    assert rr2[0] <= 1e-10 and rr2[2] <= 1e-10 and rr2[1] > 1e-10 and it2[1] == 300
+    u3, it3, _, _ = h.solve(to_dev(rho2[2:]), to_dev(b2[2:]), solver="rmr", max_iter=300)
+    assert np.array_equal(to_host(u3)[0], to_host(u2)[2]) and it3[0] == it2[2]
+    h.close()
+
+
+@pytest.mark.parametrize("basis,n", [("cheb", 512), ("fourier", 512)])
+def test_largest_systems_solve(basis, n):
+    """512 points (the kernel instantiations built apart, which spill)."""
+    from paper_2403_06654_amd.api import Visc1d
+    print(f"case visc1d solve largest {basis} n={n}", flush=True)
+    a = 1e-3
+    _, rho, systems = _case(basis, n, [2.0, 10.0], a)
+    b = np.random.default_rng(8).standard_normal(rho.shape)
+    h = Visc1d(basis, n, a)
+    for solver in ("gmres", "rmr"):
+        u, it, rr, info = h.solve(to_dev(rho), to_dev(b), solver=solver, restart=64, max_iter=3000)
+        assert info["status"] == 0, (solver, info)
+        u = to_host(u)
+        for k, (A, V) in enumerate(systems):
+            uk, bk = _inner(basis, u[k]), _inner(basis, b[k])
+            # 1e-10 plus the rounding of evaluating A u in a different order
+            # (n eps |A| |u|, relative to ||b||); ||D2|| ~ N^4 at 512 points
+            slack = n * np.finfo(float).eps * np.linalg.norm(np.abs(A) @ np.abs(uk)) / np.linalg.norm(bk)
+            assert rel2(A @ uk, bk) <= 1e-10 + slack, (solver, k, rel2(A @ uk, bk), slack)
+    h.close()
