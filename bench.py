@@ -164,12 +164,13 @@ def traffic_from_profiles(best_name):
 def csrc_hash():
     """Hash of the sources of the 3D solver kernels, so that stored counter
     readings are only used for the kernels they were taken on (the batched
-    1D viscous solver's files are not part of that path)."""
+    1D viscous solver's and the fractional-step driver's files are not part
+    of that path)."""
     from paper_2403_06654_amd.build import SOURCES
     d = os.path.join(ROOT, "paper_2403_06654_amd", "csrc")
     h = hashlib.sha256()
     for fn in sorted(os.listdir(d)):
-        if fn.startswith("visc1d"):
+        if fn.startswith(("visc1d", "ns")):
             continue
         if fn in SOURCES or fn.endswith(".hpp"):  # the library's sources
             h.update(fn.encode())
@@ -596,8 +597,10 @@ def bench_ns(args):
     ach = tr["bytes"] / (tr["ms"] * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": 8000.0, "unit": "GB/s", "frac": round(ach / 8000.0, 4),
             "traffic": None, "kernel": "FFT transform passes (k_row R2C/C2R, k_col FFT_FWD/FFT_INV)",
-            "per_unit": f"48 n^3 bytes per 3D transform (3 passes reading and writing the field), n = {n}",
-            "launches": tr["count"], "avg_us_per_transform": round(1e3 * tr["ms"] / max(tr["count"], 1), 2)}
+            "per_unit": f"48 n^3 bytes per 3D transform (3 passes reading and writing the field), n = {n}; "
+                        "a launch group is one transform or three batched",
+            "launches": tr["count"], "transforms": int(round(tr["bytes"] / (48.0 * n ** 3))),
+            "avg_us_per_transform": round(1e3 * tr["ms"] / max(tr["bytes"] / (48.0 * n ** 3), 1), 2)}
     ns.close()
     # (a) divergence history at dt = 0.01 up to t = pi/4
     print("bench: ns divergence history", file=sys.stderr, flush=True)

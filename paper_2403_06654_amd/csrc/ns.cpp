@@ -50,7 +50,8 @@ struct vd_ns {
   double *rho1 = nullptr, *rh = nullptr, *f = nullptr, *S = nullptr, *advu = nullptr, *advr = nullptr;
   double *rhs = nullptr, *ust = nullptr, *gp = nullptr, *lapb = nullptr, *d3 = nullptr, *w3 = nullptr;
   double *e3 = nullptr, *x3 = nullptr, *sc1 = nullptr;
-  void *s0 = nullptr, *s1 = nullptr, *s2 = nullptr, *swork = nullptr;
+  // spectral buffers: sa/sb/sc (three each) and the inverse transforms' scratch
+  void *sa[3] = {}, *sb[3] = {}, *sc[3] = {}, *wk[3] = {};
   double* V = nullptr;  // GMRES basis, (restart + 1) vectors of 3 N
   double* part = nullptr;
   double* dc = nullptr;
@@ -154,7 +155,14 @@ void fwd(vd_ns* h, const double* phys, void* spec) {
   timed(h, 0, transform_bytes(h), [&] { fwd_transform(h->g, phys, spec, nullptr, h->tw, h->st); });
 }
 void inv(vd_ns* h, const void* spec, double* phys) {
-  timed(h, 0, transform_bytes(h), [&] { inv_transform(h->g, spec, phys, h->swork, h->tw, h->st); });
+  timed(h, 0, transform_bytes(h), [&] { inv_transform(h->g, spec, phys, h->wk[0], h->tw, h->st); });
+}
+// three fields at once (the column passes take all three in one launch)
+void fwd3(vd_ns* h, const double* const* phys, void* const* spec) {
+  timed(h, 0, 3 * transform_bytes(h), [&] { fwd_transform_n(h->g, phys, spec, 3, h->tw, h->st); });
+}
+void inv3(vd_ns* h, const void* const* spec, double* const* phys) {
+  timed(h, 0, 3 * transform_bytes(h), [&] { inv_transform_n(h->g, spec, phys, h->wk, 3, h->tw, h->st); });
 }
 
 void lin(vd_ns* h, double* out, size_t n, std::initializer_list<std::pair<double, const double*>> terms,
@@ -178,56 +186,60 @@ void lin(vd_ns* h, double* out, size_t n, std::initializer_list<std::pair<double
 
 // out[d] = d f / dx_d
 void grad(vd_ns* h, const double* f, double* out) {
-  fwd(h, f, h->s0);
-  for (int d = 0; d < 3; ++d) {
-    ns_deriv(h->g, h->s0, h->s1, d, h->st);
-    inv(h, h->s1, out + d * h->N);
-  }
+  fwd(h, f, h->sa[0]);
+  for (int d = 0; d < 3; ++d) ns_deriv(h->g, h->sa[0], h->sb[d], d, h->st);
+  double* o[3] = {out, out + h->N, out + 2 * h->N};
+  inv3(h, h->sb, o);
 }
 
 void lap(vd_ns* h, const double* f, double* out) {
-  fwd(h, f, h->s0);
-  lap_packed(h->g, h->s0, h->s1, h->st);
-  inv(h, h->s1, out);
+  fwd(h, f, h->sa[0]);
+  lap_packed(h->g, h->sa[0], h->sb[0], h->st);
+  inv(h, h->sb[0], out);
 }
 
 void div(vd_ns* h, const double* u3, double* out) {
-  fwd(h, u3, h->s0);
-  ns_deriv(h->g, h->s0, h->s1, 0, h->st);
-  for (int d = 1; d < 3; ++d) {
-    fwd(h, u3 + d * h->N, h->s0);
-    ns_deriv(h->g, h->s0, h->s2, d, h->st);
-    lin(h, (double*)h->s1, 2 * h->nspec, {{1.0, (const double*)h->s1}, {1.0, (const double*)h->s2}});
-  }
-  inv(h, h->s1, out);
+  const double* in[3] = {u3, u3 + h->N, u3 + 2 * h->N};
+  fwd3(h, in, h->sa);
+  for (int d = 0; d < 3; ++d) ns_deriv(h->g, h->sa[d], h->sb[d], d, h->st);
+  lin(h, (double*)h->sb[0], 2 * h->nspec,
+      {{1.0, (const double*)h->sb[0]}, {1.0, (const double*)h->sb[1]}, {1.0, (const double*)h->sb[2]}});
+  inv(h, h->sb[0], out);
 }
 
 // gradient, Hessian and 1 / (rho Re) of a density
 void coefficients(vd_ns* h, const double* rho) {
-  fwd(h, rho, h->s0);
-  for (int i = 0; i < 3; ++i) {
-    ns_deriv(h->g, h->s0, h->s1, i, h->st);
-    inv(h, h->s1, h->cg + i * h->N);
-    for (int j = i; j < 3; ++j) {
-      ns_deriv(h->g, h->s1, h->s2, j, h->st);
-      inv(h, h->s2, h->ch + hidx(i, j) * h->N);
-    }
-  }
-  ns_recip(rho, h->prm.re, h->cirr, h->N, h->st);
+  const size_t N = h->N;
+  fwd(h, rho, h->sa[0]);
+  for (int i = 0; i < 3; ++i) ns_deriv(h->g, h->sa[0], h->sb[i], i, h->st);
+  double* g3[3] = {h->cg, h->cg + N, h->cg + 2 * N};
+  inv3(h, h->sb, g3);
+  // Hessian entries (0,0) (0,1) (0,2), then (1,1) (1,2) (2,2)
+  for (int d = 0; d < 3; ++d) ns_deriv(h->g, h->sb[0], h->sc[d], d, h->st);
+  double* h1[3] = {h->ch + hidx(0, 0) * N, h->ch + hidx(0, 1) * N, h->ch + hidx(0, 2) * N};
+  inv3(h, h->sc, h1);
+  ns_deriv(h->g, h->sb[1], h->sc[0], 1, h->st);
+  ns_deriv(h->g, h->sb[1], h->sc[1], 2, h->st);
+  ns_deriv(h->g, h->sb[2], h->sc[2], 2, h->st);
+  double* h2[3] = {h->ch + hidx(1, 1) * N, h->ch + hidx(1, 2) * N, h->ch + hidx(2, 2) * N};
+  inv3(h, h->sc, h2);
+  ns_recip(rho, h->prm.re, h->cirr, N, h->st);
 }
 
 // out = a x + b zeta(rho, x) for the density whose coefficients are loaded;
 // x and out are 3-field vectors and must not overlap.
 void zeta(vd_ns* h, const double* x, double a, double b, double* out) {
   const size_t N = h->N;
+  const double* in[3] = {x, x + N, x + 2 * N};
+  fwd3(h, in, h->sa);
   for (int i = 0; i < 3; ++i) {
-    fwd(h, x + i * N, h->s0);
-    lap_packed(h->g, h->s0, h->s1, h->st);
-    inv(h, h->s1, h->lapb);
-    for (int j = 0; j < 3; ++j) {
-      ns_deriv(h->g, h->s0, h->s1, j, h->st);
-      inv(h, h->s1, h->d3 + j * N);
-    }
+    lap_packed(h->g, h->sa[i], h->sb[0], h->st);
+    ns_deriv(h->g, h->sa[i], h->sb[1], 0, h->st);
+    ns_deriv(h->g, h->sa[i], h->sb[2], 1, h->st);
+    ns_deriv(h->g, h->sa[i], h->sc[0], 2, h->st);
+    double* o[3] = {h->lapb, h->d3, h->d3 + N};
+    inv3(h, h->sb, o);
+    inv(h, h->sc[0], h->d3 + 2 * N);
     ZetaArgs z{};
     for (int j = 0; j < 3; ++j) {
       z.u[j] = x + j * N;
@@ -259,18 +271,24 @@ void advect_vec(vd_ns* h, const double* u3, double* out3) {
   for (int i = 0; i < 3; ++i) advect_scalar(h, u3, u3 + i * h->N, out3 + i * h->N);
 }
 
-// out = (I - c Lap)^-1 x, componentwise (ncomp fields)
+// out = (I - c Lap)^-1 x, componentwise (1 or 3 fields)
 void helm_inv(vd_ns* h, const double* x, double c, double* out, int ncomp) {
   OpParams op{};
   op.kind = OP_HELMHOLTZ;
   op.rho0 = 1.0;
   op.nu = c;
   op.precond = 1;
-  for (int i = 0; i < ncomp; ++i) {
-    fwd(h, x + i * h->N, h->s0);
-    precond_apply<double>(h->g, op, h->s0, h->s1, h->st);
-    inv(h, h->s1, out + i * h->N);
+  if (ncomp == 3) {
+    const double* in[3] = {x, x + h->N, x + 2 * h->N};
+    double* o[3] = {out, out + h->N, out + 2 * h->N};
+    fwd3(h, in, h->sa);
+    for (int i = 0; i < 3; ++i) precond_apply<double>(h->g, op, h->sa[i], h->sb[i], h->st);
+    inv3(h, h->sb, o);
+    return;
   }
+  fwd(h, x, h->sa[0]);
+  precond_apply<double>(h->g, op, h->sa[0], h->sb[0], h->st);
+  inv(h, h->sb[0], out);
 }
 
 // out = (div grad)^-1 f (symbol -1 / sum_d k'_d^2, zero on its nullspace)
@@ -279,9 +297,9 @@ void divgrad_pinv(vd_ns* h, const double* f, double* out) {
   op.kind = OP_PRESSURE;
   op.rho0 = -1.0;
   op.precond = 1;
-  fwd(h, f, h->s0);
-  precond_apply<double>(h->g, op, h->s0, h->s1, h->st);
-  inv(h, h->s1, out);
+  fwd(h, f, h->sa[0]);
+  precond_apply<double>(h->g, op, h->sa[0], h->sb[0], h->st);
+  inv(h, h->sb[0], out);
 }
 
 // inner products of w with V_0..V_{nv-1} (stride between vectors), summed on the host
@@ -559,10 +577,12 @@ vd_status vd_ns_create(vd_ns** out, int n, const vd_ns_params* prm, hipStream_t 
     h->e3 = dalloc(h, 3 * N);
     h->x3 = dalloc(h, 3 * N);
     h->sc1 = dalloc(h, N);
-    h->s0 = dalloc(h, ns2);
-    h->s1 = dalloc(h, ns2);
-    h->s2 = dalloc(h, ns2);
-    h->swork = dalloc(h, ns2);
+    for (int i = 0; i < 3; ++i) {
+      h->sa[i] = dalloc(h, ns2);
+      h->sb[i] = dalloc(h, ns2);
+      h->sc[i] = dalloc(h, ns2);
+      h->wk[i] = dalloc(h, ns2);
+    }
     h->V = dalloc(h, (size_t)(p.restart + 1) * 3 * N);
     h->nb = ns_dot_blocks(3 * N);
     h->part = dalloc(h, (size_t)(p.restart + 1) * h->nb);

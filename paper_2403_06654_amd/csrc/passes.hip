@@ -762,6 +762,72 @@ void inv_transform(const Geom& g, const void* spec, double* phys, void* work, co
   launch_row<double, ROW_C2R>(g.M, r, twtab, st);
 }
 
+// nf <= 3 fields at once: the column passes take every field in one launch
+// (each block transforms its column of each field in turn), the x pass runs
+// per field.  work[f] are distinct spectral buffers (the inverse's scratch).
+void fwd_transform_n(const Geom& g, const double* const* phys, void* const* spec, int nf, const void* twtab,
+                     hipStream_t st) {
+  for (int f = 0; f < nf; ++f) {
+    RowArgs r = row_args(g, nullptr);
+    r.in[0] = phys[f];
+    r.out[0] = spec[f];
+    launch_row<double, ROW_R2C>(g.M, r, twtab, st);
+  }
+  if (g.cheb) return;
+  if (g.ny > 1) {
+    ColArgs b = col_args(g, nullptr);
+    b.outer = g.nz;
+    b.inner = g.M;
+    b.nf = nf;
+    for (int f = 0; f < nf; ++f) b.in[f] = b.out[f] = spec[f];
+    launch_col<double, COL_FFT_FWD>(g.ny, b, twtab, st);
+  }
+  if (g.nz > 1) {
+    ColArgs b = col_args(g, nullptr);
+    b.outer = 1;
+    b.inner = g.ny * g.M;
+    b.nf = nf;
+    for (int f = 0; f < nf; ++f) b.in[f] = b.out[f] = spec[f];
+    launch_col<double, COL_FFT_FWD>(g.nz, b, twtab, st);
+  }
+}
+
+void inv_transform_n(const Geom& g, const void* const* spec, double* const* phys, void* const* work, int nf,
+                     const void* twtab, hipStream_t st) {
+  const void* cur[3] = {spec[0], nf > 1 ? spec[1] : nullptr, nf > 2 ? spec[2] : nullptr};
+  if (g.nz > 1 && !g.cheb) {
+    ColArgs b = col_args(g, nullptr);
+    b.outer = 1;
+    b.inner = g.ny * g.M;
+    b.nf = nf;
+    for (int f = 0; f < nf; ++f) {
+      b.in[f] = cur[f];
+      b.out[f] = work[f];
+      cur[f] = work[f];
+    }
+    launch_col<double, COL_FFT_INV>(g.nz, b, twtab, st);
+  }
+  if (g.ny > 1) {
+    ColArgs b = col_args(g, nullptr);
+    b.outer = g.nz;
+    b.inner = g.M;
+    b.nf = nf;
+    for (int f = 0; f < nf; ++f) {
+      b.in[f] = cur[f];
+      b.out[f] = work[f];
+      cur[f] = work[f];
+    }
+    launch_col<double, COL_FFT_INV>(g.ny, b, twtab, st);
+  }
+  for (int f = 0; f < nf; ++f) {
+    RowArgs r = row_args(g, nullptr);
+    r.in[0] = cur[f];
+    r.out[0] = phys[f];
+    r.cscale = g.ntot_inv;
+    launch_row<double, ROW_C2R>(g.M, r, twtab, st);
+  }
+}
+
 template <typename R>
 void row_pass_p2(const Geom& g, void* f0, void* f1, const void* coef, const void* twtab, hipStream_t st, Prof* prof) {
   RowArgs r = row_args(g, nullptr);

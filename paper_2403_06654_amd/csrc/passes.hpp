@@ -77,6 +77,13 @@ void fwd_transform(const Geom& g, const double* phys, void* spec, void* work, co
 void inv_transform(const Geom& g, const void* spec, double* phys, void* work, const void* twtab,
                    hipStream_t st);
 
+// The same for nf <= 3 fields at once (column passes batched over the
+// fields); work[f] are distinct spectral buffers.
+void fwd_transform_n(const Geom& g, const double* const* phys, void* const* spec, int nf, const void* twtab,
+                     hipStream_t st);
+void inv_transform_n(const Geom& g, const void* const* spec, double* const* phys, void* const* work, int nf,
+                     const void* twtab, hipStream_t st);
+
 // y = Lap x on a packed FP64 spectrum (symbol -|k|^2, Nyquist kept); x != y.
 void lap_packed(const Geom& g, const void* x, void* y, hipStream_t st);
 
