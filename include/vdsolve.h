@@ -230,6 +230,10 @@ vd_status vd_visc1d_apply(vd_visc1d* h, int batch, const double* rho, const doub
  * RMR) is kept by the handle for later calls. */
 vd_status vd_visc1d_solve(vd_visc1d* h, int batch, const double* rho, const double* b, double* u,
                           const vd_solve_opts* opts, int* iterations, double* rel_residual, vd_solve_info* info);
+/* Duration in ms of the last apply or solve kernel, from HIP events recorded
+ * on the handle's stream immediately before and after its launch (0 before
+ * any call, -1 if the events could not be read). */
+vd_status vd_visc1d_kernel_ms(const vd_visc1d* h, double* ms);
 
 /* ------------------------------------------------------------------------
  * Fractional-step time integration of the variable-density incompressible

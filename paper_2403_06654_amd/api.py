@@ -123,6 +123,7 @@ _SIGS = {
     "vd_ns_errors": (_I, [_P, ctypes.POINTER(_D)]),
     "vd_ns_profile_enable": (_I, [_P, _I]),
     "vd_ns_profile_read": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(_D), _I]),
+    "vd_visc1d_kernel_ms": (_I, [_P, ctypes.POINTER(_D)]),
     "vd_server_create": (_I, [ctypes.POINTER(_P), ctypes.c_size_t, _I]),
     "vd_server_create_dry": (_I, [ctypes.POINTER(_P), ctypes.c_size_t, _I, _D]),
     "vd_server_submit": (_I, [_P, ctypes.POINTER(vd_request), ctypes.POINTER(ctypes.c_ulonglong)]),
@@ -370,6 +371,12 @@ class Visc1d:
                                    it.ctypes.data, rr.ctypes.data, ctypes.byref(info))
         _check(st, "vd_visc1d_solve")
         return u, it, rr, info.as_dict()
+
+    def kernel_ms(self):
+        """Duration of the last apply/solve kernel (HIP events around the launch)."""
+        ms = ctypes.c_double()
+        _check(lib().vd_visc1d_kernel_ms(self._h, ctypes.byref(ms)), "vd_visc1d_kernel_ms", False)
+        return ms.value
 
 
 class FractionalStep:

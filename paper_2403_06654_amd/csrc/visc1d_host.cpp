@@ -27,6 +27,8 @@ struct vd_visc1d {
   double* relres = nullptr;
   int* status = nullptr;
   size_t out_cap = 0;      // systems
+  hipEvent_t ev[2] = {nullptr, nullptr};  // around the last kernel launch
+  double last_ms = 0.0;
 };
 
 namespace {
@@ -127,6 +129,8 @@ bool upload_tiles(const std::vector<LD>& src, int n, int r0, int c0, int nr, int
 }
 
 void release(vd_visc1d* h) {
+  for (hipEvent_t e : h->ev)
+    if (e) hipEventDestroy(e);
   hipFree(h->D1I);
   hipFree(h->D2I);
   hipFree(h->VI);
@@ -208,6 +212,21 @@ vd_status vd_visc1d_destroy(vd_visc1d* h) {
   return VD_OK;
 }
 
+// Launch with HIP events on the handle's stream immediately around the kernel.
+static hipError_t launch_timed(vd_visc1d* h, const vd::Visc1dArgs& a) {
+  if (!h->ev[0] && (hipEventCreate(&h->ev[0]) != hipSuccess || hipEventCreate(&h->ev[1]) != hipSuccess))
+    return hipErrorOutOfMemory;
+  if (hipEventRecord(h->ev[0], h->st) != hipSuccess) return hipErrorUnknown;
+  const hipError_t e = vd::visc1d_launch(a, h->st);
+  if (e != hipSuccess) return e;
+  return hipEventRecord(h->ev[1], h->st);
+}
+
+static void read_time(vd_visc1d* h) {
+  float ms = 0.f;
+  h->last_ms = hipEventElapsedTime(&ms, h->ev[0], h->ev[1]) == hipSuccess ? ms : -1.0;
+}
+
 static vd::Visc1dArgs base_args(vd_visc1d* h, int batch, const double* rho, const double* b, double* x) {
   vd::Visc1dArgs a{};
   a.np = h->np;
@@ -274,11 +293,12 @@ vd_status vd_visc1d_apply(vd_visc1d* h, int batch, const double* rho, const doub
   a.iters = h->iters;
   a.relres = h->relres;
   a.status = h->status;
-  if (vd::visc1d_launch(a, h->st) != hipSuccess) {
+  if (launch_timed(h, a) != hipSuccess) {
     hipGetLastError();
     return VD_EDEVICE;
   }
   if (hipStreamSynchronize(h->st) != hipSuccess || hipGetLastError() != hipSuccess) return VD_EDEVICE;
+  read_time(h);
   std::vector<int> st(batch);
   if (hipMemcpy(st.data(), h->status, batch * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return VD_EDEVICE;
   for (int s : st)
@@ -313,7 +333,7 @@ vd_status vd_visc1d_solve(vd_visc1d* h, int batch, const double* rho, const doub
   a.iters = h->iters;
   a.relres = h->relres;
   a.status = h->status;
-  if (vd::visc1d_launch(a, h->st) != hipSuccess) {
+  if (launch_timed(h, a) != hipSuccess) {
     hipGetLastError();
     return VD_EDEVICE;
   }
@@ -324,6 +344,7 @@ vd_status vd_visc1d_solve(vd_visc1d* h, int batch, const double* rho, const doub
       hipMemcpyAsync(st.data(), h->status, batch * sizeof(int), hipMemcpyDeviceToHost, h->st) != hipSuccess ||
       hipStreamSynchronize(h->st) != hipSuccess || hipGetLastError() != hipSuccess)
     return VD_EDEVICE;
+  read_time(h);
   vd_status worst = VD_OK;
   vd_solve_info inf{};
   for (int i = 0; i < batch; ++i) {
@@ -338,6 +359,12 @@ vd_status vd_visc1d_solve(vd_visc1d* h, int batch, const double* rho, const doub
   inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (info) *info = inf;
   return worst;
+}
+
+vd_status vd_visc1d_kernel_ms(const vd_visc1d* h, double* ms) {
+  if (!h || !ms) return VD_EINVAL;
+  *ms = h->last_ms;
+  return VD_OK;
 }
 
 }  // extern "C"
