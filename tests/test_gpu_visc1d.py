@@ -184,3 +184,29 @@ def test_largest_systems_solve(basis, n):
             slack = n * np.finfo(float).eps * np.linalg.norm(np.abs(A) @ np.abs(uk)) / np.linalg.norm(bk)
             assert rel2(A @ uk, bk) <= 1e-10 + slack, (solver, k, rel2(A @ uk, bk), slack)
     h.close()
+
+
+def test_bench_configuration_sampled():
+    """The launch the bench times (8192 systems, 257 Chebyshev points,
+    s = 1000, a = 1e-3, exactly 40 RMR or GMRES(40) iterations): sampled
+    systems from both ends of the batch against the oracle's same 40
+    iterations.  The recurrences agree to rounding: 40 steps of a
+    kappa ~ 1e3 preconditioned operator leave ~1e-11, bound 1e-9."""
+    from paper_2403_06654_amd import workloads
+    from paper_2403_06654_amd.api import Visc1d
+    n, a, big = 257, 1e-3, 8192
+    inp = workloads.visc1d_inputs(big, n=n, s=1000.0, seed=0)
+    h = Visc1d("cheb", n, a)
+    for solver, kw in (("rmr", {}), ("gmres", {"restart": 40})):
+        print(f"case visc1d bench config {solver}", flush=True)
+        u, it, rr, info = h.solve(to_dev(inp["rho"]), to_dev(inp["b"]), solver=solver, rtol=1e-300, max_iter=40, **kw)
+        assert (it == 40).all()
+        u = to_host(u)
+        for k in (0, 1, 4095, 4096, 8190, 8191):
+            A, V = viscous.cheb_system(inp["rho"][k], a)
+            orc = getattr(krylov, solver)(lambda v: A @ v, inp["b"][k, 1:-1], lambda r: np.linalg.solve(V, r),
+                                          rtol=1e-300, max_iter=40, **kw)
+            assert orc["iterations"] == 40
+            assert rel2(u[k, 1:-1], orc["x"]) < 1e-9, (solver, k, rel2(u[k, 1:-1], orc["x"]))
+            assert abs(rr[k] / orc["rel_residual"] - 1.0) < 1e-6, (solver, k, rr[k], orc["rel_residual"])
+    h.close()
