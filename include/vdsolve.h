@@ -294,6 +294,14 @@ vd_status vd_ns_get_state(vd_ns* h, double* u, double* rho, double* p, double* t
 /* err[0..3] = RMS over the grid of |u - u_e(t)|, p - p_e(t - dt/2),
  * rho - rho_e(t) (eq. VDINSE.solexact) and div u (requires s > 0). */
 vd_status vd_ns_errors(vd_ns* h, double* err);
+/* The projection of Sec. 2, P_rho(u) = u - grad(phi) / rho with
+ * L_rho phi = div u (eq. VDINSE.Lrho.num without the 1/dt): an exact
+ * projection onto the (discretely) divergence-free fields, P_rho(P_rho(u)) =
+ * P_rho(u).  rho: device [n^3] (> 0); u, out: device [3][n^3] (out may equal
+ * u); the pressure solve uses the handle's pres_rtol, restart and max_iter
+ * and reports in info (may be NULL).  Uses the handle's scratch, not its
+ * state. */
+vd_status vd_ns_project(vd_ns* h, const double* rho, const double* u, double* out, vd_solve_info* info);
 /* Optional timing of the handle's work with HIP events on its stream, by
  * class: 0 the FFT transforms (algorithmic bytes 48 n^3 each: three passes
  * reading and writing the field), 1 the pressure solves, 2 the viscous

@@ -121,6 +121,7 @@ _SIGS = {
     "vd_ns_step": (_I, [_P, _I, ctypes.POINTER(vd_ns_info)]),
     "vd_ns_get_state": (_I, [_P, _P, _P, _P, ctypes.POINTER(_D)]),
     "vd_ns_errors": (_I, [_P, ctypes.POINTER(_D)]),
+    "vd_ns_project": (_I, [_P, _P, _P, _P, ctypes.POINTER(vd_solve_info)]),
     "vd_ns_profile_enable": (_I, [_P, _I]),
     "vd_ns_profile_read": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(_D), _I]),
     "vd_visc1d_kernel_ms": (_I, [_P, ctypes.POINTER(_D)]),
@@ -437,6 +438,16 @@ class FractionalStep:
         e = (ctypes.c_double * 4)()
         _check(lib().vd_ns_errors(self._h, e), "vd_ns_errors", False)
         return {"u": e[0], "p": e[1], "rho": e[2], "div": e[3]}
+
+    def project(self, rho, u, out=None):
+        """P_rho(u) = u - grad(phi) / rho, L_rho phi = div u (Sec. 2)."""
+        import torch
+        n = self.n
+        out = out if out is not None else torch.empty_like(u)
+        info = vd_solve_info()
+        _check(lib().vd_ns_project(self._h, _dev_f64(rho, (n, n, n), "rho"), _dev_f64(u, (3, n, n, n), "u"),
+                                   _dev_f64(out, (3, n, n, n), "out"), ctypes.byref(info)), "vd_ns_project")
+        return out, info.as_dict()
 
     def profile_enable(self, on=True):
         _check(lib().vd_ns_profile_enable(self._h, 1 if on else 0), "vd_ns_profile_enable", False)

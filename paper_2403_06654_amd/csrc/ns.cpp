@@ -695,6 +695,32 @@ vd_status vd_ns_errors(vd_ns* h, double* err) {
   return VD_OK;
 }
 
+vd_status vd_ns_project(vd_ns* h, const double* rho, const double* u, double* out, vd_solve_info* info) {
+  if (!h || !rho || !u || !out) return VD_EINVAL;
+  const size_t N = h->N;
+  vd_status ps = VD_OK;
+  try {
+    div(h, u, h->sc1);
+    if (vd_set_density(h->grid, rho) != VD_OK) return VD_EDOMAIN;
+    vd_solve_opts o;
+    vd_default_opts(&o);
+    o.solver = VD_GMRES;
+    o.restart = h->prm.restart;
+    o.rtol = h->prm.pres_rtol;
+    o.max_iter = h->prm.max_iter;
+    ps = vd_solve_pressure(h->grid, h->sc1, h->lapb, &o, info);
+    if (ps < 0 && ps != VD_NOT_CONVERGED) return ps;
+    grad(h, h->lapb, h->gp);
+    for (int i = 0; i < 3; ++i) lin(h, out + i * N, N, {{1.0, u + i * N}}, {{-1.0, h->gp + i * N}}, rho);
+    ck(hipStreamSynchronize(h->st));
+    ck(hipGetLastError());
+  } catch (const Err& e) {
+    hipGetLastError();
+    return e.s;
+  }
+  return ps;
+}
+
 vd_status vd_ns_profile_enable(vd_ns* h, int on) {
   if (!h) return VD_EINVAL;
   h->prof = on != 0;

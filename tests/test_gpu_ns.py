@@ -126,3 +126,24 @@ def test_full_size_128_matches_the_small_grid():
     for key in ("u", "p", "rho"):
         assert abs(e[key] / eo[key] - 1.0) < 1e-4, (key, e[key], eo[key])
     assert dmax < 1e-13
+
+
+def test_projection_is_exact_on_the_gpu():
+    """Sec. 2: P_rho is an exact projection; against the oracle's P_rho."""
+    from paper_2403_06654_amd.api import FractionalStep
+    n = 16
+    X, Y, Z = fs.mesh(n)
+    rho = 3.0 + np.sin(X) * np.cos(2 * Y) + 0.5 * np.sin(Z)
+    w = np.random.default_rng(0).standard_normal((3, n, n, n))
+    ns = FractionalStep(n, pres_rtol=1e-13)
+    pw, info = ns.project(to_dev(rho), to_dev(w))
+    assert info["status"] == 0
+    ppw, _ = ns.project(to_dev(rho), pw)
+    pw, ppw = to_host(pw), to_host(ppw)
+    _close(pw, fs.projection(w, rho), 1e-10)
+    assert fs.rms(fs.div(pw)) < 1e-11 * fs.rms(w)
+    assert np.abs(ppw - pw).max() < 1e-11 * np.abs(w).max()
+    v, _, _ = fs.exact(n, 0.0, 1.0)
+    pv, _ = ns.project(to_dev(rho), to_dev(v))
+    assert np.abs(to_host(pv) - v).max() < 1e-12
+    ns.close()
