@@ -110,6 +110,24 @@ def run_leg(grid, rho_dev, f_dev, g_dev, precision, steps, warmup, torch, profil
     }, (prof_warm, prof, cls)
 
 
+def apply_timing(grid, x, precision, torch, reps=20):
+    """The pressure operator alone: `reps` applications with the five pass
+    classes event-timed; time per apply = the sum of the per-pass averages,
+    bytes = their algorithmic bytes (23 field transfers of this precision)."""
+    grid.profile_read()
+    grid.profile_enable(0b11111)
+    for _ in range(reps):
+        grid.apply_operator("pressure", x, precision=precision)
+    torch.cuda.synchronize()
+    ms, cnt, nbytes = grid.profile_read()
+    grid.profile_enable(False)
+    t = sum(ms[c] / cnt[c] for c in range(5) if cnt[c])
+    b = sum(nbytes[c] / cnt[c] for c in range(5) if cnt[c])
+    gbs = b / (t * 1e-3) / 1e9
+    return {"ms": round(t, 4), "bytes": round(b), "GB_s": round(gbs, 1), "frac_of_hbm_peak": round(gbs / PEAK_HBM_GBS, 4),
+            "applies": reps}
+
+
 def dominant_class(prof):
     """Kernel class with the largest total event time."""
     ms = prof[0]
@@ -749,7 +767,14 @@ def main():
         r32, _ = run_leg(grid, rho_dev, f_dev, g_dev, "fp32_refine", args.steps, args.warmup, torch)
     print("bench: pressure forms (L_rho vs K_rho)", file=sys.stderr, flush=True)
     forms = pressure_forms(grid, rho_dev, f_dev, torch)
+    print("bench: operator applies (FP64, FP32)", file=sys.stderr, flush=True)
+    applies = {prec: apply_timing(grid, f_dev, prec, torch) for prec in ("fp64", "fp32")}
     grid.close()
+    # one GPU's share of a z-slab decomposition over 8 GPUs (local passes only)
+    slab = Grid((N // 8, N, N))
+    slab.set_density(rho_dev[1][: N // 8].contiguous())
+    applies["slab_share_fp64_32x256x256"] = apply_timing(slab, f_dev[: N // 8].contiguous(), "fp64", torch)
+    slab.close()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -783,6 +808,7 @@ def main():
                         if r32 else None),
         "roofline": roof,
         "operator_apply": op,
+        "operator_apply_direct": applies,
         "passes": passes,
         "passes_timed_over": "the warm-up steps (every class event-timed); the timed steps time only the roofline class",
         "pressure_forms": forms,
