@@ -276,8 +276,9 @@ typedef struct {
 } vd_ns_info;
 
 void vd_ns_default_params(vd_ns_params* p);
-/* VD_EINVAL for bad sizes or parameters; VD_ENOMEM.  The handle holds about
- * 40 + 3 (restart + 1) fields of n^3 doubles and a pressure grid. */
+/* VD_EINVAL for bad sizes or parameters; VD_ENOMEM.  The handle holds
+ * 65 + 3 (restart + 1) fields of n^3 doubles (2.7 GB at 128^3 with
+ * restart 30, 21 GB at 256^3) and a pressure grid. */
 vd_status vd_ns_create(vd_ns** out, int n, const vd_ns_params* prm, hipStream_t stream);
 vd_status vd_ns_destroy(vd_ns* h);
 /* Copy u^n, rho^n and p^(n-1/2) (device arrays) in and set the time; the
