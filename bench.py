@@ -716,8 +716,8 @@ def main():
     ap.add_argument("--ns-n", type=int, default=128)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on exactly one GPU; --gpus {args.gpus} is not supported "
-              f"(the multi-GPU design is described but not built)", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(the slab-decomposition design for several GPUs is described, not implemented)", file=sys.stderr)
         sys.exit(2)
     if args.workload == "serving":
         bench_serving(args)
