@@ -88,7 +88,18 @@ typedef struct {
   double rho0;       /* preconditioner density; NaN = mean of rho */
   int use_x0;        /* 1: the output array holds the initial guess on entry */
   int formulation;   /* pressure solves: vd_pressure_form (default VD_FORM_L) */
+  double* history;   /* optional host array for the residual history (default NULL) */
+  int history_cap;   /* its length in doubles (default 0: no history) */
 } vd_solve_opts;
+/* Residual history (the convergence curves of Secs. 3.1, 4.3): entry 0 is
+ * ||r_0|| / ||b||, then one entry per Krylov iteration with the method's own
+ * residual: GMRES the Givens estimate |g_(j+1)| / ||b|| (restarts add no
+ * entry), CG and RMR the recursively updated ||r|| / ||b||.  FP32_REFINE:
+ * the FP64 true residual before and after each refinement step.  Several
+ * components (vd_solve_helmholtz): component 0.  Batched 1D solves
+ * (vd_visc1d_solve): history_cap entries per system, rows one after another.
+ * At most history_cap entries are written; info->history_len says how many
+ * (for the batched solver: the longest row; row k holds iterations[k] + 1). */
 
 typedef struct {
   int status;            /* same as the return value */
@@ -98,6 +109,7 @@ typedef struct {
   double rhs_null_norm;  /* pressure: norm of the removed nullspace part of f */
   double seconds;        /* wall time of the solve on the host clock */
   int gs_second_passes;  /* GMRES: steps whose Gram-Schmidt needed a second pass */
+  int history_len;       /* entries written to opts->history */
 } vd_solve_info;
 
 typedef struct vd_grid vd_grid;

@@ -33,13 +33,14 @@ class vd_solve_opts(ctypes.Structure):
     _fields_ = [("solver", ctypes.c_int), ("restart", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("max_iter", ctypes.c_int), ("precond", ctypes.c_int), ("precision", ctypes.c_int),
                 ("inner_rtol", ctypes.c_double), ("max_outer", ctypes.c_int), ("rho0", ctypes.c_double),
-                ("use_x0", ctypes.c_int), ("formulation", ctypes.c_int)]
+                ("use_x0", ctypes.c_int), ("formulation", ctypes.c_int),
+                ("history", ctypes.POINTER(ctypes.c_double)), ("history_cap", ctypes.c_int)]
 
 
 class vd_solve_info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("iterations", ctypes.c_int), ("refinements", ctypes.c_int),
                 ("rel_residual", ctypes.c_double), ("rhs_null_norm", ctypes.c_double),
-                ("seconds", ctypes.c_double), ("gs_second_passes", ctypes.c_int)]
+                ("seconds", ctypes.c_double), ("gs_second_passes", ctypes.c_int), ("history_len", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -189,7 +190,9 @@ def dense_matmul(A, B, precision="fp64"):
 
 
 def make_opts(solver="gmres", restart=30, rtol=1e-10, max_iter=2000, precond=True, precision="fp64",
-              inner_rtol=1e-5, max_outer=10, rho0=float("nan"), use_x0=False, formulation="L"):
+              inner_rtol=1e-5, max_outer=10, rho0=float("nan"), use_x0=False, formulation="L", history=None):
+    """history: a contiguous float64 numpy array that receives the residual
+    history (its length is the capacity), or None."""
     o = vd_solve_opts()
     lib().vd_default_opts(ctypes.byref(o))
     o.solver = SOLVERS[solver] if isinstance(solver, str) else int(solver)
@@ -203,6 +206,12 @@ def make_opts(solver="gmres", restart=30, rtol=1e-10, max_iter=2000, precond=Tru
     o.rho0 = float(rho0)
     o.use_x0 = 1 if use_x0 else 0
     o.formulation = FORMULATIONS[formulation] if isinstance(formulation, str) else int(formulation)
+    if history is not None:
+        import numpy as np
+        if not (isinstance(history, np.ndarray) and history.dtype == np.float64 and history.flags.c_contiguous):
+            raise TypeError("history must be a contiguous float64 numpy array")
+        o.history = history.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        o.history_cap = int(history.size)
     return o
 
 
@@ -210,6 +219,14 @@ def workspace_bytes(shape, lengths=None, cheb=False, **opts):
     d = make_desc(shape, lengths, cheb)
     o = make_opts(**opts)
     return int(lib().vd_workspace_bytes(ctypes.byref(d), ctypes.byref(o)))
+
+
+def _with_history(info, opts):
+    d = info.as_dict()
+    h = opts.get("history")
+    if h is not None:
+        d["history"] = h.reshape(-1)[: d["history_len"]].copy() if h.ndim == 1 else h.copy()
+    return d
 
 
 def _check(st, where, allow_nc=True):
@@ -287,7 +304,7 @@ class Grid:
         st = lib().vd_solve_pressure(self._h, _dev_f64(f, self.shape, "f"), _dev_f64(p, self.shape, "p"),
                                      ctypes.byref(o), ctypes.byref(info))
         _check(st, "vd_solve_pressure")
-        return p, info.as_dict()
+        return p, _with_history(info, opts)
 
     def solve_helmholtz(self, g, dt_nu, u=None, **opts):
         import torch
@@ -300,7 +317,7 @@ class Grid:
         st = lib().vd_solve_helmholtz(self._h, float(dt_nu), int(ncomp), _dev_f64(g, shp, "g"),
                                       _dev_f64(u, shp, "u"), ctypes.byref(o), ctypes.byref(info))
         _check(st, "vd_solve_helmholtz")
-        return u, info.as_dict()
+        return u, _with_history(info, opts)
 
     def profile_enable(self, on=True):
         """on: True (every kernel class), False, or a bit mask of classes."""
@@ -364,14 +381,26 @@ class Visc1d:
         nb = self._batch(b, "b")
         if self._batch(rho, "rho") != nb or self._batch(u, "u") != nb:
             raise ValueError("batch sizes differ")
+        # history: entries per system (int), or a (batch, cap) float64 array
+        hist = opts.pop("history", None)
+        if hist is not None and not isinstance(hist, np.ndarray):
+            hist = np.zeros((nb, int(hist)))
         o = make_opts(**opts)
+        if hist is not None:
+            if hist.dtype != np.float64 or hist.ndim != 2 or hist.shape[0] != nb or not hist.flags.c_contiguous:
+                raise ValueError("history must be a contiguous float64 array of shape (batch, cap)")
+            o.history = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            o.history_cap = int(hist.shape[1])
         it = np.zeros(nb, dtype=np.int32)
         rr = np.zeros(nb, dtype=np.float64)
         info = vd_solve_info()
         st = lib().vd_visc1d_solve(self._h, nb, rho.data_ptr(), b.data_ptr(), u.data_ptr(), ctypes.byref(o),
                                    it.ctypes.data, rr.ctypes.data, ctypes.byref(info))
         _check(st, "vd_visc1d_solve")
-        return u, it, rr, info.as_dict()
+        d = info.as_dict()
+        if hist is not None:
+            d["history"] = hist
+        return u, it, rr, d
 
     def kernel_ms(self):
         """Duration of the last apply/solve kernel (HIP events around the launch)."""

@@ -257,6 +257,7 @@ struct SolveCfg {
   // never on an FP32 true residual, whose rounding floor can sit near the
   // inner tolerance; the FP64 outer loop owns the true-residual test.
   bool inner = false;
+  std::vector<double>* hist = nullptr;  // residual history sink (host), or none
 };
 constexpr int kInnerCycles = 3;
 
@@ -377,6 +378,7 @@ struct Krylov {
     } else {
       beta = true_resid(b, x, V[0]);
     }
+    if (cfg.hist) cfg.hist->push_back(beta / bnorm);
     int cycles = 0;
     while (true) {
       o.relres = beta / bnorm;
@@ -393,6 +395,7 @@ struct Krylov {
         gs_orthogonalize<R>(g, V[j + 1], P, j + 1, G->dst, G->partial, G->st, &G->prof);  // + Givens on column j
         sync_state(G);
         k = j + 1;
+        if (cfg.hist) cfg.hist->push_back(G->hst->resid / bnorm);
         if (G->hst->bad) { o.status = VD_EBREAKDOWN; return o; }
         if (G->hst->resid / bnorm <= cfg.rtol || o.iters >= cfg.max_iter) break;
       }
@@ -437,6 +440,7 @@ struct Krylov {
     void* p = buf(G, prec, B_P);
     void* q = buf(G, prec, B_Q);
     double rn = cfg.inner ? copy_rhs(b, r, bnorm) : true_resid(b, x, r);
+    if (cfg.hist) cfg.hist->push_back(rn / bnorm);
     while (true) {
       o.relres = rn / bnorm;
       if (!(rn == rn)) { o.status = VD_EBREAKDOWN; return o; }
@@ -453,6 +457,7 @@ struct Krylov {
         cg_alpha(G->dst, G->st);
         cg_xr<R>(g, x, r, p, q, G->dst, G->partial, &G->dst->nrm2, G->st);
         sync_state(G);
+        if (cfg.hist) cfg.hist->push_back(std::sqrt(std::fmax(G->hst->nrm2, 0.0)) / bnorm);
         if (G->hst->bad) { o.status = VD_EBREAKDOWN; return o; }
         if (std::sqrt(std::fmax(G->hst->nrm2, 0.0)) / bnorm <= cfg.rtol) break;
         if (cfg.inner && o.iters >= cfg.max_iter) break;
@@ -472,6 +477,7 @@ struct Krylov {
     void* r = buf(G, prec, B_R);
     void* w = buf(G, prec, B_W);
     double rn = cfg.inner ? copy_rhs(b, r, bnorm) : true_resid(b, x, r);
+    if (cfg.hist) cfg.hist->push_back(rn / bnorm);
     while (true) {
       o.relres = rn / bnorm;
       if (!(rn == rn)) { o.status = VD_EBREAKDOWN; return o; }
@@ -487,6 +493,7 @@ struct Krylov {
         prec_axpy(x, r, &G->dst->alpha);
         axpy_norm<R>(g, r, w, &G->dst->alpha, -1.0, G->partial, &G->dst->nrm2, G->st);
         sync_state(G);
+        if (cfg.hist) cfg.hist->push_back(std::sqrt(std::fmax(G->hst->nrm2, 0.0)) / bnorm);
         if (G->hst->bad) { o.status = VD_EBREAKDOWN; return o; }
         if (std::sqrt(std::fmax(G->hst->nrm2, 0.0)) / bnorm <= cfg.rtol) break;
       }
@@ -502,15 +509,17 @@ struct Krylov {
 
 // Solve A x = b in spectral space (b, x FP64 buffers of the grid).
 SolveOut solve_spectral(vd_grid* G, const vd_solve_opts& o, const OpParams& op, int coef, void* b64, void* x64,
-                        double bnorm, int* refinements) {
+                        double bnorm, int* refinements, std::vector<double>* hist = nullptr) {
   SolveCfg cfg{o.solver, o.restart, o.max_iter, o.rtol, op, coef};
   *refinements = 0;
   if (bnorm == 0.0) {
+    if (hist) hist->push_back(0.0);
     ck(hipMemsetAsync(x64, 0, G->nspec * 16, G->st));
     SolveOut s;
     return s;
   }
   if (o.precision == VD_FP64) {
+    cfg.hist = hist;
     Krylov<double> K(G, 64, cfg);
     return K.run(b64, x64, bnorm);
   }
@@ -527,6 +536,7 @@ SolveOut solve_spectral(vd_grid* G, const vd_solve_opts& o, const OpParams& op, 
   double rn = K64.true_resid(b64, x64, r64);
   while (true) {
     out.relres = rn / bnorm;
+    if (hist) hist->push_back(out.relres);
     if (!(rn == rn)) { out.status = VD_EBREAKDOWN; return out; }
     if (out.relres <= o.rtol) { out.status = VD_OK; return out; }
     if (*refinements >= o.max_outer || out.iters >= o.max_iter) { out.status = VD_NOT_CONVERGED; return out; }
@@ -594,6 +604,7 @@ bool opts_ok(const vd_solve_opts& o) {
   if (o.precision == VD_FP32_REFINE && (!(o.inner_rtol > 0.0) || o.inner_rtol >= 1.0 || o.max_outer < 1))
     return false;
   if (o.formulation != VD_FORM_L && o.formulation != VD_FORM_K) return false;
+  if (o.history_cap < 0 || (o.history_cap > 0 && !o.history)) return false;
   return true;
 }
 
@@ -680,6 +691,8 @@ void vd_default_opts(vd_solve_opts* o) {
   o->rho0 = NAN;
   o->use_x0 = 0;
   o->formulation = VD_FORM_L;
+  o->history = nullptr;
+  o->history_cap = 0;
 }
 
 const char* vd_status_string(vd_status s) {
@@ -971,7 +984,14 @@ static vd_status solve_impl(vd_grid* G, void* c) {
     }
     double bnorm = host_norm_of(G, b64);
     int refin = 0;
-    SolveOut so = solve_spectral(G, s->o, op, coef, b64, x64, bnorm, &refin);
+    std::vector<double> hist;
+    const bool want_hist = comp == 0 && s->o.history_cap > 0;
+    SolveOut so = solve_spectral(G, s->o, op, coef, b64, x64, bnorm, &refin, want_hist ? &hist : nullptr);
+    if (want_hist) {
+      const int nh = (int)std::min<size_t>(hist.size(), (size_t)s->o.history_cap);
+      std::copy(hist.begin(), hist.begin() + nh, s->o.history);
+      s->info.history_len = nh;
+    }
     // the Chebyshev preconditioner's pseudo-inverse is not Euclidean-orthogonal
     // to the nullspace: return the representative orthogonal to it
     if (G->g.cheb) c2_project(G->g, x64, G->dsmall + 1, G->st);

@@ -46,6 +46,8 @@ struct Visc1dArgs {
   int* iters;           // [batch]
   double* relres;       // [batch]
   int* status;          // [batch]
+  double* hist;         // [batch][hist_cap] residual histories, or null
+  int hist_cap;
 };
 
 size_t visc1d_work_doubles(int tpw, int mode, int solver, int restart);

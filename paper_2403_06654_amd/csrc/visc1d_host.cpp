@@ -2,6 +2,7 @@
 // differentiation matrices and (I - a D2)^-1 in long double, and the C ABI.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <new>
@@ -27,6 +28,8 @@ struct vd_visc1d {
   double* relres = nullptr;
   int* status = nullptr;
   size_t out_cap = 0;      // systems
+  double* hist = nullptr;  // device residual histories of the last solve
+  size_t hist_cap = 0;     // doubles
   hipEvent_t ev[2] = {nullptr, nullptr};  // around the last kernel launch
   double last_ms = 0.0;
 };
@@ -131,6 +134,7 @@ bool upload_tiles(const std::vector<LD>& src, int n, int r0, int c0, int nr, int
 void release(vd_visc1d* h) {
   for (hipEvent_t e : h->ev)
     if (e) hipEventDestroy(e);
+  hipFree(h->hist);
   hipFree(h->D1I);
   hipFree(h->D2I);
   hipFree(h->VI);
@@ -316,6 +320,19 @@ vd_status vd_visc1d_solve(vd_visc1d* h, int batch, const double* rho, const doub
   if (o.solver == VD_CG || o.precision != VD_FP64) return VD_ENOTSUP;
   if (o.solver != VD_GMRES && o.solver != VD_RMR) return VD_EINVAL;
   if (o.restart < 1 || o.restart > vd::kMaxVisc1dRestart || !(o.rtol > 0.0) || o.max_iter < 0) return VD_EINVAL;
+  if (o.history_cap < 0 || (o.history_cap > 0 && !o.history)) return VD_EINVAL;
+  const size_t hneed = (size_t)batch * (size_t)o.history_cap;
+  if (hneed > h->hist_cap) {
+    hipFree(h->hist);
+    h->hist = nullptr;
+    h->hist_cap = 0;
+    if (hipMalloc(&h->hist, hneed * sizeof(double)) != hipSuccess) {
+      hipGetLastError();
+      return VD_ENOMEM;
+    }
+    h->hist_cap = hneed;
+  }
+  if (hneed && hipMemsetAsync(h->hist, 0, hneed * sizeof(double), h->st) != hipSuccess) return VD_EDEVICE;
   const int m = o.restart;
   const int solver = o.solver == VD_RMR ? vd::VISC1D_RMR : vd::VISC1D_GMRES;
   const size_t per_group = vd::visc1d_work_doubles(h->tpw, vd::VISC1D_SOLVE, solver, m);
@@ -333,10 +350,14 @@ vd_status vd_visc1d_solve(vd_visc1d* h, int batch, const double* rho, const doub
   a.iters = h->iters;
   a.relres = h->relres;
   a.status = h->status;
+  a.hist = hneed ? h->hist : nullptr;
+  a.hist_cap = o.history_cap;
   if (launch_timed(h, a) != hipSuccess) {
     hipGetLastError();
     return VD_EDEVICE;
   }
+  if (hneed && hipMemcpyAsync(o.history, h->hist, hneed * sizeof(double), hipMemcpyDeviceToHost, h->st) != hipSuccess)
+    return VD_EDEVICE;
   std::vector<int> it(batch), st(batch);
   std::vector<double> rr(batch);
   if (hipMemcpyAsync(it.data(), h->iters, batch * sizeof(int), hipMemcpyDeviceToHost, h->st) != hipSuccess ||
@@ -356,6 +377,7 @@ vd_status vd_visc1d_solve(vd_visc1d* h, int batch, const double* rho, const doub
     else if (st[i] == VD_NOT_CONVERGED && worst == VD_OK) worst = VD_NOT_CONVERGED;
   }
   inf.status = worst;
+  inf.history_len = o.history_cap > 0 ? std::min(inf.iterations + 1, o.history_cap) : 0;
   inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (info) *info = inf;
   return worst;

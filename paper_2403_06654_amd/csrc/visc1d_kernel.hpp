@@ -300,6 +300,11 @@ __global__ __launch_bounds__(kT, (KIND == K_GMRES || TPW > 4) ? 1 : 2) void k_vi
       a.x[(size_t)(g0 + s) * np + (k < off ? k : ni + k)] = 0.0;
     }
   };
+  // residual history entry k of this lane's system (one writer per system)
+  double* hrow = a.hist ? a.hist + (size_t)(g0 + l.sl) * a.hist_cap : nullptr;
+  auto record = [&](int k, double v) {
+    if (hrow && live && l.wv == 0 && l.lq == 0 && k < a.hist_cap) hrow[k] = v;
+  };
   auto finish = [&](int it, double rel, int status) {
     if (l.wv == 0 && l.lq == 0 && live) {
       a.iters[g0 + l.sl] = bad ? 0 : it;
@@ -375,6 +380,8 @@ __global__ __launch_bounds__(kT, (KIND == K_GMRES || TPW > 4) ? 1 : 2) void k_vi
       // the registers hold two groups per CU.
       double rn = residual(X, R);
       vst(X, wx, l);
+      if (!done) record(0, rn / bn);
+      else if (bn == 0.0) record(0, 0.0);
       while (true) {
         if (!done) {
           rel = rn / bn;
@@ -408,7 +415,10 @@ __global__ __launch_bounds__(kT, (KIND == K_GMRES || TPW > 4) ? 1 : 2) void k_vi
         }
         double s1[1] = {pdot(R, R)};
         gsum<1>(s1, red, l);
-        if (!done) rn = sqrt(s1[0]);
+        if (!done) {
+          rn = sqrt(s1[0]);
+          record(it, rn / bn);
+        }
         // the true residual now and then, against drift of the recurrence
         const bool need = !done && (rn / bn <= a.rtol || it % 50 == 0);
         if (__syncthreads_or(need)) {
@@ -433,6 +443,8 @@ __global__ __launch_bounds__(kT, (KIND == K_GMRES || TPW > 4) ? 1 : 2) void k_vi
       const bool owner = l.wv == 0 && l.lq == 0;   // lanes 0..15 of wavefront 0 keep the per-system scalars
       double beta = residual(X, R);
       vst(X, wx, l);
+      if (!done) record(0, beta / bn);
+      else if (bn == 0.0) record(0, 0.0);
       while (true) {
         if (!done) {
           rel = beta / bn;
@@ -522,6 +534,7 @@ __global__ __launch_bounds__(kT, (KIND == K_GMRES || TPW > 4) ? 1 : 2) void k_vi
             const double gn = -sg * gj;
             wg[(j + 1) * kG + l.sl] = gn;
             wg[j * kG + l.sl] = c * gj;
+            record(it, fabs(gn) / bn);
             stop_s[l.sl] = (fabs(gn) / bn <= a.rtol || hn == 0.0 || it >= a.max_iter || !(rr == rr)) ? 1 : 0;
           }
           __syncthreads();

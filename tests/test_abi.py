@@ -36,6 +36,9 @@ def test_defaults():
     assert o.precond == 1 and o.precision == api.VD_FP64 and math.isnan(o.rho0)
     assert o.max_iter == 2000 and o.inner_rtol == 1e-5 and o.max_outer == 10
     assert o.use_x0 == 0 and o.formulation == api.VD_FORM_L
+    assert not o.history and o.history_cap == 0
+    # the ABI struct layouts the binding mirrors (C: 8-byte alignment)
+    assert ctypes.sizeof(api.vd_solve_opts) == 80 and ctypes.sizeof(api.vd_solve_info) == 48
 
 
 def test_status_strings():
