@@ -672,8 +672,10 @@ def bench_kappa(args):
     """Condition-number study (Sec. 3.1 Figs. 1-3 set-ups for V_rho, Sec. 4.2
     Figs. 5-6 set-ups for L_rho and K_rho on periodic grids) with every
     operator column computed by the library's GPU applications and kappa from
-    an SVD on the host; and iterations of the batched 1D viscous solver for
-    a in {1e-4, 1e-3, 1e-2} and s in {10, 100, 1000} (App. A set-up)."""
+    an SVD on the host; RMR and GMRES residual histories of the batched 1D
+    viscous solver (Fig. 4 set-up, N = 256, s = 2, a = 1e-3); and its
+    iterations for a in {1e-4, 1e-3, 1e-2} and s in {10, 100, 1000} (App. A
+    set-up)."""
     from paper_2403_06654_amd import conditioning as C
     t0 = time.perf_counter()
     out = {}
@@ -688,6 +690,10 @@ def bench_kappa(args):
     out["pressure_fourier_vs_N"] = {str(n): C.pressure_kappa(n, 2.0) for n in (32, 64, 128, 256, 512)}
     out["pressure_fourier_vs_s"] = {str(s): C.pressure_kappa(256, s)
                                     for s in (0.1, 0.2, 0.5, 1.0, 2.0, 5.0, 10.0, 20.0, 50.0, 100.0)}
+    print("bench: viscous histories", file=sys.stderr, flush=True)
+    out["visc_histories_N256_s2_a1e-3"] = {f"{basis}_{solver}": C.viscous_history(basis, 257 if basis == "cheb" else 256,
+                                                                                 1e-3, 2.0, solver)
+                                           for basis in ("cheb", "fourier") for solver in ("rmr", "gmres")}
     print("bench: viscous iterations", file=sys.stderr, flush=True)
     out["visc_iterations"] = {f"{solver}_a{a:g}": C.viscous_iterations(257, a, (10.0, 100.0, 1000.0), solver)
                               for solver in ("gmres", "rmr") for a in (1e-4, 1e-3, 1e-2)}

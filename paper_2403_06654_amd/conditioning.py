@@ -106,3 +106,18 @@ def viscous_iterations(n, a, s_list, solver, seed=0, rtol=1e-10, max_iter=2000, 
                            max_iter=max_iter, restart=restart)
     h.close()
     return {str(s): (int(i) if r <= rtol else None) for s, i, r in zip(s_list, it, rr)}
+
+
+def viscous_history(basis, n, a, s, solver, seed=0, rtol=1e-10, max_iter=2000, restart=128):
+    """Residual history ||r_k|| / ||b|| of the batched GPU solver for one
+    system (Fig. 4 set-up: the paper plots these curves)."""
+    import torch
+    rho = visc_density(basis, n, s)[None, :]
+    b = np.random.default_rng(seed).standard_normal(rho.shape)
+    if basis == "cheb":
+        b[:, 0] = b[:, -1] = 0.0
+    h = Visc1d(basis, n, a)
+    _, it, rr, info = h.solve(torch.from_numpy(rho).cuda(), torch.from_numpy(b).cuda(), solver=solver, rtol=rtol,
+                              max_iter=max_iter, restart=restart, history=max_iter + 1)
+    h.close()
+    return [float(v) for v in info["history"][0, : int(it[0]) + 1]]
