@@ -277,6 +277,8 @@ typedef struct {
   double pres_rtol;   /* pressure solve: relative true residual (default 1e-12) */
   int restart;        /* GMRES restart of both solves, 1..30 (default 30) */
   int max_iter;       /* per solve (default 2000) */
+  int pres_solver;    /* pressure solve: VD_GMRES (default), VD_CG or VD_RMR */
+  int pres_form;      /* pressure solve: VD_FORM_L (default) or VD_FORM_K (eq. VDINSE.Krho) */
 } vd_ns_params;
 
 typedef struct {
@@ -285,6 +287,7 @@ typedef struct {
   int visc_iters, pres_iters;            /* Krylov iterations of the last step */
   int visc_status, pres_status;          /* vd_status of the last step's solves */
   double visc_rel_residual, pres_rel_residual;
+  double pres_seconds;       /* host wall time of the last step's pressure solve */
 } vd_ns_info;
 
 void vd_ns_default_params(vd_ns_params* p);

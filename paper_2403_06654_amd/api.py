@@ -77,13 +77,14 @@ class vd_server_stats_t(ctypes.Structure):
 class vd_ns_params(ctypes.Structure):
     _fields_ = [("re", ctypes.c_double), ("sc", ctypes.c_double), ("dt", ctypes.c_double), ("s", ctypes.c_double),
                 ("visc_rtol", ctypes.c_double), ("pres_rtol", ctypes.c_double), ("restart", ctypes.c_int),
-                ("max_iter", ctypes.c_int)]
+                ("max_iter", ctypes.c_int), ("pres_solver", ctypes.c_int), ("pres_form", ctypes.c_int)]
 
 
 class vd_ns_info(ctypes.Structure):
     _fields_ = [("t", ctypes.c_double), ("steps", ctypes.c_int), ("visc_iters", ctypes.c_int),
                 ("pres_iters", ctypes.c_int), ("visc_status", ctypes.c_int), ("pres_status", ctypes.c_int),
-                ("visc_rel_residual", ctypes.c_double), ("pres_rel_residual", ctypes.c_double)]
+                ("visc_rel_residual", ctypes.c_double), ("pres_rel_residual", ctypes.c_double),
+                ("pres_seconds", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -414,7 +415,7 @@ class FractionalStep:
     equations on [0, 2 pi)^3 (vd_ns_*)."""
 
     def __init__(self, n, re=1.0, sc=1.0, dt=0.01, s=0.0, visc_rtol=1e-12, pres_rtol=1e-12, restart=30,
-                 max_iter=2000, stream=None):
+                 max_iter=2000, pres_solver="gmres", pres_form="L", stream=None):
         import torch
         self.n = int(n)
         self._stream = stream if stream is not None else torch.cuda.current_stream()
@@ -423,6 +424,8 @@ class FractionalStep:
         prm.re, prm.sc, prm.dt, prm.s = float(re), float(sc), float(dt), float(s)
         prm.visc_rtol, prm.pres_rtol = float(visc_rtol), float(pres_rtol)
         prm.restart, prm.max_iter = int(restart), int(max_iter)
+        prm.pres_solver = SOLVERS[pres_solver]
+        prm.pres_form = FORMULATIONS[pres_form]
         h = ctypes.c_void_p()
         _check(lib().vd_ns_create(ctypes.byref(h), self.n, ctypes.byref(prm),
                                   ctypes.c_void_p(self._stream.cuda_stream)), "vd_ns_create", False)

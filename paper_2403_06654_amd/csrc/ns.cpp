@@ -473,7 +473,8 @@ void step_once(vd_ns* h) {
   if (vd_set_density(h->grid, h->rh) != VD_OK) throw Err{VD_EDOMAIN};
   vd_solve_opts o;
   vd_default_opts(&o);
-  o.solver = VD_GMRES;
+  o.solver = h->prm.pres_solver;
+  o.formulation = h->prm.pres_form;
   o.restart = h->prm.restart;
   o.rtol = h->prm.pres_rtol;
   o.max_iter = h->prm.max_iter;
@@ -504,6 +505,7 @@ void step_once(vd_ns* h) {
   h->last.pres_iters = pi.iterations;
   h->last.pres_status = ps;
   h->last.pres_rel_residual = pi.rel_residual;
+  h->last.pres_seconds = pi.seconds;
 }
 
 }  // namespace
@@ -520,6 +522,8 @@ void vd_ns_default_params(vd_ns_params* p) {
   p->pres_rtol = 1e-12;
   p->restart = 30;
   p->max_iter = 2000;
+  p->pres_solver = VD_GMRES;
+  p->pres_form = VD_FORM_L;
 }
 
 vd_status vd_ns_create(vd_ns** out, int n, const vd_ns_params* prm, hipStream_t stream) {
@@ -532,6 +536,9 @@ vd_status vd_ns_create(vd_ns** out, int n, const vd_ns_params* prm, hipStream_t 
   if (!(p.re > 0) || !(p.sc > 0) || !(p.dt > 0) || !(p.s >= 0) || !std::isfinite(p.re + p.sc + p.dt + p.s))
     return VD_EINVAL;
   if (!(p.visc_rtol > 0) || !(p.pres_rtol > 0) || p.restart < 1 || p.restart > 30 || p.max_iter < 1)
+    return VD_EINVAL;
+  if ((p.pres_solver != VD_GMRES && p.pres_solver != VD_CG && p.pres_solver != VD_RMR) ||
+      (p.pres_form != VD_FORM_L && p.pres_form != VD_FORM_K))
     return VD_EINVAL;
   vd_ns* h = new (std::nothrow) vd_ns();
   if (!h) return VD_ENOMEM;

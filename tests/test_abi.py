@@ -109,9 +109,11 @@ def test_fractional_step_rejects_bad_parameters_without_touching_the_device():
     prm = api.vd_ns_params()
     L.vd_ns_default_params(ctypes.byref(prm))
     assert (prm.re, prm.sc, prm.visc_rtol, prm.pres_rtol, prm.restart) == (1.0, 1.0, 1e-12, 1e-12, 30)
+    assert (prm.pres_solver, prm.pres_form) == (api.VD_GMRES, api.VD_FORM_L)
     for n in (8, 48, 1024):
         assert L.vd_ns_create(ctypes.byref(h), n, ctypes.byref(prm), None) == -1
-    for field, bad in (("dt", 0.0), ("re", -1.0), ("s", -2.0), ("restart", 31), ("visc_rtol", 0.0)):
+    for field, bad in (("dt", 0.0), ("re", -1.0), ("s", -2.0), ("restart", 31), ("visc_rtol", 0.0),
+                       ("pres_solver", 7), ("pres_form", 2)):
         p = api.vd_ns_params()
         L.vd_ns_default_params(ctypes.byref(p))
         setattr(p, field, bad)
