@@ -147,3 +147,30 @@ def test_projection_is_exact_on_the_gpu():
     pv, _ = ns.project(to_dev(rho), to_dev(v))
     assert np.abs(to_host(pv) - v).max() < 1e-12
     ns.close()
+
+
+@pytest.mark.parametrize("solver,form", [("rmr", "K"), ("cg", "L")])
+def test_pressure_solver_and_form_choices(solver, form):
+    """The Table 2 configuration (K_rho form, RMR) and CG on L_rho inside the
+    step: the K_rho solution differs from the L_rho one only by the two
+    discretisations of the same equation (spectrally small for these smooth
+    fields), so the fields agree with the oracle's L_rho run to 1e-8.  With
+    L_rho the projection is exact and div u stays at rounding; with K_rho the
+    discrete K_rho = Lap - grad(ln rho).grad equals rho div(rho^-1 grad) only
+    up to the pseudo-spectral product-rule (aliasing) error, so div u sits at
+    that level (1e-9 here on 16^3), not at rounding."""
+    from paper_2403_06654_amd.api import FractionalStep
+    n, K = 16, 4
+    dt = T / 8
+    ns = FractionalStep(n, re=RE, sc=SC, dt=dt, s=S, pres_solver=solver, pres_form=form)
+    ns.init_taylor_green()
+    st = fs.taylor_green_state(n, S, dt)
+    for _ in range(K):
+        info = ns.step(1)
+        assert info["pres_status"] == 0 and info["pres_seconds"] > 0
+        fs.step(st, dt, RE, SC, s=S)
+    u, rho, p, _ = ns.state()
+    _close(to_host(u), st.u, 1e-8)
+    _close(to_host(rho), st.rho, 1e-8)
+    assert ns.errors()["div"] < (1e-12 if form == "L" else 1e-7)
+    ns.close()
