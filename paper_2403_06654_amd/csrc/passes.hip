@@ -304,7 +304,14 @@ __global__ __launch_bounds__(64 * row_waves<MODE>()) void k_row(RowArgs a, const
   const int fsel = MODE == ROW_P ? wave : 0;
   const int t = lane % T;
   const int rr = (MODE == ROW_P ? 0 : wave * RW) + lane / T;  // row within the block
-  const int row = blockIdx.x * RB + rr;
+  // The x passes sweep the rows last block first: the pass before them (a
+  // y pass, ascending z) leaves its most recent output in the 256 MB
+  // Infinity Cache, and the y pass after them (ascending z again) starts on
+  // what this pass wrote last.  At 256^3 FP64 the three pressure fields
+  // (384 MiB) exceed that cache; the reversed sweep takes the x pass from
+  // 218 to 199 us and the following y pass from 130 to 114 us.
+  const int bx = (MODE == ROW_P || MODE == ROW_H) ? (int)(gridDim.x - 1 - blockIdx.x) : (int)blockIdx.x;
+  const int row = bx * RB + rr;
   const bool ok = row < a.nrows;
   LdsRow<R> lds{lds_all + (MODE == ROW_P ? fsel * RW + rr : rr) * LP};
   const R sx = R(a.g.sx);

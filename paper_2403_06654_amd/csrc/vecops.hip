@@ -279,7 +279,13 @@ __global__ __launch_bounds__(256) void k_gs_update(C2<R>* __restrict__ x, VecPtr
   double acc[NV + 1];
 #pragma unroll
   for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
-  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+  // Same elements per thread as the dot pass, visited in the opposite order:
+  // the dot pass ends on the top of every vector, which is then still in the
+  // Infinity Cache (measured 299 -> 294 us at 256^3 FP64, 13 streams).
+  const size_t stride = (size_t)gridDim.x * 256, e0 = (size_t)blockIdx.x * 256 + threadIdx.x;
+  for (size_t k = (n + stride - 1) / stride; k-- > 0;) {
+    const size_t e = k * stride + e0;
+    if (e >= n) continue;
     C2<R> vv[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i)
