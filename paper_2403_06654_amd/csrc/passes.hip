@@ -93,6 +93,7 @@ struct ColArgs {
   double rho0, nu;
   int precond;
   const double* in_scale;
+  const int* gate;  // nonzero *gate: the launch does nothing
 };
 
 template <int L, int E, int RPAT, typename R>
@@ -123,6 +124,7 @@ __global__ __launch_bounds__(256) void k_col(ColArgs a, const C2<R>* __restrict_
   constexpr int R0 = S::template first_radix<false>();
   constexpr int R1 = S::template last_radix<false>();
   constexpr int LDSN = S::npass > 1 ? TC * L : 1;
+  if (a.gate && *a.gate) return;  // whole grid: the flag is written before the launch
   __shared__ C2<R> lds_raw[LDSN];
   // twiddle table staged in LDS (see k_row)
   __shared__ C2<R> tw_lds[L];
@@ -266,6 +268,7 @@ struct RowArgs {
   double rho0, nu;
   int precond;
   const double* in_scale;
+  const int* gate;  // nonzero *gate: the launch does nothing
 };
 
 // Wavefronts per block: the pressure x pass runs its (up to three) fields as
@@ -285,6 +288,7 @@ __global__ __launch_bounds__(64 * row_waves<MODE>()) void k_row(RowArgs a, const
   static_assert(RI1 == RF0, "pattern mismatch");
   constexpr int NW = row_waves<MODE>();
   constexpr int RB = MODE == ROW_P ? RW : NW * RW;  // rows per block
+  if (a.gate && *a.gate) return;
   __shared__ C2<R> lds_all[NW * RW * LP];
   // twiddle tables in LDS: a load in every butterfly pass from global memory
   // (even an L1 hit) costs latency inside the transform and address registers
@@ -568,7 +572,15 @@ static ColArgs col_args(const Geom& g, const OpParams* p) {
     a.nu = p->nu;
     a.precond = p->precond;
     a.in_scale = p->in_scale;
+    a.gate = p->gate;
   }
+  return a;
+}
+// a plain transform pass of an operator application: no operator
+// parameters, but the application's gate
+static ColArgs col_args_fft(const Geom& g, const OpParams& p) {
+  ColArgs a = col_args(g, nullptr);
+  a.gate = p.gate;
   return a;
 }
 static RowArgs row_args(const Geom& g, const OpParams* p) {
@@ -580,6 +592,7 @@ static RowArgs row_args(const Geom& g, const OpParams* p) {
     a.nu = p->nu;
     a.precond = p->precond;
     a.in_scale = p->in_scale;
+    a.gate = p->gate;
   }
   return a;
 }
@@ -669,7 +682,7 @@ void op_apply(const Geom& g, const OpParams& p, const void* v, void* y, const Op
     a.out[0] = t0;
     VD_T0(5) launch_col<R, COL_H_FIRST>(g.nz, a, twtab, st); VD_T1()
     if (g.ny > 1) {
-      ColArgs b = col_args(g, nullptr);
+      ColArgs b = col_args_fft(g, p);
       b.outer = g.nz;
       b.inner = g.M;
       b.nf = 1;
@@ -684,7 +697,7 @@ void op_apply(const Geom& g, const OpParams& p, const void* v, void* y, const Op
     r.cscale = g.ntot_inv;
     VD_T0(7) launch_row<R, ROW_H>(g.M, r, twtab, st); VD_T1()
     if (g.ny > 1) {
-      ColArgs b = col_args(g, nullptr);
+      ColArgs b = col_args_fft(g, p);
       b.outer = g.nz;
       b.inner = g.M;
       b.nf = 1;

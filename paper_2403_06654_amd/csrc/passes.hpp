@@ -27,6 +27,7 @@ struct OpParams {
   double nu;                 // Helmholtz coefficient (dt * nu)
   int precond;               // apply the constant-density inverse to the input first
   const double* in_scale;    // optional device scalar multiplying the input
+  const int* gate = nullptr; // optional device flag: when nonzero every pass returns at once
 };
 
 // Work buffers of one operator application (spectral, same precision as the
@@ -57,6 +58,11 @@ struct Prof {
   void begin(int cls, hipStream_t s, double nbytes = 0);
   void end(hipStream_t s);
   void flush();  // accumulate completed pairs (call after a stream sync)
+  // accumulate the oldest n pairs only (their end events must have completed)
+  void flush_front(size_t n);
+  // forget the pending pairs without accumulating them (launches that exited
+  // at their gate)
+  void drop();
   void release();
 };
 

@@ -69,14 +69,24 @@ void Prof::end(hipStream_t s) {
   pending.push_back(Pair{cur, cur_bytes, cur_a, b});
   cur = -1;
 }
-void Prof::flush() {
-  for (auto& p : pending) {
+void Prof::flush() { flush_front(pending.size()); }
+void Prof::flush_front(size_t n) {
+  n = std::min(n, pending.size());
+  for (size_t i = 0; i < n; ++i) {
+    const Pair& p = pending[i];
     float ms_ = 0.f;
     if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms_, p.a, p.b) == hipSuccess) {
       ms[p.cls] += ms_;
       bytes[p.cls] += p.bytes;
       cnt[p.cls] += 1;
     }
+    spare.push_back(p.a);
+    spare.push_back(p.b);
+  }
+  pending.erase(pending.begin(), pending.begin() + n);
+}
+void Prof::drop() {
+  for (const Pair& p : pending) {
     spare.push_back(p.a);
     spare.push_back(p.b);
   }
@@ -109,6 +119,8 @@ struct vd_grid {
   double* dsmall = nullptr;   // misc device scalars
   DevState* dst = nullptr;    // device solver state
   DevState* hst = nullptr;    // pinned host mirror
+  DevState* hslot = nullptr;  // two pinned mirrors of the state's tail, one per queued GMRES step
+  hipEvent_t slot_ev[2] = {nullptr, nullptr};
   std::map<int, void*> bufs;  // spectral vectors by (precision, role)
   Prof prof;
   // Chebyshev wall-normal direction (g.cheb)
@@ -300,10 +312,11 @@ struct Krylov {
     }
   }
 
-  void apply(const void* v, void* y, bool with_prec, const double* in_scale = nullptr) {
+  void apply(const void* v, void* y, bool with_prec, const double* in_scale = nullptr, const int* gate = nullptr) {
     OpParams p = cfg.op;
     p.precond = with_prec ? cfg.op.precond : 0;
     p.in_scale = in_scale;
+    p.gate = gate;  // honoured by the Fourier passes only
     if (g.cheb) c2_apply<R>(g, G->cd, p, v, y, work.t[0], work.t[1], coef, tw, G->st, &G->prof);
     else op_apply<R>(g, p, v, y, work, coef, tw, G->st, &G->prof);
   }
@@ -358,6 +371,22 @@ struct Krylov {
     return v;
   }
 
+  // Arnoldi step j: V[j+1] = A M^-1 v_j, Gram-Schmidt against V[0..j] and
+  // the Givens rotations of column j.  gate: the device halt flag, or none.
+  void arnoldi_step(const std::vector<void*>& V, int j, const int* gate) {
+    apply(V[j], V[j + 1], true, &G->dst->vs[j], gate);
+    VecPtrs P{};
+    for (int i = 0; i <= j; ++i) P.p[i] = V[i];
+    gs_orthogonalize<R>(g, V[j + 1], P, j + 1, G->dst, G->partial, G->st, &G->prof);
+  }
+  // the state's tail (resid, nrm2, bad, halt) after step j into slot j % 2
+  void post_tail(int j) {
+    const size_t off = offsetof(DevState, resid);
+    ck(hipMemcpyAsync((char*)(G->hslot + (j & 1)) + off, (const char*)G->dst + off, sizeof(DevState) - off,
+                      hipMemcpyDeviceToHost, G->st));
+    ck(hipEventRecord(G->slot_ev[j & 1], G->st));
+  }
+
   SolveOut gmres(const void* b, void* x, double bnorm) {
     const int r0 = read_nreorth();
     SolveOut o = gmres_core(b, x, bnorm);
@@ -385,19 +414,52 @@ struct Krylov {
       if (!(beta == beta)) { o.status = VD_EBREAKDOWN; return o; }
       if (o.relres <= cfg.rtol) { o.status = VD_OK; return o; }
       if (o.iters >= cfg.max_iter) { o.status = VD_NOT_CONVERGED; return o; }
-      gmres_init(G->dst, beta, m, G->st);  // v_0 = V[0] / beta via the scale vs[0]
+      // the cycle ends after step jlast at the latest (restart length or iteration budget)
+      const int jlast = std::min(m, cfg.max_iter - o.iters) - 1;
+      gmres_init(G->dst, beta, m, bnorm, cfg.rtol, jlast, G->st);  // v_0 = V[0] / beta via the scale vs[0]
       int k = 0;
-      for (int j = 0; j < m; ++j) {
-        apply(V[j], V[j + 1], true, &G->dst->vs[j]);
-        o.iters++;
-        VecPtrs P{};
-        for (int i = 0; i <= j; ++i) P.p[i] = V[i];
-        gs_orthogonalize<R>(g, V[j + 1], P, j + 1, G->dst, G->partial, G->st, &G->prof);  // + Givens on column j
-        sync_state(G);
-        k = j + 1;
-        if (cfg.hist) cfg.hist->push_back(G->hst->resid / bnorm);
+      if (g.cheb) {  // synchronous: the dense Chebyshev application has no gate
+        for (int j = 0; j <= jlast; ++j) {
+          arnoldi_step(V, j, nullptr);
+          o.iters++;
+          sync_state(G);
+          k = j + 1;
+          if (cfg.hist) cfg.hist->push_back(G->hst->resid / bnorm);
+          if (G->hst->bad) { o.status = VD_EBREAKDOWN; return o; }
+          if (G->hst->halt) break;
+        }
+      } else {
+        // Step j + 1 is queued before step j's residual reaches the host, so
+        // the GPU never idles while the host decides.  The device takes the
+        // same stopping test (k_gs_check); a step queued past the end of the
+        // cycle returns at its gates and its profile records are dropped.
+        Prof& pf = G->prof;
+        if (pf.on) pf.flush();
+        arnoldi_step(V, 0, &G->dst->halt);
+        post_tail(0);
+        size_t mark = pf.pending.size();
+        for (int j = 0; j <= jlast; ++j) {
+          if (j < jlast) {
+            arnoldi_step(V, j + 1, &G->dst->halt);
+            post_tail(j + 1);
+          }
+          ck(hipEventSynchronize(G->slot_ev[j & 1]));
+          const DevState& t = G->hslot[j & 1];
+          G->hst->resid = t.resid;
+          G->hst->nrm2 = t.nrm2;
+          G->hst->bad = t.bad;
+          G->hst->halt = t.halt;
+          if (pf.on) {
+            pf.flush_front(mark);  // step j's records; step j + 1's stay pending
+            mark = pf.pending.size();
+          }
+          o.iters++;
+          k = j + 1;
+          if (cfg.hist) cfg.hist->push_back(G->hst->resid / bnorm);
+          if (G->hst->bad || G->hst->halt) break;
+        }
+        if (pf.on) pf.drop();  // the step queued after the last one did nothing
         if (G->hst->bad) { o.status = VD_EBREAKDOWN; return o; }
-        if (G->hst->resid / bnorm <= cfg.rtol || o.iters >= cfg.max_iter) break;
       }
       gmres_backsolve(G->dst, k, G->st);
       VecPtrs P{};
@@ -738,8 +800,11 @@ vd_status vd_grid_create(vd_grid** out, const vd_grid_desc* d, hipStream_t strea
     ck(hipMalloc(&G->dsmall, 64 * sizeof(double)));
     ck(hipMalloc(&G->dst, sizeof(DevState)));
     ck(hipHostMalloc(&G->hst, sizeof(DevState)));
+    ck(hipHostMalloc(&G->hslot, 2 * sizeof(DevState)));
+    for (auto& e : G->slot_ev) ck(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     ck(hipMemset(G->dst, 0, sizeof(DevState)));
     std::memset(G->hst, 0, sizeof(DevState));
+    std::memset(G->hslot, 0, 2 * sizeof(DevState));
   } catch (...) {
     vd_grid_destroy(G);
     return VD_ENOMEM;
@@ -776,6 +841,9 @@ vd_status vd_grid_destroy(vd_grid* G) {
   hipFree(G->kc32);
   hipFree(G->dst);
   if (G->hst) hipHostFree(G->hst);
+  if (G->hslot) hipHostFree(G->hslot);
+  for (auto e : G->slot_ev)
+    if (e) hipEventDestroy(e);
   delete G;
   return VD_OK;
 }

@@ -84,7 +84,9 @@ static size_t nspec(const Geom& g) { return (size_t)g.nz * g.ny * g.M; }
 
 template <typename R, int NV>
 __global__ __launch_bounds__(256) void k_mdot(const C2<R>* __restrict__ x, VecPtrs V, int nv, int want_norm,
-                                              size_t n, int M, double* __restrict__ partial) {
+                                              size_t n, int M, double* __restrict__ partial,
+                                              const int* __restrict__ gate) {
+  if (gate && *gate) return;
   double acc[NV + 1];
 #pragma unroll
   for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
@@ -119,24 +121,24 @@ __global__ __launch_bounds__(256) void k_mdot(const C2<R>* __restrict__ x, VecPt
 // Block partials only (the caller reduces them).
 template <typename R>
 static void mdot_partials(const Geom& g, const void* x, const VecPtrs& V, int nv, bool want_norm, double* partial,
-                          hipStream_t s) {
+                          hipStream_t s, const int* gate = nullptr) {
   size_t n = nspec(g);
   dim3 gr(nblk(n)), bl(256);
   const int wn = want_norm ? 1 : 0;
   if (nv <= 1)
-    hipLaunchKernelGGL((k_mdot<R, 1>), gr, bl, 0, s, (const C2<R>*)x, V, nv, wn, n, g.M, partial);
+    hipLaunchKernelGGL((k_mdot<R, 1>), gr, bl, 0, s, (const C2<R>*)x, V, nv, wn, n, g.M, partial, gate);
   else if (nv <= 2)
-    hipLaunchKernelGGL((k_mdot<R, 2>), gr, bl, 0, s, (const C2<R>*)x, V, nv, wn, n, g.M, partial);
+    hipLaunchKernelGGL((k_mdot<R, 2>), gr, bl, 0, s, (const C2<R>*)x, V, nv, wn, n, g.M, partial, gate);
   else if (nv <= 4)
-    hipLaunchKernelGGL((k_mdot<R, 4>), gr, bl, 0, s, (const C2<R>*)x, V, nv, wn, n, g.M, partial);
+    hipLaunchKernelGGL((k_mdot<R, 4>), gr, bl, 0, s, (const C2<R>*)x, V, nv, wn, n, g.M, partial, gate);
   else if (nv <= 8)
-    hipLaunchKernelGGL((k_mdot<R, 8>), gr, bl, 0, s, (const C2<R>*)x, V, nv, wn, n, g.M, partial);
+    hipLaunchKernelGGL((k_mdot<R, 8>), gr, bl, 0, s, (const C2<R>*)x, V, nv, wn, n, g.M, partial, gate);
   else if (nv <= 16)
-    hipLaunchKernelGGL((k_mdot<R, 16>), gr, bl, 0, s, (const C2<R>*)x, V, nv, wn, n, g.M, partial);
+    hipLaunchKernelGGL((k_mdot<R, 16>), gr, bl, 0, s, (const C2<R>*)x, V, nv, wn, n, g.M, partial, gate);
   else if (nv <= 24)
-    hipLaunchKernelGGL((k_mdot<R, 24>), gr, bl, 0, s, (const C2<R>*)x, V, nv, wn, n, g.M, partial);
+    hipLaunchKernelGGL((k_mdot<R, 24>), gr, bl, 0, s, (const C2<R>*)x, V, nv, wn, n, g.M, partial, gate);
   else
-    hipLaunchKernelGGL((k_mdot<R, kMaxVec>), gr, bl, 0, s, (const C2<R>*)x, V, nv, wn, n, g.M, partial);
+    hipLaunchKernelGGL((k_mdot<R, kMaxVec>), gr, bl, 0, s, (const C2<R>*)x, V, nv, wn, n, g.M, partial, gate);
 }
 
 template <typename R>
@@ -193,6 +195,7 @@ __device__ __forceinline__ double wave_max(double v) {
 // (nv <= kMaxVec < 64), so no thread walks the device state serially.
 __global__ __launch_bounds__(1024) void k_gs_prep(DevState* st, int nv, const double* __restrict__ partial, int nb,
                                                   double scale) {
+  if (st->halt) return;
   __shared__ double val[kMaxVec + 2];
   reduce_values(partial, nb, nv, scale, val);
   __syncthreads();
@@ -212,6 +215,10 @@ __global__ __launch_bounds__(1024) void k_gs_check(DevState* st, int nv, double 
                                                    int nb, double scale) {
   __shared__ double val[kMaxVec + 2];
   __shared__ double hc[kMaxVec + 1], csl[kMaxRestart], snl[kMaxRestart];
+  if (st->halt) {  // a step queued past the end of the cycle: no second pass either
+    if (threadIdx.x == 0) st->reorth = 0;
+    return;
+  }
   reduce_values(partial, nb, nv + 1, scale, val);
   __syncthreads();
   if (threadIdx.x >= 64) return;  // one wavefront from here on
@@ -267,12 +274,16 @@ __global__ __launch_bounds__(1024) void k_gs_check(DevState* st, int nv, double 
   st->g[j] = cr * gj;
   st->resid = fabs(sr * gj);
   if (!isfinite(rr) || !isfinite(sr * gj)) st->bad = 1;
+  // the stopping test of the host loop, taken here so that the next step,
+  // when already queued, exits at its gates
+  if (st->bad || st->resid / st->stop_bnorm <= st->stop_rtol || j >= st->jlast) st->halt = 1;
 }
 
 template <typename R, int NV>
 __global__ __launch_bounds__(256) void k_gs_update(C2<R>* __restrict__ x, VecPtrs V, int nv,
                                                    const DevState* __restrict__ st, size_t n, int M,
                                                    double* __restrict__ partial) {
+  if (st->halt) return;
   double c[NV];
 #pragma unroll
   for (int i = 0; i < NV; ++i) c[i] = i < nv ? st->coef[i] : 0.0;
@@ -357,7 +368,7 @@ void gs_orthogonalize(const Geom& g, void* w, const VecPtrs& V, int nv, DevState
   const double fb = (double)nspec(g) * sizeof(C2<R>);
   if (pr) prof->begin(10, s, (nv + 1) * fb);
   const int nb = nblk(nspec(g));
-  mdot_partials<R>(g, w, V, nv, false, partial, s);
+  mdot_partials<R>(g, w, V, nv, false, partial, s, &st->halt);
   if (pr) prof->end(s);
   hipLaunchKernelGGL(k_gs_prep, dim3(1), dim3(1024), 0, s, st, nv, (const double*)partial, nb, g.ntot_inv);
   for (int second = 0; second < 2; ++second) {
@@ -609,8 +620,12 @@ void project_range(const Geom& g, void* spec, double* removed, hipStream_t st) {
 
 // ------------------------------------------------------- scalar kernels
 
-__global__ void k_gmres_init(DevState* st, double beta, int m) {
+__global__ void k_gmres_init(DevState* st, double beta, int m, double bnorm, double rtol, int jlast) {
   if (threadIdx.x != 0) return;
+  st->stop_bnorm = bnorm;
+  st->stop_rtol = rtol;
+  st->jlast = jlast;
+  st->halt = 0;
   for (int i = 0; i < (kMaxRestart + 1) * kMaxRestart; ++i) st->H[i] = 0.0;
   for (int i = 0; i <= m && i <= kMaxRestart; ++i) st->g[i] = 0.0;
   st->g[0] = beta;
@@ -655,8 +670,8 @@ __global__ void k_rmr_alpha(DevState* st) {
   if (!isfinite(st->alpha)) st->bad = 1;
 }
 
-void gmres_init(DevState* st, double beta, int m, hipStream_t s) {
-  hipLaunchKernelGGL(k_gmres_init, dim3(1), dim3(64), 0, s, st, beta, m);
+void gmres_init(DevState* st, double beta, int m, double bnorm, double rtol, int jlast, hipStream_t s) {
+  hipLaunchKernelGGL(k_gmres_init, dim3(1), dim3(64), 0, s, st, beta, m, bnorm, rtol, jlast);
 }
 void gmres_backsolve(DevState* st, int k, hipStream_t s) {
   hipLaunchKernelGGL(k_gmres_backsolve, dim3(1), dim3(64), 0, s, st, k);

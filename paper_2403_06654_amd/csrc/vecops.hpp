@@ -34,11 +34,16 @@ struct DevState {
   int reorth;                // second Gram-Schmidt pass ran for this step
   int nreorth;               // second passes since the grid was created
   double alpha, beta, rz, rz_new;
+  // GMRES stopping test, evaluated on the device after each step:
+  // resid / stop_bnorm <= stop_rtol, a non-finite scalar, or step jlast of
+  // the cycle (restart length or iteration budget) sets halt
+  double stop_bnorm, stop_rtol;
+  int jlast;
   // mirrored to the host after each step
   double resid;              // estimated (GMRES) or recursive residual norm
   double nrm2;               // last computed squared norm
   int bad;                   // non-finite scalar seen
-  int pad;
+  int halt;                  // GMRES: the cycle has ended; gated kernels return at once
 };
 
 // partial[b][i] = sum_e w_e Re(conj(V_i[e]) x[e]) (i < nv), plus |x|^2 at
@@ -105,7 +110,9 @@ void project_range(const Geom& g, void* spec, double* removed, hipStream_t st);
 void zero_mean(const Geom& g, void* spec, double* removed, hipStream_t st);
 
 // Scalar kernels (one thread) of the Krylov methods.
-void gmres_init(DevState* st, double beta, int m, hipStream_t s);
+// Starts a GMRES cycle: H, g, the basis scales and the stopping test
+// (bnorm, rtol, last step jlast of this cycle; halt cleared).
+void gmres_init(DevState* st, double beta, int m, double bnorm, double rtol, int jlast, hipStream_t s);
 void gmres_backsolve(DevState* st, int k, hipStream_t s);  // y, and coef = y * vs
 void cg_alpha(DevState* st, hipStream_t s);   // alpha = rz / red[0]
 void cg_beta(DevState* st, hipStream_t s);    // beta = red[0] / rz; rz = red[0]
