@@ -161,8 +161,10 @@ void mdot(const Geom& g, const void* x, const VecPtrs& V, int nv, bool want_norm
 //   check   c measures the orthogonality actually lost by classical
 //           Gram-Schmidt; if max|c_i| <= tol ||w'|| the step is done
 //           (H[:, j] = h, H[j+1, j] = ||w'||), else
-//   pass 3  w'' = w' - sum_i c_i v_i  (H[:, j] = h + c,
-//           ||w''||^2 = ||w'||^2 - |c|^2, accurate because |c| << ||w'||).
+//   pass 3  w'' = w' - sum_{i in S} c_i v_i over the set S of components
+//           with |c_i| > tol ||w'|| (the others already meet the test),
+//           H[:, j] = h + c_S, ||w''||^2 = ||w'||^2 - |c_S|^2, accurate
+//           because |c| << ||w'||.  It reads only the vectors in S.
 // Pass 3 exits at once when not needed, so the common step costs two
 // passes over the basis.
 //
@@ -229,19 +231,25 @@ __global__ __launch_bounds__(1024) void k_gs_check(DevState* st, int nv, double 
     v = st->vs[lane];
     h = st->hcol[lane];
     c = v * val[lane];
-    st->ccol[lane] = c;
-    st->coef[lane] = c * v;
   }
   if (lane < j) {
     csl[lane] = st->cs[lane];
     snl[lane] = st->sn[lane];
   }
   const double n2 = val[nv];
-  const double cmax = wave_max(fabs(c)), c2 = wave_sum(c * c);
-  const bool orth = n2 > 0.0 && cmax <= tol * sqrt(n2);
-  const double h2 = n2 - c2;
+  const double thr = tol * sqrt(n2);
+  const bool orth = n2 > 0.0 && wave_max(fabs(c)) <= thr;
+  // The second pass subtracts only the components that fail the test: the
+  // others already meet the tolerance accepted when no second pass runs.
+  // (n2 <= 0 selects every nonzero component.)
+  const double csel = (!orth && lane < nv && !(fabs(c) <= thr)) ? c : 0.0;
+  const double h2 = n2 - wave_sum(csel * csel);
   const double hn = orth ? sqrt(n2) : (h2 > 0.0 ? sqrt(h2) : 0.0);
-  if (lane < nv) hc[lane] = h + (orth ? 0.0 : c);  // Hessenberg column before rotation
+  if (lane < nv) {
+    st->ccol[lane] = csel;
+    st->coef[lane] = csel * v;
+    hc[lane] = h + csel;  // Hessenberg column before rotation
+  }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -341,7 +349,7 @@ __global__ __launch_bounds__(256) void k_gs_reorth(C2<R>* __restrict__ x, VecPtr
     double xr = xv.x, xi = xv.y;
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
-      if (i < nv) {
+      if (i < nv && c[i] != 0.0) {  // uniform: vectors that passed the check are not read
         C2<R> v = ldg((const C2<R>*)V.p[i] + e);
         xr -= c[i] * (double)v.x;
         xi -= c[i] * (double)v.y;
