@@ -45,8 +45,15 @@ def main(fetch_dir, write_dir):
         fv = [float(r["Counter_Value"]) * 1024 * kf for r in F if re.match(pat, r["Kernel_Name"])]
         wv = [float(r["Counter_Value"]) * 1024 * kw for r in W if re.match(pat, r["Kernel_Name"])]
         if fv and len(fv) == len(wv):
-            out["per_launch_bytes"][name] = round((sum(fv) + sum(wv)) / len(fv))
-            out["launches"][name] = len(fv)
+            # A GMRES step queued past the end of its cycle launches every
+            # kernel, which returns at its gate having read a flag only: such
+            # dispatches (under 1% of the median traffic) are not launches of
+            # the timed work and are left out, as the HIP-event timing does.
+            med = sorted(fv)[len(fv) // 2]
+            keep = [i for i in range(len(fv)) if fv[i] >= 0.01 * med]
+            out["per_launch_bytes"][name] = round(sum(fv[i] + wv[i] for i in keep) / len(keep))
+            out["launches"][name] = len(keep)
+            out.setdefault("gated_dispatches_left_out", {})[name] = len(fv) - len(keep)
     path = os.path.join(ROOT, "profiles", "traffic_counters.json")
     json.dump(out, open(path, "w"), indent=1)
     print(json.dumps(out, indent=1))
