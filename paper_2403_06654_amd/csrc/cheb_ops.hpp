@@ -28,7 +28,7 @@ struct ChebDev {
 };
 
 // y = A M^-1 (s v) (M^-1 if p.precond) on packed-x spectra [nz][nx/2];
-// work: wY one field, wT two fields.
+// work: wY one field, wT two fields.  Every launch honours p.gate.
 template <typename R>
 void c2_apply(const Geom& g, const ChebDev& cd, const OpParams& p, const void* v, void* y, void* wY, void* wT,
               const void* coef, const void* twtab, hipStream_t st, Prof* prof);
@@ -49,6 +49,7 @@ void gemm_plain(const void* A, const void* B, void* C, int M, int N, int K, hipS
 // x pass of the pressure operator on two stacked fields of nz rows each
 // (field 0: i k'_x in and out; field 1 plain), coefficient rows [nz][nx]
 template <typename R>
-void row_pass_p2(const Geom& g, void* f0, void* f1, const void* coef, const void* twtab, hipStream_t st, Prof* prof);
+void row_pass_p2(const Geom& g, void* f0, void* f1, const void* coef, const void* twtab, hipStream_t st, Prof* prof,
+                 const int* gate = nullptr);
 
 }  // namespace vd

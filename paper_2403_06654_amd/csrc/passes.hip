@@ -849,8 +849,10 @@ void inv_transform_n(const Geom& g, const void* const* spec, double* const* phys
 }
 
 template <typename R>
-void row_pass_p2(const Geom& g, void* f0, void* f1, const void* coef, const void* twtab, hipStream_t st, Prof* prof) {
+void row_pass_p2(const Geom& g, void* f0, void* f1, const void* coef, const void* twtab, hipStream_t st, Prof* prof,
+                 const int* gate) {
   RowArgs r = row_args(g, nullptr);
+  r.gate = gate;
   r.nf = 2;
   r.in[0] = f0;
   r.in[1] = f1;
@@ -863,8 +865,10 @@ void row_pass_p2(const Geom& g, void* f0, void* f1, const void* coef, const void
   launch_row<R, ROW_P>(g.M, r, twtab, st);
   if (pr) prof->end(st);
 }
-template void row_pass_p2<double>(const Geom&, void*, void*, const void*, const void*, hipStream_t, Prof*);
-template void row_pass_p2<float>(const Geom&, void*, void*, const void*, const void*, hipStream_t, Prof*);
+template void row_pass_p2<double>(const Geom&, void*, void*, const void*, const void*, hipStream_t, Prof*,
+                                  const int*);
+template void row_pass_p2<float>(const Geom&, void*, void*, const void*, const void*, hipStream_t, Prof*,
+                                 const int*);
 
 template void op_apply<double>(const Geom&, const OpParams&, const void*, void*, const OpWork&, const void*,
                                const void*, hipStream_t, Prof*);

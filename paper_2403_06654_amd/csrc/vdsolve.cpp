@@ -316,7 +316,7 @@ struct Krylov {
     OpParams p = cfg.op;
     p.precond = with_prec ? cfg.op.precond : 0;
     p.in_scale = in_scale;
-    p.gate = gate;  // honoured by the Fourier passes only
+    p.gate = gate;
     if (g.cheb) c2_apply<R>(g, G->cd, p, v, y, work.t[0], work.t[1], coef, tw, G->st, &G->prof);
     else op_apply<R>(g, p, v, y, work, coef, tw, G->st, &G->prof);
   }
@@ -418,49 +418,37 @@ struct Krylov {
       const int jlast = std::min(m, cfg.max_iter - o.iters) - 1;
       gmres_init(G->dst, beta, m, bnorm, cfg.rtol, jlast, G->st);  // v_0 = V[0] / beta via the scale vs[0]
       int k = 0;
-      if (g.cheb) {  // synchronous: the dense Chebyshev application has no gate
-        for (int j = 0; j <= jlast; ++j) {
-          arnoldi_step(V, j, nullptr);
-          o.iters++;
-          sync_state(G);
-          k = j + 1;
-          if (cfg.hist) cfg.hist->push_back(G->hst->resid / bnorm);
-          if (G->hst->bad) { o.status = VD_EBREAKDOWN; return o; }
-          if (G->hst->halt) break;
+      // Step j + 1 is queued before step j's residual reaches the host, so
+      // the GPU never idles while the host decides.  The device takes the
+      // same stopping test (k_gs_check); a step queued past the end of the
+      // cycle returns at its gates and its profile records are dropped.
+      Prof& pf = G->prof;
+      if (pf.on) pf.flush();
+      arnoldi_step(V, 0, &G->dst->halt);
+      post_tail(0);
+      size_t mark = pf.pending.size();
+      for (int j = 0; j <= jlast; ++j) {
+        if (j < jlast) {
+          arnoldi_step(V, j + 1, &G->dst->halt);
+          post_tail(j + 1);
         }
-      } else {
-        // Step j + 1 is queued before step j's residual reaches the host, so
-        // the GPU never idles while the host decides.  The device takes the
-        // same stopping test (k_gs_check); a step queued past the end of the
-        // cycle returns at its gates and its profile records are dropped.
-        Prof& pf = G->prof;
-        if (pf.on) pf.flush();
-        arnoldi_step(V, 0, &G->dst->halt);
-        post_tail(0);
-        size_t mark = pf.pending.size();
-        for (int j = 0; j <= jlast; ++j) {
-          if (j < jlast) {
-            arnoldi_step(V, j + 1, &G->dst->halt);
-            post_tail(j + 1);
-          }
-          ck(hipEventSynchronize(G->slot_ev[j & 1]));
-          const DevState& t = G->hslot[j & 1];
-          G->hst->resid = t.resid;
-          G->hst->nrm2 = t.nrm2;
-          G->hst->bad = t.bad;
-          G->hst->halt = t.halt;
-          if (pf.on) {
-            pf.flush_front(mark);  // step j's records; step j + 1's stay pending
-            mark = pf.pending.size();
-          }
-          o.iters++;
-          k = j + 1;
-          if (cfg.hist) cfg.hist->push_back(G->hst->resid / bnorm);
-          if (G->hst->bad || G->hst->halt) break;
+        ck(hipEventSynchronize(G->slot_ev[j & 1]));
+        const DevState& t = G->hslot[j & 1];
+        G->hst->resid = t.resid;
+        G->hst->nrm2 = t.nrm2;
+        G->hst->bad = t.bad;
+        G->hst->halt = t.halt;
+        if (pf.on) {
+          pf.flush_front(mark);  // step j's records; step j + 1's stay pending
+          mark = pf.pending.size();
         }
-        if (pf.on) pf.drop();  // the step queued after the last one did nothing
-        if (G->hst->bad) { o.status = VD_EBREAKDOWN; return o; }
+        o.iters++;
+        k = j + 1;
+        if (cfg.hist) cfg.hist->push_back(G->hst->resid / bnorm);
+        if (G->hst->bad || G->hst->halt) break;
       }
+      if (pf.on) pf.drop();  // the step queued after the last one did nothing
+      if (G->hst->bad) { o.status = VD_EBREAKDOWN; return o; }
       gmres_backsolve(G->dst, k, G->st);
       VecPtrs P{};
       for (int i = 0; i < k; ++i) P.p[i] = V[i];

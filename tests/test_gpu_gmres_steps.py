@@ -1,4 +1,4 @@
-"""GMRES cycle boundaries on Fourier grids (Sec. 3.2 solver), where each
+"""GMRES cycle boundaries (Sec. 3.2 solver), where each
 Arnoldi step is queued before the host has read the previous step's
 residual and the device takes the stopping test: restarts, an iteration
 budget that ends inside a cycle, the residual history, back-to-back solves,
@@ -98,3 +98,39 @@ def test_back_to_back_solves_and_profile_counts(precision):
     applies = cnt[0]
     assert all(cnt[c] == applies for c in range(1, 5))
     assert i1["iterations"] < applies <= i1["iterations"] + 2 * (i1["iterations"] // 6 + 2) + 2 * i1.get("refinements", 0)
+
+
+@pytest.mark.parametrize("restart,max_iter", [(4, None), (30, 7), (4, 9)])
+def test_chebyshev_grid_cycles(restart, max_iter):
+    """The same on a Fourier x Chebyshev grid (64 x 33, Neumann walls), whose
+    queued steps gate the dense z contractions and the x pass: converged
+    restarted solves reach the oracle-evaluated true residual; a budget ends
+    after exactly max_iter steps with NOT_CONVERGED and the returned
+    rel_residual is the iterate's true residual; a repeat solve returns the
+    same bits."""
+    from paper_2403_06654_amd.api import Grid
+    print(f"case gmres cheb restart={restart} max_iter={max_iter}", flush=True)
+    nx, nz = 64, 33
+    fc = operators.FourierChebyshev2D(nx=nx, m=nz - 1, lx=2.0)
+    xx, zz = fc.x[None, :], fc.z[:, None]
+    rho = np.ascontiguousarray(2.0 + np.tanh((zz - 0.2 * np.sin(np.pi * xx)) / 0.3) + 0.0 * xx)
+    f = np.cos(np.pi * xx) * np.cos(np.pi * zz) + 0.3 * np.sin(2 * np.pi * xx) * zz ** 2
+    g = Grid((nz, nx), lengths=(2.0, 2.0), cheb=True)
+    g.set_density(to_dev(rho))
+    kw = {"solver": "gmres", "restart": restart, "history": np.zeros(256)}
+    if max_iter is not None:
+        kw["max_iter"] = max_iter
+    p, info = g.solve_pressure(to_dev(f), **kw)
+    p2, info2 = g.solve_pressure(to_dev(f), **kw)
+    g.close()
+    assert bool((p == p2).all()) and info["iterations"] == info2["iterations"]
+    p = to_host(p)
+    b, _ = operators.project_range(fc.rhs(f), fc.nullspace_basis())
+    true = rel2(fc.apply_pressure(p, rho), b)
+    assert info["history_len"] == info["iterations"] + 1
+    if max_iter is None:
+        assert info["status"] == 0 and info["iterations"] > restart
+        assert true <= 1.01e-10
+    else:
+        assert info["status"] == 1 and info["iterations"] == max_iter
+        assert info["rel_residual"] == pytest.approx(true, rel=1e-6)
