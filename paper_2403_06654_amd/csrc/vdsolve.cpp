@@ -269,6 +269,9 @@ struct SolveCfg {
   // never on an FP32 true residual, whose rounding floor can sit near the
   // inner tolerance; the FP64 outer loop owns the true-residual test.
   bool inner = false;
+  // x starts at zero: the initial residual is b itself, with norm bnorm, and
+  // no operator application is spent on A x
+  bool x_zero = false;
   std::vector<double>* hist = nullptr;  // residual history sink (host), or none
 };
 constexpr int kInnerCycles = 3;
@@ -401,7 +404,7 @@ struct Krylov {
     for (int i = 0; i <= m; ++i) V[i] = buf(G, prec, B_V0 + i);
     void* tmp = buf(G, prec, B_TMP);
     double beta;
-    if (cfg.inner) {  // x = 0: r = b
+    if (cfg.inner || cfg.x_zero) {  // x = 0: r = b
       ck(hipMemcpyAsync(V[0], b, G->nspec * elem_bytes(prec), hipMemcpyDeviceToDevice, G->st));
       beta = bnorm;
     } else {
@@ -489,7 +492,7 @@ struct Krylov {
     void* r = buf(G, prec, B_R);
     void* p = buf(G, prec, B_P);
     void* q = buf(G, prec, B_Q);
-    double rn = cfg.inner ? copy_rhs(b, r, bnorm) : true_resid(b, x, r);
+    double rn = (cfg.inner || cfg.x_zero) ? copy_rhs(b, r, bnorm) : true_resid(b, x, r);
     if (cfg.hist) cfg.hist->push_back(rn / bnorm);
     while (true) {
       o.relres = rn / bnorm;
@@ -526,7 +529,7 @@ struct Krylov {
     SolveOut o;
     void* r = buf(G, prec, B_R);
     void* w = buf(G, prec, B_W);
-    double rn = cfg.inner ? copy_rhs(b, r, bnorm) : true_resid(b, x, r);
+    double rn = (cfg.inner || cfg.x_zero) ? copy_rhs(b, r, bnorm) : true_resid(b, x, r);
     if (cfg.hist) cfg.hist->push_back(rn / bnorm);
     while (true) {
       o.relres = rn / bnorm;
@@ -561,6 +564,7 @@ struct Krylov {
 SolveOut solve_spectral(vd_grid* G, const vd_solve_opts& o, const OpParams& op, int coef, void* b64, void* x64,
                         double bnorm, int* refinements, std::vector<double>* hist = nullptr) {
   SolveCfg cfg{o.solver, o.restart, o.max_iter, o.rtol, op, coef};
+  cfg.x_zero = !o.use_x0;  // the caller zeroed x64
   *refinements = 0;
   if (bnorm == 0.0) {
     if (hist) hist->push_back(0.0);
@@ -583,7 +587,7 @@ SolveOut solve_spectral(vd_grid* G, const vd_solve_opts& o, const OpParams& op, 
   void* r32 = buf(G, 32, B_B);
   void* d32 = buf(G, 32, B_X);
   SolveOut out;
-  double rn = K64.true_resid(b64, x64, r64);
+  double rn = o.use_x0 ? K64.true_resid(b64, x64, r64) : K64.copy_rhs(b64, r64, bnorm);
   while (true) {
     out.relres = rn / bnorm;
     if (hist) hist->push_back(out.relres);
