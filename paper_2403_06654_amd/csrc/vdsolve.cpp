@@ -236,6 +236,13 @@ void fill_twiddles(vd_grid* G) {
   ck(hipMemcpy(G->tw32, t32.data(), t32.size() * sizeof(float), hipMemcpyHostToDevice));
 }
 
+// sqrt of a computed squared norm: a small negative value from rounding is
+// zero, a NaN stays NaN (so that a non-finite residual is never taken for
+// convergence)
+static double norm_from_sq(double s) { return s < 0.0 ? 0.0 : std::sqrt(s); }
+// max that keeps a NaN of either argument
+static double max_keep_nan(double a, double b) { return (a != a || b != b) ? NAN : std::max(a, b); }
+
 void sync_state(vd_grid* G) {
   // only the tail (resid, nrm2, bad) is read on the host
   const size_t off = offsetof(DevState, resid);
@@ -349,7 +356,7 @@ struct Krylov {
     void* tmp = buf(G, prec, B_TMP);
     apply(x, tmp, false);
     sub_norm<R>(g, b, tmp, r, G->partial, &G->dst->nrm2, G->st);
-    return std::sqrt(std::fmax(read_scalar(G, &G->dst->nrm2), 0.0));
+    return norm_from_sq(read_scalar(G, &G->dst->nrm2));
   }
 
   double copy_rhs(const void* b, void* r, double bnorm) {
@@ -510,14 +517,14 @@ struct Krylov {
         cg_alpha(G->dst, G->st);
         cg_xr<R>(g, x, r, p, q, G->dst, G->partial, &G->dst->nrm2, G->st);
         sync_state(G);
-        if (cfg.hist) cfg.hist->push_back(std::sqrt(std::fmax(G->hst->nrm2, 0.0)) / bnorm);
-        if (G->hst->bad) { o.status = VD_EBREAKDOWN; return o; }
-        if (std::sqrt(std::fmax(G->hst->nrm2, 0.0)) / bnorm <= cfg.rtol) break;
+        if (cfg.hist) cfg.hist->push_back(norm_from_sq(G->hst->nrm2) / bnorm);
+        if (G->hst->bad || !(G->hst->nrm2 == G->hst->nrm2)) { o.status = VD_EBREAKDOWN; return o; }
+        if (norm_from_sq(G->hst->nrm2) / bnorm <= cfg.rtol) break;
         if (cfg.inner && o.iters >= cfg.max_iter) break;
         rz_and_p(r, p, false);
       }
       if (cfg.inner) {
-        o.relres = std::sqrt(std::fmax(G->hst->nrm2, 0.0)) / bnorm;
+        o.relres = norm_from_sq(G->hst->nrm2) / bnorm;
         o.status = VD_OK;
         return o;
       }
@@ -546,12 +553,12 @@ struct Krylov {
         prec_axpy(x, r, &G->dst->alpha);
         axpy_norm<R>(g, r, w, &G->dst->alpha, -1.0, G->partial, &G->dst->nrm2, G->st);
         sync_state(G);
-        if (cfg.hist) cfg.hist->push_back(std::sqrt(std::fmax(G->hst->nrm2, 0.0)) / bnorm);
-        if (G->hst->bad) { o.status = VD_EBREAKDOWN; return o; }
-        if (std::sqrt(std::fmax(G->hst->nrm2, 0.0)) / bnorm <= cfg.rtol) break;
+        if (cfg.hist) cfg.hist->push_back(norm_from_sq(G->hst->nrm2) / bnorm);
+        if (G->hst->bad || !(G->hst->nrm2 == G->hst->nrm2)) { o.status = VD_EBREAKDOWN; return o; }
+        if (norm_from_sq(G->hst->nrm2) / bnorm <= cfg.rtol) break;
       }
       if (cfg.inner) {
-        o.relres = std::sqrt(std::fmax(G->hst->nrm2, 0.0)) / bnorm;
+        o.relres = norm_from_sq(G->hst->nrm2) / bnorm;
         o.status = VD_OK;
         return o;
       }
@@ -623,7 +630,7 @@ vd_status guard(vd_grid* G, vd_status (*fn)(vd_grid*, void*), void* ctx) {
 double host_norm_of(vd_grid* G, const void* spec64) {
   VecPtrs P{};
   mdot<double>(G->g, spec64, P, 0, true, G->partial, &G->dst->nrm2, G->st);
-  return std::sqrt(std::fmax(read_scalar(G, &G->dst->nrm2), 0.0));
+  return norm_from_sq(read_scalar(G, &G->dst->nrm2));
 }
 
 // The modified pressure form's pointwise coefficient, -c = Lap(psi)/psi with
@@ -1068,7 +1075,7 @@ static vd_status solve_impl(vd_grid* G, void* c) {
     s->info.iterations += so.iters;
     s->info.refinements += refin;
     s->info.gs_second_passes += so.reorth;
-    s->info.rel_residual = std::fmax(s->info.rel_residual, so.relres);
+    s->info.rel_residual = max_keep_nan(s->info.rel_residual, so.relres);
     if (so.status < 0) worst = (vd_status)so.status;
     else if (so.status == VD_NOT_CONVERGED && worst == VD_OK) worst = VD_NOT_CONVERGED;
     if (so.status < 0) break;

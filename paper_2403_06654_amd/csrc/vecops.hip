@@ -244,6 +244,8 @@ __global__ __launch_bounds__(1024) void k_gs_check(DevState* st, int nv, double 
   // (n2 <= 0 selects every nonzero component.)
   const double csel = (!orth && lane < nv && !(fabs(c) <= thr)) ? c : 0.0;
   const double h2 = n2 - wave_sum(csel * csel);
+  // wave_max drops NaN, and a NaN norm would read as a lucky breakdown
+  const bool finite = isfinite(n2) && isfinite(wave_sum(c * c));
   const double hn = orth ? sqrt(n2) : (h2 > 0.0 ? sqrt(h2) : 0.0);
   if (lane < nv) {
     st->ccol[lane] = csel;
@@ -254,6 +256,7 @@ __global__ __launch_bounds__(1024) void k_gs_check(DevState* st, int nv, double 
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   if (lane != 0) return;
+  if (!finite) st->bad = 1;
   st->reorth = orth ? 0 : 1;
   if (!orth) st->nreorth += 1;
   st->hn = hn;

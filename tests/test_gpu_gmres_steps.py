@@ -134,3 +134,34 @@ def test_chebyshev_grid_cycles(restart, max_iter):
     else:
         assert info["status"] == 1 and info["iterations"] == max_iter
         assert info["rel_residual"] == pytest.approx(true, rel=1e-6)
+
+
+@pytest.mark.parametrize("solver", ["gmres", "cg", "rmr"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_non_finite_input_reports_breakdown_and_the_grid_recovers(solver, precision):
+    """A NaN in the right-hand side (cold start) or in the initial iterate
+    (warm start) ends the solve with VD_EBREAKDOWN rather than a hang or a
+    wrong answer, and the next solve on the same grid is unaffected (no stale
+    halt flag or state): it returns the same bits as on a fresh grid."""
+    from paper_2403_06654_amd.api import Grid, VdError
+    rho, f, _ = _problem()
+    g = Grid(SHAPE)
+    g.set_density(to_dev(rho))
+    bad = f.copy()
+    bad[3, 4, 5] = np.nan
+    with pytest.raises(VdError) as e:
+        g.solve_pressure(to_dev(bad), solver=solver, precision=precision)
+    assert e.value.status == -4
+    p0 = np.zeros(SHAPE)
+    p0[1, 2, 3] = np.nan
+    with pytest.raises(VdError) as e:
+        g.solve_pressure(to_dev(f), p=to_dev(p0), use_x0=True, solver=solver, precision=precision)
+    assert e.value.status == -4
+    p, info = g.solve_pressure(to_dev(f), solver=solver, precision=precision)
+    g.close()
+    h = Grid(SHAPE)
+    h.set_density(to_dev(rho))
+    q, info2 = h.solve_pressure(to_dev(f), solver=solver, precision=precision)
+    h.close()
+    assert info["status"] == 0 and info["iterations"] == info2["iterations"]
+    assert bool((p == q).all())
