@@ -34,7 +34,8 @@ void c2_apply(const Geom& g, const ChebDev& cd, const OpParams& p, const void* v
               const void* coef, const void* twtab, hipStream_t st, Prof* prof);
 // z = M^-1 r (two contractions through the eigenbasis); wY one field
 template <typename R>
-void c2_precond(const Geom& g, const ChebDev& cd, double rho0, const void* r, void* z, void* wY, hipStream_t st);
+void c2_precond(const Geom& g, const ChebDev& cd, double rho0, const void* r, void* z, void* wY, hipStream_t st,
+                const int* gate = nullptr);
 // b = -I^T W I f on packed-x spectra (FP64)
 void c2_rhs(const Geom& g, const ChebDev& cd, const void* fhat, void* b, hipStream_t st);
 // rho_L = I rho and the x-pass coefficient h_x w_LGL / rho_L; *bad counts non-positive values

@@ -194,7 +194,8 @@ void c2_apply(const Geom& g, const ChebDev& cd, const OpParams& p, const void* v
 }
 
 template <typename R>
-void c2_precond(const Geom& g, const ChebDev& cd, double rho0, const void* r, void* z, void* wY, hipStream_t st) {
+void c2_precond(const Geom& g, const ChebDev& cd, double rho0, const void* r, void* z, void* wY, hipStream_t st,
+                const int* gate) {
   const int nz = g.nz, n = 2 * g.M;
   EpiArgs e{};
   e.kind = 1;
@@ -202,8 +203,11 @@ void c2_precond(const Geom& g, const ChebDev& cd, double rho0, const void* r, vo
   e.lam = cd.lam;
   e.scale = rho0 / cd.hx;
   e.sx = g.sx;
+  e.gate = gate;
+  EpiArgs e2 = plain();
+  e2.gate = gate;
   gemm<R>(mat<R>(cd, CH_VT), nz, (const R*)r, n, (R*)wY, n, nz, n, nz, e, st);
-  gemm<R>(mat<R>(cd, CH_V), nz, (const R*)wY, n, (R*)z, n, nz, n, nz, plain(), st);
+  gemm<R>(mat<R>(cd, CH_V), nz, (const R*)wY, n, (R*)z, n, nz, n, nz, e2, st);
 }
 
 void c2_rhs(const Geom& g, const ChebDev& cd, const void* fhat, void* b, hipStream_t st) {
@@ -282,7 +286,9 @@ template void c2_apply<double>(const Geom&, const ChebDev&, const OpParams&, con
                                const void*, const void*, hipStream_t, Prof*);
 template void c2_apply<float>(const Geom&, const ChebDev&, const OpParams&, const void*, void*, void*, void*,
                               const void*, const void*, hipStream_t, Prof*);
-template void c2_precond<double>(const Geom&, const ChebDev&, double, const void*, void*, void*, hipStream_t);
-template void c2_precond<float>(const Geom&, const ChebDev&, double, const void*, void*, void*, hipStream_t);
+template void c2_precond<double>(const Geom&, const ChebDev&, double, const void*, void*, void*, hipStream_t,
+                                 const int*);
+template void c2_precond<float>(const Geom&, const ChebDev&, double, const void*, void*, void*, hipStream_t,
+                                const int*);
 
 }  // namespace vd

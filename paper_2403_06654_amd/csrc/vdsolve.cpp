@@ -335,20 +335,26 @@ struct Krylov {
   // the fly inside the vector kernels) and two dense contractions on
   // Chebyshev grids (materialised into B_Z first).
   bool dense_prec() const { return g.cheb && cfg.op.precond; }
-  const void* materialise_prec(const void* r) {
+  const void* materialise_prec(const void* r, const int* gate = nullptr) {
     void* z = buf(G, prec, B_Z);
-    c2_precond<R>(g, G->cd, cfg.op.rho0, r, z, buf(G, prec, B_T0), G->st);
+    c2_precond<R>(g, G->cd, cfg.op.rho0, r, z, buf(G, prec, B_T0), G->st, gate);
     return z;
   }
-  OpParams ident() const {
+  OpParams ident(const int* gate = nullptr) const {
     OpParams q = cfg.op;
     q.precond = 0;
+    q.gate = gate;
+    return q;
+  }
+  OpParams gated(const int* gate) const {
+    OpParams q = cfg.op;
+    q.gate = gate;
     return q;
   }
   // x += a M^-1 z
-  void prec_axpy(void* x, const void* z, const double* a_dev) {
-    if (dense_prec()) precond_axpy<R>(g, ident(), x, materialise_prec(z), a_dev, 1.0, G->st);
-    else precond_axpy<R>(g, cfg.op, x, z, a_dev, 1.0, G->st);
+  void prec_axpy(void* x, const void* z, const double* a_dev, const int* gate = nullptr) {
+    if (dense_prec()) precond_axpy<R>(g, ident(gate), x, materialise_prec(z, gate), a_dev, 1.0, G->st);
+    else precond_axpy<R>(g, gated(gate), x, z, a_dev, 1.0, G->st);
   }
 
   // ||b - A x|| into r (and G->dst->nrm2); returns the norm
@@ -474,24 +480,62 @@ struct Krylov {
     }
   }
 
-  // rz = (r, M^-1 r); then p = M^-1 r (restart) or p = M^-1 r + beta p
-  void rz_and_p(const void* r, void* p, bool restart) {
+  // rz = (r, M^-1 r); then p = M^-1 r (restart, never gated) or
+  // p = M^-1 r + beta p
+  void rz_and_p(const void* r, void* p, bool restart, const int* gate = nullptr) {
     if (dense_prec()) {
-      const void* z = materialise_prec(r);
+      const void* z = materialise_prec(r, gate);
       VecPtrs P{};
       P.p[0] = r;
-      mdot<R>(g, z, P, 1, false, G->partial, G->dst->red, G->st);
-      cg_beta(G->dst, G->st);
+      mdot<R>(g, z, P, 1, false, G->partial, G->dst->red, G->st, nullptr, gate);
+      cg_beta(G->dst, G->st, gate);
       if (restart) ck(hipMemcpyAsync(p, z, G->nspec * elem_bytes(prec), hipMemcpyDeviceToDevice, G->st));
-      else cg_p<R>(g, ident(), p, z, G->dst, G->st);
+      else cg_p<R>(g, ident(gate), p, z, G->dst, G->st);
       return;
     }
-    OpParams op = cfg.op;
+    const OpParams op = gated(gate);
     dot_rMr<R>(g, op, r, G->partial, G->dst->red, G->st);
-    cg_beta(G->dst, G->st);  // rz = red[0]
+    cg_beta(G->dst, G->st, gate);  // rz = red[0]
     if (!restart) cg_p<R>(g, op, p, r, G->dst, G->st);
     else if (op.precond) precond_apply<R>(g, op, r, p, G->st);
     else ck(hipMemcpyAsync(p, r, G->nspec * elem_bytes(prec), hipMemcpyDeviceToDevice, G->st));
+  }
+
+  // Steps 0..jlast of a CG or RMR run, each queued before the previous
+  // step's state reaches the host, as for GMRES: step(j, gate) enqueues
+  // step j with its stopping test (rec_check), every launch gated by the
+  // halt flag.  Returns the steps that ran; G->hst holds the state after the
+  // last of them.
+  template <typename Step>
+  int run_queued(int jlast, double bnorm, Step&& step) {
+    Prof& pf = G->prof;
+    if (pf.on) pf.flush();
+    const int* gate = &G->dst->halt;
+    step(0, gate);
+    post_tail(0);
+    size_t mark = pf.pending.size();
+    int done = 0;
+    for (int j = 0; j <= jlast; ++j) {
+      if (j < jlast) {
+        step(j + 1, gate);
+        post_tail(j + 1);
+      }
+      ck(hipEventSynchronize(G->slot_ev[j & 1]));
+      const DevState& t = G->hslot[j & 1];
+      G->hst->resid = t.resid;
+      G->hst->nrm2 = t.nrm2;
+      G->hst->bad = t.bad;
+      G->hst->halt = t.halt;
+      if (pf.on) {
+        pf.flush_front(mark);
+        mark = pf.pending.size();
+      }
+      done = j + 1;
+      if (cfg.hist) cfg.hist->push_back(norm_from_sq(G->hst->nrm2) / bnorm);
+      if (G->hst->bad || G->hst->halt || !(G->hst->nrm2 == G->hst->nrm2)) break;
+    }
+    if (pf.on) pf.drop();
+    return done;
   }
 
   SolveOut cg(const void* b, void* x, double bnorm) {
@@ -507,22 +551,20 @@ struct Krylov {
       if (o.relres <= cfg.rtol) { o.status = VD_OK; return o; }
       if (o.iters >= cfg.max_iter) { o.status = VD_NOT_CONVERGED; return o; }
       // p = M^-1 r, rz = (r, M^-1 r)
+      const int jlast = cfg.max_iter - o.iters - 1;
+      rec_init(G->dst, bnorm, cfg.rtol, jlast, G->st);
       rz_and_p(r, p, true);
-      while (o.iters < cfg.max_iter) {
-        apply(p, q, false);
-        o.iters++;
+      o.iters += run_queued(jlast, bnorm, [&](int j, const int* gate) {
+        if (j > 0) rz_and_p(r, p, false, gate);
+        apply(p, q, false, nullptr, gate);
         VecPtrs P{};
         P.p[0] = p;
-        mdot<R>(g, q, P, 1, false, G->partial, G->dst->red, G->st);
-        cg_alpha(G->dst, G->st);
-        cg_xr<R>(g, x, r, p, q, G->dst, G->partial, &G->dst->nrm2, G->st);
-        sync_state(G);
-        if (cfg.hist) cfg.hist->push_back(norm_from_sq(G->hst->nrm2) / bnorm);
-        if (G->hst->bad || !(G->hst->nrm2 == G->hst->nrm2)) { o.status = VD_EBREAKDOWN; return o; }
-        if (norm_from_sq(G->hst->nrm2) / bnorm <= cfg.rtol) break;
-        if (cfg.inner && o.iters >= cfg.max_iter) break;
-        rz_and_p(r, p, false);
-      }
+        mdot<R>(g, q, P, 1, false, G->partial, G->dst->red, G->st, nullptr, gate);
+        cg_alpha(G->dst, G->st, gate);
+        cg_xr<R>(g, x, r, p, q, G->dst, G->partial, &G->dst->nrm2, G->st, gate);
+        rec_check(G->dst, G->st, gate);
+      });
+      if (G->hst->bad || !(G->hst->nrm2 == G->hst->nrm2)) { o.status = VD_EBREAKDOWN; return o; }
       if (cfg.inner) {
         o.relres = norm_from_sq(G->hst->nrm2) / bnorm;
         o.status = VD_OK;
@@ -543,20 +585,19 @@ struct Krylov {
       if (!(rn == rn)) { o.status = VD_EBREAKDOWN; return o; }
       if (o.relres <= cfg.rtol) { o.status = VD_OK; return o; }
       if (o.iters >= cfg.max_iter) { o.status = VD_NOT_CONVERGED; return o; }
-      while (o.iters < cfg.max_iter) {
-        apply(r, w, true);  // w = A M^-1 r
-        o.iters++;
+      const int jlast = cfg.max_iter - o.iters - 1;
+      rec_init(G->dst, bnorm, cfg.rtol, jlast, G->st);
+      o.iters += run_queued(jlast, bnorm, [&](int, const int* gate) {
+        apply(r, w, true, nullptr, gate);  // w = A M^-1 r
         VecPtrs P{};
         P.p[0] = r;
-        mdot<R>(g, w, P, 1, true, G->partial, G->dst->red, G->st);
-        rmr_alpha(G->dst, G->st);
-        prec_axpy(x, r, &G->dst->alpha);
-        axpy_norm<R>(g, r, w, &G->dst->alpha, -1.0, G->partial, &G->dst->nrm2, G->st);
-        sync_state(G);
-        if (cfg.hist) cfg.hist->push_back(norm_from_sq(G->hst->nrm2) / bnorm);
-        if (G->hst->bad || !(G->hst->nrm2 == G->hst->nrm2)) { o.status = VD_EBREAKDOWN; return o; }
-        if (norm_from_sq(G->hst->nrm2) / bnorm <= cfg.rtol) break;
-      }
+        mdot<R>(g, w, P, 1, true, G->partial, G->dst->red, G->st, nullptr, gate);
+        rmr_alpha(G->dst, G->st, gate);
+        prec_axpy(x, r, &G->dst->alpha, gate);
+        axpy_norm<R>(g, r, w, &G->dst->alpha, -1.0, G->partial, &G->dst->nrm2, G->st, gate);
+        rec_check(G->dst, G->st, gate);
+      });
+      if (G->hst->bad || !(G->hst->nrm2 == G->hst->nrm2)) { o.status = VD_EBREAKDOWN; return o; }
       if (cfg.inner) {
         o.relres = norm_from_sq(G->hst->nrm2) / bnorm;
         o.status = VD_OK;

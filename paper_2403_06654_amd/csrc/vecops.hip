@@ -70,12 +70,16 @@ __device__ __forceinline__ void reduce_values(const double* __restrict__ partial
 }
 
 __global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ partial, int nblk, int K, double scale,
-                                                 double* __restrict__ out) {
+                                                 double* __restrict__ out, const int* __restrict__ gate) {
+  if (gate && *gate) return;
   reduce_values(partial, nblk, K, scale, out);
 }
 
-static void reduce(const double* partial, int nb, int K, double scale, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, partial, nb, K, scale, out);
+// gate (here and below): optional device flag; when nonzero the launch does
+// nothing (a Krylov step queued past the end of its run)
+static void reduce(const double* partial, int nb, int K, double scale, double* out, hipStream_t s,
+                   const int* gate = nullptr) {
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, partial, nb, K, scale, out, gate);
 }
 
 static size_t nspec(const Geom& g) { return (size_t)g.nz * g.ny * g.M; }
@@ -143,10 +147,10 @@ static void mdot_partials(const Geom& g, const void* x, const VecPtrs& V, int nv
 
 template <typename R>
 void mdot(const Geom& g, const void* x, const VecPtrs& V, int nv, bool want_norm, double* partial, double* out,
-          hipStream_t s, Prof* prof) {
-  mdot_partials<R>(g, x, V, nv, want_norm, partial, s);
+          hipStream_t s, Prof* prof, const int* gate) {
+  mdot_partials<R>(g, x, V, nv, want_norm, partial, s, gate);
   if (prof) prof->end(s);
-  reduce(partial, nblk(nspec(g)), nv + (want_norm ? 1 : 0), g.ntot_inv, out, s);
+  reduce(partial, nblk(nspec(g)), nv + (want_norm ? 1 : 0), g.ntot_inv, out, s, gate);
 }
 
 // ------------------------------------------------ Gram-Schmidt (GMRES)
@@ -467,7 +471,8 @@ void sub_norm(const Geom& g, const void* b, const void* q, void* r, double* part
 template <typename R>
 __global__ __launch_bounds__(256) void k_precond_axpy(C2<R>* __restrict__ x, const C2<R>* __restrict__ z, Geom g,
                                                       int kind, double rho0, double nu, const double* ad, double ah,
-                                                      size_t n) {
+                                                      size_t n, const int* __restrict__ gate) {
+  if (gate && *gate) return;
   const double a = (ad ? *ad : 1.0) * ah;
   for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
     C2<R> mz = precond_at<R>(z, e, g, kind, rho0, nu);
@@ -479,12 +484,14 @@ template <typename R>
 void precond_axpy(const Geom& g, const OpParams& p, void* x, const void* z, const double* a_dev, double a_host,
                   hipStream_t s) {
   hipLaunchKernelGGL((k_precond_axpy<R>), dim3(nblk(nspec(g))), dim3(256), 0, s, (C2<R>*)x, (const C2<R>*)z, g,
-                     p.precond ? p.kind : -1, p.rho0, p.nu, a_dev, a_host, nspec(g));
+                     p.precond ? p.kind : -1, p.rho0, p.nu, a_dev, a_host, nspec(g), p.gate);
 }
 
 template <typename R>
 __global__ __launch_bounds__(256) void k_dot_rMr(const C2<R>* __restrict__ r, Geom g, int kind, double rho0,
-                                                 double nu, size_t n, double* __restrict__ partial) {
+                                                 double nu, size_t n, double* __restrict__ partial,
+                                                 const int* __restrict__ gate) {
+  if (gate && *gate) return;
   double acc = 0.0;
   for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
     C2<R> rv = ldg(r + e), mz = precond_at<R>(r, e, g, kind, rho0, nu);
@@ -495,15 +502,16 @@ __global__ __launch_bounds__(256) void k_dot_rMr(const C2<R>* __restrict__ r, Ge
 template <typename R>
 void dot_rMr(const Geom& g, const OpParams& p, const void* r, double* partial, double* out, hipStream_t s) {
   hipLaunchKernelGGL((k_dot_rMr<R>), dim3(nblk(nspec(g))), dim3(256), 0, s, (const C2<R>*)r, g,
-                     p.precond ? p.kind : -1, p.rho0, p.nu, nspec(g), partial);
-  reduce(partial, nblk(nspec(g)), 1, g.ntot_inv, out, s);
+                     p.precond ? p.kind : -1, p.rho0, p.nu, nspec(g), partial, p.gate);
+  reduce(partial, nblk(nspec(g)), 1, g.ntot_inv, out, s, p.gate);
 }
 
 template <typename R>
 __global__ __launch_bounds__(256) void k_cg_xr(C2<R>* __restrict__ x, C2<R>* __restrict__ r,
                                                const C2<R>* __restrict__ p, const C2<R>* __restrict__ q,
                                                const DevState* __restrict__ st, size_t n, int M,
-                                               double* __restrict__ partial) {
+                                               double* __restrict__ partial, const int* __restrict__ gate) {
+  if (gate && *gate) return;
   const double a = st->alpha;
   double acc = 0.0;
   for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
@@ -517,15 +525,17 @@ __global__ __launch_bounds__(256) void k_cg_xr(C2<R>* __restrict__ x, C2<R>* __r
 }
 template <typename R>
 void cg_xr(const Geom& g, void* x, void* r, const void* p, const void* q, const DevState* st, double* partial,
-           double* out, hipStream_t s) {
+           double* out, hipStream_t s, const int* gate) {
   hipLaunchKernelGGL((k_cg_xr<R>), dim3(nblk(nspec(g))), dim3(256), 0, s, (C2<R>*)x, (C2<R>*)r, (const C2<R>*)p,
-                     (const C2<R>*)q, st, nspec(g), g.M, partial);
-  reduce(partial, nblk(nspec(g)), 1, g.ntot_inv, out, s);
+                     (const C2<R>*)q, st, nspec(g), g.M, partial, gate);
+  reduce(partial, nblk(nspec(g)), 1, g.ntot_inv, out, s, gate);
 }
 
 template <typename R>
 __global__ __launch_bounds__(256) void k_cg_p(C2<R>* __restrict__ p, const C2<R>* __restrict__ r, Geom g, int kind,
-                                              double rho0, double nu, const DevState* __restrict__ st, size_t n) {
+                                              double rho0, double nu, const DevState* __restrict__ st, size_t n,
+                                              const int* __restrict__ gate) {
+  if (gate && *gate) return;
   const double b = st->beta;
   for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
     C2<R> mz = precond_at<R>(r, e, g, kind, rho0, nu);
@@ -536,13 +546,14 @@ __global__ __launch_bounds__(256) void k_cg_p(C2<R>* __restrict__ p, const C2<R>
 template <typename R>
 void cg_p(const Geom& g, const OpParams& op, void* p, const void* r, const DevState* st, hipStream_t s) {
   hipLaunchKernelGGL((k_cg_p<R>), dim3(nblk(nspec(g))), dim3(256), 0, s, (C2<R>*)p, (const C2<R>*)r, g,
-                     op.precond ? op.kind : -1, op.rho0, op.nu, st, nspec(g));
+                     op.precond ? op.kind : -1, op.rho0, op.nu, st, nspec(g), op.gate);
 }
 
 template <typename R>
 __global__ __launch_bounds__(256) void k_axpy_norm(C2<R>* __restrict__ r, const C2<R>* __restrict__ w,
                                                    const double* __restrict__ ad, double sign, size_t n, int M,
-                                                   double* __restrict__ partial) {
+                                                   double* __restrict__ partial, const int* __restrict__ gate) {
+  if (gate && *gate) return;
   const double a = *ad * sign;
   double acc = 0.0;
   for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
@@ -555,10 +566,10 @@ __global__ __launch_bounds__(256) void k_axpy_norm(C2<R>* __restrict__ r, const 
 }
 template <typename R>
 void axpy_norm(const Geom& g, void* r, const void* w, const double* a_dev, double sign, double* partial, double* out,
-               hipStream_t s) {
+               hipStream_t s, const int* gate) {
   hipLaunchKernelGGL((k_axpy_norm<R>), dim3(nblk(nspec(g))), dim3(256), 0, s, (C2<R>*)r, (const C2<R>*)w, a_dev, sign,
-                     nspec(g), g.M, partial);
-  reduce(partial, nblk(nspec(g)), 1, g.ntot_inv, out, s);
+                     nspec(g), g.M, partial, gate);
+  reduce(partial, nblk(nspec(g)), 1, g.ntot_inv, out, s, gate);
 }
 
 // ---------------------------------------------------------------- casts
@@ -661,21 +672,21 @@ __global__ void k_gmres_backsolve(DevState* st, int k) {
   for (int i = 0; i < k; ++i) st->coef[i] = st->y[i] * st->vs[i];  // stored basis is unnormalised
 }
 
-__global__ void k_cg_alpha(DevState* st) {
-  if (threadIdx.x) return;
+__global__ void k_cg_alpha(DevState* st, const int* gate) {
+  if (threadIdx.x || (gate && *gate)) return;
   const double pq = st->red[0];
   st->alpha = pq != 0.0 ? st->rz / pq : 0.0;
   if (!isfinite(st->alpha) || pq <= 0.0) st->bad = 1;
 }
-__global__ void k_cg_beta(DevState* st) {
-  if (threadIdx.x) return;
+__global__ void k_cg_beta(DevState* st, const int* gate) {
+  if (threadIdx.x || (gate && *gate)) return;
   const double rzn = st->red[0];
   st->beta = st->rz != 0.0 ? rzn / st->rz : 0.0;
   st->rz = rzn;
   if (!isfinite(st->beta)) st->bad = 1;
 }
-__global__ void k_rmr_alpha(DevState* st) {
-  if (threadIdx.x) return;
+__global__ void k_rmr_alpha(DevState* st, const int* gate) {
+  if (threadIdx.x || (gate && *gate)) return;
   const double ww = st->red[1];
   st->alpha = ww > 0.0 ? st->red[0] / ww : 0.0;
   if (!isfinite(st->alpha)) st->bad = 1;
@@ -687,9 +698,41 @@ void gmres_init(DevState* st, double beta, int m, double bnorm, double rtol, int
 void gmres_backsolve(DevState* st, int k, hipStream_t s) {
   hipLaunchKernelGGL(k_gmres_backsolve, dim3(1), dim3(64), 0, s, st, k);
 }
-void cg_alpha(DevState* st, hipStream_t s) { hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(64), 0, s, st); }
-void cg_beta(DevState* st, hipStream_t s) { hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(64), 0, s, st); }
-void rmr_alpha(DevState* st, hipStream_t s) { hipLaunchKernelGGL(k_rmr_alpha, dim3(1), dim3(64), 0, s, st); }
+void cg_alpha(DevState* st, hipStream_t s, const int* gate) {
+  hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(64), 0, s, st, gate);
+}
+void cg_beta(DevState* st, hipStream_t s, const int* gate) {
+  hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(64), 0, s, st, gate);
+}
+void rmr_alpha(DevState* st, hipStream_t s, const int* gate) {
+  hipLaunchKernelGGL(k_rmr_alpha, dim3(1), dim3(64), 0, s, st, gate);
+}
+
+// Stopping test of a CG or RMR step on its recursive residual (st->nrm2),
+// the host loop's test taken on the device: a non-finite scalar, the
+// tolerance, or the last step of the run sets halt.  step counts the steps.
+__global__ void k_rec_check(DevState* st, const int* gate) {
+  if (threadIdx.x || (gate && *gate)) return;
+  const int j = st->step;
+  st->step = j + 1;
+  const double n2 = st->nrm2;
+  const double rn = n2 < 0.0 ? 0.0 : sqrt(n2);
+  if (st->bad || !(n2 == n2) || rn / st->stop_bnorm <= st->stop_rtol || j >= st->jlast) st->halt = 1;
+}
+__global__ void k_rec_init(DevState* st, double bnorm, double rtol, int jlast) {
+  if (threadIdx.x) return;
+  st->stop_bnorm = bnorm;
+  st->stop_rtol = rtol;
+  st->jlast = jlast;
+  st->step = 0;
+  st->halt = 0;
+}
+void rec_init(DevState* st, double bnorm, double rtol, int jlast, hipStream_t s) {
+  hipLaunchKernelGGL(k_rec_init, dim3(1), dim3(64), 0, s, st, bnorm, rtol, jlast);
+}
+void rec_check(DevState* st, hipStream_t s, const int* gate) {
+  hipLaunchKernelGGL(k_rec_check, dim3(1), dim3(64), 0, s, st, gate);
+}
 
 // --------------------------------------------------------- density set-up
 
@@ -787,7 +830,7 @@ void kcoef_finish(const double* rho, const double* lap_psi, double* kc64, float*
 
 #define VD_INST(R)                                                                                             \
   template void mdot<R>(const Geom&, const void*, const VecPtrs&, int, bool, double*, double*, hipStream_t,    \
-                        Prof*);                                                                                \
+                        Prof*, const int*);                                                                    \
   template void lincomb<R>(const Geom&, void*, const VecPtrs&, int, const double*, hipStream_t);               \
   template void scale<R>(const Geom&, void*, const double*, double, hipStream_t);                              \
   template void gs_orthogonalize<R>(const Geom&, void*, const VecPtrs&, int, DevState*, double*, hipStream_t,  \
@@ -797,10 +840,10 @@ void kcoef_finish(const double* rho, const double* lap_psi, double* kc64, float*
                                 hipStream_t);                                                                  \
   template void dot_rMr<R>(const Geom&, const OpParams&, const void*, double*, double*, hipStream_t);          \
   template void cg_xr<R>(const Geom&, void*, void*, const void*, const void*, const DevState*, double*,       \
-                         double*, hipStream_t);                                                                \
+                         double*, hipStream_t, const int*);                                                    \
   template void cg_p<R>(const Geom&, const OpParams&, void*, const void*, const DevState*, hipStream_t);       \
   template void axpy_norm<R>(const Geom&, void*, const void*, const double*, double, double*, double*,         \
-                             hipStream_t);
+                             hipStream_t, const int*);
 
 VD_INST(double)
 VD_INST(float)

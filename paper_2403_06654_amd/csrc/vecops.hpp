@@ -34,23 +34,25 @@ struct DevState {
   int reorth;                // second Gram-Schmidt pass ran for this step
   int nreorth;               // second passes since the grid was created
   double alpha, beta, rz, rz_new;
-  // GMRES stopping test, evaluated on the device after each step:
-  // resid / stop_bnorm <= stop_rtol, a non-finite scalar, or step jlast of
-  // the cycle (restart length or iteration budget) sets halt
+  // Krylov stopping test, evaluated on the device after each step (GMRES:
+  // resid / stop_bnorm <= stop_rtol on the Givens estimate; CG and RMR: on
+  // the recursive residual), a non-finite scalar, or step jlast of the cycle
+  // or run (restart length or iteration budget) sets halt
   double stop_bnorm, stop_rtol;
   int jlast;
+  int step;                  // CG / RMR: steps completed in the current run
   // mirrored to the host after each step
   double resid;              // estimated (GMRES) or recursive residual norm
   double nrm2;               // last computed squared norm
   int bad;                   // non-finite scalar seen
-  int halt;                  // GMRES: the cycle has ended; gated kernels return at once
+  int halt;                  // the cycle or run has ended; gated kernels return at once
 };
 
 // partial[b][i] = sum_e w_e Re(conj(V_i[e]) x[e]) (i < nv), plus |x|^2 at
 // index nv when want_norm.  Then reduce into st->red (times 1/N).
 template <typename R>
 void mdot(const Geom& g, const void* x, const VecPtrs& V, int nv, bool want_norm, double* partial,
-          double* out, hipStream_t s, Prof* prof = nullptr);
+          double* out, hipStream_t s, Prof* prof = nullptr, const int* gate = nullptr);
 
 // GMRES step: orthogonalise w against the stored basis V_0..V_{nv-1}
 // (v_i = vs[i] V_i) in place; classical Gram-Schmidt with a measured
@@ -75,6 +77,8 @@ template <typename R>
 void sub_norm(const Geom& g, const void* b, const void* q, void* r, double* partial, double* out,
               hipStream_t s);
 
+// Gates: the kernels below that take OpParams honour p.gate; the others take
+// an explicit gate.  A nonzero *gate makes the launch do nothing.
 // x += a M^-1 z   (a = (*a_dev) * a_host; M^-1 diagonal, Helmholtz kx = 0 mirrored)
 template <typename R>
 void precond_axpy(const Geom& g, const OpParams& p, void* x, const void* z, const double* a_dev,
@@ -88,14 +92,14 @@ void dot_rMr(const Geom& g, const OpParams& p, const void* r, double* partial, d
 // CG: x += alpha p; r -= alpha q; |r|^2 -> out[0]   (alpha = st->alpha)
 template <typename R>
 void cg_xr(const Geom& g, void* x, void* r, const void* p, const void* q, const DevState* st,
-           double* partial, double* out, hipStream_t s);
+           double* partial, double* out, hipStream_t s, const int* gate = nullptr);
 // CG: p = M^-1 r + beta p   (beta = st->beta)
 template <typename R>
 void cg_p(const Geom& g, const OpParams& op, void* p, const void* r, const DevState* st, hipStream_t s);
 // RMR: r -= alpha w; |r|^2 -> out[0]
 template <typename R>
 void axpy_norm(const Geom& g, void* r, const void* w, const double* a_dev, double sign, double* partial,
-               double* out, hipStream_t s);
+               double* out, hipStream_t s, const int* gate = nullptr);
 
 // precision casts between spectral vectors: dst(float) = src(double) * s
 void cast_d2f(const Geom& g, const void* src, void* dst, double s, hipStream_t st);
@@ -114,9 +118,15 @@ void zero_mean(const Geom& g, void* spec, double* removed, hipStream_t st);
 // (bnorm, rtol, last step jlast of this cycle; halt cleared).
 void gmres_init(DevState* st, double beta, int m, double bnorm, double rtol, int jlast, hipStream_t s);
 void gmres_backsolve(DevState* st, int k, hipStream_t s);  // y, and coef = y * vs
-void cg_alpha(DevState* st, hipStream_t s);   // alpha = rz / red[0]
-void cg_beta(DevState* st, hipStream_t s);    // beta = red[0] / rz; rz = red[0]
-void rmr_alpha(DevState* st, hipStream_t s);  // alpha = red[0] / red[1]
+void cg_alpha(DevState* st, hipStream_t s, const int* gate = nullptr);   // alpha = rz / red[0]
+void cg_beta(DevState* st, hipStream_t s, const int* gate = nullptr);    // beta = red[0] / rz; rz = red[0]
+void rmr_alpha(DevState* st, hipStream_t s, const int* gate = nullptr);  // alpha = red[0] / red[1]
+// Starts a CG or RMR run: its stopping test (bnorm, rtol, last step jlast),
+// step = 0, halt cleared.
+void rec_init(DevState* st, double bnorm, double rtol, int jlast, hipStream_t s);
+// After a CG or RMR step: halt on a non-finite scalar, on the recursive
+// residual sqrt(nrm2) / bnorm <= rtol, or on step jlast.
+void rec_check(DevState* st, hipStream_t s, const int* gate);
 
 // Density set-up: a = 1/rho and copies, min/max/sum reductions.
 void density_setup(const double* rho, size_t n, double* a64, float* a32, float* rho32, double* partial,
