@@ -63,11 +63,13 @@ struct ColCfg {
 
 template <int L, typename R>
 struct RowCfg {
-  // FP64 rows (and long FP32 rows) use 8 points per thread: the x pass
-  // keeps a field's inverse and forward transforms plus the half-length
-  // pre/post-processing live at once, and 16 points per thread would cap
-  // occupancy at one wave/SIMD or spill
-  static constexpr int E = L >= 16 ? ((sizeof(R) == 8 || L >= 256) ? 8 : 16) : L;
+  // 8 points per thread: the x pass keeps a field's inverse and forward
+  // transforms plus the half-length pre/post-processing live at once, and
+  // 16 points per thread would cap FP64 occupancy at one wave/SIMD or spill.
+  // FP32 rows too: at 256^3 (128-point rows) 16 points per thread took the
+  // pressure x pass 126 us and the Helmholtz x pass 48 us, 8 points 113 and
+  // 40 us.
+  static constexpr int E = L >= 16 ? 8 : L;
   static constexpr int T = L / E;
   static_assert(T <= 64, "a row must fit one wavefront");
   // A row's T threads are adjacent lanes of one wavefront and each row owns
