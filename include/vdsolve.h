@@ -54,7 +54,8 @@ typedef enum {
   VD_EINVAL = -1,     /* bad argument (null pointer, size, option) */
   VD_ENOMEM = -2,     /* device allocation failed */
   VD_EDOMAIN = -3,    /* density not strictly positive and finite */
-  VD_EBREAKDOWN = -4, /* non-finite Krylov scalar */
+  VD_EBREAKDOWN = -4, /* non-finite Krylov scalar or residual (also from a non-finite
+                         right-hand side or initial iterate) */
   VD_EDEVICE = -5,    /* HIP runtime error */
   VD_ETOOBIG = -6,    /* request larger than a serving budget */
   VD_ENOTSUP = -7     /* valid but not implemented */
