@@ -433,37 +433,10 @@ struct Krylov {
       // the cycle ends after step jlast at the latest (restart length or iteration budget)
       const int jlast = std::min(m, cfg.max_iter - o.iters) - 1;
       gmres_init(G->dst, beta, m, bnorm, cfg.rtol, jlast, G->st);  // v_0 = V[0] / beta via the scale vs[0]
-      int k = 0;
-      // Step j + 1 is queued before step j's residual reaches the host, so
-      // the GPU never idles while the host decides.  The device takes the
-      // same stopping test (k_gs_check); a step queued past the end of the
-      // cycle returns at its gates and its profile records are dropped.
-      Prof& pf = G->prof;
-      if (pf.on) pf.flush();
-      arnoldi_step(V, 0, &G->dst->halt);
-      post_tail(0);
-      size_t mark = pf.pending.size();
-      for (int j = 0; j <= jlast; ++j) {
-        if (j < jlast) {
-          arnoldi_step(V, j + 1, &G->dst->halt);
-          post_tail(j + 1);
-        }
-        ck(hipEventSynchronize(G->slot_ev[j & 1]));
-        const DevState& t = G->hslot[j & 1];
-        G->hst->resid = t.resid;
-        G->hst->nrm2 = t.nrm2;
-        G->hst->bad = t.bad;
-        G->hst->halt = t.halt;
-        if (pf.on) {
-          pf.flush_front(mark);  // step j's records; step j + 1's stay pending
-          mark = pf.pending.size();
-        }
-        o.iters++;
-        k = j + 1;
-        if (cfg.hist) cfg.hist->push_back(G->hst->resid / bnorm);
-        if (G->hst->bad || G->hst->halt) break;
-      }
-      if (pf.on) pf.drop();  // the step queued after the last one did nothing
+      // the step count k of this cycle: its basis size for the back-solve
+      const int k = run_queued(jlast, [&](int j, const int* gate) { arnoldi_step(V, j, gate); },
+                               [&] { return G->hst->resid / bnorm; });
+      o.iters += k;
       if (G->hst->bad) { o.status = VD_EBREAKDOWN; return o; }
       gmres_backsolve(G->dst, k, G->st);
       VecPtrs P{};
@@ -501,13 +474,15 @@ struct Krylov {
     else ck(hipMemcpyAsync(p, r, G->nspec * elem_bytes(prec), hipMemcpyDeviceToDevice, G->st));
   }
 
-  // Steps 0..jlast of a CG or RMR run, each queued before the previous
-  // step's state reaches the host, as for GMRES: step(j, gate) enqueues
-  // step j with its stopping test (rec_check), every launch gated by the
-  // halt flag.  Returns the steps that ran; G->hst holds the state after the
-  // last of them.
-  template <typename Step>
-  int run_queued(int jlast, double bnorm, Step&& step) {
+  // Steps 0..jlast of a GMRES cycle or a CG/RMR run.  Step j + 1 is queued
+  // before step j's state reaches the host, so the GPU never idles while the
+  // host decides: step(j, gate) enqueues step j with its stopping test on the
+  // device (k_gs_check, k_rec_check), every launch gated by the halt flag, so
+  // that a step queued past the end returns at once (its profile records are
+  // dropped).  history() gives the residual recorded after each step.
+  // Returns the steps that ran; G->hst holds the state after the last.
+  template <typename Step, typename Hist>
+  int run_queued(int jlast, Step&& step, Hist&& history) {
     Prof& pf = G->prof;
     if (pf.on) pf.flush();
     const int* gate = &G->dst->halt;
@@ -531,7 +506,7 @@ struct Krylov {
         mark = pf.pending.size();
       }
       done = j + 1;
-      if (cfg.hist) cfg.hist->push_back(norm_from_sq(G->hst->nrm2) / bnorm);
+      if (cfg.hist) cfg.hist->push_back(history());
       if (G->hst->bad || G->hst->halt || !(G->hst->nrm2 == G->hst->nrm2)) break;
     }
     if (pf.on) pf.drop();
@@ -554,7 +529,7 @@ struct Krylov {
       const int jlast = cfg.max_iter - o.iters - 1;
       rec_init(G->dst, bnorm, cfg.rtol, jlast, G->st);
       rz_and_p(r, p, true);
-      o.iters += run_queued(jlast, bnorm, [&](int j, const int* gate) {
+      o.iters += run_queued(jlast, [&](int j, const int* gate) {
         if (j > 0) rz_and_p(r, p, false, gate);
         apply(p, q, false, nullptr, gate);
         VecPtrs P{};
@@ -563,7 +538,7 @@ struct Krylov {
         cg_alpha(G->dst, G->st, gate);
         cg_xr<R>(g, x, r, p, q, G->dst, G->partial, &G->dst->nrm2, G->st, gate);
         rec_check(G->dst, G->st, gate);
-      });
+      }, [&] { return norm_from_sq(G->hst->nrm2) / bnorm; });
       if (G->hst->bad || !(G->hst->nrm2 == G->hst->nrm2)) { o.status = VD_EBREAKDOWN; return o; }
       if (cfg.inner) {
         o.relres = norm_from_sq(G->hst->nrm2) / bnorm;
@@ -587,7 +562,7 @@ struct Krylov {
       if (o.iters >= cfg.max_iter) { o.status = VD_NOT_CONVERGED; return o; }
       const int jlast = cfg.max_iter - o.iters - 1;
       rec_init(G->dst, bnorm, cfg.rtol, jlast, G->st);
-      o.iters += run_queued(jlast, bnorm, [&](int, const int* gate) {
+      o.iters += run_queued(jlast, [&](int, const int* gate) {
         apply(r, w, true, nullptr, gate);  // w = A M^-1 r
         VecPtrs P{};
         P.p[0] = r;
@@ -596,7 +571,7 @@ struct Krylov {
         prec_axpy(x, r, &G->dst->alpha, gate);
         axpy_norm<R>(g, r, w, &G->dst->alpha, -1.0, G->partial, &G->dst->nrm2, G->st, gate);
         rec_check(G->dst, G->st, gate);
-      });
+      }, [&] { return norm_from_sq(G->hst->nrm2) / bnorm; });
       if (G->hst->bad || !(G->hst->nrm2 == G->hst->nrm2)) { o.status = VD_EBREAKDOWN; return o; }
       if (cfg.inner) {
         o.relres = norm_from_sq(G->hst->nrm2) / bnorm;
