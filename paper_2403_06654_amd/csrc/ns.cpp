@@ -55,6 +55,7 @@ struct vd_ns {
   double* V = nullptr;  // GMRES basis, (restart + 1) vectors of 3 N
   double* part = nullptr;
   double* dc = nullptr;
+  double* dh = nullptr;  // GMRES: the Hessenberg column being built, then ||w||^2
   int nb = 0;
   std::vector<double> hpart;
   vd_ns_info last{};
@@ -367,14 +368,19 @@ void solve_viscous(vd_ns* h, const double* b, double* x, int& iters, int& status
       helm_inv(h, vj, c, z, 3);
       zeta(h, z, 1.0, -hdt, w);
       ++iters;
-      std::fill(cf.begin(), cf.end(), 0.0);
+      // both Gram-Schmidt passes on the device (coefficients reduced there
+      // in a fixed order), then one read of the column and ||w||^2
       for (int pass = 0; pass < 2; ++pass) {
-        dots(h, h->V, n3, j + 1, w, n3, c2.data());
-        for (int i = 0; i <= j; ++i) cf[i] += c2[i];
-        to_dev(h, c2.data(), j + 1);
+        timed(h, 2, 8.0 * (double)n3 * (j + 2), [&] { ns_dots(h->V, n3, j + 1, w, n3, h->part, h->nb, h->st); });
+        ns_dsum(h->part, h->nb, j + 1, h->dc, h->dh, pass, h->st);
         timed(h, 2, 8.0 * (double)n3 * (j + 3), [&] { ns_mupdate(h->V, n3, j + 1, h->dc, w, n3, 0, h->st); });
       }
-      const double hn = norm(h, w, n3);
+      timed(h, 2, 8.0 * (double)n3 * 2, [&] { ns_dots(w, 0, 1, w, n3, h->part, h->nb, h->st); });
+      ns_dsum(h->part, h->nb, 1, h->dh + j + 1, nullptr, 0, h->st);
+      ck(hipMemcpyAsync(c2.data(), h->dh, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, h->st));
+      ck(hipStreamSynchronize(h->st));
+      for (int i = 0; i <= j; ++i) cf[i] = c2[i];
+      const double hn = std::sqrt(c2[j + 1]);
       double hj = cf[0];
       for (int i = 0; i < j; ++i) {
         const double hb = cf[i + 1];
@@ -594,6 +600,7 @@ vd_status vd_ns_create(vd_ns** out, int n, const vd_ns_params* prm, hipStream_t 
     h->nb = ns_dot_blocks(3 * N);
     h->part = dalloc(h, (size_t)(p.restart + 1) * h->nb);
     h->dc = dalloc(h, p.restart + 1);
+    h->dh = dalloc(h, p.restart + 2);
   } catch (const Err& e) {
     release(h);
     return e.s;

@@ -71,6 +71,9 @@ void ns_tg_fields(int n, double t, double s, double* u, double* p, double* rho, 
 // Partial inner products: part[i * nb + b] = sum over block b's share of
 // V_i . w, V_i = V + i * stride, i < nv.  Fixed order within a block.
 int ns_dot_blocks(size_t n);
+// c[i] = sum over blocks of part[i][b] on the device, in a fixed order;
+// hacc (optional) = c (acc = 0) or += c (acc = 1)
+void ns_dsum(const double* part, int nb, int nv, double* c, double* hacc, int acc, hipStream_t st);
 void ns_dots(const double* V, size_t stride, int nv, const double* w, size_t n, double* part, int nb,
              hipStream_t st);
 

@@ -155,6 +155,32 @@ void ns_tg_fields(int n, double t, double s, double* u, double* p, double* rho, 
   hipLaunchKernelGGL(k_tg, dim3(grid_of(N)), dim3(kT), 0, st, n, t, s, u, p, rho, du, drho);
 }
 
+// c[i] = the block partials of dot i summed by block i of the launch in a
+// fixed order (strided per thread, then a fixed tree), so the result does
+// not depend on scheduling; hacc[i] = c[i] (acc = 0) or += c[i] (acc = 1)
+// when given
+__global__ __launch_bounds__(kT) void k_dsum(const double* __restrict__ part, int nb, double* __restrict__ c,
+                                             double* __restrict__ hacc, int acc) {
+  __shared__ double sh[kT];
+  const int i = blockIdx.x;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kT) s += part[(size_t)i * nb + b];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = kT / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    c[i] = sh[0];
+    if (hacc) hacc[i] = acc ? hacc[i] + sh[0] : sh[0];
+  }
+}
+
+void ns_dsum(const double* part, int nb, int nv, double* c, double* hacc, int acc, hipStream_t st) {
+  hipLaunchKernelGGL(k_dsum, dim3(nv), dim3(kT), 0, st, part, nb, c, hacc, acc);
+}
+
 int ns_dot_blocks(size_t n) {
   size_t b = (n + 8 * kT - 1) / (8 * kT);
   return (int)(b < 1024 ? (b > 0 ? b : 1) : 1024);
