@@ -38,6 +38,11 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int kT = 256;            // threads per workgroup (4 wavefronts)
 constexpr int kG = kVisc1dGroup;   // systems per workgroup
 constexpr int kRed = 16;           // Gram-Schmidt coefficients reduced together
+// GMRES: components of the new vector along the basis above this fraction of
+// its norm are removed by a second Gram-Schmidt pass (the 3D solver's FP64
+// tolerance; the residual estimate then differs from the true one by at most
+// sqrt(1 + (m+1) tol) - 1)
+constexpr double kVisc1dOrthTol = 1e-8;
 
 enum Kind { K_APPLY = 0, K_RMR = 1, K_GMRES = 2 };
 
@@ -226,6 +231,8 @@ __global__ __launch_bounds__(kT, (KIND == K_GMRES || TPW > 4) ? 1 : 2) void k_vi
   double* cco = hco + (m + 1) * kG;   // [m + 1][kG] coefficients of the current pass, then y
   int* bad_s = reinterpret_cast<int*>(cco + (m + 1) * kG);  // [kG] density rejected
   int* stop_s = bad_s + kG;                                  // [kG] Arnoldi stop flags
+  double* thr = reinterpret_cast<double*>(stop_s + kG);      // [kG] orthogonality threshold per system
+  int* need = reinterpret_cast<int*>(thr + kG);              // [m + 1] basis vectors of the second pass
   const Ln l{(int)threadIdx.x & 63, (int)threadIdx.x >> 6, (int)threadIdx.x & 15, ((int)threadIdx.x >> 4) & 3};
   const int g0 = blockIdx.x * kG;
   const int nsys = min(kG, a.batch - g0);
@@ -478,7 +485,12 @@ __global__ __launch_bounds__(kT, (KIND == K_GMRES || TPW > 4) ? 1 : 2) void k_vi
           apply(Z, Wv);
           if (!park) ++it;
           for (int e = threadIdx.x; e < (j + 1) * kG; e += kT) hco[e] = 0.0;
-          for (int pass = 0; pass < 2; ++pass) {
+          // Classical Gram-Schmidt with a measured check, as in the 3D solver:
+          // h = V^T w, w' = w - V h, then c = V^T w'.  A second pass subtracts
+          // only the components with |c_i| > tol ||w'|| of some system of the
+          // group and reads only those basis vectors (CGS2 read the basis four
+          // times per step, this reads it three times plus the few selected).
+          auto basis_dots = [&]() {  // cco[i][s] = (v_i, w) for i <= j
             for (int i0 = 0; i0 <= j; i0 += kRed) {
               double p[kRed];
 #pragma unroll
@@ -497,17 +509,47 @@ __global__ __launch_bounds__(kT, (KIND == K_GMRES || TPW > 4) ? 1 : 2) void k_vi
                   if (i0 + c <= j) cco[(i0 + c) * kG + l.sl] = p[c];
               }
             }
-            __syncthreads();
-            for (int e = threadIdx.x; e < (j + 1) * kG; e += kT) hco[e] += cco[e];
-            for (int i = 0; i <= j; ++i) {
-              const double c = cco[i * kG + l.sl];
-              Vec<TPW> vi;
-              vld(vi, wbas + (size_t)i * L::V, l);
+          };
+          basis_dots();
+          __syncthreads();
+          for (int e = threadIdx.x; e < (j + 1) * kG; e += kT) hco[e] += cco[e];
+          for (int i = 0; i <= j; ++i) {
+            const double c = cco[i * kG + l.sl];
+            Vec<TPW> vi;
+            vld(vi, wbas + (size_t)i * L::V, l);
 #pragma unroll
-              for (int t = 0; t < TPW; ++t) Wv.t[t] -= c * vi.t[t];
-            }
-            __syncthreads();
+            for (int t = 0; t < TPW; ++t) Wv.t[t] -= c * vi.t[t];
           }
+          __syncthreads();
+          basis_dots();
+          {
+            double s2[1] = {pdot(Wv, Wv)};
+            gsum<1>(s2, red, l);
+            if (owner) thr[l.sl] = kVisc1dOrthTol * sqrt(s2[0]);
+          }
+          __syncthreads();
+          // keep c_i[s] only where it fails the test (NaN fails); vector i is
+          // read when any system keeps it
+          for (int i = threadIdx.x; i <= j; i += kT) {
+            int any = 0;
+            for (int q = 0; q < kG; ++q) {
+              const double c = cco[i * kG + q];
+              if (fabs(c) <= thr[q]) cco[i * kG + q] = 0.0;
+              else any = 1;
+            }
+            need[i] = any;
+          }
+          __syncthreads();
+          for (int i = 0; i <= j; ++i) {
+            if (!need[i]) continue;  // uniform across the block
+            const double c = cco[i * kG + l.sl];
+            Vec<TPW> vi;
+            vld(vi, wbas + (size_t)i * L::V, l);
+#pragma unroll
+            for (int t = 0; t < TPW; ++t) Wv.t[t] -= c * vi.t[t];
+          }
+          for (int e = threadIdx.x; e < (j + 1) * kG; e += kT) hco[e] += cco[e];
+          __syncthreads();
           double s[1] = {pdot(Wv, Wv)};
           gsum<1>(s, red, l);
           const double hn = sqrt(s[0]);
@@ -594,7 +636,8 @@ hipError_t launch_tpw(const Visc1dArgs& a, hipStream_t st) {
   using L = Lay<TPW>;
   const int kind = a.mode != VISC1D_SOLVE ? K_APPLY : (a.solver == VISC1D_RMR ? K_RMR : K_GMRES);
   const int m = kind == K_GMRES ? a.restart : 0;
-  const size_t lds = (size_t)(L::NB + kRed * 4 * kG + 2 * (m + 1) * kG) * sizeof(double) + 2 * kG * sizeof(int);
+  const size_t lds = (size_t)(L::NB + kRed * 4 * kG + 2 * (m + 1) * kG + kG) * sizeof(double) +
+                     (2 * kG + m + 1) * sizeof(int);
   const void* fn = kind == K_APPLY ? reinterpret_cast<const void*>(&k_visc1d<TPW, K_APPLY>)
                    : kind == K_RMR ? reinterpret_cast<const void*>(&k_visc1d<TPW, K_RMR>)
                                    : reinterpret_cast<const void*>(&k_visc1d<TPW, K_GMRES>);
