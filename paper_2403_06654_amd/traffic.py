@@ -30,22 +30,23 @@ def _rows(d):
     return list(csv.DictReader(open(path)))
 
 
-def main(fetch_dir, write_dir):
-    from bench import csrc_hash  # noqa: E402
-    F, W = _rows(fetch_dir), _rows(write_dir)
+def summarize(F, W, source_hash):
+    """Calibrated per-launch HBM bytes of the timed kernel classes from the
+    FETCH_SIZE rows F and the WRITE_SIZE rows W (rocprofv3 counter CSV rows,
+    in dispatch order)."""
     copy_bytes = 1 << 30
     cf = next(r for r in F if r["Kernel_Name"].startswith("__amd_rocclr_copyBuffer"))
     cw = next(r for r in W if r["Kernel_Name"].startswith("__amd_rocclr_copyBuffer"))
     kf = copy_bytes / (float(cf["Counter_Value"]) * 1024)
     kw = copy_bytes / (float(cw["Counter_Value"]) * 1024)
-    out = {"csrc_sha256_16": csrc_hash(), "calibration": {"copy_bytes": copy_bytes, "fetch_factor": kf,
+    out = {"csrc_sha256_16": source_hash, "calibration": {"copy_bytes": copy_bytes, "fetch_factor": kf,
                                                            "write_factor": kw},
            "per_launch_bytes": {}, "launches": {}}
     for name, pat in CLASS_PATTERNS.items():
         fv = [float(r["Counter_Value"]) * 1024 * kf for r in F if re.match(pat, r["Kernel_Name"])]
         wv = [float(r["Counter_Value"]) * 1024 * kw for r in W if re.match(pat, r["Kernel_Name"])]
         if fv and len(fv) == len(wv):
-            # A GMRES step queued past the end of its cycle launches every
+            # A Krylov step queued past the end of its run launches every
             # kernel, which returns at its gate having read a flag only: such
             # dispatches (under 1% of the median traffic) are not launches of
             # the timed work and are left out, as the HIP-event timing does.
@@ -54,6 +55,12 @@ def main(fetch_dir, write_dir):
             out["per_launch_bytes"][name] = round(sum(fv[i] + wv[i] for i in keep) / len(keep))
             out["launches"][name] = len(keep)
             out.setdefault("gated_dispatches_left_out", {})[name] = len(fv) - len(keep)
+    return out
+
+
+def main(fetch_dir, write_dir):
+    from bench import csrc_hash  # noqa: E402
+    out = summarize(_rows(fetch_dir), _rows(write_dir), csrc_hash())
     path = os.path.join(ROOT, "profiles", "traffic_counters.json")
     json.dump(out, open(path, "w"), indent=1)
     print(json.dumps(out, indent=1))
