@@ -123,3 +123,14 @@ def test_fractional_step_rejects_bad_parameters_without_touching_the_device():
     assert L.vd_ns_step(None, 1, None) == -1
     assert L.vd_ns_errors(None, None) == -1
     assert L.vd_ns_init_taylor_green(None) == -1
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """No fallback: without the built HIP library every entry point raises."""
+    from paper_2403_06654_amd import api
+    monkeypatch.setattr(api, "LIB_PATH", str(tmp_path / "libvdsolve.so"))
+    monkeypatch.setattr(api, "_LIB", None)
+    with pytest.raises(RuntimeError, match="is missing"):
+        api.lib()
+    with pytest.raises(RuntimeError, match="is missing"):
+        api.vd_status_string(0)
