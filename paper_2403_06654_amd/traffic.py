@@ -22,6 +22,16 @@ sys.path.insert(0, ROOT)
 CLASS_PATTERNS = {
     "gmres gram-schmidt update (k_gs_update)": r"^void vd::k_gs_update<double,",
     "pressure x pass (k_row ROW_P)": r"^void vd::k_row<128, double, 2>",
+    # the other passes of the 256^3 FP64 operator applications
+    "pressure z-first (k_col COL_P_FIRST)": r"^void vd::k_col<256, double, 2>",
+    "pressure y-inverse (k_col COL_P_MIDINV)": r"^void vd::k_col<256, double, 3>",
+    "pressure y-forward (k_col COL_P_MIDFWD)": r"^void vd::k_col<256, double, 4>",
+    "pressure z-last (k_col COL_P_LAST)": r"^void vd::k_col<256, double, 5>",
+    "helmholtz z-first (k_col COL_H_FIRST)": r"^void vd::k_col<256, double, 6>",
+    "y inverse FFT, one field (k_col COL_FFT_INV)": r"^void vd::k_col<256, double, 1>",
+    "helmholtz x pass (k_row ROW_H)": r"^void vd::k_row<128, double, 4>",
+    "y forward FFT, one field (k_col COL_FFT_FWD)": r"^void vd::k_col<256, double, 0>",
+    "helmholtz z-last (k_col COL_H_LAST)": r"^void vd::k_col<256, double, 7>",
 }
 
 
