@@ -191,7 +191,9 @@ size_t vd_workspace_bytes(const vd_grid_desc* desc, const vd_solve_opts* opts);
  * launches read and wrote (3D grids), for c < nclass (<= 12); any output
  * pointer may be NULL.  Reading resets the totals.  `classes` is a bit mask
  * of the classes to time (bit c = class c; -1 times all, 0 disables); each
- * timed launch adds an event pair on the grid's stream. */
+ * timed launch adds an event pair on the grid's stream.  A Krylov step that
+ * the solver queued past the end of a run does nothing, and its launches are
+ * not counted. */
 vd_status vd_profile_enable(vd_grid* grid, int classes);
 vd_status vd_profile_read(vd_grid* grid, double* ms, long long* count, double* bytes, int nclass);
 
