@@ -197,7 +197,7 @@ def csrc_hash():
 
 
 def pressure_forms(grid, rho_dev, f_dev, torch):
-    """The paper's modified pressure form (Sec. 4.2, eq. VDINSE.Krho) beside
+    """The paper's modified pressure form (Sec. 3.2, eq. VDINSE.Krho; the 3D choice of Sec. 4.2) beside
     the direct one on the same 256^3 pressure problems (FP64 GMRES(30), rtol
     1e-10, one solve per density after one untimed solve): iterations,
     milliseconds per solve and the relative difference of the two answers."""
@@ -580,7 +580,7 @@ def visc1d_cpu_baseline(inp, a):
 
 def bench_ns(args):
     """Fractional-step steps of the variable-density Navier-Stokes equations
-    (Sec. 2) on the manufactured Taylor-Green solution (Sec. 5.1,
+    (Sec. 2) on the manufactured Taylor-Green solution (Sec. 4.1,
     eq. VDINSE.solexact): 128^3, Re = Sc = 1, s = 10.  (a) dt = 0.01 (the
     divergence-history set-up): time per step with warm-started solves,
     Krylov iterations, ||div u|| after every step up to t = pi/4; (b) errors
@@ -671,7 +671,7 @@ def ns_cpu_baseline(n):
 
 
 def bench_kappa(args):
-    """Condition-number study (Sec. 3.1 Figs. 1-3 set-ups for V_rho, Sec. 4.2
+    """Condition-number study (Sec. 3.1 Figs. 1-3 set-ups for V_rho, Sec. 3.2
     Figs. 5-6 set-ups for L_rho and K_rho on periodic grids) with every
     operator column computed by the library's GPU applications and kappa from
     an SVD on the host; RMR and GMRES residual histories of the batched 1D

@@ -4,7 +4,7 @@ Taylor-Green solution that measures its accuracy.  Oracle; test
 infrastructure only.
 
 Equations (Sec. 2, eq. VDINSE, with the body force f of eq. VDINSE.momentum
-and a mass source S added for the manufactured solution of Sec. 5.1):
+and a mass source S added for the manufactured solution of Sec. 4.1):
     du/dt + (u.grad) u + grad(p) / rho = zeta(rho, u) + f
     drho/dt + u.grad(rho) = Lap(rho) / (Re Sc) + S,     div u = 0
     zeta(rho, u) = Lap(u) / (rho Re)
@@ -244,7 +244,7 @@ def projection(w, rho, rtol=1e-13):
 
 
 def errors(st, s, dt):
-    """epsilon_u, epsilon_p, epsilon_rho of Sec. 5.1 as RMS grid norms: u^n and
+    """epsilon_u, epsilon_p, epsilon_rho of Sec. 4.1 as RMS grid norms: u^n and
     rho^n against the exact fields at t^n, p^(n-1/2) against p_e(t^n - dt/2);
     and the RMS of div u^n."""
     n = st.rho.shape[0]

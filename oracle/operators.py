@@ -159,7 +159,7 @@ def project_range(b, basis):
 
 # ------------------------------------------ modified pressure (K_rho form)
 #
-# Sec. 4.2, eq. VDINSE.Krho: with Phi = phi / sqrt(rho) the pressure equation
+# Sec. 3.2, eq. VDINSE.Krho (used in 3D in Sec. 4.2): with Phi = phi / sqrt(rho) the pressure equation
 # L_rho phi = f becomes the modified Helmholtz equation
 #     K_rho Phi = Lap Phi + c Phi = sqrt(rho) f,
 #     c = Lap(rho) / (2 rho) - (3/4) |grad rho|^2 / rho^2,

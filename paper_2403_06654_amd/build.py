@@ -13,9 +13,6 @@ SOURCES = ["passes.hip", "vecops.hip", "gemm.hip", "cheb.cpp", "vdsolve.cpp", "v
 # per-source extra flags: the batched viscous kernels keep their MFMA
 # accumulators in VGPRs instead of copying them through AGPRs every k step
 EXTRA_FLAGS = {"visc1d.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
-# standalone stream-bandwidth ceiling probe (not part of the library)
-CEILING_SRC = "stream_ceiling.hip"
-CEILING_OUT = os.path.join(HERE, "stream_ceiling")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
@@ -46,10 +43,6 @@ def build(verbose=False):
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr[-4000:]}")
     os.replace(tmp, OUT)
-    cmd = [HIPCC, *FLAGS, "-x", "hip", os.path.join(CSRC, CEILING_SRC), "-o", CEILING_OUT]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed for {CEILING_SRC}:\n{r.stderr[-4000:]}")
     return OUT
 
 

@@ -1015,7 +1015,7 @@ static vd_status solve_impl(vd_grid* G, void* c) {
   op.rho0 = std::isnan(s->o.rho0) ? G->rho_mean : s->o.rho0;
   op.nu = s->nu;
   op.precond = s->o.precond ? 1 : 0;
-  // Modified pressure form (Sec. 4.2, eq. VDINSE.Krho): unknown Phi =
+  // Modified pressure form (Sec. 3.2, eq. VDINSE.Krho; used in 3D in Sec. 4.2): unknown Phi =
   // phi / sqrt(rho), A = -K_rho = -Lap - c on the Helmholtz skeleton (x-pass
   // coefficient -c, diagonal |k|^2, preconditioner the pseudo-inverse of
   // -Lap), b = -sqrt(rho) f projected onto the range (orthogonal to psi).

@@ -1,4 +1,4 @@
-"""GPU parity of the modified pressure form (Sec. 4.2, eq. VDINSE.Krho)
+"""GPU parity of the modified pressure form (Sec. 3.2, eq. VDINSE.Krho; the 3D setting of Sec. 4.2)
 against the oracle: the operator A_K = -K_rho and its preconditioner element
 by element, the exact null vector rho^-1/2, and solves whose returned
 p = sqrt(rho) Phi must match the oracle's K_rho solution (same gauge) and,

@@ -1,4 +1,4 @@
-"""GPU parity of the fractional-step driver (Sec. 2 scheme, Sec. 5.1
+"""GPU parity of the fractional-step driver (Sec. 2 scheme, Sec. 4.1
 manufactured Taylor-Green solution) against oracle.fractional_step, and the
 paper's accuracy statements on the GPU path.
 
@@ -78,7 +78,7 @@ def test_unforced_steps_from_a_given_state_match_the_oracle():
 
 
 def test_second_order_in_time_and_divergence_on_the_gpu():
-    """Sec. 5.1 at 32^3: second order in dt for u, p and rho; ||div u|| at
+    """Sec. 4.1 at 32^3: second order in dt for u, p and rho; ||div u|| at
     machine precision (the paper reaches 1e-14 from 32^3)."""
     from paper_2403_06654_amd.api import FractionalStep
     n = 32

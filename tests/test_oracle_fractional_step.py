@@ -1,4 +1,4 @@
-"""Pins for oracle.fractional_step (Sec. 2 scheme, Sec. 5.1 manufactured
+"""Pins for oracle.fractional_step (Sec. 2 scheme, Sec. 4.1 manufactured
 Taylor-Green solution): closed forms of zeta, time derivatives of the exact
 fields by finite differences, the paper's second-order temporal accuracy,
 divergence at machine precision, exactness of the projection, and the mass
@@ -61,7 +61,7 @@ def _run(n, K, s=S):
 
 
 def test_second_order_in_time():
-    """Sec. 5.1: the scheme is globally second order in time (u, p, rho)."""
+    """Sec. 4.1: the scheme is globally second order in time (u, p, rho)."""
     errs = [_run(16, K)[1] for K in (8, 16, 32)]
     for key in ("u", "rho"):
         orders = [np.log2(errs[i][key] / errs[i + 1][key]) for i in range(2)]
@@ -71,7 +71,7 @@ def test_second_order_in_time():
 
 
 def test_divergence_at_machine_precision():
-    """Sec. 5.1: ||div u|| is at machine precision at every step."""
+    """Sec. 4.1: ||div u|| is at machine precision at every step."""
     _, _, dmax = _run(16, 8)
     assert dmax < 1e-13
 

@@ -1,4 +1,4 @@
-"""Conditioning of the pressure operators (Sec. 4.2, Figs. 5-6 set-ups) on
+"""Conditioning of the pressure operators (Sec. 3.2, Figs. 5-6 set-ups) on
 periodic 1D grids, the stand-in for the paper's Chebyshev collocation: L_rho
 and K_rho are ill-conditioned (kappa grows like N^2) with K_rho the better of
 the two, and both preconditioned forms have kappa = O(10^0)-O(10^2),
