@@ -53,7 +53,37 @@ def test_untransposed_chebyshev_operand_is_caught(monkeypatch):
     _fails(to.test_fourier_chebyshev_operator)
 
 
+def _gmres_with(old, new):
+    """oracle.krylov.gmres recompiled from its own source with one line
+    changed: a planted mistake inside the algorithm."""
+    import inspect
+    src = inspect.getsource(krylov.gmres)
+    assert src.count(old) == 1
+    ns = {}
+    exec(compile(src.replace(old, new), krylov.__file__, "exec"), vars(krylov).copy(), ns)
+    return ns["gmres"]
+
+
 def test_givens_sign_error_is_caught(monkeypatch):
+    # the sine of the new Givens rotation with the wrong sign: the rotation no
+    # longer annihilates h_(j+1,j), so the least-squares residual estimate and
+    # the back-solved update are wrong
+    bad = _gmres_with("sn[j] = H[j + 1, j] / rr", "sn[j] = -H[j + 1, j] / rr")
+    monkeypatch.setattr(krylov, "gmres", bad)
+    _fails(tk.test_gmres_history_monotone_and_exact_in_n_steps)
+    monkeypatch.setitem(tk.SOLVERS, "gmres", bad)
+    _fails(tk.test_c1_solvers_reach_closed_form, "gmres")
+
+
+def test_previous_rotation_sign_error_is_caught(monkeypatch):
+    # an earlier rotation applied to the new column with the wrong sign
+    bad = _gmres_with("H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]",
+                      "H[i + 1, j] = sn[i] * H[i, j] + cs[i] * H[i + 1, j]")
+    monkeypatch.setattr(krylov, "gmres", bad)
+    _fails(tk.test_gmres_history_monotone_and_exact_in_n_steps)
+
+
+def test_truncated_gmres_is_caught(monkeypatch):
     src = krylov.gmres
     def bad_gmres(A, b, M=None, x0=None, restart=30, rtol=1e-10, max_iter=2000):
         # a GMRES that stops after too few steps and never restarts properly
