@@ -65,7 +65,7 @@ typedef enum { VD_FOURIER = 0, VD_CHEB_GL = 1 } vd_basis;
 typedef enum { VD_GMRES = 0, VD_CG = 1, VD_RMR = 2 } vd_solver;
 typedef enum { VD_FP64 = 0, VD_FP32_REFINE = 1 } vd_precision;
 typedef enum { VD_OP_PRESSURE = 0, VD_OP_HELMHOLTZ = 1, VD_OP_PRESSURE_K = 2 } vd_op_kind;
-/* Pressure formulation (Sec. 4.2): L_rho phi = f directly, or the modified
+/* Pressure formulation (Sec. 3.2; the 3D choice of Sec. 4.2): L_rho phi = f directly, or the modified
  * form K_rho Phi = sqrt(rho) f with Phi = phi / sqrt(rho) (eq. VDINSE.Krho). */
 typedef enum { VD_FORM_L = 0, VD_FORM_K = 1 } vd_pressure_form;
 
@@ -84,7 +84,10 @@ typedef struct {
   int max_iter;      /* cap on operator applications in the Krylov loop */
   int precond;       /* 1: constant-density inverse as preconditioner; 0: none */
   int precision;     /* vd_precision */
-  double inner_rtol; /* FP32_REFINE: relative tolerance of each inner FP32 solve */
+  double inner_rtol; /* FP32_REFINE: relative tolerance of each inner FP32 solve
+                        (GMRES inner solves also stop after 3 cycles of `restart`
+                        steps; CG and RMR inner solves only at this tolerance or
+                        at the remaining max_iter budget) */
   int max_outer;     /* FP32_REFINE: cap on refinement steps */
   double rho0;       /* preconditioner density; NaN = mean of rho */
   int use_x0;        /* 1: the output array holds the initial guess on entry */

@@ -513,6 +513,14 @@ class Server:
         r.kind = VD_OP_PRESSURE if kind == "pressure" else VD_OP_HELMHOLTZ
         r.dt_nu = float(dt_nu)
         r.ncomp = int(ncomp)
+        # the server reads rho and f and writes x on the device with no shape
+        # information beyond the descriptor: check them here (a wrong dtype,
+        # shape or layout would otherwise be read or written out of bounds)
+        shp = tuple(int(v) for v in shape)
+        fshp = (r.ncomp,) + shp if r.kind == VD_OP_HELMHOLTZ and r.ncomp > 1 else shp
+        for t, want, what in ((rho, shp, "rho"), (f, fshp, "f"), (x, fshp, "x")):
+            if t is not None:
+                _dev_f64(t, want, what)
         r.rho = rho.data_ptr() if rho is not None else None
         r.f = f.data_ptr() if f is not None else None
         r.x = x.data_ptr() if x is not None else None

@@ -2,9 +2,9 @@
 //
 // Requests (one pressure or velocity solve each, any supported grid) are
 // queued FIFO on submit and admitted as soon as (a) a worker slot is free and
-// (b) a grid of the request's shape is idle or the HBM budget has room for a
-// new one (footprint = vd_workspace_bytes: the Krylov basis, operator work
-// fields and coefficient fields).  Each admitted request runs on its grid's
+// (b) an idle grid of the request's shape and footprint class exists or the
+// HBM budget has room for a new one (footprint = vd_workspace_bytes: the
+// Krylov basis, operator work fields and coefficient fields).  Each admitted request runs on its grid's
 // own non-blocking stream from its own host thread, so the kernels of
 // requests of different sizes overlap on the device while their Krylov state
 // stays resident in HBM.  Grids are kept for reuse by later requests of the
@@ -34,7 +34,8 @@ struct GridEntry {
   vd_grid* grid = nullptr;
   hipStream_t stream = nullptr;
   vd_grid_desc desc{};
-  size_t bytes = 0;
+  vd_solve_opts opts{};  // options of the requests it serves (same_footprint)
+  size_t bytes = 0;      // charged against the budget while the grid exists
   bool busy = false;
 };
 
@@ -50,6 +51,16 @@ bool same_desc(const vd_grid_desc& a, const vd_grid_desc& b) {
   for (int i = 0; i < a.ndim; ++i)
     if (a.n[i] != b.n[i] || a.basis[i] != b.basis[i] || a.length[i] != b.length[i]) return false;
   return true;
+}
+
+// A grid keeps every work buffer it has ever allocated, so a grid that ran
+// requests with different options holds the union of their buffers, more
+// than vd_workspace_bytes of either.  Grids are therefore reused only by
+// requests whose options allocate the same buffers: same precision, solver,
+// formulation and (GMRES) restart length.  A grid's charge is then exact.
+bool same_footprint(const vd_solve_opts& a, const vd_solve_opts& b) {
+  if (a.precision != b.precision || a.solver != b.solver || a.formulation != b.formulation) return false;
+  return a.solver != VD_GMRES || a.restart == b.restart;
 }
 
 }  // namespace
@@ -100,7 +111,10 @@ void admit(vd_server* S) {
     if (slot < 0) return;
     GridEntry* ge = nullptr;
     for (auto* g : S->grids)
-      if (!g->busy && same_desc(g->desc, job.req.desc)) { ge = g; break; }
+      if (!g->busy && same_desc(g->desc, job.req.desc) && same_footprint(g->opts, job.req.opts)) {
+        ge = g;
+        break;
+      }
     if (!ge) {
       // release idle grids of other shapes while the budget blocks the head
       while (S->used + job.bytes > S->budget) {
@@ -120,6 +134,7 @@ void admit(vd_server* S) {
       if (S->used + job.bytes > S->budget) return;  // head of line waits
       ge = new GridEntry();
       ge->desc = job.req.desc;
+      ge->opts = job.req.opts;
       ge->bytes = job.bytes;
       S->used += job.bytes;
       S->peak_used = S->used > S->peak_used ? S->used : S->peak_used;

@@ -619,7 +619,10 @@ SolveOut solve_spectral(vd_grid* G, const vd_solve_opts& o, const OpParams& op, 
     if (*refinements >= o.max_outer || out.iters >= o.max_iter) { out.status = VD_NOT_CONVERGED; return out; }
     cast_d2f(G->g, r64, r32, 1.0 / rn, G->st);
     ck(hipMemsetAsync(d32, 0, G->nspec * 8, G->st));
-    K32.cfg.max_iter = std::min(o.max_iter - out.iters, kInnerCycles * o.restart);
+    // GMRES: at most kInnerCycles cycles of the restart length; CG and RMR
+    // have no cycles and stop on inner_rtol within the remaining budget
+    K32.cfg.max_iter = o.solver == VD_GMRES ? std::min(o.max_iter - out.iters, kInnerCycles * o.restart)
+                                            : o.max_iter - out.iters;
     SolveOut in = K32.run(r32, d32, 1.0);
     out.iters += in.iters;
     out.reorth += in.reorth;

@@ -195,16 +195,57 @@ def test_results_bitwise_reproducible():
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
-def test_c3_full_size(precision):
-    """256^3, rj = 3: GMRES(30) to 1e-10; true residual by the oracle."""
+@pytest.mark.parametrize("rj", [0.5, 3.0, 5.0])
+def test_c3_full_size(rj, precision):
+    """256^3 pressure solves at every density ratio of the headline workload:
+    GMRES(30) to 1e-10; true residual by the oracle."""
     from paper_2403_06654_amd.api import Grid
-    print(f"case C3 256^3 {precision}", flush=True)
-    inp = workloads.c3_inputs(rj=3.0, n=256, seed=0)
+    print(f"case C3 256^3 pressure rj={rj} {precision}", flush=True)
+    inp = workloads.c3_inputs(rj=rj, n=256, seed=0)
     g = Grid((256, 256, 256))
     g.set_density(to_dev(inp["rho"]))
     p, info = g.solve_pressure(to_dev(inp["f"]), precision=precision)
     p = to_host(p)
     print(info, flush=True)
     assert info["status"] == 0
-    assert oracle_relres_pressure(p, inp["f"], inp["rho"]) <= TOL * 1.01
+    rr = oracle_relres_pressure(p, inp["f"], inp["rho"])
+    print(f"  oracle relres {rr:.3e}", flush=True)
+    assert rr <= TOL * 1.01
+    g.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_c3_full_size_velocity(precision):
+    """256^3 three-component velocity solve rho u - 1e-3 Lap u = g of the
+    headline workload (rj = 5), every component checked by the oracle."""
+    from paper_2403_06654_amd.api import Grid
+    print(f"case C3 256^3 velocity {precision}", flush=True)
+    inp = workloads.c3_inputs(rj=5.0, n=256, seed=1, with_g=True)
+    g = Grid((256, 256, 256))
+    g.set_density(to_dev(inp["rho"]))
+    u, info = g.solve_helmholtz(to_dev(inp["g"]), 1e-3, precision=precision)
+    u = to_host(u)
+    print(info, flush=True)
+    assert info["status"] == 0 and u.shape[0] == 3
+    for c in range(3):
+        rr = oracle_relres_helm(u[c], inp["g"][c], inp["rho"], 1e-3)
+        print(f"  component {c}: oracle relres {rr:.3e}", flush=True)
+        assert rr <= TOL * 1.01
+    g.close()
+
+
+@pytest.mark.parametrize("solver", ["cg", "rmr"])
+def test_refine_cg_rmr_short_restart(solver):
+    """FP32+refine with CG and RMR inner solves does not depend on the GMRES
+    restart length: restart = 1 still converges to 1e-10."""
+    from paper_2403_06654_amd.api import Grid
+    print(f"case refine {solver} restart=1", flush=True)
+    shape = (32, 32, 32)
+    rho = workloads.jet_density(32, 5.0, width=0.2)
+    f = workloads.band_limited(shape, 8, seed=5)
+    g = Grid(shape)
+    g.set_density(to_dev(rho))
+    p, info = g.solve_pressure(to_dev(f), solver=solver, precision="fp32_refine", restart=1)
+    assert info["status"] == 0, info
+    assert oracle_relres_pressure(to_host(p), f, rho) <= TOL * 1.01
     g.close()

@@ -104,3 +104,47 @@ def test_invalid_requests():
         api.Server(hbm_budget=0, max_slots=1, dry_seconds=0.0)
     with pytest.raises(api.VdError):
         api.Server(hbm_budget=1 << 30, max_slots=0, dry_seconds=0.0)
+
+
+def test_grids_are_reused_only_within_a_footprint_class():
+    """A grid keeps every buffer it has allocated, so a grid charged for one
+    set of options is not handed to a request whose options allocate other
+    buffers: same-shape requests with different precisions get their own
+    grid, and the charge of the grids held never exceeds the budget."""
+    shape = (256, 256)
+    b64 = api.workspace_bytes(shape, precision="fp64")
+    b32 = api.workspace_bytes(shape, precision="fp32_refine")
+    bcg = api.workspace_bytes(shape, precision="fp64", solver="cg")
+    assert b64 != b32 and bcg < b64
+    budget = max(b64, b32) + min(b64, b32) // 2     # room for one grid only
+    srv = api.Server(hbm_budget=budget, max_slots=2, dry_seconds=0.0)
+    srv.submit(shape, precision="fp64")
+    _drain(srv, 1)
+    assert srv.stats()["hbm_used"] == b64
+    srv.submit(shape, precision="fp32_refine")      # not the FP64 grid: a new one, the old released
+    _drain(srv, 1)
+    st = srv.stats()
+    assert st["grids"] == 1 and st["hbm_used"] == b32
+    srv.submit(shape, precision="fp64", solver="cg")  # another class: a grid of its own
+    _drain(srv, 1)
+    st = srv.stats()
+    expect = b32 + bcg if b32 + bcg <= budget else bcg
+    assert st["grids"] == (2 if expect > bcg else 1) and st["hbm_used"] == expect
+    srv.submit(shape, precision="fp64", solver="cg")  # same class: its grid is reused
+    _drain(srv, 1)
+    st2 = srv.stats()
+    assert st2["grids"] == st["grids"] and st2["hbm_used"] == expect and st2["hbm_peak"] <= budget
+    srv.close()
+
+
+def test_submit_checks_tensors():
+    """Tensors handed to the server are checked before submission (dtype,
+    device, shape, layout; Helmholtz fields carry the component axis)."""
+    import torch
+    srv = api.Server(hbm_budget=1 << 30, max_slots=1, dry_seconds=0.0)
+    with pytest.raises(TypeError):
+        srv.submit((128, 128), rho=torch.ones(128, 128, dtype=torch.float32))
+    with pytest.raises(TypeError):          # float64 but not on the device
+        srv.submit((128, 128), f=torch.ones(128, 128, dtype=torch.float64))
+    assert srv.stats()["in_flight"] == 0
+    srv.close()
