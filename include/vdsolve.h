@@ -230,22 +230,49 @@ typedef struct vd_visc1d vd_visc1d;
  * points (Chebyshev 9..512; Fourier even, 16..512) and a > 0.  Errors:
  * VD_EINVAL, VD_ENOMEM. */
 vd_status vd_visc1d_create(vd_visc1d** out, int basis, int n, double length, double a, hipStream_t stream);
+
+/* The pressure operators of the one-dimensional Chebyshev-collocation study
+ * of Sec. 3.2 (Figs. 5-7) on the same batched solver:
+ *     form VD_FORM_L:  L_rho u = (1/rho) D2 u - (rho'/rho^2) D1 u
+ *                      (eq. VDINSE.Lrho, expanded; rho' = D1 rho),
+ *     form VD_FORM_K:  K_rho u = D2 u + c u,  c = -D2 psi / psi with
+ *                      psi = rho^-1/2 (eq. VDINSE.Krho; by the chain rule the
+ *                      printed c, in a form that makes psi an exact null
+ *                      vector),
+ * on the n Chebyshev-Gauss-Lobatto points of [-1, 1] (descending) with
+ * Neumann walls (Sec. 3.2: d(rho)/dn = d(phi)/dn = 0): the unknowns are the
+ * n - 2 interior values, the wall values are those that zero the
+ * collocation derivative at both walls (D1 and D2 above include that
+ * extension), and the equations are the interior collocation rows.  The
+ * preconditioner is the Moore-Penrose pseudo-inverse of the Neumann
+ * Laplacian D2 (the inverse of K_rho at constant density; it annihilates
+ * the constants).  Both operators are singular (null vectors: constants for
+ * L_rho, psi for K_rho), so a right-hand side must lie in the range of the
+ * operator, else its component outside the range remains in the residual.
+ * The handle is used with vd_visc1d_apply, vd_visc1d_solve,
+ * vd_visc1d_kernel_ms and vd_visc1d_destroy: b's
+ * wall values are ignored; solutions and preconditioned vectors carry the
+ * wall values of the Neumann extension; operator outputs (equation rows)
+ * have zero walls.  n: 9..512.  Errors: VD_EINVAL, VD_ENOMEM, VD_EDEVICE. */
+vd_status vd_pres1d_create(vd_visc1d** out, int n, int form, hipStream_t stream);
 vd_status vd_visc1d_destroy(vd_visc1d* h);
 
-/* y = V_rho u (precond 0) or y = V^-1 u (precond 1) for `batch` systems;
+/* y = A u (precond 0) or y = M^-1 u (precond 1) for `batch` systems, A the
+ * handle's operator (V_rho, L_rho or K_rho) and M^-1 its preconditioner;
  * rho, u, y: device FP64 [batch][n].  VD_EDOMAIN if a density is not
  * strictly positive and finite. */
 vd_status vd_visc1d_apply(vd_visc1d* h, int batch, const double* rho, const double* u, double* y, int precond);
 
 /* Solve the batch: rho, b: device FP64 [batch][n]; u: device output (initial
- * guess if opts->use_x0).  opts: solver VD_GMRES (restart 1..128) or VD_RMR
- * (VD_CG and VD_FP32_REFINE give VD_ENOTSUP), rtol on each system's true
- * relative residual ||b - V_rho u|| / ||b|| over the unknowns, max_iter,
- * precond.  Per-system iterations and relative residuals go to the host
- * arrays when given; info gets the largest of each and the worst status.
- * The workspace (per group of 16 systems: 16 (5 + restart + 1) rows
- * padded to 64 plus the Hessenberg and rotation arrays, GMRES; 80 rows,
- * RMR) is kept by the handle for later calls. */
+ * guess if opts->use_x0).  opts: solver VD_GMRES (restart 1..128), VD_RMR or
+ * VD_CG (preconditioned conjugate gradient, run as the paper runs it on
+ * these non-symmetric operators; VD_FP32_REFINE gives VD_ENOTSUP), rtol on
+ * each system's true relative residual ||b - A u|| / ||b|| over the
+ * unknowns, max_iter, precond.  Per-system iterations and relative residuals
+ * go to the host arrays when given; info gets the largest of each and the
+ * worst status.  The workspace (per group of 16 systems: 16 (5 + restart
+ * + 1) rows padded to 64 plus the Hessenberg and rotation arrays, GMRES; 80
+ * rows, RMR; 96 rows, CG) is kept by the handle for later calls. */
 vd_status vd_visc1d_solve(vd_visc1d* h, int batch, const double* rho, const double* b, double* u,
                           const vd_solve_opts* opts, int* iterations, double* rel_residual, vd_solve_info* info);
 /* Duration in ms of the last apply or solve kernel, from HIP events recorded

@@ -112,6 +112,7 @@ _SIGS = {
     "vd_dense_matmul": (_I, [_I, _P, _P, _P, _I, _I, _I, _P]),
     "vd_visc1d_create": (_I, [ctypes.POINTER(_P), _I, _I, _D, _D, _P]),
     "vd_visc1d_destroy": (_I, [_P]),
+    "vd_pres1d_create": (_I, [ctypes.POINTER(_P), _I, _I, _P]),
     "vd_visc1d_apply": (_I, [_P, _I, _P, _P, _P, _I]),
     "vd_visc1d_solve": (_I, [_P, _I, _P, _P, _P, ctypes.POINTER(vd_solve_opts), _P, _P,
                              ctypes.POINTER(vd_solve_info)]),
@@ -336,6 +337,20 @@ class Grid:
 class Visc1d:
     """Batched 1D implicit viscous systems V_rho u = b (vd_visc1d_*)."""
 
+    @classmethod
+    def pressure(cls, n, form="K", stream=None):
+        """Batched 1D Chebyshev-collocation pressure operators with Neumann
+        walls, L_rho or K_rho (vd_pres1d_create); same methods."""
+        import torch
+        self = cls.__new__(cls)
+        self.n = int(n)
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        _check(lib().vd_pres1d_create(ctypes.byref(h), self.n, FORMULATIONS[form],
+                                      ctypes.c_void_p(self._stream.cuda_stream)), "vd_pres1d_create", False)
+        self._h = h
+        return self
+
     def __init__(self, basis, n, a, length=2 * math.pi, stream=None):
         import torch
         self.n = int(n)
@@ -375,6 +390,9 @@ class Visc1d:
         return y
 
     def solve(self, rho, b, u=None, **opts):
+        return self._solve(lib().vd_visc1d_solve, "vd_visc1d_solve", rho, b, u, **opts)
+
+    def _solve(self, fn, name, rho, b, u=None, **opts):
         import numpy as np
         import torch
         if u is None:
@@ -395,9 +413,9 @@ class Visc1d:
         it = np.zeros(nb, dtype=np.int32)
         rr = np.zeros(nb, dtype=np.float64)
         info = vd_solve_info()
-        st = lib().vd_visc1d_solve(self._h, nb, rho.data_ptr(), b.data_ptr(), u.data_ptr(), ctypes.byref(o),
-                                   it.ctypes.data, rr.ctypes.data, ctypes.byref(info))
-        _check(st, "vd_visc1d_solve")
+        st = fn(self._h, nb, rho.data_ptr(), b.data_ptr(), u.data_ptr(), ctypes.byref(o),
+                it.ctypes.data, rr.ctypes.data, ctypes.byref(info))
+        _check(st, name)
         d = info.as_dict()
         if hist is not None:
             d["history"] = hist

@@ -9,10 +9,10 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libvdsolve.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["passes.hip", "vecops.hip", "gemm.hip", "cheb.cpp", "vdsolve.cpp", "vdserve.cpp", "visc1d.hip",
-           "visc1d_large.hip", "visc1d_host.cpp", "ns_kernels.hip", "ns.cpp"]
+           "visc1d_large.hip", "pres1d.hip", "pres1d_large.hip", "visc1d_host.cpp", "ns_kernels.hip", "ns.cpp"]
 # per-source extra flags: the batched viscous kernels keep their MFMA
 # accumulators in VGPRs instead of copying them through AGPRs every k step
-EXTRA_FLAGS = {"visc1d.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+EXTRA_FLAGS = {"visc1d.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"], "pres1d.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

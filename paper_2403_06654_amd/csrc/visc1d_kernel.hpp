@@ -21,6 +21,16 @@
 //
 // Unknowns: all n points (Fourier) or the n - 2 interior points (Chebyshev,
 // u(+-1) = 0); rho' = D1 rho and rho'' = D2 rho use every point.
+//
+// The same kernel runs the pressure operators of the one-dimensional
+// Chebyshev-collocation study of Sec. 3.2 (template parameter OP): on the
+// interior values, with the wall values eliminated by the Neumann condition
+// (D1 P, D2 P: the extension P folded into the matrices),
+//   L_rho z = (1/rho) D2 P z - (rho'/rho^2) D1 P z      (eq. VDINSE.Lrho)
+//   K_rho z = D2 P z + c z,  c = -D2 P psi / psi, psi = rho^-1/2
+//                                                      (eq. VDINSE.Krho)
+// preconditioned by the pseudo-inverse of D2 P; solutions and preconditioned
+// vectors get their wall values from the same extension.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -44,7 +54,7 @@ constexpr int kRed = 16;           // Gram-Schmidt coefficients reduced together
 // sqrt(1 + (m+1) tol) - 1)
 constexpr double kVisc1dOrthTol = 1e-8;
 
-enum Kind { K_APPLY = 0, K_RMR = 1, K_GMRES = 2 };
+enum Kind { K_APPLY = 0, K_RMR = 1, K_GMRES = 2, K_CG = 3 };
 
 template <int TPW>
 struct Lay {
@@ -193,34 +203,55 @@ __device__ __forceinline__ void gsum(double (&v)[NV], double* red, const Ln& l) 
   __syncthreads();
 }
 
-// w = V_rho z with z in the operand buffer.  D1 z and D2 z are two passes
-// over the buffer (one matrix each, fewer live registers than both at once);
-// z itself is read back from the buffer for the pointwise terms.
-template <int TPW>
+// w = A z with z in the operand buffer (A = V_rho, L_rho or K_rho).  D1 z
+// and D2 z are two passes over the buffer (one matrix each, fewer live
+// registers than both at once); z itself is read back from the buffer for
+// the pointwise terms.  Coefficients (tiled): viscous ca = a/rho, rp = rho',
+// rpp = rho''; L_rho ca = 1/rho, rp = -rho'/rho^2; K_rho rpp = c.
+template <int TPW, int OP>
 __device__ __forceinline__ void op_buf(const Visc1dArgs& a, const double* buf, Vec<TPW>& w, const double* wca,
                                        const double* wrp, const double* wrpp, const Ln& l) {
-  Vec<TPW> d1[1], d2[1];
-  const double* const M1[1] = {a.D1I};
-  const double* const M2[1] = {a.D2I};
-  mv<TPW, 1>(M1, Lay<TPW>::KT, buf, l, d1);
-  mv<TPW, 1>(M2, Lay<TPW>::KT, buf, l, d2);
   const v4d* zq = reinterpret_cast<const v4d*>(buf);
   const v4d* caq = reinterpret_cast<const v4d*>(wca);
   const v4d* rpq = reinterpret_cast<const v4d*>(wrp);
   const v4d* rppq = reinterpret_cast<const v4d*>(wrpp);
+  if constexpr (OP == OP1D_PRES_K) {
+    Vec<TPW> d2[1];
+    const double* const M2[1] = {a.D2I};
+    mv<TPW, 1>(M2, Lay<TPW>::KT, buf, l, d2);
 #pragma unroll
-  for (int t = 0; t < TPW; ++t) {
-    const int i = vi4<TPW>(l, t);
-    const v4d z = zq[i], ca = caq[i], rp = rpq[i], rpp = rppq[i];
+    for (int t = 0; t < TPW; ++t) {
+      const int i = vi4<TPW>(l, t);
+      const v4d z = zq[i], c = rppq[i];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-      w.t[t][r] = z[r] - ca[r] * (d2[0].t[t][r] + rpp[r] * z[r] + rp[r] * d1[0].t[t][r]);
+      for (int r = 0; r < 4; ++r) w.t[t][r] = d2[0].t[t][r] + c[r] * z[r];
+    }
+  } else {
+    Vec<TPW> d1[1], d2[1];
+    const double* const M1[1] = {a.D1I};
+    const double* const M2[1] = {a.D2I};
+    mv<TPW, 1>(M1, Lay<TPW>::KT, buf, l, d1);
+    mv<TPW, 1>(M2, Lay<TPW>::KT, buf, l, d2);
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+      const int i = vi4<TPW>(l, t);
+      if constexpr (OP == OP1D_VISC) {
+        const v4d z = zq[i], ca = caq[i], rp = rpq[i], rpp = rppq[i];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          w.t[t][r] = z[r] - ca[r] * (d2[0].t[t][r] + rpp[r] * z[r] + rp[r] * d1[0].t[t][r]);
+      } else {
+        const v4d ca = caq[i], rp = rpq[i];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) w.t[t][r] = ca[r] * d2[0].t[t][r] + rp[r] * d1[0].t[t][r];
+      }
+    }
   }
 }
 
 }  // namespace
 
-template <int TPW, int KIND>
+template <int TPW, int KIND, int OP>
 __global__ __launch_bounds__(kT, (KIND == K_GMRES || TPW > 4) ? 1 : 2) void k_visc1d(Visc1dArgs a) {
   using L = Lay<TPW>;
   extern __shared__ __attribute__((aligned(32))) double lds[];
@@ -256,11 +287,33 @@ __global__ __launch_bounds__(kT, (KIND == K_GMRES || TPW > 4) ? 1 : 2) void k_vi
       v = a.rho[(size_t)(g0 + s) * np + i];
       if (!(v > 0.0) || !isfinite(v)) bad_s[s] = 1;
     }
-    buf[tidx(i, s)] = v;
+    if constexpr (OP == OP1D_PRES_K) {  // psi = rho^-1/2 on the unknowns, the operand of D2 P
+      const int k = i - off;
+      if (k >= 0 && k < ni) buf[tidx(k, s)] = 1.0 / sqrt(v);
+    } else {
+      buf[tidx(i, s)] = v;
+    }
   }
   __syncthreads();
   const bool bad = bad_s[l.sl] != 0;
-  {
+  if constexpr (OP == OP1D_PRES_K) {
+    // c = -(D2 P psi) / psi
+    Vec<TPW> acc[1], c, zero;
+    const double* const M[1] = {a.D2I};
+    mv<TPW, 1>(M, Lay<TPW>::KT, buf, l, acc);
+    vzero(zero);
+#pragma unroll
+    for (int t = 0; t < TPW; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = vrow<TPW>(l, t, r);
+        const bool ok = live && !bad && i < ni;
+        c.t[t][r] = ok ? -acc[0].t[t][r] / buf[tidx(i, l.sl)] : 0.0;
+      }
+    vst(zero, wca, l);
+    vst(zero, wrp, l);
+    vst(c, wrpp, l);
+  } else {
     Vec<TPW> acc[2], ca;
     const double* const M[2] = {a.D1F, a.D2F};
     mv<TPW, 2>(M, a.kt_full, buf, l, acc);
@@ -270,7 +323,14 @@ __global__ __launch_bounds__(kT, (KIND == K_GMRES || TPW > 4) ? 1 : 2) void k_vi
       for (int r = 0; r < 4; ++r) {
         const int i = vrow<TPW>(l, t, r);
         const bool ok = live && !bad && i < ni;
-        ca.t[t][r] = ok ? a.a / buf[tidx(i + off, l.sl)] : 0.0;
+        const double rho_i = ok ? buf[tidx(i + off, l.sl)] : 1.0;
+        if constexpr (OP == OP1D_VISC) {
+          ca.t[t][r] = ok ? a.a / rho_i : 0.0;
+        } else {  // L_rho: 1/rho and -rho'/rho^2
+          ca.t[t][r] = ok ? 1.0 / rho_i : 0.0;
+          acc[0].t[t][r] = ok ? -acc[0].t[t][r] / (rho_i * rho_i) : 0.0;
+          acc[1].t[t][r] = 0.0;
+        }
         if (!ok) {
           acc[0].t[t][r] = 0.0;
           acc[1].t[t][r] = 0.0;
@@ -293,7 +353,10 @@ __global__ __launch_bounds__(kT, (KIND == K_GMRES || TPW > 4) ? 1 : 2) void k_vi
     vld(v, buf, l);
     __syncthreads();
   };
-  auto scatter = [&](const Vec<TPW>& v) {
+  // write a group vector to a.x; `field`: a pressure field (solution or
+  // preconditioned vector), whose wall values follow from the Neumann
+  // extension, else zero walls (viscous fields, pressure equation rows)
+  auto scatter = [&](const Vec<TPW>& v, bool field) {
 #pragma unroll
     for (int t = 0; t < TPW; ++t)
 #pragma unroll
@@ -301,6 +364,27 @@ __global__ __launch_bounds__(kT, (KIND == K_GMRES || TPW > 4) ? 1 : 2) void k_vi
         const int i = vrow<TPW>(l, t, r);
         if (live && i < ni) a.x[(size_t)(g0 + l.sl) * np + off + i] = bad ? 0.0 : v.t[t][r];
       }
+    if constexpr (OP != OP1D_VISC) {
+      if (field) {
+        double wsum[2] = {0.0, 0.0};
+#pragma unroll
+        for (int t = 0; t < TPW; ++t)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = vrow<TPW>(l, t, r);
+            if (i < ni) {
+              wsum[0] += a.E0[i] * v.t[t][r];
+              wsum[1] += a.EM[i] * v.t[t][r];
+            }
+          }
+        gsum<2>(wsum, red, l);
+        if (l.wv == 0 && l.lq == 0 && live) {
+          a.x[(size_t)(g0 + l.sl) * np] = bad ? 0.0 : wsum[0];
+          a.x[(size_t)(g0 + l.sl) * np + np - 1] = bad ? 0.0 : wsum[1];
+        }
+        return;
+      }
+    }
     const int nw = np - ni;  // points outside the unknowns: the two walls
     for (int e = threadIdx.x; e < nsys * nw; e += kT) {
       const int s = e / nw, k = e - s * nw;
@@ -337,7 +421,7 @@ __global__ __launch_bounds__(kT, (KIND == K_GMRES || TPW > 4) ? 1 : 2) void k_vi
   auto apply = [&](const Vec<TPW>& Z, Vec<TPW>& Wv) {
     vst(Z, buf, l);
     __syncthreads();
-    op_buf(a, buf, Wv, wca, wrp, wrpp, l);
+    op_buf<TPW, OP>(a, buf, Wv, wca, wrp, wrpp, l);
     __syncthreads();
   };
   // R = b - V_rho X; returns ||R|| of this lane's system
@@ -356,12 +440,13 @@ __global__ __launch_bounds__(kT, (KIND == K_GMRES || TPW > 4) ? 1 : 2) void k_vi
   gather(a.b, B);
   if constexpr (KIND == K_APPLY) {
     Vec<TPW> Y;
-    if (a.mode == VISC1D_APPLY_PREC) {
+    const bool pre = a.mode == VISC1D_APPLY_PREC;
+    if (pre) {
       prec(B, Y);
     } else {
       apply(B, Y);
     }
-    scatter(Y);
+    scatter(Y, pre);
     finish(0, 0.0, 0);
     return;
   } else {
@@ -439,7 +524,103 @@ __global__ __launch_bounds__(kT, (KIND == K_GMRES || TPW > 4) ? 1 : 2) void k_vi
         }
       }
       vld(X, wx, l);
-      scatter(X);
+      scatter(X, true);
+    } else if constexpr (KIND == K_CG) {
+      // Preconditioned conjugate gradient (Sec. 3.1 solver list): z = M^-1 r;
+      // p = z (first step and restarts) or z + beta p with
+      // beta = (r, z) / (r, z)_previous; q = A p; alpha = (r, z) / (p, q);
+      // x += alpha p; r -= alpha q.  x and p live in the workspace.  When the
+      // recursive residual meets the tolerance the true residual replaces
+      // it, and if that does not, the iteration restarts from it.  CG is not
+      // meant for the non-symmetric collocation operators; the paper runs it
+      // on them anyway and reports how it fails (Secs. 3.1 and 3.2).
+      double* wp = W + 5 * L::V;
+      double rn = residual(X, R);
+      vst(X, wx, l);
+      if (!done) record(0, rn / bn);
+      else if (bn == 0.0) record(0, 0.0);
+      double rz = 0.0;
+      bool fresh = true;
+      while (true) {
+        if (!done) {
+          rel = rn / bn;
+          if (!(rn == rn)) {
+            status = -4;
+            done = true;
+          } else if (rel <= a.rtol) {
+            done = true;
+          } else if (it >= a.max_iter) {
+            status = 1;
+            done = true;
+          }
+        }
+        if (!__syncthreads_or(!done)) break;
+        {
+          Vec<TPW> Z, P;
+          prec(R, Z);
+          double s1[1] = {pdot(R, Z)};
+          gsum<1>(s1, red, l);
+          if (fresh) {
+            P = Z;
+          } else {
+            vld(P, wp, l);
+            const double beta = rz != 0.0 ? s1[0] / rz : 0.0;
+#pragma unroll
+            for (int t = 0; t < TPW; ++t) P.t[t] = Z.t[t] + beta * P.t[t];
+          }
+          rz = s1[0];
+          fresh = false;
+          vst(P, wp, l);
+        }
+        // q = A p with p in the operand buffer; p is read back from there
+        // (each lane its own entries) rather than kept in registers
+        {
+          Vec<TPW> P;
+          vld(P, wp, l);
+          vst(P, buf, l);
+        }
+        __syncthreads();
+        Vec<TPW> Q;
+        op_buf<TPW, OP>(a, buf, Q, wca, wrp, wrpp, l);
+        const v4d* pq = reinterpret_cast<const v4d*>(buf);
+        double s2[1] = {0.0};
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) {
+          const v4d pv = pq[vi4<TPW>(l, t)];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) s2[0] += pv[r] * Q.t[t][r];
+        }
+        gsum<1>(s2, red, l);
+        const double alpha = s2[0] != 0.0 ? rz / s2[0] : 0.0;
+        if (!done) {
+          v4d* xq = reinterpret_cast<v4d*>(wx);
+#pragma unroll
+          for (int t = 0; t < TPW; ++t) {
+            xq[vi4<TPW>(l, t)] += alpha * pq[vi4<TPW>(l, t)];
+            R.t[t] -= alpha * Q.t[t];
+          }
+          ++it;
+        }
+        double s1[1] = {pdot(R, R)};
+        gsum<1>(s1, red, l);
+        if (!done) {
+          rn = sqrt(s1[0]);
+          record(it, rn / bn);
+        }
+        const bool need = !done && rn / bn <= a.rtol;
+        if (__syncthreads_or(need)) {
+          Vec<TPW> R2, Xc;
+          vld(Xc, wx, l);
+          const double rn2 = residual(Xc, R2);
+          if (need) {
+            R = R2;
+            rn = rn2;
+            fresh = true;
+          }
+        }
+      }
+      vld(X, wx, l);
+      scatter(X, true);
     } else {
       // right-preconditioned GMRES(m), classical Gram-Schmidt applied twice
       double* wbas = W + 5 * L::V;                 // [m + 1] tiled basis vectors
@@ -623,7 +804,7 @@ __global__ __launch_bounds__(kT, (KIND == K_GMRES || TPW > 4) ? 1 : 2) void k_vi
         beta = residual(X, R);
       }
       vld(X, wx, l);
-      scatter(X);
+      scatter(X, true);
     }
     finish(it, rel, status);
   }
@@ -631,24 +812,29 @@ __global__ __launch_bounds__(kT, (KIND == K_GMRES || TPW > 4) ? 1 : 2) void k_vi
 
 namespace {
 
-template <int TPW>
+template <int TPW, int OP>
 hipError_t launch_tpw(const Visc1dArgs& a, hipStream_t st) {
   using L = Lay<TPW>;
-  const int kind = a.mode != VISC1D_SOLVE ? K_APPLY : (a.solver == VISC1D_RMR ? K_RMR : K_GMRES);
+  const int kind = a.mode != VISC1D_SOLVE    ? K_APPLY
+                   : a.solver == VISC1D_RMR ? K_RMR
+                   : a.solver == VISC1D_CG  ? K_CG
+                                            : K_GMRES;
   const int m = kind == K_GMRES ? a.restart : 0;
   const size_t lds = (size_t)(L::NB + kRed * 4 * kG + 2 * (m + 1) * kG + kG) * sizeof(double) +
                      (2 * kG + m + 1) * sizeof(int);
-  const void* fn = kind == K_APPLY ? reinterpret_cast<const void*>(&k_visc1d<TPW, K_APPLY>)
-                   : kind == K_RMR ? reinterpret_cast<const void*>(&k_visc1d<TPW, K_RMR>)
-                                   : reinterpret_cast<const void*>(&k_visc1d<TPW, K_GMRES>);
+  const void* fn = kind == K_APPLY ? reinterpret_cast<const void*>(&k_visc1d<TPW, K_APPLY, OP>)
+                   : kind == K_RMR ? reinterpret_cast<const void*>(&k_visc1d<TPW, K_RMR, OP>)
+                   : kind == K_CG  ? reinterpret_cast<const void*>(&k_visc1d<TPW, K_CG, OP>)
+                                   : reinterpret_cast<const void*>(&k_visc1d<TPW, K_GMRES, OP>);
   if (lds > 65536) {
     const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
   const dim3 grid((a.batch + kG - 1) / kG);
-  if (kind == K_APPLY) hipLaunchKernelGGL((k_visc1d<TPW, K_APPLY>), grid, dim3(kT), lds, st, a);
-  else if (kind == K_RMR) hipLaunchKernelGGL((k_visc1d<TPW, K_RMR>), grid, dim3(kT), lds, st, a);
-  else hipLaunchKernelGGL((k_visc1d<TPW, K_GMRES>), grid, dim3(kT), lds, st, a);
+  if (kind == K_APPLY) hipLaunchKernelGGL((k_visc1d<TPW, K_APPLY, OP>), grid, dim3(kT), lds, st, a);
+  else if (kind == K_RMR) hipLaunchKernelGGL((k_visc1d<TPW, K_RMR, OP>), grid, dim3(kT), lds, st, a);
+  else if (kind == K_CG) hipLaunchKernelGGL((k_visc1d<TPW, K_CG, OP>), grid, dim3(kT), lds, st, a);
+  else hipLaunchKernelGGL((k_visc1d<TPW, K_GMRES, OP>), grid, dim3(kT), lds, st, a);
   return hipGetLastError();
 }
 

@@ -8,10 +8,10 @@ namespace vd {
 
 hipError_t visc1d_launch_large(const Visc1dArgs& a, hipStream_t st) {
   switch (visc1d_tpw(a.ni)) {
-    case 5: return launch_tpw<5>(a, st);
-    case 6: return launch_tpw<6>(a, st);
-    case 7: return launch_tpw<7>(a, st);
-    case 8: return launch_tpw<8>(a, st);
+    case 5: return launch_tpw<5, OP1D_VISC>(a, st);
+    case 6: return launch_tpw<6, OP1D_VISC>(a, st);
+    case 7: return launch_tpw<7, OP1D_VISC>(a, st);
+    case 8: return launch_tpw<8, OP1D_VISC>(a, st);
     default: return hipErrorInvalidValue;
   }
 }

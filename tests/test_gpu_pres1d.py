@@ -1,0 +1,178 @@
+"""GPU parity of the batched 1D Chebyshev-collocation pressure operators with
+Neumann walls (Sec. 3.2; eqs. VDINSE.Lrho and VDINSE.Krho; the study of
+Figs. 5-7) against oracle.pressure1d.
+
+Tolerances: applications are dense FP64 products whose rounding grows with
+the matrix norms (the Neumann Laplacian D2 P ~ N^4), so operators are
+compared at 1e-13 ||D2 P|| ||u|| / ||A u||, and the preconditioner (the
+pseudo-inverse, built in long double here and by an FP64 SVD in the
+oracle) at 1e-14 kappa(D2 P) on its range.  Solves use right-hand sides
+b = A x (in the range of the singular operators): the oracle's operator
+must give a relative residual <= 1e-10 for the returned field, and the
+field must equal x modulo the null vector to within the error that residual
+allows (kappa(A) on the range is ~1e7 at N = 256; observed <= 2e-5).
+Iteration counts of the same methods may differ by rounding."""
+import numpy as np
+import pytest
+
+from oracle import krylov, pressure1d as p1
+from tests.gpu_util import rel2, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def _rho(n, s_list):
+    x = p1.points(n)
+    return np.stack([p1.tophat(x, s) for s in s_list])
+
+
+def _op(form, rho):
+    return p1.operator_L(rho) if form == "L" else p1.operator_K(rho)
+
+
+def _null(form, rho):
+    v = np.ones(rho.size - 2) if form == "L" else rho[1:-1] ** -0.5
+    return v / np.linalg.norm(v)
+
+
+@pytest.mark.parametrize("form", ["L", "K"])
+@pytest.mark.parametrize("n", [17, 65, 257, 300, 512])
+def test_apply_parity(form, n):
+    from paper_2403_06654_amd.api import Visc1d
+    print(f"case pres1d apply {form} n={n}", flush=True)
+    rho = _rho(n, [0.1, 2.0, 10.0, 100.0])
+    u = np.random.default_rng(3).standard_normal(rho.shape)   # wall values are ignored
+    h = Visc1d.pressure(n, form)
+    y = to_host(h.apply(to_dev(rho), to_dev(u)))
+    z = to_host(h.apply(to_dev(rho), to_dev(u), precond=True))
+    d2n = p1.laplacian(n)
+    X = p1.laplacian_pinv(n)
+    kap = p1.kappa(d2n, 1)
+    nd2 = np.linalg.norm(d2n, 2)
+    for k in range(rho.shape[0]):
+        ui = u[k, 1:-1]
+        ref = _op(form, rho[k]) @ ui
+        tol = 1e-13 * nd2 * np.linalg.norm(ui) / np.linalg.norm(ref)
+        assert rel2(y[k, 1:-1], ref) <= max(tol, 1e-14), (k, rel2(y[k, 1:-1], ref), tol)
+        assert y[k, 0] == 0.0 and y[k, -1] == 0.0       # equation rows: no wall entries
+        zr = p1.extend(X @ ui)                          # a field: walls from the Neumann extension
+        assert rel2(z[k], zr) <= 1e-14 * kap, (k, rel2(z[k], zr), kap)
+    h.close()
+
+
+@pytest.mark.parametrize("n", [65, 257])
+@pytest.mark.parametrize("solver", ["gmres", "rmr", "cg"])
+@pytest.mark.parametrize("form", ["L", "K"])
+def test_solve_parity(form, solver, n):
+    from paper_2403_06654_amd.api import Visc1d
+    print(f"case pres1d solve {form} {solver} n={n}", flush=True)
+    s_list = [0.5, 2.0]
+    rho = _rho(n, s_list)
+    xs = np.random.default_rng(5).standard_normal((len(s_list), n - 2))
+    b = np.zeros_like(rho)
+    for k in range(len(s_list)):
+        b[k, 1:-1] = _op(form, rho[k]) @ xs[k]
+    h = Visc1d.pressure(n, form)
+    u, it, rr, info = h.solve(to_dev(rho), to_dev(b), solver=solver, restart=30, max_iter=600, rtol=1e-10)
+    u = to_host(u)
+    print(it, rr, info["status"], flush=True)
+    X = p1.laplacian_pinv(n)
+    for k, s in enumerate(s_list):
+        A = _op(form, rho[k])
+        orc = getattr(krylov, "pcg" if solver == "cg" else solver)(
+            lambda v: A @ v, b[k, 1:-1], lambda r: X @ r, rtol=1e-10, max_iter=600,
+            **({"restart": 30} if solver == "gmres" else {}))
+        if orc["status"] != "converged":      # CG on L_rho can fail (non-symmetric); so must the GPU
+            assert rr[k] > 1e-10 and info["status"] == 1, (k, rr[k])
+            continue
+        assert rel2(A @ u[k, 1:-1], b[k, 1:-1]) <= 1.01e-10, (k, rel2(A @ u[k, 1:-1], b[k, 1:-1]))
+        # the solution: x modulo the null vector, and the Neumann wall values
+        nv = _null(form, rho[k])
+        d = u[k, 1:-1] - xs[k]
+        d -= (nv @ d) * nv
+        xp = xs[k] - (nv @ xs[k]) * nv
+        assert np.linalg.norm(d) <= 1e-4 * np.linalg.norm(xp), (k, np.linalg.norm(d) / np.linalg.norm(xp))
+        np.testing.assert_allclose(u[k], p1.extend(u[k, 1:-1]), atol=1e-12 * np.abs(u[k]).max())
+        assert abs(int(it[k]) - orc["iterations"]) <= 3, (k, it[k], orc["iterations"])
+    h.close()
+
+
+def test_paper_statements_on_the_gpu():
+    """Sec. 3.2, K_rho at N = 256, s = 10: GMRES reaches 1e-10 where RMR and
+    CG do not (RMR stalls near 1e-1, CG does not converge)."""
+    from paper_2403_06654_amd.api import Visc1d, VdError
+    n = 257
+    rho = _rho(n, [10.0])
+    xs = np.random.default_rng(6).standard_normal(n - 2)
+    b = np.zeros_like(rho)
+    b[0, 1:-1] = p1.operator_K(rho[0]) @ xs
+    h = Visc1d.pressure(n, "K")
+    _, it, rr, info = h.solve(to_dev(rho), to_dev(b), solver="gmres", restart=30, max_iter=300)
+    assert info["status"] == 0
+    _, it, rr, info = h.solve(to_dev(rho), to_dev(b), solver="rmr", max_iter=300, history=301)
+    assert info["status"] == 1 and it[0] == 300
+    assert info["history"][0, :info["history_len"]].min() > 1e-3
+    # CG wanders without converging (it may also break down on a vanishing (p, A p))
+    try:
+        _, it, rr, info = h.solve(to_dev(rho), to_dev(b), solver="cg", max_iter=300, history=301)
+        assert info["status"] == 1 and info["history"][0, :info["history_len"]].min() > 1e-8
+    except VdError as e:
+        assert e.status == -4
+    h.close()
+
+
+def test_histories_match_the_oracle():
+    """Residual histories (the curves of Fig. 7) against the oracle's for
+    the same methods: GMRES's Givens estimates, RMR's and CG's recursive
+    residuals, K_rho, N = 256, s = 2; compared while above 1e-8."""
+    from paper_2403_06654_amd.api import Visc1d
+    n = 257
+    rho = _rho(n, [2.0])
+    A = p1.operator_K(rho[0])
+    X = p1.laplacian_pinv(n)
+    xs = np.random.default_rng(7).standard_normal(n - 2)
+    b = np.zeros_like(rho)
+    b[0, 1:-1] = A @ xs
+    h = Visc1d.pressure(n, "K")
+    for solver in ("gmres", "rmr", "cg"):
+        _, it, rr, info = h.solve(to_dev(rho), to_dev(b), solver=solver, restart=30, max_iter=60,
+                                  rtol=1e-12, history=61)
+        hg = info["history"][0, :info["history_len"]]
+        orc = getattr(krylov, "pcg" if solver == "cg" else solver)(
+            lambda v: A @ v, b[0, 1:-1], lambda r: X @ r, rtol=1e-12, max_iter=60,
+            **({"restart": 30} if solver == "gmres" else {}))
+        ho = np.asarray(orc["history"])
+        m = min(hg.size, ho.size)
+        sel = ho[:m] > 1e-8
+        assert sel.sum() >= 4, solver
+        np.testing.assert_allclose(hg[:m][sel], ho[:m][sel], rtol=1e-4, err_msg=solver)
+    h.close()
+
+
+def test_batch_invariance_and_edge_cases():
+    from paper_2403_06654_amd.api import Visc1d, VdError
+    n = 65
+    s_list = [0.5, 2.0, 3.0, 10.0, 1.5] * 4   # 20 systems: a ragged second group
+    rho = _rho(n, s_list)
+    b = np.zeros_like(rho)
+    rng = np.random.default_rng(8)
+    for k in range(len(s_list)):
+        b[k, 1:-1] = p1.operator_K(rho[k]) @ rng.standard_normal(n - 2)
+    h = Visc1d.pressure(n, "K")
+    u_all, it_all, _, _ = h.solve(to_dev(rho), to_dev(b), solver="gmres", restart=30, max_iter=200)
+    u_one, it_one, _, _ = h.solve(to_dev(rho[17:18]), to_dev(b[17:18]), solver="gmres", restart=30, max_iter=200)
+    assert np.array_equal(to_host(u_all)[17], to_host(u_one)[0]) and it_all[17] == it_one[0]
+    # zero right-hand side: zero solution (walls included), no iterations
+    u, it, rr, info = h.solve(to_dev(rho[:2]), to_dev(np.zeros((2, n))), solver="cg")
+    assert info["status"] == 0 and it.max() == 0 and float(u.abs().max()) == 0.0
+    # a density that is not positive: that system reports VD_EDOMAIN
+    bad = rho[:2].copy()
+    bad[1, 7] = -1.0
+    with pytest.raises(VdError) as e:
+        h.apply(to_dev(bad), to_dev(b[:2]))
+    assert e.value.status == -3
+    h.close()
+    with pytest.raises(VdError):
+        Visc1d.pressure(8, "K")
+    with pytest.raises(VdError):
+        Visc1d.pressure(600, "L")

@@ -198,3 +198,53 @@ def test_wrong_sign_of_mass_source_is_caught(monkeypatch):
     orig = fs.forcing
     monkeypatch.setattr(fs, "forcing", lambda n, t, s, re, sc: (orig(n, t, s, re, sc)[0], -orig(n, t, s, re, sc)[1]))
     _fails(tf.test_second_order_in_time)
+
+
+# ------------------------------------------------ 1D Chebyshev pressure (Sec. 3.2)
+
+def test_pressure1d_wrong_sign_of_density_gradient_is_caught(monkeypatch):
+    from oracle import pressure1d as p1
+    from tests import test_oracle_pressure1d as tp
+    def bad_L(rho):
+        n = rho.size
+        _, d1, _, d1n, d2n, _ = p1.matrices(n)
+        rp = (d1 @ rho)[1:-1]
+        ri = rho[1:-1]
+        return (1.0 / ri)[:, None] * d2n + (rp / ri ** 2)[:, None] * d1n   # + instead of -
+    monkeypatch.setattr(p1, "operator_L", bad_L)
+    _fails(tp.test_L_closed_form, 17)
+
+
+def test_pressure1d_dirichlet_walls_are_caught(monkeypatch):
+    from oracle import pressure1d as p1
+    from tests import test_oracle_pressure1d as tp
+    def dirichlet(n):   # wall values 0 instead of the Neumann extension
+        P = np.zeros((n, n - 2))
+        P[1:n - 1] = np.eye(n - 2)
+        return P
+    monkeypatch.setattr(p1, "neumann_extension", dirichlet)
+    _fails(tp.test_neumann_extension, 17)
+    _fails(tp.test_L_closed_form, 17)
+    _fails(tp.test_nullspaces, 17)
+
+
+def test_pressure1d_literal_coefficient_error_is_caught(monkeypatch):
+    from oracle import pressure1d as p1
+    from tests import test_oracle_pressure1d as tp
+    def bad(rho):   # rho''/rho instead of rho''/(2 rho)
+        _, d1, d2, _, _, _ = p1.matrices(rho.size)
+        rp, rpp = d1 @ rho, d2 @ rho
+        return (rpp / rho - 0.75 * rp ** 2 / rho ** 2)[1:-1]
+    monkeypatch.setattr(p1, "k_coefficient_literal", bad)
+    _fails(tp.test_K_literal_closed_form, 17)
+
+
+def test_pressure1d_psi_coefficient_sign_is_caught(monkeypatch):
+    from oracle import pressure1d as p1
+    from tests import test_oracle_pressure1d as tp
+    def bad(rho):
+        _, _, _, _, d2n, _ = p1.matrices(rho.size)
+        psi = rho[1:-1] ** -0.5
+        return (d2n @ psi) / psi
+    monkeypatch.setattr(p1, "k_coefficient", bad)
+    _fails(tp.test_K_psi_form_closed_form_and_null_vector, 17)
