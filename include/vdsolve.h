@@ -250,7 +250,7 @@ vd_status vd_visc1d_create(vd_visc1d** out, int basis, int n, double length, dou
  * L_rho, psi for K_rho), so a right-hand side must lie in the range of the
  * operator, else its component outside the range remains in the residual.
  * The handle is used with vd_visc1d_apply, vd_visc1d_solve,
- * vd_visc1d_kernel_ms and vd_visc1d_destroy: b's
+ * vd_visc1d_solve_noalloc, vd_visc1d_kernel_ms and vd_visc1d_destroy: b's
  * wall values are ignored; solutions and preconditioned vectors carry the
  * wall values of the Neumann extension; operator outputs (equation rows)
  * have zero walls.  n: 9..512.  Errors: VD_EINVAL, VD_ENOMEM, VD_EDEVICE. */
@@ -275,6 +275,26 @@ vd_status vd_visc1d_apply(vd_visc1d* h, int batch, const double* rho, const doub
  * rows, RMR; 96 rows, CG) is kept by the handle for later calls. */
 vd_status vd_visc1d_solve(vd_visc1d* h, int batch, const double* rho, const double* b, double* u,
                           const vd_solve_opts* opts, int* iterations, double* rel_residual, vd_solve_info* info);
+/* The same solve for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the workspace, per-system outputs and residual histories live in a static
+ * device array of VD_NOALLOC_SCRATCH_BYTES that the library holds on every
+ * GPU it runs on until the process ends, so the call allocates nothing (the
+ * handle, created beforehand, holds the matrices).  It needs
+ *   ceil(batch / 16) x per-group workspace (16 (5 + restart + 1) rows padded
+ *   to 64 doubles plus the Hessenberg and rotation arrays, GMRES; 80 rows,
+ *   RMR; 96 rows, CG) + batch (4 + 8 + 4 + 8 history_cap) bytes, each part rounded up to
+ *   256 bytes;
+ * e.g. 256 unknowns, GMRES(30): 816 systems; RMR: 6528.  A larger call
+ * returns VD_ETOOBIG and does nothing.  Results, iterations and histories are
+ * those of vd_visc1d_solve (same kernel).  All calls on one GPU share its
+ * array, which keeps the last call's contents: two calls that overlap in time
+ * on one GPU (other threads, other streams) race and give undefined results.
+ * Histories are cleared with a kernel, not a memset. */
+#define VD_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+vd_status vd_visc1d_solve_noalloc(vd_visc1d* h, int batch, const double* rho, const double* b, double* u,
+                                  const vd_solve_opts* opts, int* iterations, double* rel_residual,
+                                  vd_solve_info* info);
 /* Duration in ms of the last apply or solve kernel, from HIP events recorded
  * on the handle's stream immediately before and after its launch (0 before
  * any call, -1 if the events could not be read). */

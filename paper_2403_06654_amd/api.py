@@ -128,6 +128,8 @@ _SIGS = {
     "vd_ns_profile_enable": (_I, [_P, _I]),
     "vd_ns_profile_read": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(_D), _I]),
     "vd_visc1d_kernel_ms": (_I, [_P, ctypes.POINTER(_D)]),
+    "vd_visc1d_solve_noalloc": (_I, [_P, _I, _P, _P, _P, ctypes.POINTER(vd_solve_opts), _P, _P,
+                                     ctypes.POINTER(vd_solve_info)]),
     "vd_server_create": (_I, [ctypes.POINTER(_P), ctypes.c_size_t, _I]),
     "vd_server_create_dry": (_I, [ctypes.POINTER(_P), ctypes.c_size_t, _I, _D]),
     "vd_server_submit": (_I, [_P, ctypes.POINTER(vd_request), ctypes.POINTER(ctypes.c_ulonglong)]),
@@ -391,6 +393,11 @@ class Visc1d:
 
     def solve(self, rho, b, u=None, **opts):
         return self._solve(lib().vd_visc1d_solve, "vd_visc1d_solve", rho, b, u, **opts)
+
+    def solve_noalloc(self, rho, b, u=None, **opts):
+        """vd_visc1d_solve_noalloc: the same solve on the library's static
+        device scratch (no device allocation in the call)."""
+        return self._solve(lib().vd_visc1d_solve_noalloc, "vd_visc1d_solve_noalloc", rho, b, u, **opts)
 
     def _solve(self, fn, name, rho, b, u=None, **opts):
         import numpy as np

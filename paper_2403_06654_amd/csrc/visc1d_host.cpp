@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -39,12 +40,44 @@ struct vd_visc1d {
   size_t hist_cap = 0;     // doubles
   hipEvent_t ev[2] = {nullptr, nullptr};  // around the last kernel launch
   double last_ms = 0.0;
+  void* scratch = nullptr;  // this device's allocation-free scratch (device address)
 };
 
+// Device scratch of vd_visc1d_solve_noalloc: one call's per-group workspace,
+// per-system outputs and residual histories.  Each GPU the library runs on
+// holds its own copy until the process ends.  In host code this name is a
+// host-side stand-in, never a device address: kernels and copies get the
+// address from hipGetSymbolAddress (scratch_address below).
+static __device__ __align__(256) unsigned char scratch[VD_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
 const LD kPi = 3.14159265358979323846264338327950288L;
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of the current device's scratch array, looked up once per
+// device with that device current.
+vd_status scratch_address(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    hipGetLastError();
+    return VD_EDEVICE;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      hipGetLastError();
+      return VD_EDEVICE;
+    }
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return VD_OK;
+}
 
 // p[0..n) = 0 (a kernel rather than hipMemsetAsync, so that a caller may
 // capture the call's work in a graph)
@@ -59,6 +92,8 @@ hipError_t zero_async(double* p, size_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, st, p, n);
   return hipGetLastError();
 }
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // Chebyshev-Gauss-Lobatto first derivative, x_j = cos(pi j / m): off-diagonal
 // (c_i / c_j)(-1)^(i+j) / (x_i - x_j) with the node difference from the
@@ -273,12 +308,15 @@ vd_status vd_visc1d_create(vd_visc1d** out, int basis, int n, double length, dou
   }
   h->tpw = vd::visc1d_tpw(ni);
   h->kt_full = (n + 15) / 16;
-  // the events around each launch
+  // the events around each launch, and the set-up of the allocation-free
+  // entry point: this device's scratch address (if it cannot be found, that
+  // entry point reports VD_EDEVICE and the others are unaffected)
   if (hipEventCreate(&h->ev[0]) != hipSuccess || hipEventCreate(&h->ev[1]) != hipSuccess) {
     hipGetLastError();
     release(h);
     return VD_EDEVICE;
   }
+  if (scratch_address(&h->scratch) != VD_OK) h->scratch = nullptr;
   const int rt = vd::visc1d_rows(h->tpw) / 16;
   if (!upload_tiles(d1, n, off, off, ni, ni, rt, rt, &h->D1I) || !upload_tiles(d2, n, off, off, ni, ni, rt, rt, &h->D2I) ||
       !upload_tiles(Vinv, ni, 0, 0, ni, ni, rt, rt, &h->VI) ||
@@ -369,6 +407,7 @@ vd_status vd_pres1d_create(vd_visc1d** out, int n, int form, hipStream_t stream)
     release(h);
     return VD_EDEVICE;
   }
+  if (scratch_address(&h->scratch) != VD_OK) h->scratch = nullptr;
   *out = h;
   return VD_OK;
 }
@@ -590,6 +629,45 @@ vd_status vd_visc1d_solve(vd_visc1d* h, int batch, const double* rho, const doub
   B.relres = h->relres;
   B.status = h->status;
   B.hist = h->hist;
+  return run_solve(h, batch, rho, b, u, o, B, iterations, rel_residual, info, t0);
+}
+
+// Scratch bytes one allocation-free solve of `batch` systems needs.
+static size_t noalloc_bytes(const vd_visc1d* h, int batch, const vd_solve_opts& o) {
+  const size_t groups = ((size_t)batch + vd::kVisc1dGroup - 1) / vd::kVisc1dGroup;
+  return align256(groups * solve_per_group(h, o) * sizeof(double)) + align256((size_t)batch * sizeof(int)) +
+         align256((size_t)batch * sizeof(double)) + align256((size_t)batch * sizeof(int)) +
+         align256((size_t)batch * (size_t)o.history_cap * sizeof(double));
+}
+
+vd_status vd_visc1d_solve_noalloc(vd_visc1d* h, int batch, const double* rho, const double* b, double* u,
+                                  const vd_solve_opts* opts, int* iterations, double* rel_residual,
+                                  vd_solve_info* info) {
+  if (!h || batch < 1 || !rho || !b || !u) return VD_EINVAL;
+  auto t0 = std::chrono::steady_clock::now();
+  vd_solve_opts o;
+  if (opts) o = *opts;
+  else vd_default_opts(&o);
+  const vd_status ok = check_solve_opts(o);
+  if (ok != VD_OK) return ok;
+  if (!h->scratch) return VD_EDEVICE;
+  const size_t need = noalloc_bytes(h, batch, o);
+  if (need > (size_t)VD_NOALLOC_SCRATCH_BYTES) return VD_ETOOBIG;
+  // carve the call's buffers out of the scratch array (device address)
+  unsigned char* base = static_cast<unsigned char*>(h->scratch);
+  const size_t groups = ((size_t)batch + vd::kVisc1dGroup - 1) / vd::kVisc1dGroup;
+  SolveBufs B;
+  B.per_group = solve_per_group(h, o);
+  size_t off = 0;
+  B.work = reinterpret_cast<double*>(base + off);
+  off += align256(groups * B.per_group * sizeof(double));
+  B.iters = reinterpret_cast<int*>(base + off);
+  off += align256((size_t)batch * sizeof(int));
+  B.relres = reinterpret_cast<double*>(base + off);
+  off += align256((size_t)batch * sizeof(double));
+  B.status = reinterpret_cast<int*>(base + off);
+  off += align256((size_t)batch * sizeof(int));
+  B.hist = reinterpret_cast<double*>(base + off);
   return run_solve(h, batch, rho, b, u, o, B, iterations, rel_residual, info, t0);
 }
 
