@@ -221,22 +221,87 @@ def pressure_forms(grid, rho_dev, f_dev, torch):
     return out
 
 
+def host_threads():
+    """Threads for the all-cores oracle leg: the CPUs this process may run on,
+    capped at the 16 a one-GPU share of the host provides."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
 def cpu_baseline(inp):
     """The oracle as it stands, on the host: GMRES on the same 256^3 pressure
-    problem (rj = 3), stopped after a fixed number of iterations."""
-    import numpy as np
+    problem (rj = 3), stopped after a fixed number of iterations; once with
+    numpy's one-thread FFTs and once with the same FFTs on all cores
+    (operators.use_workers).  The all-cores figure is the reported baseline."""
     from oracle import krylov, operators
     rho, f = inp["rho"], inp["f"]
     b, _ = operators.project_range(-f, operators.nullspace_basis(f.shape))
-    k = 2
-    t0 = time.perf_counter()
-    res = krylov.gmres(lambda u: operators.apply_pressure(u, rho), b,
-                       lambda r: operators.precond_pressure(r, rho.mean()), max_iter=k)
-    dt = time.perf_counter() - t0
-    return {"value": round(res["iterations"] / dt, 4), "unit": "Krylov iters/s", "cores": 1, "kind": "oracle",
-            "sample": (f"oracle.krylov.gmres(restart 30) on the 256^3 pressure problem (rj=3), stopped after "
-                       f"{res['iterations']} iterations; {dt:.1f} s wall including its initial and final "
-                       f"true-residual applications; NumPy FFTs run on one thread")}
+
+    def leg(k, workers):
+        operators.use_workers(workers)
+        try:
+            t0 = time.perf_counter()
+            res = krylov.gmres(lambda u: operators.apply_pressure(u, rho), b,
+                               lambda r: operators.precond_pressure(r, rho.mean()), max_iter=k)
+            return res["iterations"], time.perf_counter() - t0
+        finally:
+            operators.use_workers(None)
+
+    it1, dt1 = leg(2, None)
+    nt = host_threads()
+    itn, dtn = leg(4, nt)
+    sample = ("oracle.krylov.gmres(restart 30) on the 256^3 pressure problem (rj=3), stopped after {k} "
+              "iterations; {dt:.1f} s wall including its initial and final true-residual applications; {how}")
+    return {"value": round(itn / dtn, 4), "unit": "Krylov iters/s", "cores": nt, "kind": "oracle",
+            "sample": sample.format(k=itn, dt=dtn, how=f"FFTs on {nt} threads (scipy.fft), the rest of the "
+                                                      "oracle's NumPy arithmetic as it stands"),
+            "single_thread": {"value": round(it1 / dt1, 4), "unit": "Krylov iters/s", "cores": 1,
+                              "sample": sample.format(k=it1, dt=dt1, how="NumPy FFTs on one thread")}}
+
+
+def oracle_check(grid, rho_dev, dens, inp, f_dev, g_dev, torch):
+    """Error against the FP64 oracle for a sample of the headline's results:
+    the rj = 3 pressure solve and the first velocity component, each in FP64
+    and FP32+refine, solved on the GPU as in the timed steps.  Per result: the
+    oracle-evaluated true relative residual and ||x - x_oracle|| / ||x_oracle||,
+    x_oracle the oracle's GMRES(30) solution to 1e-13 (FFTs on all cores)."""
+    import numpy as np
+    from oracle import krylov, operators
+    rho, f, g0 = dens[3.0], inp["f"], inp["g"][0]
+    basis = operators.nullspace_basis(f.shape)
+    b, _ = operators.project_range(-f, basis)
+    Ap = lambda u: operators.apply_pressure(u, rho)
+    Ah = lambda u: operators.apply_helmholtz(u, rho, DT_NU)
+    operators.use_workers(host_threads())
+    try:
+        t0 = time.perf_counter()
+        ref_p = krylov.gmres(Ap, b, lambda r: operators.precond_pressure(r, rho.mean()), rtol=1e-13)
+        ref_u = krylov.gmres(Ah, g0, lambda r: operators.precond_helmholtz(r, rho.mean(), DT_NU), rtol=1e-13)
+        t_ref = time.perf_counter() - t0
+        xp = operators.project_range(ref_p["x"], basis)[0]
+        grid.set_density(rho_dev[RJS.index(3.0)])
+        out = {"oracle_reference": {"pressure_iterations": ref_p["iterations"],
+                                    "pressure_rel_residual": ref_p["rel_residual"],
+                                    "velocity_iterations": ref_u["iterations"],
+                                    "velocity_rel_residual": ref_u["rel_residual"], "seconds": round(t_ref, 1)}}
+        for prec in ("fp64", "fp32_refine"):
+            p, ip = grid.solve_pressure(f_dev, precision=prec)
+            u, iu = grid.solve_helmholtz(g_dev[0].contiguous(), DT_NU, precision=prec)
+            p, u = p.cpu().numpy(), u.cpu().numpy()
+            nr = lambda a, c: float(np.linalg.norm(a - c) / np.linalg.norm(c))
+            out[prec] = {
+                "pressure_rj3": {"gpu_rel_residual": ip["rel_residual"], "oracle_rel_residual": nr(Ap(p), b),
+                                 "rel_error_vs_oracle": nr(operators.project_range(p, basis)[0], xp),
+                                 "iterations": ip["iterations"]},
+                "velocity_rj3_component0": {"gpu_rel_residual": iu["rel_residual"],
+                                            "oracle_rel_residual": nr(Ah(u), g0),
+                                            "rel_error_vs_oracle": nr(u, ref_u["x"]), "iterations": iu["iterations"]}}
+        return out
+    finally:
+        operators.use_workers(None)
 
 
 def bench_serving(args):
@@ -670,11 +735,48 @@ def ns_cpu_baseline(n):
             "sample": f"oracle.fractional_step.step, 1 step at {n}^3 from the initial state, {el:.1f} s"}
 
 
+def cheb_statements(out):
+    """The paper's statements about the Chebyshev pressure operators (Sec.
+    3.2), evaluated on the study's GPU-assembled numbers."""
+    vs_s, vs_n = out["pressure_cheb_vs_s"], out["pressure_cheb_vs_N"]
+    hist = out["pressure_cheb_histories_N256"]
+
+    def first_below(h, t):
+        for i, v in enumerate(h):
+            if isinstance(v, float) and v <= t:
+                return i
+        return None
+
+    big = {k: v for k, v in vs_n.items() if int(k) >= 32}
+    pk = [v["PK"] for v in big.values()]
+    kp = [v["KP"] for v in big.values()]
+    pl = [v["PL"] for v in big.values()]
+    return {
+        # at s = 1 both preconditioned operators are the identity on the range (kappa 1)
+        "kappa(P K) < kappa(P L) for 0.1 <= s <= 100, s != 1": all(v["PK"] < v["PL"] for k, v in vs_s.items()
+                                                                     if float(k) != 1.0),
+        "kappa(P K), kappa(K P) independent of N (max/min over N >= 32, s = 2)": [max(pk) / min(pk),
+                                                                                   max(kp) / min(kp)],
+        "kappa(P L) independent of N (max/min over N >= 32, s = 2; not the paper's picture)": max(pl) / min(pl),
+        "GMRES 12 decades, iterations at s = 2, 10, 100 (paper: about 10)":
+            [first_below(hist[f"s{s:g}_K_gmres"], 1e-12) for s in (2.0, 10.0, 100.0)],
+        "RMR iterations to 1e-9 vs GMRES at s = 2 (paper: 4x)":
+            [first_below(hist["s2_K_rmr"], 1e-9), first_below(hist["s2_K_gmres"], 1e-9)],
+        "RMR converges for s = 10, 100 (paper: no)":
+            [first_below(hist[f"s{s:g}_K_rmr"], 1e-9) is not None for s in (10.0, 100.0)],
+        "CG smallest residual at s = 2, 10, 100 (paper: plateau near 0.5)":
+            [min((v for v in hist[f"s{s:g}_K_cg"] if isinstance(v, float)), default=None) for s in (2.0, 10.0, 100.0)],
+    }
+
+
 def bench_kappa(args):
     """Condition-number study (Sec. 3.1 Figs. 1-3 set-ups for V_rho, Sec. 3.2
-    Figs. 5-6 set-ups for L_rho and K_rho on periodic grids) with every
+    Figs. 5-6 set-ups for L_rho and K_rho on periodic grids and on the
+    paper's Chebyshev-collocation grid with Neumann walls) with every
     operator column computed by the library's GPU applications and kappa from
-    an SVD on the host; RMR and GMRES residual histories of the batched 1D
+    an SVD on the host; GMRES, RMR and CG residual histories of the
+    Chebyshev pressure systems (Fig. 7 set-up, N = 256, s = 2, 10, 100);
+    RMR and GMRES residual histories of the batched 1D
     viscous solver (Fig. 4 set-up, N = 256, s = 2, a = 1e-3); and its
     iterations for a in {1e-4, 1e-3, 1e-2} and s in {10, 100, 1000} (App. A
     set-up)."""
@@ -692,6 +794,15 @@ def bench_kappa(args):
     out["pressure_fourier_vs_N"] = {str(n): C.pressure_kappa(n, 2.0) for n in (32, 64, 128, 256, 512)}
     out["pressure_fourier_vs_s"] = {str(s): C.pressure_kappa(256, s)
                                     for s in (0.1, 0.2, 0.5, 1.0, 2.0, 5.0, 10.0, 20.0, 50.0, 100.0)}
+    print("bench: kappa pressure, Chebyshev collocation", file=sys.stderr, flush=True)
+    out["pressure_cheb_vs_N"] = {str(n - 1): C.cheb_pressure_kappa(n, 2.0) for n in (17, 33, 65, 129, 257, 512)}
+    out["pressure_cheb_vs_s"] = {str(s): C.cheb_pressure_kappa(257, s)
+                                 for s in (0.1, 0.2, 0.5, 1.0, 2.0, 5.0, 10.0, 20.0, 50.0, 100.0)}
+    print("bench: pressure histories, Chebyshev collocation", file=sys.stderr, flush=True)
+    out["pressure_cheb_histories_N256"] = {f"s{s:g}_{form}_{solver}": C.cheb_pressure_history(257, s, form, solver)
+                                           for s in (2.0, 10.0, 100.0) for form in ("K", "L")
+                                           for solver in ("gmres", "rmr", "cg")}
+    out["pressure_cheb_statements"] = cheb_statements(out)
     print("bench: viscous histories", file=sys.stderr, flush=True)
     out["visc_histories_N256_s2_a1e-3"] = {f"{basis}_{solver}": C.viscous_history(basis, 257 if basis == "cheb" else 256,
                                                                                  1e-3, 2.0, solver)
@@ -705,7 +816,8 @@ def bench_kappa(args):
            "data": "synthetic",
            "config": {"workload": "top-hat densities of eq. VDINSE.rho.hat (d = 0.1, x0 a fifth of the domain); "
                                   "V_rho on Chebyshev (N+1 points, no-slip) and Fourier grids, a = dt/(2 Re); "
-                                  "L_rho and K_rho on periodic 1D grids"},
+                                  "L_rho and K_rho on periodic 1D grids and on Chebyshev collocation with Neumann "
+                                  "walls (N+1 points)"},
            "kappa": out}
     print(json.dumps(res))
 
@@ -760,6 +872,7 @@ def main():
     ap.add_argument("--steps", type=int, default=6)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-oracle-check", action="store_true", help="skip the oracle check of sampled results")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--workload", choices=["c3", "serving", "c5", "c2", "pmc", "visc1d", "ns", "kappa", "table2"], default="c3")
     ap.add_argument("--requests", type=int, default=4096)
@@ -824,6 +937,10 @@ def main():
     forms = pressure_forms(grid, rho_dev, f_dev, torch)
     print("bench: operator applies (FP64, FP32)", file=sys.stderr, flush=True)
     applies = {prec: apply_timing(grid, f_dev, prec, torch) for prec in ("fp64", "fp32")}
+    ocheck = None
+    if not args.no_oracle_check:
+        print("bench: oracle check of sampled results (FP64, FP32+refine)", file=sys.stderr, flush=True)
+        ocheck = oracle_check(grid, rho_dev, dens, inp, f_dev, g_dev, torch)
     grid.close()
     # one GPU's share of a z-slab decomposition over 8 GPUs (local passes only)
     slab = Grid((N // 8, N, N))
@@ -867,6 +984,7 @@ def main():
         "passes": passes,
         "passes_timed_over": "the warm-up steps (every class event-timed); the timed steps time only the roofline class",
         "pressure_forms": forms,
+        "oracle_check": ocheck,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

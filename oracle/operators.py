@@ -35,6 +35,47 @@ import numpy as np
 
 from . import grids
 
+# Every discrete Fourier transform below goes through these four routines.
+# By default they are numpy's (one thread).  use_workers(n) runs the same
+# transforms through scipy.fft with n threads -- the same discrete Fourier
+# transform, evaluated in parallel -- so that the oracle can also be timed
+# on all of a host's cores; the arithmetic of the operators is unchanged.
+_WORKERS = None
+
+
+def use_workers(n):
+    """Run the FFTs on n threads (scipy.fft); None: numpy, one thread."""
+    global _WORKERS
+    _WORKERS = None if n is None else int(n)
+
+
+def _fft(u, axis):
+    if _WORKERS is None:
+        return np.fft.fft(u, axis=axis)
+    import scipy.fft
+    return scipy.fft.fft(u, axis=axis, workers=_WORKERS)
+
+
+def _ifft(u, axis):
+    if _WORKERS is None:
+        return np.fft.ifft(u, axis=axis)
+    import scipy.fft
+    return scipy.fft.ifft(u, axis=axis, workers=_WORKERS)
+
+
+def _fftn(u):
+    if _WORKERS is None:
+        return np.fft.fftn(u)
+    import scipy.fft
+    return scipy.fft.fftn(u, workers=_WORKERS)
+
+
+def _ifftn(u):
+    if _WORKERS is None:
+        return np.fft.ifftn(u)
+    import scipy.fft
+    return scipy.fft.ifftn(u, workers=_WORKERS)
+
 
 # ----------------------------------------------------------------- Fourier
 
@@ -51,20 +92,20 @@ def deriv(u, axis, length=2.0 * np.pi):
     kp = grids.fourier_kprime(n, length)
     shp = [1] * u.ndim
     shp[axis] = n
-    uh = np.fft.fft(u, axis=axis)
-    return np.real(np.fft.ifft(1j * kp.reshape(shp) * uh, axis=axis))
+    uh = _fft(u, axis)
+    return np.real(_ifft(1j * kp.reshape(shp) * uh, axis))
 
 
 def laplacian(u, lengths=None):
     """Spectral Laplacian, symbol -|k|^2 with the Nyquist entries kept."""
     lengths = _axis_len(u.shape, lengths)
-    uh = np.fft.fftn(u)
+    uh = _fftn(u)
     ksq = np.zeros(u.shape)
     for d, (n, ln) in enumerate(zip(u.shape, lengths)):
         shp = [1] * u.ndim
         shp[d] = n
         ksq = ksq + grids.fourier_k(n, ln).reshape(shp) ** 2
-    return np.real(np.fft.ifftn(-ksq * uh))
+    return np.real(_ifftn(-ksq * uh))
 
 
 def L_rho(u, rho, lengths=None):
@@ -108,7 +149,7 @@ def precond_pressure(r, rho0, lengths=None):
     sym = np.zeros_like(ksq)
     nz = ksq > 0
     sym[nz] = rho0 / ksq[nz]
-    return np.real(np.fft.ifftn(sym * np.fft.fftn(r)))
+    return np.real(_ifftn(sym * _fftn(r)))
 
 
 def precond_helmholtz(r, rho0, nu, lengths=None):
@@ -119,7 +160,7 @@ def precond_helmholtz(r, rho0, nu, lengths=None):
         shp = [1] * r.ndim
         shp[d] = n
         ksq = ksq + grids.fourier_k(n, ln).reshape(shp) ** 2
-    return np.real(np.fft.ifftn(np.fft.fftn(r) / (rho0 + nu * ksq)))
+    return np.real(_ifftn(_fftn(r) / (rho0 + nu * ksq)))
 
 
 def nullspace_basis(shape):
@@ -206,7 +247,7 @@ def precond_pressure_k(r, lengths=None):
         ksq = ksq + grids.fourier_k(n, ln).reshape(shp) ** 2
     sym = np.zeros_like(ksq)
     sym[ksq > 0] = 1.0 / ksq[ksq > 0]
-    return np.real(np.fft.ifftn(sym * np.fft.fftn(r)))
+    return np.real(_ifftn(sym * _fftn(r)))
 
 
 def pressure_k_rhs(f, rho):

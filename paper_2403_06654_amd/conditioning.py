@@ -9,6 +9,12 @@ counts of its batched 1D viscous solver.
 * Pressure operators L_rho (eq. VDINSE.Lrho) and K_rho (eq. VDINSE.Krho) with
   their preconditioners on periodic 1D grids: columns from `vd_apply_operator`
   and `vd_apply_precond`.
+* The same pressure operators on the paper's own 1D discretisation of
+  Sec. 3.2 (Figs. 5-7): Chebyshev collocation with Neumann walls, unknowns
+  the interior values, preconditioned by the pseudo-inverse of the Neumann
+  Laplacian: columns from batched `vd_visc1d_apply` calls on
+  `vd_pres1d_create` handles, and residual histories of the batched
+  GMRES, RMR and CG solvers.
 
 kappa = sigma_max / sigma_min from a singular value decomposition (the
 paper's definition, Sec. 3.1), taken on the operator's range when it is
@@ -121,3 +127,67 @@ def viscous_history(basis, n, a, s, solver, seed=0, rtol=1e-10, max_iter=2000, r
                               max_iter=max_iter, restart=restart, history=max_iter + 1)
     h.close()
     return [float(v) for v in info["history"][0, : int(it[0]) + 1]]
+
+
+def cheb_pressure_density(n, s):
+    x = np.cos(np.pi * np.arange(n) / (n - 1))
+    return workloads.tophat(x, s, 0.4)
+
+
+def cheb_pressure_matrices(n, s):
+    """Columns (numpy, on the n - 2 interior values) of L_rho, K_rho, the
+    preconditioner P (pseudo-inverse of the Neumann Laplacian), and P L_rho,
+    L_rho P, P K_rho, K_rho P, on n Chebyshev-Gauss-Lobatto points."""
+    import torch
+    rho = cheb_pressure_density(n, s)
+    ni = n - 2
+    R = torch.from_numpy(np.tile(rho, (ni, 1))).cuda()
+    E = np.zeros((ni, n))
+    E[np.arange(ni), 1 + np.arange(ni)] = 1.0
+    E = torch.from_numpy(E).cuda()
+    cut = lambda T: T.cpu().numpy()[:, 1:1 + ni].T.copy()  # columns
+    out = {}
+    for form in ("L", "K"):
+        h = Visc1d.pressure(n, form)
+        A = h.apply(R, E)                 # row j: A e_j
+        P = h.apply(R, E, precond=True)   # row j: P e_j (a field: walls extended)
+        out[form] = cut(A)
+        out["P" + form] = cut(h.apply(R, A, precond=True))
+        out[form + "P"] = cut(h.apply(R, P))
+        out["P"] = cut(P)
+        h.close()
+    return out
+
+
+def cheb_pressure_kappa(n, s):
+    """kappa on the range (each operator and each product has one null
+    direction): L_rho, K_rho, Lap^-1 L_rho (left), L_rho Lap^-1 (right),
+    and the same for K_rho."""
+    m = cheb_pressure_matrices(n, s)
+    return {k: kappa(m[k], 1) for k in ("L", "K", "PL", "LP", "PK", "KP")}
+
+
+def cheb_pressure_history(n, s, form, solver, seed=0, max_iter=120, rtol=1e-13, restart=30):
+    """Residual history of the batched GPU solver for one Chebyshev pressure
+    system (Fig. 7 set-up).  The paper does not give its right-hand side;
+    here b is a standard normal vector on the interior values projected onto
+    the operator's range (the operators are singular): its component along
+    the left null vector of the GPU-assembled operator (host SVD) is
+    removed."""
+    import torch
+    A = cheb_pressure_matrices(n, s)[form]
+    U, _, _ = np.linalg.svd(A)
+    w = U[:, -1]
+    f = np.random.default_rng(seed).standard_normal(n - 2)
+    b = np.zeros((1, n))
+    b[0, 1:-1] = f - (w @ f) * w
+    rho = torch.from_numpy(cheb_pressure_density(n, s)[None, :]).cuda()
+    h = Visc1d.pressure(n, form)
+    try:
+        _, it, rr, info = h.solve(rho, torch.from_numpy(b).cuda(), solver=solver, rtol=rtol, max_iter=max_iter,
+                                  restart=restart, history=max_iter + 1)
+        hist = [float(v) for v in info["history"][0, : int(info["history_len"])]]
+    except Exception as e:  # a breakdown (non-finite scalar) ends a diverging CG
+        hist = [repr(e)]
+    h.close()
+    return hist

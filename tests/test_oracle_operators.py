@@ -231,3 +231,23 @@ def test_fourier_chebyshev_variable_density_converges_spectrally():
         pr, _ = operators.project_range(p, fc.nullspace_basis())
         errs.append(np.abs(res["x"] - pr).max())
     assert errs[2] < 1e-13 and errs[1] < errs[0] * 1e-5 and errs[2] < errs[1] * 1e-2, errs
+
+
+def test_threaded_fft_execution_is_the_same_transform():
+    """operators.use_workers runs the oracle's FFTs through scipy.fft on
+    several threads (used only to time the oracle on all cores): the
+    operators then agree with the numpy-FFT ones to rounding."""
+    shape = (16, 24, 32)
+    rng = np.random.default_rng(9)
+    rho = 1.5 + rng.uniform(0, 1, shape)
+    u = rng.standard_normal(shape)
+    ref = [operators.apply_pressure(u, rho), operators.apply_helmholtz(u, rho, 1e-3),
+           operators.precond_pressure(u, 2.0), operators.precond_helmholtz(u, 2.0, 1e-3)]
+    try:
+        operators.use_workers(4)
+        got = [operators.apply_pressure(u, rho), operators.apply_helmholtz(u, rho, 1e-3),
+               operators.precond_pressure(u, 2.0), operators.precond_helmholtz(u, 2.0, 1e-3)]
+    finally:
+        operators.use_workers(None)
+    for a, b in zip(got, ref):
+        assert np.abs(a - b).max() <= 1e-13 * np.abs(b).max()
