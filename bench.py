@@ -167,10 +167,10 @@ def roofline(prof, cls):
     }
 
 
-def traffic_from_profiles(best_name):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+def traffic_from_profiles(best_name, fname="traffic_counters.json"):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
     was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "traffic_counters.json")
+    path = os.path.join(ROOT, "profiles", fname)
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -179,20 +179,21 @@ def traffic_from_profiles(best_name):
     return rec.get("per_launch_bytes", {}).get(best_name)
 
 
+# kernel sources of the 3D solves' passes and Krylov vector kernels: the
+# stored counter readings are used only while these are unchanged
+KERNEL_SOURCES_3D = ("fft_core.hpp", "passes.hip", "passes.hpp", "spectral.hpp", "vd_common.hpp", "vecops.hip",
+                     "vecops.hpp")
+
+
 def csrc_hash():
-    """Hash of the sources of the 3D solver kernels, so that stored counter
-    readings are only used for the kernels they were taken on (the batched
-    1D viscous solver's and the fractional-step driver's files are not part
-    of that path)."""
-    from paper_2403_06654_amd.build import SOURCES
+    """Hash of the kernel sources of the 3D solves (the operator passes and
+    the Krylov vector kernels), so that stored counter readings are only used
+    for the kernels they were taken on."""
     d = os.path.join(ROOT, "paper_2403_06654_amd", "csrc")
     h = hashlib.sha256()
-    for fn in sorted(os.listdir(d)):
-        if fn.startswith(("visc1d", "ns")):
-            continue
-        if fn in SOURCES or fn.endswith(".hpp"):  # the library's sources
-            h.update(fn.encode())
-            h.update(open(os.path.join(d, fn), "rb").read())
+    for fn in KERNEL_SOURCES_3D:
+        h.update(fn.encode())
+        h.update(open(os.path.join(d, fn), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -444,6 +445,7 @@ def bench_c5(args):
             prof = grid.profile_read()
             grid.profile_enable(False)
             roof = roofline(prof, best)
+            roof["traffic"] = traffic_from_profiles(roof["kernel"], "traffic_counters_c5.json")
             passes, op = pass_table(prof_warm, field_bytes)
     grid.close()
     res = {
@@ -456,6 +458,37 @@ def bench_c5(args):
         "passes": passes,
     }
     print(json.dumps(res))
+
+
+def bench_pmc5(args):
+    """Short 512^3 run for hardware-counter passes: the 1 GiB calibration
+    copy, then `--steps` FP64 and FP32 pressure-operator applications and
+    one FP64 GMRES(30) pressure solve of the 512^3 workload capped at 12
+    iterations (its Gram-Schmidt kernels), without timing."""
+    import torch
+    from paper_2403_06654_amd import workloads
+    from paper_2403_06654_amd.api import Grid
+    nbytes = 1 << 30
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    n = 512
+    inp = workloads.c5_inputs(n, seed=0)
+    rho = torch.from_numpy(inp["rho"]).cuda()
+    f = torch.from_numpy(inp["f"]).cuda()
+    grid = Grid((n, n, n))
+    grid.set_density(rho)
+    for prec in ("fp64", "fp32"):
+        for _ in range(args.steps):
+            grid.apply_operator("pressure", f, precision=prec)
+    _, info = grid.solve_pressure(f, max_iter=12)
+    torch.cuda.synchronize()
+    grid.close()
+    print(json.dumps({"pmc_run": True, "grid": n, "copy_bytes": nbytes, "applies": args.steps,
+                      "solve_iterations": info["iterations"]}))
 
 
 def bench_c2(args):
@@ -874,7 +907,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle-check", action="store_true", help="skip the oracle check of sampled results")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--workload", choices=["c3", "serving", "c5", "c2", "pmc", "visc1d", "ns", "kappa", "table2"], default="c3")
+    ap.add_argument("--workload", choices=["c3", "serving", "c5", "c2", "pmc", "pmc5", "visc1d", "ns", "kappa", "table2"],
+                    default="c3")
     ap.add_argument("--requests", type=int, default=4096)
     ap.add_argument("--slots", type=int, default=8)
     ap.add_argument("--batch", type=int, default=8192)
@@ -895,6 +929,9 @@ def main():
         return
     if args.workload == "pmc":
         bench_pmc(args)
+        return
+    if args.workload == "pmc5":
+        bench_pmc5(args)
         return
     if args.workload == "visc1d":
         bench_visc1d(args)

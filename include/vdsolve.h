@@ -397,8 +397,11 @@ typedef struct {
   double dt_nu;        /* Helmholtz coefficient */
   int ncomp;           /* Helmholtz components (0 or 1 = one) */
   const double* rho;   /* device density, caller-owned until its result is returned */
-  const double* f;     /* device right-hand side (ready before submit) */
-  double* x;           /* device output (initial guess if opts.use_x0) */
+  const double* f;     /* device right-hand side */
+  double* x;           /* device output (initial guess if opts.use_x0); rho, f and x
+                          must be ready before submit (the server's streams are not
+                          ordered after any of the caller's) and stay allocated until
+                          the result is returned */
   vd_solve_opts opts;
   unsigned long long user_tag;
 } vd_request;

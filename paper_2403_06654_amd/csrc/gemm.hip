@@ -4,10 +4,10 @@
 // C[M][N] = epilogue(alpha * A[M][K] * B[K][N]): A a small dense matrix of the
 // z direction, B a field whose rows are z levels and whose columns are the
 // packed x spectrum viewed as reals (the z matrices are real, so complex
-// columns contract as pairs of real columns).  One wave computes a 32 x 32
-// tile as 2 x 2 blocks of v_mfma_f64_16x16x4_f64 (FP32:
-// v_mfma_f32_16x16x4_f32), stepping K by 4; operands are read straight from
-// global memory (the A matrix and the field each fit in L2).  Lane l feeds
+// columns contract as pairs of real columns).  A block computes a 16 x 16
+// tile with v_mfma_f64_16x16x4_f64 (FP32: v_mfma_f32_16x16x4_f32), stepping
+// K by 4; operands are read straight from global memory (the A matrix and
+// the field each fit in L2).  Lane l feeds
 // A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator r of lane l holds
 // D[4 (l / 16) + r][l % 16] for the FP32 instruction and D[l / 16 + 4 r][l % 16]
 // for the FP64 one (both checked by a one-hot probe of each lane).
@@ -55,85 +55,67 @@ struct EpiArgs {
   const int* gate;         // nonzero *gate: the launch does nothing
 };
 
-// One 256-thread block per 32 x 32 tile of C; the 4 waves split K (wave w
-// takes the k-steps w, w+4, w+8, ...) so each wave's dependent chain of
-// loads and MFMAs is a quarter of K, and the partial tiles are summed through
-// LDS before the epilogue.  AT: A is stored transposed ([K][M]), so a load of
-// 16 consecutive rows is one contiguous run.
+// One 256-thread block per 16 x 16 tile of C; the 4 waves split K (wave w
+// takes the k-steps w, w+4, w+8, ...), and the four partial tiles are summed
+// through LDS before the epilogue.  The Chebyshev contractions are small
+// (M = 257 or 514 rows, N = 512 real columns, K = 257 or 514): 32 x 32 tiles
+// gave only 144-272 blocks for 256 CUs, one wave per SIMD, each waiting on
+// L2 latency; 16 x 16 tiles give 544-1056 blocks.  Each wave loads its whole
+// K-slice (up to KU k-steps) before its first MFMA, so it waits on memory
+// once, then issues the MFMAs on two independent accumulators (alternate
+// k-steps) so that consecutive MFMAs do not wait on each other's result.
+// AT: A is stored transposed ([K][M]), so a load of 16 consecutive rows is
+// one contiguous run.
 template <typename R, bool AT>
 __global__ __launch_bounds__(256) void k_gemm(const R* __restrict__ A, int lda, const R* __restrict__ B, int ldb,
                                               R* __restrict__ C, int ldc, int M, int N, int K, EpiArgs e) {
   using MF = Mfma<R>;
   if (e.gate && *e.gate) return;
-  __shared__ double part[4][32 * 33];
+  __shared__ double part[4][16 * 17];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+  const int r0 = blockIdx.y * 16, c0 = blockIdx.x * 16;
   const int li = lane & 15, lk = lane >> 4;
-  typename MF::V acc[2][2];
+  const int ra = r0 + li, cb = c0 + li;
+  const bool rin = ra < M, cin = cb < N;
+  typename MF::V acc0{0, 0, 0, 0}, acc1{0, 0, 0, 0};
+  constexpr int KU = 17;  // k-steps per wave loaded at once: all of K = 257, half of K = 514
+  for (int s0 = w; 4 * s0 < K; s0 += 4 * KU) {
+    R a[KU], b[KU];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = typename MF::V{0, 0, 0, 0};
-  const int ra0 = r0 + li, ra1 = r0 + 16 + li;
-  const int cb0 = c0 + li, cb1 = c0 + 16 + li;
-  auto ld_a = [&](int row, int k) -> R {
-    if (row >= M || k >= K) return R(0);
-    return AT ? A[(size_t)k * lda + row] : A[(size_t)row * lda + k];
-  };
-  // All of a batch's operands are loaded before its first MFMA, so a wave
-  // waits for memory once per batch of U k-steps instead of once per step.
-  // Measured on the 512 x 257 Chebyshev solves (FP64 PCG solves/s): U = 4
-  // 505-527, 6 545, 8 522, 12 520, 16 462-466; the previous loop (unrolled
-  // by 4, loads and MFMAs interleaved) 434.  U = 6 holds 116 VGPRs (three
-  // waves per SIMD).
-  constexpr int U = 6;
-  for (int kb = 4 * w; kb < K; kb += 16 * U) {
-    R a0[U], a1[U], b0[U], b1[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int k = kb + 16 * u + lk;
-      a0[u] = ld_a(ra0, k);
-      a1[u] = ld_a(ra1, k);
+    for (int u = 0; u < KU; ++u) {
+      const int k = 4 * (s0 + 4 * u) + lk;
       const bool kin = k < K;
-      b0[u] = (kin && cb0 < N) ? B[(size_t)k * ldb + cb0] : R(0);
-      b1[u] = (kin && cb1 < N) ? B[(size_t)k * ldb + cb1] : R(0);
+      a[u] = (kin && rin) ? (AT ? A[(size_t)k * lda + ra] : A[(size_t)ra * lda + k]) : R(0);
+      b[u] = (kin && cin) ? B[(size_t)k * ldb + cb] : R(0);
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      acc[0][0] = MF::mac(a0[u], b0[u], acc[0][0]);
-      acc[0][1] = MF::mac(a0[u], b1[u], acc[0][1]);
-      acc[1][0] = MF::mac(a1[u], b0[u], acc[1][0]);
-      acc[1][1] = MF::mac(a1[u], b1[u], acc[1][1]);
+    for (int u = 0; u < KU; u += 2) {
+      acc0 = MF::mac(a[u], b[u], acc0);
+      if (u + 1 < KU) acc1 = MF::mac(a[u + 1], b[u + 1], acc1);
     }
   }
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) part[w][(16 * a + MF::row(lk, r)) * 33 + 16 * b + li] = (double)acc[a][b][r];
+  for (int r = 0; r < 4; ++r) part[w][MF::row(lk, r) * 17 + li] = (double)acc0[r] + (double)acc1[r];
   __syncthreads();
   const double al = (e.alpha_dev ? *e.alpha_dev : 1.0) * e.alpha;
-  for (int idx = threadIdx.x; idx < 1024; idx += 256) {
-    const int tr = idx >> 5, tc = idx & 31;
-    const int row = r0 + tr, col = c0 + tc;
-    if (row >= M || col >= N) continue;
-    const int o = tr * 33 + tc;
-    double v = ((part[0][o] + part[1][o]) + part[2][o] + part[3][o]) * al;
-    if (e.kind == 1) {
-      const int kx = col >> 1;
-      const double kp = kx * e.sx;  // slot 0: k' = 0 for both halves
-      if (kx == 0 && row == 0) v = 0.0;
-      else v *= e.scale / (kp * kp + e.lam[row]);
-    }
-    C[(size_t)row * ldc + col] = R(v);
+  const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
+  const int row = r0 + tr, col = c0 + tc;
+  if (row >= M || col >= N) return;
+  const int o = tr * 17 + tc;
+  double v = ((part[0][o] + part[1][o]) + part[2][o] + part[3][o]) * al;
+  if (e.kind == 1) {
+    const int kx = col >> 1;
+    const double kp = kx * e.sx;  // slot 0: k' = 0 for both halves
+    if (kx == 0 && row == 0) v = 0.0;
+    else v *= e.scale / (kp * kp + e.lam[row]);
   }
+  C[(size_t)row * ldc + col] = R(v);
 }
 
 template <typename R, bool AT = true>
 static void gemm(const R* A, int lda, const R* B, int ldb, R* C, int ldc, int M, int N, int K, const EpiArgs& e,
                  hipStream_t s) {
-  dim3 grid((N + 31) / 32, (M + 31) / 32);
+  dim3 grid((N + 15) / 16, (M + 15) / 16);
   hipLaunchKernelGGL((k_gemm<R, AT>), grid, dim3(256), 0, s, A, lda, B, ldb, C, ldc, M, N, K, e);
 }
 

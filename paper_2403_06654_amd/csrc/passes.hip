@@ -52,13 +52,19 @@ enum ColMode {
   COL_H_LAST,       // Q2, v -> Fz Q2 + nu |k|^2 M v
 };
 
+// Lines of 512 points: points per thread and threads per block (the tile is
+// NT / (512 / E) columns wide, and holds that many lines in LDS).
+template <typename R>
+constexpr int kColE512 = 16;
+constexpr int kColNT512 = 256;
+
 template <int L, typename R, int MODE>
 struct ColCfg {
   static constexpr bool E8 = sizeof(R) == 8 && L < 512 && MODE != COL_P_LAST && MODE != COL_P_MIDFWD;
-  static constexpr int E = E8 ? (L >= 8 ? 8 : L) : (L >= 16 ? 16 : L);
+  static constexpr int E = L == 512 ? kColE512<R> : E8 ? (L >= 8 ? 8 : L) : (L >= 16 ? 16 : L);
   static constexpr int T = L / E;
-  static constexpr int TC = 256 / T;  // columns per tile (256 threads)
-  static constexpr int NT = 256;
+  static constexpr int NT = L == 512 ? kColNT512 : 256;  // threads per block
+  static constexpr int TC = NT / T;                      // columns per tile
 };
 
 template <int L, typename R>
@@ -119,7 +125,7 @@ __device__ __forceinline__ void col_store(const C2<R>* reg, C2<R>* p, size_t bas
 }
 
 template <int L, typename R, int MODE>
-__global__ __launch_bounds__(256) void k_col(ColArgs a, const C2<R>* __restrict__ twtab) {
+__global__ __launch_bounds__((ColCfg<L, R, MODE>::NT)) void k_col(ColArgs a, const C2<R>* __restrict__ twtab) {
   using Cf = ColCfg<L, R, MODE>;
   constexpr int E = Cf::E, T = Cf::T, TC = Cf::TC;
   using S = Sched<L, E>;
@@ -526,7 +532,7 @@ static void launch_col_L(const ColArgs& a0, const void* tw, hipStream_t st) {
   ColArgs a = a0;
   a.ntile = (a.inner + ColCfg<L, R, MODE>::TC - 1) / ColCfg<L, R, MODE>::TC;
   dim3 grid(a.outer * a.ntile);
-  hipLaunchKernelGGL((k_col<L, R, MODE>), grid, dim3(256), 0, st, a, (const C2<R>*)tw);
+  hipLaunchKernelGGL((k_col<L, R, MODE>), grid, dim3(ColCfg<L, R, MODE>::NT), 0, st, a, (const C2<R>*)tw);
 }
 
 template <typename R, int MODE>

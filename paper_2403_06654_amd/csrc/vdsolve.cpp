@@ -456,19 +456,18 @@ struct Krylov {
   // rz = (r, M^-1 r); then p = M^-1 r (restart, never gated) or
   // p = M^-1 r + beta p
   void rz_and_p(const void* r, void* p, bool restart, const int* gate = nullptr) {
+    const Post beta{POST_CG_BETA, G->dst};  // rz = red[0] (the reduction's launch takes the step)
     if (dense_prec()) {
       const void* z = materialise_prec(r, gate);
       VecPtrs P{};
       P.p[0] = r;
-      mdot<R>(g, z, P, 1, false, G->partial, G->dst->red, G->st, nullptr, gate);
-      cg_beta(G->dst, G->st, gate);
+      mdot<R>(g, z, P, 1, false, G->partial, G->dst->red, G->st, nullptr, gate, beta);
       if (restart) ck(hipMemcpyAsync(p, z, G->nspec * elem_bytes(prec), hipMemcpyDeviceToDevice, G->st));
       else cg_p<R>(g, ident(gate), p, z, G->dst, G->st);
       return;
     }
     const OpParams op = gated(gate);
-    dot_rMr<R>(g, op, r, G->partial, G->dst->red, G->st);
-    cg_beta(G->dst, G->st, gate);  // rz = red[0]
+    dot_rMr<R>(g, op, r, G->partial, G->dst->red, G->st, beta);
     if (!restart) cg_p<R>(g, op, p, r, G->dst, G->st);
     else if (op.precond) precond_apply<R>(g, op, r, p, G->st);
     else ck(hipMemcpyAsync(p, r, G->nspec * elem_bytes(prec), hipMemcpyDeviceToDevice, G->st));
@@ -534,10 +533,8 @@ struct Krylov {
         apply(p, q, false, nullptr, gate);
         VecPtrs P{};
         P.p[0] = p;
-        mdot<R>(g, q, P, 1, false, G->partial, G->dst->red, G->st, nullptr, gate);
-        cg_alpha(G->dst, G->st, gate);
-        cg_xr<R>(g, x, r, p, q, G->dst, G->partial, &G->dst->nrm2, G->st, gate);
-        rec_check(G->dst, G->st, gate);
+        mdot<R>(g, q, P, 1, false, G->partial, G->dst->red, G->st, nullptr, gate, Post{POST_CG_ALPHA, G->dst});
+        cg_xr<R>(g, x, r, p, q, G->dst, G->partial, &G->dst->nrm2, G->st, gate, Post{POST_REC_CHECK, G->dst});
       }, [&] { return norm_from_sq(G->hst->nrm2) / bnorm; });
       if (G->hst->bad || !(G->hst->nrm2 == G->hst->nrm2)) { o.status = VD_EBREAKDOWN; return o; }
       if (cfg.inner) {
@@ -566,11 +563,10 @@ struct Krylov {
         apply(r, w, true, nullptr, gate);  // w = A M^-1 r
         VecPtrs P{};
         P.p[0] = r;
-        mdot<R>(g, w, P, 1, true, G->partial, G->dst->red, G->st, nullptr, gate);
-        rmr_alpha(G->dst, G->st, gate);
+        mdot<R>(g, w, P, 1, true, G->partial, G->dst->red, G->st, nullptr, gate, Post{POST_RMR_ALPHA, G->dst});
         prec_axpy(x, r, &G->dst->alpha, gate);
-        axpy_norm<R>(g, r, w, &G->dst->alpha, -1.0, G->partial, &G->dst->nrm2, G->st, gate);
-        rec_check(G->dst, G->st, gate);
+        axpy_norm<R>(g, r, w, &G->dst->alpha, -1.0, G->partial, &G->dst->nrm2, G->st, gate,
+                     Post{POST_REC_CHECK, G->dst});
       }, [&] { return norm_from_sq(G->hst->nrm2) / bnorm; });
       if (G->hst->bad || !(G->hst->nrm2 == G->hst->nrm2)) { o.status = VD_EBREAKDOWN; return o; }
       if (cfg.inner) {

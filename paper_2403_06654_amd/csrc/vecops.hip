@@ -69,17 +69,56 @@ __device__ __forceinline__ void reduce_values(const double* __restrict__ partial
   }
 }
 
+// Scalar steps of CG and RMR, taken by one thread on the reduced values.
+__device__ __forceinline__ void cg_alpha_step(DevState* st) {  // alpha = rz / (p, A p)
+  const double pq = st->red[0];
+  st->alpha = pq != 0.0 ? st->rz / pq : 0.0;
+  if (!isfinite(st->alpha) || pq <= 0.0) st->bad = 1;
+}
+__device__ __forceinline__ void cg_beta_step(DevState* st) {  // beta = (r, M r)_new / (r, M r)
+  const double rzn = st->red[0];
+  st->beta = st->rz != 0.0 ? rzn / st->rz : 0.0;
+  st->rz = rzn;
+  if (!isfinite(st->beta)) st->bad = 1;
+}
+__device__ __forceinline__ void rmr_alpha_step(DevState* st) {  // alpha = (r, w) / (w, w)
+  const double ww = st->red[1];
+  st->alpha = ww > 0.0 ? st->red[0] / ww : 0.0;
+  if (!isfinite(st->alpha)) st->bad = 1;
+}
+// Stopping test of a CG or RMR step on its recursive residual (st->nrm2),
+// the host loop's test taken on the device: a non-finite scalar, the
+// tolerance, or the last step of the run sets halt.  step counts the steps.
+__device__ __forceinline__ void rec_check_step(DevState* st) {
+  const int j = st->step;
+  st->step = j + 1;
+  const double n2 = st->nrm2;
+  const double rn = n2 < 0.0 ? 0.0 : sqrt(n2);
+  if (st->bad || !(n2 == n2) || rn / st->stop_bnorm <= st->stop_rtol || j >= st->jlast) st->halt = 1;
+}
+
+// The final reduction, optionally followed (same launch, after a block
+// barrier) by the scalar step that consumes its result: one launch less per
+// step than a separate one-thread kernel.
 __global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ partial, int nblk, int K, double scale,
-                                                 double* __restrict__ out, const int* __restrict__ gate) {
+                                                 double* __restrict__ out, const int* __restrict__ gate, int post,
+                                                 DevState* st) {
   if (gate && *gate) return;
   reduce_values(partial, nblk, K, scale, out);
+  if (post == POST_NONE) return;
+  __syncthreads();
+  if (threadIdx.x) return;
+  if (post == POST_CG_ALPHA) cg_alpha_step(st);
+  else if (post == POST_CG_BETA) cg_beta_step(st);
+  else if (post == POST_RMR_ALPHA) rmr_alpha_step(st);
+  else if (post == POST_REC_CHECK) rec_check_step(st);
 }
 
 // gate (here and below): optional device flag; when nonzero the launch does
 // nothing (a Krylov step queued past the end of its run)
 static void reduce(const double* partial, int nb, int K, double scale, double* out, hipStream_t s,
-                   const int* gate = nullptr) {
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, partial, nb, K, scale, out, gate);
+                   const int* gate = nullptr, const Post& post = Post{}) {
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, partial, nb, K, scale, out, gate, post.op, post.st);
 }
 
 static size_t nspec(const Geom& g) { return (size_t)g.nz * g.ny * g.M; }
@@ -147,10 +186,10 @@ static void mdot_partials(const Geom& g, const void* x, const VecPtrs& V, int nv
 
 template <typename R>
 void mdot(const Geom& g, const void* x, const VecPtrs& V, int nv, bool want_norm, double* partial, double* out,
-          hipStream_t s, Prof* prof, const int* gate) {
+          hipStream_t s, Prof* prof, const int* gate, const Post& post) {
   mdot_partials<R>(g, x, V, nv, want_norm, partial, s, gate);
   if (prof) prof->end(s);
-  reduce(partial, nblk(nspec(g)), nv + (want_norm ? 1 : 0), g.ntot_inv, out, s, gate);
+  reduce(partial, nblk(nspec(g)), nv + (want_norm ? 1 : 0), g.ntot_inv, out, s, gate, post);
 }
 
 // ------------------------------------------------ Gram-Schmidt (GMRES)
@@ -500,10 +539,11 @@ __global__ __launch_bounds__(256) void k_dot_rMr(const C2<R>* __restrict__ r, Ge
   block_store<1>(&acc, 1, partial + blockIdx.x);
 }
 template <typename R>
-void dot_rMr(const Geom& g, const OpParams& p, const void* r, double* partial, double* out, hipStream_t s) {
+void dot_rMr(const Geom& g, const OpParams& p, const void* r, double* partial, double* out, hipStream_t s,
+             const Post& post) {
   hipLaunchKernelGGL((k_dot_rMr<R>), dim3(nblk(nspec(g))), dim3(256), 0, s, (const C2<R>*)r, g,
                      p.precond ? p.kind : -1, p.rho0, p.nu, nspec(g), partial, p.gate);
-  reduce(partial, nblk(nspec(g)), 1, g.ntot_inv, out, s, p.gate);
+  reduce(partial, nblk(nspec(g)), 1, g.ntot_inv, out, s, p.gate, post);
 }
 
 template <typename R>
@@ -525,10 +565,10 @@ __global__ __launch_bounds__(256) void k_cg_xr(C2<R>* __restrict__ x, C2<R>* __r
 }
 template <typename R>
 void cg_xr(const Geom& g, void* x, void* r, const void* p, const void* q, const DevState* st, double* partial,
-           double* out, hipStream_t s, const int* gate) {
+           double* out, hipStream_t s, const int* gate, const Post& post) {
   hipLaunchKernelGGL((k_cg_xr<R>), dim3(nblk(nspec(g))), dim3(256), 0, s, (C2<R>*)x, (C2<R>*)r, (const C2<R>*)p,
                      (const C2<R>*)q, st, nspec(g), g.M, partial, gate);
-  reduce(partial, nblk(nspec(g)), 1, g.ntot_inv, out, s, gate);
+  reduce(partial, nblk(nspec(g)), 1, g.ntot_inv, out, s, gate, post);
 }
 
 template <typename R>
@@ -566,10 +606,10 @@ __global__ __launch_bounds__(256) void k_axpy_norm(C2<R>* __restrict__ r, const 
 }
 template <typename R>
 void axpy_norm(const Geom& g, void* r, const void* w, const double* a_dev, double sign, double* partial, double* out,
-               hipStream_t s, const int* gate) {
+               hipStream_t s, const int* gate, const Post& post) {
   hipLaunchKernelGGL((k_axpy_norm<R>), dim3(nblk(nspec(g))), dim3(256), 0, s, (C2<R>*)r, (const C2<R>*)w, a_dev, sign,
                      nspec(g), g.M, partial, gate);
-  reduce(partial, nblk(nspec(g)), 1, g.ntot_inv, out, s, gate);
+  reduce(partial, nblk(nspec(g)), 1, g.ntot_inv, out, s, gate, post);
 }
 
 // ---------------------------------------------------------------- casts
@@ -674,22 +714,15 @@ __global__ void k_gmres_backsolve(DevState* st, int k) {
 
 __global__ void k_cg_alpha(DevState* st, const int* gate) {
   if (threadIdx.x || (gate && *gate)) return;
-  const double pq = st->red[0];
-  st->alpha = pq != 0.0 ? st->rz / pq : 0.0;
-  if (!isfinite(st->alpha) || pq <= 0.0) st->bad = 1;
+  cg_alpha_step(st);
 }
 __global__ void k_cg_beta(DevState* st, const int* gate) {
   if (threadIdx.x || (gate && *gate)) return;
-  const double rzn = st->red[0];
-  st->beta = st->rz != 0.0 ? rzn / st->rz : 0.0;
-  st->rz = rzn;
-  if (!isfinite(st->beta)) st->bad = 1;
+  cg_beta_step(st);
 }
 __global__ void k_rmr_alpha(DevState* st, const int* gate) {
   if (threadIdx.x || (gate && *gate)) return;
-  const double ww = st->red[1];
-  st->alpha = ww > 0.0 ? st->red[0] / ww : 0.0;
-  if (!isfinite(st->alpha)) st->bad = 1;
+  rmr_alpha_step(st);
 }
 
 void gmres_init(DevState* st, double beta, int m, double bnorm, double rtol, int jlast, hipStream_t s) {
@@ -708,16 +741,9 @@ void rmr_alpha(DevState* st, hipStream_t s, const int* gate) {
   hipLaunchKernelGGL(k_rmr_alpha, dim3(1), dim3(64), 0, s, st, gate);
 }
 
-// Stopping test of a CG or RMR step on its recursive residual (st->nrm2),
-// the host loop's test taken on the device: a non-finite scalar, the
-// tolerance, or the last step of the run sets halt.  step counts the steps.
 __global__ void k_rec_check(DevState* st, const int* gate) {
   if (threadIdx.x || (gate && *gate)) return;
-  const int j = st->step;
-  st->step = j + 1;
-  const double n2 = st->nrm2;
-  const double rn = n2 < 0.0 ? 0.0 : sqrt(n2);
-  if (st->bad || !(n2 == n2) || rn / st->stop_bnorm <= st->stop_rtol || j >= st->jlast) st->halt = 1;
+  rec_check_step(st);
 }
 __global__ void k_rec_init(DevState* st, double bnorm, double rtol, int jlast) {
   if (threadIdx.x) return;
@@ -830,7 +856,7 @@ void kcoef_finish(const double* rho, const double* lap_psi, double* kc64, float*
 
 #define VD_INST(R)                                                                                             \
   template void mdot<R>(const Geom&, const void*, const VecPtrs&, int, bool, double*, double*, hipStream_t,    \
-                        Prof*, const int*);                                                                    \
+                        Prof*, const int*, const Post&);                                                       \
   template void lincomb<R>(const Geom&, void*, const VecPtrs&, int, const double*, hipStream_t);               \
   template void scale<R>(const Geom&, void*, const double*, double, hipStream_t);                              \
   template void gs_orthogonalize<R>(const Geom&, void*, const VecPtrs&, int, DevState*, double*, hipStream_t,  \
@@ -838,12 +864,13 @@ void kcoef_finish(const double* rho, const double* lap_psi, double* kc64, float*
   template void sub_norm<R>(const Geom&, const void*, const void*, void*, double*, double*, hipStream_t);      \
   template void precond_axpy<R>(const Geom&, const OpParams&, void*, const void*, const double*, double,       \
                                 hipStream_t);                                                                  \
-  template void dot_rMr<R>(const Geom&, const OpParams&, const void*, double*, double*, hipStream_t);          \
+  template void dot_rMr<R>(const Geom&, const OpParams&, const void*, double*, double*, hipStream_t,           \
+                           const Post&);                                                                       \
   template void cg_xr<R>(const Geom&, void*, void*, const void*, const void*, const DevState*, double*,       \
-                         double*, hipStream_t, const int*);                                                    \
+                         double*, hipStream_t, const int*, const Post&);                                       \
   template void cg_p<R>(const Geom&, const OpParams&, void*, const void*, const DevState*, hipStream_t);       \
   template void axpy_norm<R>(const Geom&, void*, const void*, const double*, double, double*, double*,         \
-                             hipStream_t, const int*);
+                             hipStream_t, const int*, const Post&);
 
 VD_INST(double)
 VD_INST(float)

@@ -48,11 +48,23 @@ struct DevState {
   int halt;                  // the cycle or run has ended; gated kernels return at once
 };
 
+// A scalar step of CG or RMR that the final reduction of a vector kernel
+// takes in its own launch once the reduced value is written (st: the
+// solver's device state): alpha = rz / red[0] (CG), beta = red[0] / rz and
+// rz = red[0] (CG), alpha = red[0] / red[1] (RMR), or the stopping test on
+// nrm2 (CG and RMR; see rec_check).  The same steps exist as separate
+// launches (cg_alpha, ...).
+enum PostOp { POST_NONE = 0, POST_CG_ALPHA, POST_CG_BETA, POST_RMR_ALPHA, POST_REC_CHECK };
+struct Post {
+  int op = POST_NONE;
+  DevState* st = nullptr;
+};
+
 // partial[b][i] = sum_e w_e Re(conj(V_i[e]) x[e]) (i < nv), plus |x|^2 at
 // index nv when want_norm.  Then reduce into st->red (times 1/N).
 template <typename R>
 void mdot(const Geom& g, const void* x, const VecPtrs& V, int nv, bool want_norm, double* partial,
-          double* out, hipStream_t s, Prof* prof = nullptr, const int* gate = nullptr);
+          double* out, hipStream_t s, Prof* prof = nullptr, const int* gate = nullptr, const Post& post = Post{});
 
 // GMRES step: orthogonalise w against the stored basis V_0..V_{nv-1}
 // (v_i = vs[i] V_i) in place; classical Gram-Schmidt with a measured
@@ -87,19 +99,19 @@ void precond_axpy(const Geom& g, const OpParams& p, void* x, const void* z, cons
 // (r, M^-1 r) reduced into out[0]
 template <typename R>
 void dot_rMr(const Geom& g, const OpParams& p, const void* r, double* partial, double* out,
-             hipStream_t s);
+             hipStream_t s, const Post& post = Post{});
 
 // CG: x += alpha p; r -= alpha q; |r|^2 -> out[0]   (alpha = st->alpha)
 template <typename R>
 void cg_xr(const Geom& g, void* x, void* r, const void* p, const void* q, const DevState* st,
-           double* partial, double* out, hipStream_t s, const int* gate = nullptr);
+           double* partial, double* out, hipStream_t s, const int* gate = nullptr, const Post& post = Post{});
 // CG: p = M^-1 r + beta p   (beta = st->beta)
 template <typename R>
 void cg_p(const Geom& g, const OpParams& op, void* p, const void* r, const DevState* st, hipStream_t s);
 // RMR: r -= alpha w; |r|^2 -> out[0]
 template <typename R>
 void axpy_norm(const Geom& g, void* r, const void* w, const double* a_dev, double sign, double* partial,
-               double* out, hipStream_t s, const int* gate = nullptr);
+               double* out, hipStream_t s, const int* gate = nullptr, const Post& post = Post{});
 
 // precision casts between spectral vectors: dst(float) = src(double) * s
 void cast_d2f(const Geom& g, const void* src, void* dst, double s, hipStream_t st);

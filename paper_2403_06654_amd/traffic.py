@@ -1,8 +1,10 @@
-"""Turn two rocprofv3 --pmc runs of `bench.py --workload pmc` (FETCH_SIZE,
-then WRITE_SIZE) into calibrated HBM bytes per launch of the timed kernel
-classes, stored in profiles/traffic_counters.json for bench.py's roofline.
+"""Turn two rocprofv3 --pmc runs of `bench.py --workload pmc` (256^3) or
+`--workload pmc5` (512^3) (FETCH_SIZE, then WRITE_SIZE) into calibrated HBM
+bytes per launch of the timed kernel classes, stored in
+profiles/traffic_counters.json (256^3) or profiles/traffic_counters_c5.json
+(512^3) for bench.py's roofline.
 
-    python -m paper_2403_06654_amd.traffic FETCH_DIR WRITE_DIR
+    python -m paper_2403_06654_amd.traffic FETCH_DIR WRITE_DIR [512]
 
 Calibration: the first device copy of the run moves exactly 1 GiB each way;
 the ratio of that to what each counter reports for it scales every other
@@ -19,20 +21,33 @@ import sys
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 
-CLASS_PATTERNS = {
-    "gmres gram-schmidt update (k_gs_update)": r"^void vd::k_gs_update<double,",
-    "pressure x pass (k_row ROW_P)": r"^void vd::k_row<128, double, 2>",
-    # the other passes of the 256^3 FP64 operator applications
-    "pressure z-first (k_col COL_P_FIRST)": r"^void vd::k_col<256, double, 2>",
-    "pressure y-inverse (k_col COL_P_MIDINV)": r"^void vd::k_col<256, double, 3>",
-    "pressure y-forward (k_col COL_P_MIDFWD)": r"^void vd::k_col<256, double, 4>",
-    "pressure z-last (k_col COL_P_LAST)": r"^void vd::k_col<256, double, 5>",
-    "helmholtz z-first (k_col COL_H_FIRST)": r"^void vd::k_col<256, double, 6>",
-    "y inverse FFT, one field (k_col COL_FFT_INV)": r"^void vd::k_col<256, double, 1>",
-    "helmholtz x pass (k_row ROW_H)": r"^void vd::k_row<128, double, 4>",
-    "y forward FFT, one field (k_col COL_FFT_FWD)": r"^void vd::k_col<256, double, 0>",
-    "helmholtz z-last (k_col COL_H_LAST)": r"^void vd::k_col<256, double, 7>",
-}
+def class_patterns(n=256):
+    """Kernel-name patterns of the timed classes on an n^3 grid (column
+    passes of length n, row passes of n/2 complex points)."""
+    c, r = n, n // 2
+    return {
+        "gmres gram-schmidt update (k_gs_update)": r"^void vd::k_gs_update<double,",
+        "gmres gram-schmidt dots (k_mdot)": r"^void vd::k_mdot<double, (?!1>)",
+        "pressure x pass (k_row ROW_P)": rf"^void vd::k_row<{r}, double, 2>",
+        "pressure z-first (k_col COL_P_FIRST)": rf"^void vd::k_col<{c}, double, 2>",
+        "pressure y-inverse (k_col COL_P_MIDINV)": rf"^void vd::k_col<{c}, double, 3>",
+        "pressure y-forward (k_col COL_P_MIDFWD)": rf"^void vd::k_col<{c}, double, 4>",
+        "pressure z-last (k_col COL_P_LAST)": rf"^void vd::k_col<{c}, double, 5>",
+        "helmholtz z-first (k_col COL_H_FIRST)": rf"^void vd::k_col<{c}, double, 6>",
+        "y inverse FFT, one field (k_col COL_FFT_INV)": rf"^void vd::k_col<{c}, double, 1>",
+        "helmholtz x pass (k_row ROW_H)": rf"^void vd::k_row<{r}, double, 4>",
+        "y forward FFT, one field (k_col COL_FFT_FWD)": rf"^void vd::k_col<{c}, double, 0>",
+        "helmholtz z-last (k_col COL_H_LAST)": rf"^void vd::k_col<{c}, double, 7>",
+        # FP32 operator passes (the inner solves of iterative refinement)
+        "fp32 pressure z-first (k_col COL_P_FIRST)": rf"^void vd::k_col<{c}, float, 2>",
+        "fp32 pressure y-inverse (k_col COL_P_MIDINV)": rf"^void vd::k_col<{c}, float, 3>",
+        "fp32 pressure x pass (k_row ROW_P)": rf"^void vd::k_row<{r}, float, 2>",
+        "fp32 pressure y-forward (k_col COL_P_MIDFWD)": rf"^void vd::k_col<{c}, float, 4>",
+        "fp32 pressure z-last (k_col COL_P_LAST)": rf"^void vd::k_col<{c}, float, 5>",
+    }
+
+
+CLASS_PATTERNS = class_patterns(256)
 
 
 def _rows(d):
@@ -40,7 +55,7 @@ def _rows(d):
     return list(csv.DictReader(open(path)))
 
 
-def summarize(F, W, source_hash):
+def summarize(F, W, source_hash, patterns=None):
     """Calibrated per-launch HBM bytes of the timed kernel classes from the
     FETCH_SIZE rows F and the WRITE_SIZE rows W (rocprofv3 counter CSV rows,
     in dispatch order)."""
@@ -52,7 +67,7 @@ def summarize(F, W, source_hash):
     out = {"csrc_sha256_16": source_hash, "calibration": {"copy_bytes": copy_bytes, "fetch_factor": kf,
                                                            "write_factor": kw},
            "per_launch_bytes": {}, "launches": {}}
-    for name, pat in CLASS_PATTERNS.items():
+    for name, pat in (patterns or CLASS_PATTERNS).items():
         fv = [float(r["Counter_Value"]) * 1024 * kf for r in F if re.match(pat, r["Kernel_Name"])]
         wv = [float(r["Counter_Value"]) * 1024 * kw for r in W if re.match(pat, r["Kernel_Name"])]
         if fv and len(fv) == len(wv):
@@ -68,13 +83,15 @@ def summarize(F, W, source_hash):
     return out
 
 
-def main(fetch_dir, write_dir):
+def main(fetch_dir, write_dir, n=256):
     from bench import csrc_hash  # noqa: E402
-    out = summarize(_rows(fetch_dir), _rows(write_dir), csrc_hash())
-    path = os.path.join(ROOT, "profiles", "traffic_counters.json")
+    out = summarize(_rows(fetch_dir), _rows(write_dir), csrc_hash(), class_patterns(n))
+    out["grid"] = n
+    name = "traffic_counters.json" if n == 256 else f"traffic_counters_c{5 if n == 512 else n}.json"
+    path = os.path.join(ROOT, "profiles", name)
     json.dump(out, open(path, "w"), indent=1)
     print(json.dumps(out, indent=1))
 
 
 if __name__ == "__main__":
-    main(sys.argv[1], sys.argv[2])
+    main(sys.argv[1], sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 256)

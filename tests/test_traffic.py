@@ -25,3 +25,12 @@ def test_calibration_and_gated_dispatches():
     assert out["per_launch_bytes"][name] == round(((1000 + 3000) * 2 + (100 + 300)) * 1024 / 2)
     xname = "pressure x pass (k_row ROW_P)"
     assert out["launches"][xname] == 1 and out["per_launch_bytes"][xname] == (400 * 2 + 200) * 1024
+
+
+def test_class_patterns_follow_the_grid():
+    p5 = traffic.class_patterns(512)
+    assert p5["pressure x pass (k_row ROW_P)"].endswith("k_row<256, double, 2>")
+    assert p5["pressure z-last (k_col COL_P_LAST)"].endswith("k_col<512, double, 5>")
+    import re
+    assert re.match(p5["gmres gram-schmidt dots (k_mdot)"], "void vd::k_mdot<double, 16>(x)")
+    assert not re.match(p5["gmres gram-schmidt dots (k_mdot)"], "void vd::k_mdot<double, 1>(x)")
