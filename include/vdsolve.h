@@ -185,6 +185,14 @@ vd_status vd_solve_helmholtz(vd_grid* grid, double dt_nu, int ncomp, const doubl
  * invalid options; opts == NULL means defaults. */
 size_t vd_workspace_bytes(const vd_grid_desc* desc, const vd_solve_opts* opts);
 
+/* The same for vd_solve_helmholtz with ncomp components.  With GMRES on a
+ * Fourier grid of two or three dimensions, up to three components are
+ * solved together (one launch per operator pass and per Gram-Schmidt kernel
+ * for all of them), each with its own Krylov vectors; their results are
+ * those of separate solves.  Otherwise equal to vd_workspace_bytes.
+ * Returns 0 where vd_workspace_bytes does, or for ncomp < 1. */
+size_t vd_workspace_bytes_helmholtz(const vd_grid_desc* desc, const vd_solve_opts* opts, int ncomp);
+
 /* Time spent in each hot kernel since the last read, measured with HIP
  * events on the grid's stream while enabled.  Classes 0..4: the pressure
  * operator's z-first, y-inverse, x, y-forward and z-last passes; 5..9: the

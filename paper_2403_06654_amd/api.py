@@ -106,6 +106,8 @@ _SIGS = {
     "vd_solve_helmholtz": (_I, [_P, _D, _I, _P, _P, ctypes.POINTER(vd_solve_opts),
                                 ctypes.POINTER(vd_solve_info)]),
     "vd_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(vd_grid_desc), ctypes.POINTER(vd_solve_opts)]),
+    "vd_workspace_bytes_helmholtz": (ctypes.c_size_t, [ctypes.POINTER(vd_grid_desc), ctypes.POINTER(vd_solve_opts),
+                                                       ctypes.c_int]),
     "vd_profile_enable": (_I, [_P, _I]),
     "vd_profile_read": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(_D), _I]),
     "vd_status_string": (ctypes.c_char_p, [_I]),
@@ -219,9 +221,13 @@ def make_opts(solver="gmres", restart=30, rtol=1e-10, max_iter=2000, precond=Tru
     return o
 
 
-def workspace_bytes(shape, lengths=None, cheb=False, **opts):
+def workspace_bytes(shape, lengths=None, cheb=False, helmholtz_ncomp=None, **opts):
+    """Device bytes of a grid plus one solve; helmholtz_ncomp: of a velocity
+    solve with that many components (several are solved together)."""
     d = make_desc(shape, lengths, cheb)
     o = make_opts(**opts)
+    if helmholtz_ncomp is not None:
+        return int(lib().vd_workspace_bytes_helmholtz(ctypes.byref(d), ctypes.byref(o), int(helmholtz_ncomp)))
     return int(lib().vd_workspace_bytes(ctypes.byref(d), ctypes.byref(o)))
 
 

@@ -53,10 +53,14 @@ enum ColMode {
 };
 
 // Lines of 512 points: points per thread and threads per block (the tile is
-// NT / (512 / E) columns wide, and holds that many lines in LDS).
+// NT / (512 / E) columns wide, and holds that many lines in LDS).  Measured
+// at 512^3 (pressure operator, FP64 / FP32 ms): E = 16 with 256 threads
+// (8 columns) 5.50 / 3.44, with 512 threads (16 columns, 136 KiB of LDS in
+// FP64, one block per CU) 5.42 / 2.89; E = 8 with 1024 threads 5.63 / 2.91.
+// The wider tile writes longer contiguous runs per line segment.
 template <typename R>
 constexpr int kColE512 = 16;
-constexpr int kColNT512 = 256;
+constexpr int kColNT512 = 512;
 
 template <int L, typename R, int MODE>
 struct ColCfg {
@@ -102,6 +106,15 @@ struct ColArgs {
   int precond;
   const double* in_scale;
   const int* gate;  // nonzero *gate: the launch does nothing
+  // Batched launch (nb > 0): blockIdx.y selects field f of nb independent
+  // fields, with its own inputs, output, input scale and gate (the Helmholtz
+  // passes of several systems solved together; nf = 1 per field).
+  int nb;
+  const void* fin[kMaxBatch];
+  const void* fin2[kMaxBatch];
+  void* fout[kMaxBatch];
+  const double* fscale[kMaxBatch];
+  const int* fgate[kMaxBatch];
 };
 
 template <int L, int E, int RPAT, typename R>
@@ -124,6 +137,15 @@ __device__ __forceinline__ void col_store(const C2<R>* reg, C2<R>* p, size_t bas
   }
 }
 
+// Entry f of a per-field argument array by constant indices only: indexing
+// a by-value kernel argument with a run-time index makes the compiler copy
+// the whole argument block to scratch memory first.
+template <typename T>
+__device__ __forceinline__ T pick(const T (&v)[kMaxBatch], int f) {
+  static_assert(kMaxBatch == 3, "one select per entry");
+  return f == 0 ? v[0] : (f == 1 ? v[1] : v[2]);
+}
+
 template <int L, typename R, int MODE>
 __global__ __launch_bounds__((ColCfg<L, R, MODE>::NT)) void k_col(ColArgs a, const C2<R>* __restrict__ twtab) {
   using Cf = ColCfg<L, R, MODE>;
@@ -132,7 +154,14 @@ __global__ __launch_bounds__((ColCfg<L, R, MODE>::NT)) void k_col(ColArgs a, con
   constexpr int R0 = S::template first_radix<false>();
   constexpr int R1 = S::template last_radix<false>();
   constexpr int LDSN = S::npass > 1 ? TC * L : 1;
-  if (a.gate && *a.gate) return;  // whole grid: the flag is written before the launch
+  // this block's field: the launch's own pointers, or field blockIdx.y of a batch
+  const int fb = a.nb ? (int)blockIdx.y : 0;
+  const int* gate = a.nb ? pick(a.fgate, fb) : a.gate;
+  if (gate && *gate) return;  // the flag is written before the launch
+  const void* in0 = a.nb ? pick(a.fin, fb) : a.in[0];
+  const void* in1 = a.nb ? pick(a.fin2, fb) : a.in[1];
+  void* out0 = a.nb ? pick(a.fout, fb) : a.out[0];
+  const double* iscale = a.nb ? pick(a.fscale, fb) : a.in_scale;
   __shared__ C2<R> lds_raw[LDSN];
   // twiddle table staged in LDS (see k_row)
   __shared__ C2<R> tw_lds[L];
@@ -151,10 +180,11 @@ __global__ __launch_bounds__((ColCfg<L, R, MODE>::NT)) void k_col(ColArgs a, con
 
   if constexpr (MODE == COL_FFT_FWD || MODE == COL_FFT_INV) {
     constexpr int DIR = MODE == COL_FFT_FWD ? -1 : +1;
-    for (int f = 0; f < a.nf; ++f) {
-      col_load<L, E, R0>(reg, (const C2<R>*)a.in[f], base, a.inner, t, ok);
+    const int nf = a.nb ? 1 : a.nf;
+    for (int f = 0; f < nf; ++f) {
+      col_load<L, E, R0>(reg, (const C2<R>*)(f ? a.in[f] : in0), base, a.inner, t, ok);
       fft_line<L, E, DIR, false>(reg, lds, tw, t);
-      col_store<L, E, R1>(reg, (C2<R>*)a.out[f], base, a.inner, t, ok);
+      col_store<L, E, R1>(reg, (C2<R>*)(f ? a.out[f] : out0), base, a.inner, t, ok);
     }
   } else if constexpr (MODE == COL_P_FIRST) {
     // z pass: line index = kz; column = ky * M + kx
@@ -210,8 +240,8 @@ __global__ __launch_bounds__((ColCfg<L, R, MODE>::NT)) void k_col(ColArgs a, con
     constexpr bool FIRST = MODE == COL_H_FIRST;
     constexpr int RP = FIRST ? R0 : R1;  // pattern in which v is needed
     const int ky = col / a.g.M, kx = col % a.g.M;
-    const R sc = in_scale_of<R>(a.in_scale);
-    const C2<R>* v = (const C2<R>*)(FIRST ? a.in[0] : a.in[1]);
+    const R sc = in_scale_of<R>(iscale);
+    const C2<R>* v = (const C2<R>*)(FIRST ? in0 : in1);
     C2<R> mv[E];
     col_load<L, E, RP>(mv, v, base, a.inner, t, ok);
     const bool need_mirror = (kx == 0) && (a.precond || !FIRST);
@@ -243,13 +273,13 @@ __global__ __launch_bounds__((ColCfg<L, R, MODE>::NT)) void k_col(ColArgs a, con
     }
     if constexpr (FIRST) {
       fft_line<L, E, +1, false>(mv, lds, tw, t);
-      col_store<L, E, R1>(mv, (C2<R>*)a.out[0], base, a.inner, t, ok);
+      col_store<L, E, R1>(mv, (C2<R>*)out0, base, a.inner, t, ok);
     } else {
-      col_load<L, E, R0>(reg, (const C2<R>*)a.in[0], base, a.inner, t, ok);
+      col_load<L, E, R0>(reg, (const C2<R>*)in0, base, a.inner, t, ok);
       fft_line<L, E, -1, false>(reg, lds, tw, t);
 #pragma unroll
       for (int s = 0; s < E; ++s) reg[s] = reg[s] + mv[s];
-      col_store<L, E, R1>(reg, (C2<R>*)a.out[0], base, a.inner, t, ok);
+      col_store<L, E, R1>(reg, (C2<R>*)out0, base, a.inner, t, ok);
     }
   }
 }
@@ -263,6 +293,7 @@ enum RowMode {
   ROW_P1,       // 1D pressure: y = -i k'_x F(a F^-1(i k'_x M v))
   ROW_H,        // Helmholtz x pass (rho times), one field
   ROW_H1,       // 1D Helmholtz: y = F(rho F^-1(M v)) + nu k^2 M v
+  ROW_HB,       // Helmholtz x pass of nf <= 3 independent fields (one wavefront each), gate per field
 };
 
 struct RowArgs {
@@ -277,13 +308,17 @@ struct RowArgs {
   int precond;
   const double* in_scale;
   const int* gate;  // nonzero *gate: the launch does nothing
+  const int* fgate[kMaxBatch];  // ROW_HB: field f's gate
 };
 
 // Wavefronts per block: the pressure x pass runs its (up to three) fields as
-// one wavefront each over the same rows; the other modes run four
-// wavefronts over consecutive row groups.
+// one wavefront each over the same rows, and so does the batched Helmholtz
+// x pass (several systems); the other modes run four wavefronts over
+// consecutive row groups.
 template <int MODE>
-constexpr int row_waves() { return MODE == ROW_P ? 3 : 4; }
+constexpr bool row_field_waves() { return MODE == ROW_P || MODE == ROW_HB; }
+template <int MODE>
+constexpr int row_waves() { return row_field_waves<MODE>() ? 3 : 4; }
 
 template <int L, typename R, int MODE>
 __global__ __launch_bounds__(64 * row_waves<MODE>()) void k_row(RowArgs a, const C2<R>* __restrict__ twtab) {
@@ -295,7 +330,8 @@ __global__ __launch_bounds__(64 * row_waves<MODE>()) void k_row(RowArgs a, const
   constexpr int RF0 = S::template first_radix<true>();   // forward input pattern (== RI1)
   static_assert(RI1 == RF0, "pattern mismatch");
   constexpr int NW = row_waves<MODE>();
-  constexpr int RB = MODE == ROW_P ? RW : NW * RW;  // rows per block
+  constexpr bool FW = row_field_waves<MODE>();
+  constexpr int RB = FW ? RW : NW * RW;  // rows per block
   if (a.gate && *a.gate) return;
   __shared__ C2<R> lds_all[NW * RW * LP];
   // twiddle tables in LDS: a load in every butterfly pass from global memory
@@ -313,19 +349,27 @@ __global__ __launch_bounds__(64 * row_waves<MODE>()) void k_row(RowArgs a, const
   // field's pointers stay in scalar registers.
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
   const int lane = threadIdx.x % 64;
-  const int fsel = MODE == ROW_P ? wave : 0;
+  const int fsel = FW ? wave : 0;
+  // ROW_HB: a field whose system has stopped is skipped by its wavefront
+  // (after the block barrier above; the rest of the pass has wavefront-level
+  // synchronisation only)
+  if constexpr (MODE == ROW_HB) {
+    const int* fg = pick(a.fgate, fsel);
+    if (fg && *fg) return;
+  }
   const int t = lane % T;
-  const int rr = (MODE == ROW_P ? 0 : wave * RW) + lane / T;  // row within the block
+  const int rr = (FW ? 0 : wave * RW) + lane / T;  // row within the block
   // The x passes sweep the rows last block first: the pass before them (a
   // y pass, ascending z) leaves its most recent output in the 256 MB
   // Infinity Cache, and the y pass after them (ascending z again) starts on
   // what this pass wrote last.  At 256^3 FP64 the three pressure fields
   // (384 MiB) exceed that cache; the reversed sweep takes the x pass from
   // 218 to 199 us and the following y pass from 130 to 114 us.
-  const int bx = (MODE == ROW_P || MODE == ROW_H) ? (int)(gridDim.x - 1 - blockIdx.x) : (int)blockIdx.x;
+  const int bx = (MODE == ROW_P || MODE == ROW_H || MODE == ROW_HB) ? (int)(gridDim.x - 1 - blockIdx.x)
+                                                                   : (int)blockIdx.x;
   const int row = bx * RB + rr;
   const bool ok = row < a.nrows;
-  LdsRow<R> lds{lds_all + (MODE == ROW_P ? fsel * RW + rr : rr) * LP};
+  LdsRow<R> lds{lds_all + (FW ? fsel * RW + rr : rr) * LP};
   const R sx = R(a.g.sx);
   C2<R> reg[E];
 
@@ -531,7 +575,7 @@ template <typename R, int MODE, int L>
 static void launch_col_L(const ColArgs& a0, const void* tw, hipStream_t st) {
   ColArgs a = a0;
   a.ntile = (a.inner + ColCfg<L, R, MODE>::TC - 1) / ColCfg<L, R, MODE>::TC;
-  dim3 grid(a.outer * a.ntile);
+  dim3 grid(a.outer * a.ntile, a.nb > 0 ? a.nb : 1);
   hipLaunchKernelGGL((k_col<L, R, MODE>), grid, dim3(ColCfg<L, R, MODE>::NT), 0, st, a, (const C2<R>*)tw);
 }
 
@@ -552,9 +596,10 @@ static void launch_col(int L, const ColArgs& a, const void* tw, hipStream_t st) 
 template <typename R, int MODE, int L>
 static void launch_row_L(const RowArgs& a, const void* tw, hipStream_t st) {
   constexpr int RW = RowCfg<L, R>::RW;
-  const int rb = MODE == ROW_P ? RW : row_waves<MODE>() * RW;
+  const int rb = row_field_waves<MODE>() ? RW : row_waves<MODE>() * RW;
   dim3 grid((a.nrows + rb - 1) / rb);
-  const int waves = MODE == ROW_P ? a.nf : row_waves<MODE>();  // ROW_P: one wavefront per field (<= 3)
+  // ROW_P, ROW_HB: one wavefront per field (<= 3)
+  const int waves = row_field_waves<MODE>() ? a.nf : row_waves<MODE>();
   hipLaunchKernelGGL((k_row<L, R, MODE>), grid, dim3(64 * waves), 0, st, a, (const C2<R>*)tw);
 }
 
@@ -726,6 +771,78 @@ void op_apply(const Geom& g, const OpParams& p, const void* v, void* y, const Op
 }
 
 template <typename R>
+void op_apply_helm_batch(const Geom& g, const OpParams& p, const OpBatch& b, const void* coef, const void* twtab,
+                         hipStream_t st, Prof* prof) {
+  const int nb = b.nb;
+  const bool pr = prof && prof->on;
+  const double fb = (double)g.nz * g.ny * g.M * sizeof(C2<R>);  // one field
+  const size_t zin = (size_t)g.ny * g.M;
+  // per-field inputs, outputs, scales and gates of a column launch
+  auto cset = [&](ColArgs& a, const void* const* in, const void* const* in2, void* const* out, bool scaled) {
+    a.gate = nullptr;
+    a.in_scale = nullptr;
+    a.nb = nb;
+    for (int f = 0; f < nb; ++f) {
+      a.fin[f] = in[f];
+      a.fin2[f] = in2 ? in2[f] : nullptr;
+      a.fout[f] = out[f];
+      a.fscale[f] = scaled ? b.in_scale[f] : nullptr;
+      a.fgate[f] = b.gate[f];
+    }
+  };
+  const void* tin[kMaxBatch];
+  for (int f = 0; f < nb; ++f) tin[f] = b.t[f];
+  ColArgs a = col_args(g, &p);
+  a.outer = 1;
+  a.inner = (int)zin;
+  cset(a, b.v, nullptr, b.t, true);
+  if (pr) prof->begin(5, st, 2 * nb * fb);
+  launch_col<R, COL_H_FIRST>(g.nz, a, twtab, st);
+  if (pr) prof->end(st);
+  if (g.ny > 1) {
+    ColArgs c = col_args_fft(g, p);
+    c.outer = g.nz;
+    c.inner = g.M;
+    c.nf = 1;
+    cset(c, tin, nullptr, b.t, false);
+    if (pr) prof->begin(6, st, 2 * nb * fb);
+    launch_col<R, COL_FFT_INV>(g.ny, c, twtab, st);
+    if (pr) prof->end(st);
+  }
+  RowArgs r = row_args(g, &p);
+  r.gate = nullptr;
+  r.in_scale = nullptr;
+  r.nf = nb;
+  for (int f = 0; f < nb; ++f) {
+    r.in[f] = b.t[f];
+    r.out[f] = b.t[f];
+    r.fgate[f] = b.gate[f];
+  }
+  r.coef = coef;
+  r.cscale = g.ntot_inv;
+  if (pr) prof->begin(7, st, (2 * nb + 1) * fb);  // the coefficient row is read once for every field
+  launch_row<R, ROW_HB>(g.M, r, twtab, st);
+  if (pr) prof->end(st);
+  if (g.ny > 1) {
+    ColArgs c = col_args_fft(g, p);
+    c.outer = g.nz;
+    c.inner = g.M;
+    c.nf = 1;
+    cset(c, tin, nullptr, b.t, false);
+    if (pr) prof->begin(8, st, 2 * nb * fb);
+    launch_col<R, COL_FFT_FWD>(g.ny, c, twtab, st);
+    if (pr) prof->end(st);
+  }
+  ColArgs d = col_args(g, &p);
+  d.outer = 1;
+  d.inner = (int)zin;
+  cset(d, tin, b.v, b.y, true);
+  if (pr) prof->begin(9, st, 3 * nb * fb);
+  launch_col<R, COL_H_LAST>(g.nz, d, twtab, st);
+  if (pr) prof->end(st);
+}
+
+template <typename R>
 void precond_apply(const Geom& g, const OpParams& p, const void* r, void* z, hipStream_t st) {
   size_t n = (size_t)g.nz * g.ny * g.M;
   hipLaunchKernelGGL((k_precond<R>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (const C2<R>*)r,
@@ -882,6 +999,10 @@ template void op_apply<double>(const Geom&, const OpParams&, const void*, void*,
                                const void*, hipStream_t, Prof*);
 template void op_apply<float>(const Geom&, const OpParams&, const void*, void*, const OpWork&, const void*,
                               const void*, hipStream_t, Prof*);
+template void op_apply_helm_batch<double>(const Geom&, const OpParams&, const OpBatch&, const void*, const void*,
+                                          hipStream_t, Prof*);
+template void op_apply_helm_batch<float>(const Geom&, const OpParams&, const OpBatch&, const void*, const void*,
+                                         hipStream_t, Prof*);
 template void precond_apply<double>(const Geom&, const OpParams&, const void*, void*, hipStream_t);
 template void precond_apply<float>(const Geom&, const OpParams&, const void*, void*, hipStream_t);
 

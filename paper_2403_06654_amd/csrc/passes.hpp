@@ -21,6 +21,10 @@ struct Geom {
 
 enum OpKind { OP_PRESSURE = 0, OP_HELMHOLTZ = 1 };
 
+// Independent systems solved together in one set of launches (the
+// components of a velocity solve).
+constexpr int kMaxBatch = 3;
+
 struct OpParams {
   int kind;                  // OpKind
   double rho0;               // constant density of the preconditioner
@@ -71,6 +75,24 @@ template <typename R>
 void op_apply(const Geom& g, const OpParams& p, const void* v, void* y, const OpWork& w,
               const void* coef /* real [nz][ny][nx]: 1/rho (pressure) or rho (Helmholtz) */,
               const void* twtab, hipStream_t st, Prof* prof = nullptr);
+
+// The Helmholtz-type operator for nb <= kMaxBatch independent fields
+// (3D or 2D grids): y[f] = A (M^-1 (s_f v[f])), one launch per pass for all
+// fields, the x pass reading each coefficient row once for every field.
+// t[f]: one work field each; in_scale[f]: device scalar or null; gate[f]:
+// device flag, nonzero = field f is skipped.  Each field's arithmetic is that
+// of op_apply (bitwise the same result).
+struct OpBatch {
+  int nb;
+  const void* v[kMaxBatch];
+  void* y[kMaxBatch];
+  void* t[kMaxBatch];
+  const double* in_scale[kMaxBatch];
+  const int* gate[kMaxBatch];
+};
+template <typename R>
+void op_apply_helm_batch(const Geom& g, const OpParams& p, const OpBatch& b, const void* coef, const void* twtab,
+                         hipStream_t st, Prof* prof = nullptr);
 
 // Diagonal preconditioner in spectral space: z = M^-1 r (separate buffers).
 template <typename R>

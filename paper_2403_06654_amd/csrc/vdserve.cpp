@@ -3,8 +3,9 @@
 // Requests (one pressure or velocity solve each, any supported grid) are
 // queued FIFO on submit and admitted as soon as (a) a worker slot is free and
 // (b) an idle grid of the request's shape and footprint class exists or the
-// HBM budget has room for a new one (footprint = vd_workspace_bytes: the
-// Krylov basis, operator work fields and coefficient fields).  Each admitted request runs on its grid's
+// HBM budget has room for a new one (footprint = vd_workspace_bytes, or
+// vd_workspace_bytes_helmholtz for velocity solves: the Krylov basis,
+// operator work fields and coefficient fields).  Each admitted request runs on its grid's
 // own non-blocking stream from its own host thread, so the kernels of
 // requests of different sizes overlap on the device while their Krylov state
 // stays resident in HBM.  Grids are kept for reuse by later requests of the
@@ -111,7 +112,9 @@ void admit(vd_server* S) {
     if (slot < 0) return;
     GridEntry* ge = nullptr;
     for (auto* g : S->grids)
-      if (!g->busy && same_desc(g->desc, job.req.desc) && same_footprint(g->opts, job.req.opts)) {
+      // equal charges: the same number of Helmholtz components solved together
+      if (!g->busy && same_desc(g->desc, job.req.desc) && same_footprint(g->opts, job.req.opts) &&
+          g->bytes == job.bytes) {
         ge = g;
         break;
       }
@@ -258,7 +261,9 @@ vd_status vd_server_submit(vd_server* S, const vd_request* r, unsigned long long
   if (!S || !r) return VD_EINVAL;
   if (!S->dry && (!r->rho || !r->f || !r->x)) return VD_EINVAL;
   if (r->kind != VD_OP_PRESSURE && r->kind != VD_OP_HELMHOLTZ) return VD_EINVAL;
-  size_t bytes = vd_workspace_bytes(&r->desc, &r->opts);
+  size_t bytes = r->kind == VD_OP_HELMHOLTZ
+                     ? vd_workspace_bytes_helmholtz(&r->desc, &r->opts, r->ncomp > 0 ? r->ncomp : 1)
+                     : vd_workspace_bytes(&r->desc, &r->opts);
   if (bytes == 0) return VD_EINVAL;
   if (bytes > S->budget) return VD_ETOOBIG;
   {

@@ -121,6 +121,10 @@ struct vd_grid {
   DevState* hst = nullptr;    // pinned host mirror
   DevState* hslot = nullptr;  // two pinned mirrors of the state's tail, one per queued GMRES step
   hipEvent_t slot_ev[2] = {nullptr, nullptr};
+  // the other systems of a batched solve (index 0 is dst, partial, hslot)
+  DevState* dstx[kMaxBatch] = {};
+  double* partialx[kMaxBatch] = {};
+  DevState* hslotx[kMaxBatch] = {};
   std::map<int, void*> bufs;  // spectral vectors by (precision, role)
   Prof prof;
   // Chebyshev wall-normal direction (g.cheb)
@@ -149,6 +153,8 @@ namespace {
 enum Role {
   B_B = 0, B_X, B_R, B_TMP, B_T0, B_T1, B_T2, B_W, B_P, B_Q, B_Z, B_PSI, B_V0 = 32,
 };
+// system k of a batched solve uses role + k * kSysRoles (k = 0: the roles above)
+constexpr int kSysRoles = 100;
 
 struct DevErr {};
 
@@ -629,6 +635,368 @@ SolveOut solve_spectral(vd_grid* G, const vd_solve_opts& o, const OpParams& op, 
   }
 }
 
+// ------------------------------------------- several systems in lockstep
+//
+// The components of a velocity solve are independent systems with the same
+// operator.  They are solved together: every GMRES step applies the operator
+// to all of them in one launch per pass (the x pass reads each rho row once
+// for all) and orthogonalises all of them in one launch per Gram-Schmidt
+// kernel.  Each system keeps its own device state, basis, partials and
+// stopping test, so its kernels stop (return at their gate) when it
+// converges, and its result is the one it would have alone: the kernels and
+// reduction orders are those of a single system.
+
+// Device state, partials and pinned tail slots of system k (k = 0: the grid's own).
+void ensure_systems(vd_grid* G, int n) {
+  for (int k = 1; k < n; ++k) {
+    if (G->dstx[k]) continue;
+    ck(hipMalloc(&G->dstx[k], sizeof(DevState)));
+    ck(hipMalloc(&G->partialx[k], nred_partial() * sizeof(double)));
+    ck(hipHostMalloc(&G->hslotx[k], 2 * sizeof(DevState)));
+    ck(hipMemsetAsync(G->dstx[k], 0, sizeof(DevState), G->st));
+    std::memset(G->hslotx[k], 0, 2 * sizeof(DevState));
+  }
+}
+DevState* sys_dst(vd_grid* G, int k) { return k ? G->dstx[k] : G->dst; }
+double* sys_partial(vd_grid* G, int k) { return k ? G->partialx[k] : G->partial; }
+DevState* sys_slots(vd_grid* G, int k) { return k ? G->hslotx[k] : G->hslot; }
+
+// The operator passes take all the systems in one launch only while their
+// fields fit the 256 MB Infinity Cache together: a pass then finds much of
+// what the pass before it wrote still cached.  Larger fields (three FP64
+// components at 256^3: 3 x 134 MB) are applied one system after another,
+// each pass's output (one field) staying cached for the next pass.
+constexpr double kBatchOpBytes = 200.0 * (1 << 20);
+
+template <typename R>
+struct KrylovBatch {
+  vd_grid* G;
+  int prec;
+  const Geom& g;
+  SolveCfg cfg;
+  const void* coef;
+  const void* tw;
+  bool batch_ops = false;  // one launch per pass for all systems
+  DevState* dst[kMaxBatch];
+  double* part[kMaxBatch];
+  DevState* slots[kMaxBatch];
+  void* t[kMaxBatch];
+  int max_iter[kMaxBatch];  // per system (refinement gives each its remaining budget)
+
+  KrylovBatch(vd_grid* G_, int prec_, const SolveCfg& c, int n) : G(G_), prec(prec_), g(G_->g), cfg(c) {
+    coef = prec == 64 ? (const void*)G->rho : (const void*)G->rho32;
+    tw = prec == 64 ? G->tw64 : G->tw32;
+    for (int k = 0; k < n; ++k) {
+      dst[k] = sys_dst(G, k);
+      part[k] = sys_partial(G, k);
+      slots[k] = sys_slots(G, k);
+      t[k] = buf(G, prec, B_T0 + k * kSysRoles);
+      max_iter[k] = cfg.max_iter;
+    }
+    batch_ops = (double)n * G->nspec * elem_bytes(prec) <= kBatchOpBytes;
+  }
+  void* vec(int k, int role) { return buf(G, prec, role + k * kSysRoles); }
+
+  // y_q = A M^-1 v_q (with_prec) or A v_q for the systems of ob, each with
+  // its input scale and gate
+  void apply_set(const OpBatch& ob, bool with_prec) {
+    OpParams p = cfg.op;
+    p.precond = with_prec ? cfg.op.precond : 0;
+    if (batch_ops) {
+      op_apply_helm_batch<R>(g, p, ob, coef, tw, G->st, &G->prof);
+      return;
+    }
+    for (int q = 0; q < ob.nb; ++q) {
+      OpParams pq = p;
+      pq.in_scale = ob.in_scale[q];
+      pq.gate = ob.gate[q];
+      OpWork w{};
+      w.t[0] = ob.t[q];
+      op_apply<R>(g, pq, ob.v[q], ob.y[q], w, coef, tw, G->st, &G->prof);
+    }
+  }
+  void* basis(int k, int i) { return vec(k, B_V0 + i); }
+
+  // true residuals r_k = b_k - A x_k of the systems sys[0..ns), returned in rn
+  void true_resid(const int* sys, int ns, void* const* b, void* const* x, void* const* r, double* rn) {
+    OpBatch ob{};
+    ob.nb = ns;
+    for (int q = 0; q < ns; ++q) {
+      const int k = sys[q];
+      ob.v[q] = x[k];
+      ob.y[q] = vec(k, B_TMP);
+      ob.t[q] = t[k];
+    }
+    apply_set(ob, false);
+    for (int q = 0; q < ns; ++q) {
+      const int k = sys[q];
+      sub_norm<R>(g, b[k], vec(k, B_TMP), r[k], part[k], &dst[k]->nrm2, G->st);
+    }
+    for (int q = 0; q < ns; ++q) rn[sys[q]] = norm_from_sq(read_scalar(G, &dst[sys[q]]->nrm2));
+  }
+
+  int read_nreorth(int k) {
+    ck(hipMemcpyAsync(&G->hst->nreorth, &dst[k]->nreorth, sizeof(int), hipMemcpyDeviceToHost, G->st));
+    ck(hipStreamSynchronize(G->st));
+    return G->hst->nreorth;
+  }
+
+  // Arnoldi step j of the systems sys[0..ns)
+  void step(int j, const int* sys, int ns) {
+    OpBatch ob{};
+    ob.nb = ns;
+    void* w[kMaxBatch];
+    VecPtrs V[kMaxBatch];
+    DevState* ds[kMaxBatch];
+    double* ps[kMaxBatch];
+    for (int q = 0; q < ns; ++q) {
+      const int k = sys[q];
+      ob.v[q] = basis(k, j);
+      ob.y[q] = basis(k, j + 1);
+      ob.t[q] = t[k];
+      ob.in_scale[q] = &dst[k]->vs[j];
+      ob.gate[q] = &dst[k]->halt;
+      w[q] = basis(k, j + 1);
+      V[q] = VecPtrs{};
+      for (int i = 0; i <= j; ++i) V[q].p[i] = basis(k, i);
+      ds[q] = dst[k];
+      ps[q] = part[k];
+    }
+    apply_set(ob, true);
+    gs_orthogonalize_batch<R>(g, w, V, j + 1, ds, ps, ns, G->st, &G->prof);
+  }
+  void post_tails(int j, const int* sys, int ns) {
+    const size_t off = offsetof(DevState, resid);
+    for (int q = 0; q < ns; ++q) {
+      const int k = sys[q];
+      ck(hipMemcpyAsync((char*)(slots[k] + (j & 1)) + off, (const char*)dst[k] + off, sizeof(DevState) - off,
+                        hipMemcpyDeviceToHost, G->st));
+    }
+    ck(hipEventRecord(G->slot_ev[j & 1], G->st));
+  }
+
+  // Steps 0..jlast of a cycle of the systems sys[0..ns), queued one step ahead
+  // of the host like Krylov::run_queued; each system stops at its own halt
+  // flag.  steps[q], resid[q], bad[q]: per system at its end.
+  void run_queued(int jlast, const int* sys, int ns, int* steps, double* resid, int* bad,
+                  std::vector<double>* hist, double hist_bnorm) {
+    Prof& pf = G->prof;
+    if (pf.on) pf.flush();
+    step(0, sys, ns);
+    post_tails(0, sys, ns);
+    size_t mark = pf.pending.size();
+    bool stopped[kMaxBatch] = {};
+    int nstop = 0;
+    for (int j = 0; j <= jlast; ++j) {
+      if (j < jlast) {
+        step(j + 1, sys, ns);
+        post_tails(j + 1, sys, ns);
+      }
+      ck(hipEventSynchronize(G->slot_ev[j & 1]));
+      if (pf.on) {
+        pf.flush_front(mark);
+        mark = pf.pending.size();
+      }
+      for (int q = 0; q < ns; ++q) {
+        if (stopped[q]) continue;
+        const DevState& tt = slots[sys[q]][j & 1];
+        steps[q] = j + 1;
+        resid[q] = tt.resid;
+        bad[q] = tt.bad;
+        if (hist && sys[q] == 0) hist->push_back(tt.resid / hist_bnorm);
+        if (tt.bad || tt.halt || !(tt.nrm2 == tt.nrm2)) {
+          stopped[q] = true;
+          ++nstop;
+        }
+      }
+      if (nstop == ns) break;
+    }
+    if (pf.on) pf.drop();
+  }
+
+  // GMRES(m) for the systems sys[0..ns) (right preconditioned, restarts on
+  // the true residual), as Krylov::gmres_core for each of them
+  void gmres(const int* sys, int ns, void* const* b, void* const* x, const double* bnorm, SolveOut* out,
+             std::vector<double>* hist) {
+    const int m = cfg.restart;
+    double beta[kMaxBatch] = {};
+    int cycles[kMaxBatch] = {}, r0[kMaxBatch] = {};
+    bool active[kMaxBatch] = {};
+    for (int q = 0; q < ns; ++q) {
+      const int k = sys[q];
+      r0[k] = read_nreorth(k);
+      ck(hipMemsetAsync(&dst[k]->bad, 0, sizeof(int), G->st));
+      active[k] = true;
+    }
+    void* v0[kMaxBatch];
+    for (int q = 0; q < ns; ++q) v0[sys[q]] = basis(sys[q], 0);
+    if (cfg.inner || cfg.x_zero) {  // x = 0: r = b
+      for (int q = 0; q < ns; ++q) {
+        const int k = sys[q];
+        ck(hipMemcpyAsync(v0[k], b[k], G->nspec * elem_bytes(prec), hipMemcpyDeviceToDevice, G->st));
+        beta[k] = bnorm[k];
+      }
+    } else {
+      true_resid(sys, ns, b, x, v0, beta);
+    }
+    if (hist && sys[0] == 0) hist->push_back(beta[0] / bnorm[0]);
+    while (true) {
+      int act[kMaxBatch], na = 0;
+      for (int q = 0; q < ns; ++q) {
+        const int k = sys[q];
+        if (!active[k]) continue;
+        SolveOut& o = out[k];
+        o.relres = beta[k] / bnorm[k];
+        if (!(beta[k] == beta[k])) o.status = VD_EBREAKDOWN;
+        else if (o.relres <= cfg.rtol) o.status = VD_OK;
+        else if (o.iters >= max_iter[k]) o.status = VD_NOT_CONVERGED;
+        else {
+          act[na++] = k;
+          continue;
+        }
+        active[k] = false;
+      }
+      if (na == 0) break;
+      int jlast = 0;
+      for (int q = 0; q < na; ++q) {
+        const int k = act[q];
+        const int jl = std::min(m, max_iter[k] - out[k].iters) - 1;
+        gmres_init(dst[k], beta[k], m, bnorm[k], cfg.rtol, jl, G->st);
+        jlast = std::max(jlast, jl);
+      }
+      int steps[kMaxBatch] = {}, bad[kMaxBatch] = {};
+      double resid[kMaxBatch] = {};
+      run_queued(jlast, act, na, steps, resid, bad, hist, bnorm[0]);
+      int nres = 0, res_sys[kMaxBatch];
+      for (int q = 0; q < na; ++q) {
+        const int k = act[q];
+        SolveOut& o = out[k];
+        o.iters += steps[q];
+        if (bad[q]) {
+          o.status = VD_EBREAKDOWN;
+          active[k] = false;
+          continue;
+        }
+        gmres_backsolve(dst[k], steps[q], G->st);
+        VecPtrs P{};
+        for (int i = 0; i < steps[q]; ++i) P.p[i] = basis(k, i);
+        void* tmp = vec(k, B_TMP);
+        lincomb<R>(g, tmp, P, steps[q], dst[k]->coef, G->st);
+        OpParams plain = cfg.op;
+        plain.gate = nullptr;
+        precond_axpy<R>(g, plain, x[k], tmp, nullptr, 1.0, G->st);
+        ++cycles[k];
+        if (cfg.inner && (resid[q] / bnorm[k] <= cfg.rtol || cycles[k] >= kInnerCycles || o.iters >= max_iter[k])) {
+          o.relres = resid[q] / bnorm[k];  // estimate
+          o.status = VD_OK;
+          active[k] = false;
+          continue;
+        }
+        res_sys[nres++] = k;
+      }
+      if (nres) true_resid(res_sys, nres, b, x, v0, beta);
+    }
+    for (int q = 0; q < ns; ++q) out[sys[q]].reorth = read_nreorth(sys[q]) - r0[sys[q]];
+  }
+};
+
+// Solve A x_k = b_k for the n <= kMaxBatch systems together (b64[k], x64[k]:
+// FP64 spectral buffers of the grid; GMRES, Helmholtz-type operator, 2D or
+// 3D grid), in FP64 or FP32 inside FP64 iterative refinement, as
+// solve_spectral does for one system.  hist: system 0's history.
+void solve_spectral_batch(vd_grid* G, const vd_solve_opts& o, const OpParams& op, int n, void* const* b64,
+                          void* const* x64, const double* bnorm, SolveOut* out, int* refinements,
+                          std::vector<double>* hist) {
+  ensure_systems(G, n);
+  SolveCfg cfg{o.solver, o.restart, o.max_iter, o.rtol, op, -1};
+  cfg.x_zero = !o.use_x0;
+  int sys[kMaxBatch], ns = 0;
+  for (int k = 0; k < n; ++k) {
+    out[k] = SolveOut{};
+    refinements[k] = 0;
+    if (bnorm[k] == 0.0) {
+      if (hist && k == 0) hist->push_back(0.0);
+      ck(hipMemsetAsync(x64[k], 0, G->nspec * 16, G->st));
+    } else {
+      sys[ns++] = k;
+    }
+  }
+  if (ns == 0) return;
+  if (o.precision == VD_FP64) {
+    KrylovBatch<double> K(G, 64, cfg, n);
+    K.gmres(sys, ns, b64, x64, bnorm, out, hist);
+    return;
+  }
+  // FP32 inner solves inside FP64 iterative refinement, per system
+  KrylovBatch<double> K64(G, 64, cfg, n);
+  SolveCfg c32 = cfg;
+  c32.rtol = o.inner_rtol;
+  c32.inner = true;
+  KrylovBatch<float> K32(G, 32, c32, n);
+  void *r64[kMaxBatch], *r32[kMaxBatch], *d32[kMaxBatch];
+  double rn[kMaxBatch] = {}, one[kMaxBatch];
+  bool active[kMaxBatch] = {};
+  for (int k = 0; k < n; ++k) {
+    r64[k] = buf(G, 64, B_R + k * kSysRoles);
+    r32[k] = buf(G, 32, B_B + k * kSysRoles);
+    d32[k] = buf(G, 32, B_X + k * kSysRoles);
+    one[k] = 1.0;
+  }
+  if (o.use_x0) {
+    K64.true_resid(sys, ns, b64, x64, r64, rn);
+  } else {
+    for (int q = 0; q < ns; ++q) {
+      const int k = sys[q];
+      ck(hipMemcpyAsync(r64[k], b64[k], G->nspec * 16, hipMemcpyDeviceToDevice, G->st));
+      rn[k] = bnorm[k];
+    }
+  }
+  for (int q = 0; q < ns; ++q) active[sys[q]] = true;
+  while (true) {
+    int act[kMaxBatch], na = 0;
+    for (int q = 0; q < ns; ++q) {
+      const int k = sys[q];
+      if (!active[k]) continue;
+      SolveOut& s = out[k];
+      s.relres = rn[k] / bnorm[k];
+      if (hist && k == 0) hist->push_back(s.relres);
+      if (!(rn[k] == rn[k])) s.status = VD_EBREAKDOWN;
+      else if (s.relres <= o.rtol) s.status = VD_OK;
+      else if (refinements[k] >= o.max_outer || s.iters >= o.max_iter) s.status = VD_NOT_CONVERGED;
+      else {
+        act[na++] = k;
+        continue;
+      }
+      active[k] = false;
+    }
+    if (na == 0) break;
+    SolveOut in[kMaxBatch];
+    for (int q = 0; q < na; ++q) {
+      const int k = act[q];
+      cast_d2f(G->g, r64[k], r32[k], 1.0 / rn[k], G->st);
+      ck(hipMemsetAsync(d32[k], 0, G->nspec * 8, G->st));
+      K32.max_iter[k] = std::min(o.max_iter - out[k].iters, kInnerCycles * o.restart);
+      in[k] = SolveOut{};
+    }
+    K32.gmres(act, na, r32, d32, one, in, nullptr);
+    int nres = 0, res_sys[kMaxBatch];
+    for (int q = 0; q < na; ++q) {
+      const int k = act[q];
+      out[k].iters += in[k].iters;
+      out[k].reorth += in[k].reorth;
+      refinements[k]++;
+      if (in[k].status == VD_EBREAKDOWN) {
+        out[k].status = VD_EBREAKDOWN;
+        active[k] = false;
+        continue;
+      }
+      axpy_f2d(G->g, d32[k], x64[k], rn[k], G->st);
+      res_sys[nres++] = k;
+    }
+    if (nres) K64.true_resid(res_sys, nres, b64, x64, r64, rn);
+  }
+}
+
 vd_status guard(vd_grid* G, vd_status (*fn)(vd_grid*, void*), void* ctx) {
   try {
     return fn(G, ctx);
@@ -854,6 +1222,11 @@ vd_status vd_grid_destroy(vd_grid* G) {
   hipFree(G->kc64);
   hipFree(G->kc32);
   hipFree(G->dst);
+  for (int k = 1; k < kMaxBatch; ++k) {
+    hipFree(G->dstx[k]);
+    hipFree(G->partialx[k]);
+    if (G->hslotx[k]) hipHostFree(G->hslotx[k]);
+  }
   if (G->hst) hipHostFree(G->hst);
   if (G->hslot) hipHostFree(G->hslot);
   for (auto e : G->slot_ev)
@@ -1006,6 +1379,56 @@ double project_psi(vd_grid* G, void* b64) {
   return std::fabs(dot) / std::sqrt(G->psi2);
 }
 
+// Components solved together (solve_spectral_batch): a Helmholtz solve of
+// several components with GMRES on a Fourier grid of two or three
+// dimensions.  Each component's result equals that of a solve of it alone.
+bool batches_components(const Geom& g, int kind, int ncomp, const vd_solve_opts& o) {
+  return kind == VD_OP_HELMHOLTZ && ncomp > 1 && o.solver == VD_GMRES && !g.cheb && g.nz > 1;
+}
+
+static vd_status solve_helm_batched(vd_grid* G, SolveCtx* s, const OpParams& op) {
+  vd_status worst = VD_OK;
+  for (int c0 = 0; c0 < s->ncomp; c0 += kMaxBatch) {
+    const int n = std::min(kMaxBatch, s->ncomp - c0);
+    void *b64[kMaxBatch], *x64[kMaxBatch];
+    double bnorm[kMaxBatch];
+    for (int k = 0; k < n; ++k) {
+      b64[k] = buf(G, 64, B_B + k * kSysRoles);
+      x64[k] = buf(G, 64, B_X + k * kSysRoles);
+      fwd_transform(G->g, s->f + (size_t)(c0 + k) * G->nreal, b64[k], nullptr, G->tw64, G->st);
+      if (s->o.use_x0) fwd_transform(G->g, s->x + (size_t)(c0 + k) * G->nreal, x64[k], nullptr, G->tw64, G->st);
+      else ck(hipMemsetAsync(x64[k], 0, G->nspec * 16, G->st));
+      bnorm[k] = host_norm_of(G, b64[k]);
+    }
+    SolveOut so[kMaxBatch];
+    int refin[kMaxBatch];
+    std::vector<double> hist;
+    const bool want_hist = c0 == 0 && s->o.history_cap > 0;
+    solve_spectral_batch(G, s->o, op, n, b64, x64, bnorm, so, refin, want_hist ? &hist : nullptr);
+    if (want_hist) {
+      const int nh = (int)std::min<size_t>(hist.size(), (size_t)s->o.history_cap);
+      std::copy(hist.begin(), hist.begin() + nh, s->o.history);
+      s->info.history_len = nh;
+    }
+    for (int k = 0; k < n; ++k)
+      inv_transform(G->g, x64[k], s->x + (size_t)(c0 + k) * G->nreal, buf(G, 64, B_TMP), G->tw64, G->st);
+    ck(hipStreamSynchronize(G->st));
+    ck(hipGetLastError());
+    bool stop = false;
+    for (int k = 0; k < n; ++k) {
+      s->info.iterations += so[k].iters;
+      s->info.refinements += refin[k];
+      s->info.gs_second_passes += so[k].reorth;
+      s->info.rel_residual = max_keep_nan(s->info.rel_residual, so[k].relres);
+      if (so[k].status < 0) worst = (vd_status)so[k].status;
+      else if (so[k].status == VD_NOT_CONVERGED && worst == VD_OK) worst = VD_NOT_CONVERGED;
+      stop = stop || so[k].status < 0;
+    }
+    if (stop) break;
+  }
+  return worst;
+}
+
 static vd_status solve_impl(vd_grid* G, void* c) {
   SolveCtx* s = (SolveCtx*)c;
   auto t0 = std::chrono::steady_clock::now();
@@ -1027,10 +1450,16 @@ static vd_status solve_impl(vd_grid* G, void* c) {
     op.nu = 1.0;
     coef = COEF_KC;
   }
+  s->info = vd_solve_info{};
+  if (batches_components(G->g, s->kind, s->ncomp, s->o)) {
+    const vd_status worst = solve_helm_batched(G, s, op);
+    s->info.status = worst;
+    s->info.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return worst;
+  }
   void* b64 = buf(G, 64, B_B);
   void* x64 = buf(G, 64, B_X);
   vd_status worst = VD_OK;
-  s->info = vd_solve_info{};
   for (int comp = 0; comp < s->ncomp; ++comp) {
     const double* f = s->f + (size_t)comp * G->nreal;
     double* x = s->x + (size_t)comp * G->nreal;
@@ -1163,6 +1592,24 @@ size_t vd_workspace_bytes(const vd_grid_desc* d, const vd_solve_opts* opts) {
     bytes += nspec * 16 * 2;                     // preconditioner and second work field
   }
   return bytes;
+}
+
+size_t vd_workspace_bytes_helmholtz(const vd_grid_desc* d, const vd_solve_opts* opts, int ncomp) {
+  const size_t base = vd_workspace_bytes(d, opts);
+  if (base == 0 || ncomp < 1) return 0;
+  vd_solve_opts o;
+  if (opts) o = *opts;
+  else vd_default_opts(&o);
+  Geom g = make_geom(d);
+  if (!batches_components(g, VD_OP_HELMHOLTZ, ncomp, o)) return base;
+  // per further system: b, x, basis V_0..V_m, operator result and work
+  // (FP64); with FP32 inner solves, the FP64 residual too and the basis,
+  // work, inner b and x in FP32
+  const size_t nspec = (size_t)g.M * g.ny * g.nz, m = (size_t)o.restart;
+  size_t sys = nred_partial() * 8 + sizeof(DevState);
+  if (o.precision == VD_FP64) sys += nspec * 16 * (m + 5);
+  else sys += nspec * 16 * 5 + nspec * 8 * (m + 5);
+  return base + (size_t)(std::min(ncomp, kMaxBatch) - 1) * sys;
 }
 
 vd_status vd_profile_enable(vd_grid* G, int classes) {

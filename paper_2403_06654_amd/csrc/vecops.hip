@@ -69,49 +69,60 @@ __device__ __forceinline__ void reduce_values(const double* __restrict__ partial
   }
 }
 
-// Scalar steps of CG and RMR, taken by one thread on the reduced values.
-__device__ __forceinline__ void cg_alpha_step(DevState* st) {  // alpha = rz / (p, A p)
-  const double pq = st->red[0];
+// Scalar steps of CG and RMR, taken by one thread on the reduced values
+// (passed in: see k_reduce).
+__device__ __forceinline__ void cg_alpha_step(DevState* st, double pq) {  // alpha = rz / (p, A p)
   st->alpha = pq != 0.0 ? st->rz / pq : 0.0;
   if (!isfinite(st->alpha) || pq <= 0.0) st->bad = 1;
 }
-__device__ __forceinline__ void cg_beta_step(DevState* st) {  // beta = (r, M r)_new / (r, M r)
-  const double rzn = st->red[0];
+__device__ __forceinline__ void cg_beta_step(DevState* st, double rzn) {  // beta = (r, M r)_new / (r, M r)
   st->beta = st->rz != 0.0 ? rzn / st->rz : 0.0;
   st->rz = rzn;
   if (!isfinite(st->beta)) st->bad = 1;
 }
-__device__ __forceinline__ void rmr_alpha_step(DevState* st) {  // alpha = (r, w) / (w, w)
-  const double ww = st->red[1];
-  st->alpha = ww > 0.0 ? st->red[0] / ww : 0.0;
+__device__ __forceinline__ void rmr_alpha_step(DevState* st, double rw, double ww) {  // alpha = (r, w) / (w, w)
+  st->alpha = ww > 0.0 ? rw / ww : 0.0;
   if (!isfinite(st->alpha)) st->bad = 1;
 }
-// Stopping test of a CG or RMR step on its recursive residual (st->nrm2),
-// the host loop's test taken on the device: a non-finite scalar, the
-// tolerance, or the last step of the run sets halt.  step counts the steps.
-__device__ __forceinline__ void rec_check_step(DevState* st) {
+// Stopping test of a CG or RMR step on its recursive residual (n2 = its
+// square, also in st->nrm2), the host loop's test taken on the device: a
+// non-finite scalar, the tolerance, or the last step of the run sets halt.
+// step counts the steps.
+__device__ __forceinline__ void rec_check_step(DevState* st, double n2) {
   const int j = st->step;
   st->step = j + 1;
-  const double n2 = st->nrm2;
   const double rn = n2 < 0.0 ? 0.0 : sqrt(n2);
   if (st->bad || !(n2 == n2) || rn / st->stop_bnorm <= st->stop_rtol || j >= st->jlast) st->halt = 1;
 }
 
 // The final reduction, optionally followed (same launch, after a block
 // barrier) by the scalar step that consumes its result: one launch less per
-// step than a separate one-thread kernel.
+// step than a separate one-thread kernel.  The step takes the reduced values
+// from LDS, not from out: out is written by other lanes (other waves for the
+// second value) in this launch, and a load of it through st is not ordered
+// after those stores (the compiler may serve it from the scalar cache).
 __global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ partial, int nblk, int K, double scale,
                                                  double* __restrict__ out, const int* __restrict__ gate, int post,
                                                  DevState* st) {
   if (gate && *gate) return;
-  reduce_values(partial, nblk, K, scale, out);
+  __shared__ double val[2];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int i = w; i < K; i += 16) {
+    double v = 0.0;
+    for (int b = lane; b < nblk; b += 64) v += partial[(size_t)i * kRedBlocks + b];
+    v = wave_sum(v) * scale;
+    if (lane == 0) {
+      out[i] = v;
+      if (i < 2) val[i] = v;
+    }
+  }
   if (post == POST_NONE) return;
   __syncthreads();
   if (threadIdx.x) return;
-  if (post == POST_CG_ALPHA) cg_alpha_step(st);
-  else if (post == POST_CG_BETA) cg_beta_step(st);
-  else if (post == POST_RMR_ALPHA) rmr_alpha_step(st);
-  else if (post == POST_REC_CHECK) rec_check_step(st);
+  if (post == POST_CG_ALPHA) cg_alpha_step(st, val[0]);
+  else if (post == POST_CG_BETA) cg_beta_step(st, val[0]);
+  else if (post == POST_RMR_ALPHA) rmr_alpha_step(st, val[0], val[1]);
+  else if (post == POST_REC_CHECK) rec_check_step(st, val[0]);
 }
 
 // gate (here and below): optional device flag; when nonzero the launch does
@@ -125,11 +136,27 @@ static size_t nspec(const Geom& g) { return (size_t)g.nz * g.ny * g.M; }
 
 // ------------------------------------------------------------ multi-dot
 
+// The Gram-Schmidt kernels (and the dot pass) serve several independent
+// systems in one launch (the components of a velocity solve): blockIdx.y
+// selects system k of the set, with its own vector, basis, device state,
+// partials and gate; one system is a set of one.
+template <typename R>
+struct SysSet {
+  C2<R>* x[kMaxBatch];
+  VecPtrs V[kMaxBatch];
+  DevState* st[kMaxBatch];
+  double* partial[kMaxBatch];
+  const int* gate[kMaxBatch];
+};
+
 template <typename R, int NV>
-__global__ __launch_bounds__(256) void k_mdot(const C2<R>* __restrict__ x, VecPtrs V, int nv, int want_norm,
-                                              size_t n, int M, double* __restrict__ partial,
-                                              const int* __restrict__ gate) {
+__global__ __launch_bounds__(256) void k_mdot(SysSet<R> S, int nv, int want_norm, size_t n, int M) {
+  const int sy = blockIdx.y;
+  const int* gate = S.gate[sy];
   if (gate && *gate) return;
+  const C2<R>* __restrict__ x = S.x[sy];
+  const VecPtrs& V = S.V[sy];
+  double* __restrict__ partial = S.partial[sy];
   double acc[NV + 1];
 #pragma unroll
   for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
@@ -161,28 +188,38 @@ __global__ __launch_bounds__(256) void k_mdot(const C2<R>* __restrict__ x, VecPt
   block_store<NV + 1>(out, nv + (want_norm ? 1 : 0), partial + blockIdx.x);
 }
 
-// Block partials only (the caller reduces them).
+template <typename R>
+static SysSet<R> one_system(const void* x, const VecPtrs& V, DevState* st, double* partial, const int* gate) {
+  SysSet<R> S{};
+  S.x[0] = (C2<R>*)x;
+  S.V[0] = V;
+  S.st[0] = st;
+  S.partial[0] = partial;
+  S.gate[0] = gate;
+  return S;
+}
+
+// Block partials only (the caller reduces them), for nsys systems.
+template <typename R>
+static void mdot_partials_set(const Geom& g, const SysSet<R>& S, int nsys, int nv, bool want_norm, hipStream_t s) {
+  size_t n = nspec(g);
+  dim3 gr(nblk(n), nsys), bl(256);
+  const int wn = want_norm ? 1 : 0;
+  if (nv <= 1) hipLaunchKernelGGL((k_mdot<R, 1>), gr, bl, 0, s, S, nv, wn, n, g.M);
+  else if (nv <= 2) hipLaunchKernelGGL((k_mdot<R, 2>), gr, bl, 0, s, S, nv, wn, n, g.M);
+  else if (nv <= 4) hipLaunchKernelGGL((k_mdot<R, 4>), gr, bl, 0, s, S, nv, wn, n, g.M);
+  else if (nv <= 8) hipLaunchKernelGGL((k_mdot<R, 8>), gr, bl, 0, s, S, nv, wn, n, g.M);
+  else if (nv <= 16) hipLaunchKernelGGL((k_mdot<R, 16>), gr, bl, 0, s, S, nv, wn, n, g.M);
+  else if (nv <= 24) hipLaunchKernelGGL((k_mdot<R, 24>), gr, bl, 0, s, S, nv, wn, n, g.M);
+  else hipLaunchKernelGGL((k_mdot<R, kMaxVec>), gr, bl, 0, s, S, nv, wn, n, g.M);
+}
+
 template <typename R>
 static void mdot_partials(const Geom& g, const void* x, const VecPtrs& V, int nv, bool want_norm, double* partial,
                           hipStream_t s, const int* gate = nullptr) {
-  size_t n = nspec(g);
-  dim3 gr(nblk(n)), bl(256);
-  const int wn = want_norm ? 1 : 0;
-  if (nv <= 1)
-    hipLaunchKernelGGL((k_mdot<R, 1>), gr, bl, 0, s, (const C2<R>*)x, V, nv, wn, n, g.M, partial, gate);
-  else if (nv <= 2)
-    hipLaunchKernelGGL((k_mdot<R, 2>), gr, bl, 0, s, (const C2<R>*)x, V, nv, wn, n, g.M, partial, gate);
-  else if (nv <= 4)
-    hipLaunchKernelGGL((k_mdot<R, 4>), gr, bl, 0, s, (const C2<R>*)x, V, nv, wn, n, g.M, partial, gate);
-  else if (nv <= 8)
-    hipLaunchKernelGGL((k_mdot<R, 8>), gr, bl, 0, s, (const C2<R>*)x, V, nv, wn, n, g.M, partial, gate);
-  else if (nv <= 16)
-    hipLaunchKernelGGL((k_mdot<R, 16>), gr, bl, 0, s, (const C2<R>*)x, V, nv, wn, n, g.M, partial, gate);
-  else if (nv <= 24)
-    hipLaunchKernelGGL((k_mdot<R, 24>), gr, bl, 0, s, (const C2<R>*)x, V, nv, wn, n, g.M, partial, gate);
-  else
-    hipLaunchKernelGGL((k_mdot<R, kMaxVec>), gr, bl, 0, s, (const C2<R>*)x, V, nv, wn, n, g.M, partial, gate);
+  mdot_partials_set<R>(g, one_system<R>(x, V, nullptr, partial, gate), 1, nv, want_norm, s);
 }
+
 
 template <typename R>
 void mdot(const Geom& g, const void* x, const VecPtrs& V, int nv, bool want_norm, double* partial, double* out,
@@ -238,8 +275,10 @@ __device__ __forceinline__ double wave_max(double v) {
 // reduction of the pass before them (one launch instead of two).  Reduced
 // values stay in LDS; per-vector work runs one lane per basis vector
 // (nv <= kMaxVec < 64), so no thread walks the device state serially.
-__global__ __launch_bounds__(1024) void k_gs_prep(DevState* st, int nv, const double* __restrict__ partial, int nb,
-                                                  double scale) {
+// blockIdx.y: the system (st[k], partial[k]) of a set
+__global__ __launch_bounds__(1024) void k_gs_prep(DevStates S, int nv, int nb, double scale) {
+  DevState* st = S.st[blockIdx.y];
+  const double* __restrict__ partial = S.partial[blockIdx.y];
   if (st->halt) return;
   __shared__ double val[kMaxVec + 2];
   reduce_values(partial, nb, nv, scale, val);
@@ -256,8 +295,9 @@ __global__ __launch_bounds__(1024) void k_gs_prep(DevState* st, int nv, const do
 // Orthogonality check of the first pass, then the Givens rotations of GMRES
 // on the new Hessenberg column j = nv - 1 (the second pass, if any, changes
 // only w, not H).
-__global__ __launch_bounds__(1024) void k_gs_check(DevState* st, int nv, double tol, const double* __restrict__ partial,
-                                                   int nb, double scale) {
+__global__ __launch_bounds__(1024) void k_gs_check(DevStates S, int nv, double tol, int nb, double scale) {
+  DevState* st = S.st[blockIdx.y];
+  const double* __restrict__ partial = S.partial[blockIdx.y];
   __shared__ double val[kMaxVec + 2];
   __shared__ double hc[kMaxVec + 1], csl[kMaxRestart], snl[kMaxRestart];
   if (st->halt) {  // a step queued past the end of the cycle: no second pass either
@@ -334,10 +374,13 @@ __global__ __launch_bounds__(1024) void k_gs_check(DevState* st, int nv, double 
 }
 
 template <typename R, int NV>
-__global__ __launch_bounds__(256) void k_gs_update(C2<R>* __restrict__ x, VecPtrs V, int nv,
-                                                   const DevState* __restrict__ st, size_t n, int M,
-                                                   double* __restrict__ partial) {
+__global__ __launch_bounds__(256) void k_gs_update(SysSet<R> S, int nv, size_t n, int M) {
+  const int sy = blockIdx.y;
+  const DevState* __restrict__ st = S.st[sy];
   if (st->halt) return;
+  C2<R>* __restrict__ x = S.x[sy];
+  const VecPtrs& V = S.V[sy];
+  double* __restrict__ partial = S.partial[sy];
   double c[NV];
 #pragma unroll
   for (int i = 0; i < NV; ++i) c[i] = i < nv ? st->coef[i] : 0.0;
@@ -384,9 +427,12 @@ __global__ __launch_bounds__(256) void k_gs_update(C2<R>* __restrict__ x, VecPtr
 
 // The second pass is its own kernel symbol so that profiles separate it.
 template <typename R, int NV>
-__global__ __launch_bounds__(256) void k_gs_reorth(C2<R>* __restrict__ x, VecPtrs V, int nv,
-                                                   const DevState* __restrict__ st, size_t n) {
+__global__ __launch_bounds__(256) void k_gs_reorth(SysSet<R> S, int nv, size_t n) {
+  const int sy = blockIdx.y;
+  const DevState* __restrict__ st = S.st[sy];
   if (!st->reorth) return;
+  C2<R>* __restrict__ x = S.x[sy];
+  const VecPtrs& V = S.V[sy];
   double c[NV];
 #pragma unroll
   for (int i = 0; i < NV; ++i) c[i] = i < nv ? st->coef[i] : 0.0;
@@ -406,37 +452,60 @@ __global__ __launch_bounds__(256) void k_gs_reorth(C2<R>* __restrict__ x, VecPtr
 }
 
 template <typename R, int NV>
-static void launch_gs(const Geom& g, void* x, const VecPtrs& V, int nv, const DevState* st, int second,
-                      double* partial, hipStream_t s) {
-  if (second)
-    hipLaunchKernelGGL((k_gs_reorth<R, NV>), dim3(nblk(nspec(g))), dim3(256), 0, s, (C2<R>*)x, V, nv, st, nspec(g));
-  else
-    hipLaunchKernelGGL((k_gs_update<R, NV>), dim3(nblk(nspec(g))), dim3(256), 0, s, (C2<R>*)x, V, nv, st, nspec(g),
-                       g.M, partial);
+static void launch_gs(const Geom& g, const SysSet<R>& S, int nsys, int nv, int second, hipStream_t s) {
+  const dim3 gr(nblk(nspec(g)), nsys);
+  if (second) hipLaunchKernelGGL((k_gs_reorth<R, NV>), gr, dim3(256), 0, s, S, nv, nspec(g));
+  else hipLaunchKernelGGL((k_gs_update<R, NV>), gr, dim3(256), 0, s, S, nv, nspec(g), g.M);
+}
+
+// One Arnoldi orthogonalisation for nsys independent systems at the same
+// step (nv basis vectors each); each system's kernels return at once once
+// its own halt flag is set.
+template <typename R>
+static void gs_orthogonalize_set(const Geom& g, const SysSet<R>& S, int nsys, int nv, hipStream_t s, Prof* prof) {
+  const bool pr = prof && prof->on;
+  const double fb = (double)nspec(g) * sizeof(C2<R>) * nsys;
+  if (pr) prof->begin(10, s, (nv + 1) * fb);
+  const int nb = nblk(nspec(g));
+  mdot_partials_set<R>(g, S, nsys, nv, false, s);
+  if (pr) prof->end(s);
+  DevStates D{};
+  for (int k = 0; k < nsys; ++k) {
+    D.st[k] = S.st[k];
+    D.partial[k] = S.partial[k];
+  }
+  hipLaunchKernelGGL(k_gs_prep, dim3(1, nsys), dim3(1024), 0, s, D, nv, nb, g.ntot_inv);
+  for (int second = 0; second < 2; ++second) {
+    if (pr && !second) prof->begin(11, s, (nv + 2) * fb);
+    if (nv <= 4) launch_gs<R, 4>(g, S, nsys, nv, second, s);
+    else if (nv <= 8) launch_gs<R, 8>(g, S, nsys, nv, second, s);
+    else if (nv <= 16) launch_gs<R, 16>(g, S, nsys, nv, second, s);
+    else if (nv <= 24) launch_gs<R, 24>(g, S, nsys, nv, second, s);
+    else launch_gs<R, kMaxVec>(g, S, nsys, nv, second, s);
+    if (pr && !second) prof->end(s);
+    if (!second) hipLaunchKernelGGL(k_gs_check, dim3(1, nsys), dim3(1024), 0, s, D, nv, orth_tol<R>(), nb, g.ntot_inv);
+  }
 }
 
 template <typename R>
 void gs_orthogonalize(const Geom& g, void* w, const VecPtrs& V, int nv, DevState* st, double* partial,
                       hipStream_t s, Prof* prof) {
-  const bool pr = prof && prof->on;
-  const double fb = (double)nspec(g) * sizeof(C2<R>);
-  if (pr) prof->begin(10, s, (nv + 1) * fb);
-  const int nb = nblk(nspec(g));
-  mdot_partials<R>(g, w, V, nv, false, partial, s, &st->halt);
-  if (pr) prof->end(s);
-  hipLaunchKernelGGL(k_gs_prep, dim3(1), dim3(1024), 0, s, st, nv, (const double*)partial, nb, g.ntot_inv);
-  for (int second = 0; second < 2; ++second) {
-    if (pr && !second) prof->begin(11, s, (nv + 2) * fb);
-    if (nv <= 4) launch_gs<R, 4>(g, w, V, nv, st, second, partial, s);
-    else if (nv <= 8) launch_gs<R, 8>(g, w, V, nv, st, second, partial, s);
-    else if (nv <= 16) launch_gs<R, 16>(g, w, V, nv, st, second, partial, s);
-    else if (nv <= 24) launch_gs<R, 24>(g, w, V, nv, st, second, partial, s);
-    else launch_gs<R, kMaxVec>(g, w, V, nv, st, second, partial, s);
-    if (pr && !second) prof->end(s);
-    if (!second)
-      hipLaunchKernelGGL(k_gs_check, dim3(1), dim3(1024), 0, s, st, nv, orth_tol<R>(), (const double*)partial, nb,
-                         g.ntot_inv);
+  // the dot pass is gated by the system's halt flag like the other kernels
+  gs_orthogonalize_set<R>(g, one_system<R>(w, V, st, partial, &st->halt), 1, nv, s, prof);
+}
+
+template <typename R>
+void gs_orthogonalize_batch(const Geom& g, void* const* w, const VecPtrs* V, int nv, DevState* const* st,
+                            double* const* partial, int nsys, hipStream_t s, Prof* prof) {
+  SysSet<R> S{};
+  for (int k = 0; k < nsys; ++k) {
+    S.x[k] = (C2<R>*)w[k];
+    S.V[k] = V[k];
+    S.st[k] = st[k];
+    S.partial[k] = partial[k];
+    S.gate[k] = &st[k]->halt;
   }
+  gs_orthogonalize_set<R>(g, S, nsys, nv, s, prof);
 }
 
 // ------------------------------------------------------------- lincomb
@@ -714,15 +783,15 @@ __global__ void k_gmres_backsolve(DevState* st, int k) {
 
 __global__ void k_cg_alpha(DevState* st, const int* gate) {
   if (threadIdx.x || (gate && *gate)) return;
-  cg_alpha_step(st);
+  cg_alpha_step(st, st->red[0]);
 }
 __global__ void k_cg_beta(DevState* st, const int* gate) {
   if (threadIdx.x || (gate && *gate)) return;
-  cg_beta_step(st);
+  cg_beta_step(st, st->red[0]);
 }
 __global__ void k_rmr_alpha(DevState* st, const int* gate) {
   if (threadIdx.x || (gate && *gate)) return;
-  rmr_alpha_step(st);
+  rmr_alpha_step(st, st->red[0], st->red[1]);
 }
 
 void gmres_init(DevState* st, double beta, int m, double bnorm, double rtol, int jlast, hipStream_t s) {
@@ -743,7 +812,7 @@ void rmr_alpha(DevState* st, hipStream_t s, const int* gate) {
 
 __global__ void k_rec_check(DevState* st, const int* gate) {
   if (threadIdx.x || (gate && *gate)) return;
-  rec_check_step(st);
+  rec_check_step(st, st->nrm2);
 }
 __global__ void k_rec_init(DevState* st, double bnorm, double rtol, int jlast) {
   if (threadIdx.x) return;
@@ -861,6 +930,8 @@ void kcoef_finish(const double* rho, const double* lap_psi, double* kc64, float*
   template void scale<R>(const Geom&, void*, const double*, double, hipStream_t);                              \
   template void gs_orthogonalize<R>(const Geom&, void*, const VecPtrs&, int, DevState*, double*, hipStream_t,  \
                                     Prof*);                                                                    \
+  template void gs_orthogonalize_batch<R>(const Geom&, void* const*, const VecPtrs*, int, DevState* const*,   \
+                                          double* const*, int, hipStream_t, Prof*);                          \
   template void sub_norm<R>(const Geom&, const void*, const void*, void*, double*, double*, hipStream_t);      \
   template void precond_axpy<R>(const Geom&, const OpParams&, void*, const void*, const double*, double,       \
                                 hipStream_t);                                                                  \

@@ -76,6 +76,22 @@ template <typename R>
 void gs_orthogonalize(const Geom& g, void* w, const VecPtrs& V, int nv, DevState* st, double* partial,
                       hipStream_t s, Prof* prof = nullptr);
 
+// The same step for nsys <= kMaxBatch independent systems together (one
+// launch per pass for all of them; system k: w[k], V[k], st[k], partial[k];
+// a system whose halt flag is set is skipped).  The kernels and reduction
+// orders are those of one system, so each system's result is the same as
+// when it is orthogonalised alone.
+template <typename R>
+void gs_orthogonalize_batch(const Geom& g, void* const* w, const VecPtrs* V, int nv, DevState* const* st,
+                            double* const* partial, int nsys, hipStream_t s, Prof* prof = nullptr);
+
+// Device states and reduction partials of a set of systems (single-block
+// scalar kernels index them by blockIdx.y).
+struct DevStates {
+  DevState* st[kMaxBatch];
+  double* partial[kMaxBatch];
+};
+
 // z = sum_i c_i V_i
 template <typename R>
 void lincomb(const Geom& g, void* z, const VecPtrs& V, int nv, const double* coef, hipStream_t s);

@@ -69,6 +69,31 @@ def test_workspace_bytes():
     assert api.lib().vd_workspace_bytes(ctypes.byref(d), None) == 0
 
 
+def test_workspace_bytes_helmholtz():
+    """GMRES velocity solves on Fourier grids of two or three dimensions
+    hold up to three systems' Krylov vectors at once; other solves one."""
+    wb = api.workspace_bytes
+    shape = (256, 256, 256)
+    nspec = 256 * 256 * 128          # packed half spectrum (kx = 0 and nx/2 share slot 0)
+    one = wb(shape)
+    assert wb(shape, helmholtz_ncomp=1) == one
+    extra = wb(shape, helmholtz_ncomp=2) - one
+    # b, x, basis V_0..V_30, operator result and work: 35 FP64 spectral vectors (+ partials, state)
+    assert 35 * nspec * 16 <= extra < 35 * nspec * 16 + (1 << 20)
+    assert wb(shape, helmholtz_ncomp=3) - one == 2 * extra
+    assert wb(shape, helmholtz_ncomp=7) == wb(shape, helmholtz_ncomp=3)
+    e32 = wb(shape, helmholtz_ncomp=2, precision="fp32_refine") - wb(shape, precision="fp32_refine")
+    assert 5 * nspec * 16 + 35 * nspec * 8 <= e32 < 5 * nspec * 16 + 35 * nspec * 8 + (1 << 20)
+    assert wb((64, 128), helmholtz_ncomp=3) > wb((64, 128))
+    # one system at a time: CG, RMR, 1D and Fourier-Chebyshev grids
+    for kw in (dict(solver="cg"), dict(solver="rmr")):
+        assert wb(shape, helmholtz_ncomp=3, **kw) == wb(shape, **kw)
+    assert wb((512,), helmholtz_ncomp=3) == wb((512,))
+    assert wb((65, 128), cheb=True, helmholtz_ncomp=3) == wb((65, 128), cheb=True)
+    assert wb(shape, helmholtz_ncomp=0) == 0
+    assert wb((100, 100), helmholtz_ncomp=3) == 0
+
+
 def test_grid_create_rejects_bad_descriptors_without_touching_the_device():
     h = ctypes.c_void_p()
     for shape in [(100,), (8, 8), (4096,)]:

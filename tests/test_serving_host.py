@@ -137,6 +137,34 @@ def test_grids_are_reused_only_within_a_footprint_class():
     srv.close()
 
 
+def test_velocity_requests_are_charged_for_their_components():
+    """A velocity request of three components with GMRES holds three
+    systems' Krylov vectors (the components are solved together): it is
+    charged vd_workspace_bytes_helmholtz, and its grid is not handed to a
+    one-component request (nor the other way round)."""
+    shape = (64, 64, 64)
+    one = api.workspace_bytes(shape)
+    three = api.workspace_bytes(shape, helmholtz_ncomp=3)
+    assert three > 2 * one
+    srv = api.Server(hbm_budget=one + three, max_slots=1, dry_seconds=0.0)
+    srv.submit(shape, kind="helmholtz", dt_nu=1e-3, ncomp=3)
+    _drain(srv, 1)
+    assert srv.stats()["hbm_used"] == three
+    srv.submit(shape, kind="helmholtz", dt_nu=1e-3, ncomp=1)     # a grid of its own next to it
+    _drain(srv, 1)
+    st = srv.stats()
+    assert st["grids"] == 2 and st["hbm_used"] == one + three
+    srv.submit(shape, kind="helmholtz", dt_nu=1e-3, ncomp=3)     # reuses the three-component grid
+    srv.submit(shape, kind="pressure")                            # reuses the one-system grid
+    _drain(srv, 2)
+    st = srv.stats()
+    assert st["grids"] == 2 and st["hbm_used"] == one + three and st["hbm_peak"] == one + three
+    with pytest.raises(api.VdError) as e:                         # larger than the whole budget
+        srv.submit((256, 256, 256), kind="helmholtz", dt_nu=1e-3, ncomp=3)
+    assert e.value.status == -6
+    srv.close()
+
+
 def test_submit_checks_tensors():
     """Tensors handed to the server are checked before submission (dtype,
     device, shape, layout; Helmholtz fields carry the component axis)."""
