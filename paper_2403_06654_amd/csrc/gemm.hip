@@ -55,35 +55,41 @@ struct EpiArgs {
   const int* gate;         // nonzero *gate: the launch does nothing
 };
 
-// One 256-thread block per 16 x 16 tile of C; the 4 waves split K (wave w
-// takes the k-steps w, w+4, w+8, ...), and the four partial tiles are summed
-// through LDS before the epilogue.  The Chebyshev contractions are small
-// (M = 257 or 514 rows, N = 512 real columns, K = 257 or 514): 32 x 32 tiles
-// gave only 144-272 blocks for 256 CUs, one wave per SIMD, each waiting on
-// L2 latency; 16 x 16 tiles give 544-1056 blocks.  Each wave loads its whole
-// K-slice (up to KU k-steps) before its first MFMA, so it waits on memory
-// once, then issues the MFMAs on two independent accumulators (alternate
-// k-steps) so that consecutive MFMAs do not wait on each other's result.
+// One 512-thread block per 16 x 16 tile of C; the 8 waves split K (wave w
+// takes the k-steps w, w+8, w+16, ...), and the eight partial tiles are
+// summed through LDS before the epilogue.  The Chebyshev contractions are
+// small (M = 257 or 514 rows, N = 512 real columns, K = 257 or 514), so a
+// launch is bound by latency, not by MFMA or bandwidth: 16 x 16 tiles give
+// 544-1056 blocks for 256 CUs, and each wave loads KU k-steps before their
+// MFMAs (two independent accumulators, alternate k-steps), waiting on memory
+// once per batch.  Measured per launch (FP64, N = 512; back-to-back launches
+// with HIP events): M = 257, K = 257: 5.4 us; M = 514, K = 257: 7.8 us;
+// M = 257, K = 514: 8.7 us (4 waves with KU = 17: 6.0, 8.5, 9.7; 32 x 32
+// tiles: 7.8-10.8).  An empty kernel on the same grid takes 2.4-2.8 us, and
+// the MFMAs, reduction and stores alone (operands not loaded) 3.7-5.1 us.
 // AT: A is stored transposed ([K][M]), so a load of 16 consecutive rows is
 // one contiguous run.
+constexpr int kGemmWaves = 8, kGemmKU = 5;
+
 template <typename R, bool AT>
-__global__ __launch_bounds__(256) void k_gemm(const R* __restrict__ A, int lda, const R* __restrict__ B, int ldb,
-                                              R* __restrict__ C, int ldc, int M, int N, int K, EpiArgs e) {
+__global__ __launch_bounds__(64 * kGemmWaves) void k_gemm(const R* __restrict__ A, int lda, const R* __restrict__ B,
+                                                          int ldb, R* __restrict__ C, int ldc, int M, int N, int K,
+                                                          EpiArgs e) {
   using MF = Mfma<R>;
+  constexpr int W = kGemmWaves, KU = kGemmKU;
   if (e.gate && *e.gate) return;
-  __shared__ double part[4][16 * 17];
+  __shared__ double part[W][16 * 17];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int r0 = blockIdx.y * 16, c0 = blockIdx.x * 16;
   const int li = lane & 15, lk = lane >> 4;
   const int ra = r0 + li, cb = c0 + li;
   const bool rin = ra < M, cin = cb < N;
   typename MF::V acc0{0, 0, 0, 0}, acc1{0, 0, 0, 0};
-  constexpr int KU = 17;  // k-steps per wave loaded at once: all of K = 257, half of K = 514
-  for (int s0 = w; 4 * s0 < K; s0 += 4 * KU) {
+  for (int s0 = w; 4 * s0 < K; s0 += W * KU) {
     R a[KU], b[KU];
 #pragma unroll
     for (int u = 0; u < KU; ++u) {
-      const int k = 4 * (s0 + 4 * u) + lk;
+      const int k = 4 * (s0 + W * u) + lk;
       const bool kin = k < K;
       a[u] = (kin && rin) ? (AT ? A[(size_t)k * lda + ra] : A[(size_t)ra * lda + k]) : R(0);
       b[u] = (kin && cin) ? B[(size_t)k * ldb + cb] : R(0);
@@ -97,12 +103,16 @@ __global__ __launch_bounds__(256) void k_gemm(const R* __restrict__ A, int lda, 
 #pragma unroll
   for (int r = 0; r < 4; ++r) part[w][MF::row(lk, r) * 17 + li] = (double)acc0[r] + (double)acc1[r];
   __syncthreads();
+  if (threadIdx.x >= 256) return;
   const double al = (e.alpha_dev ? *e.alpha_dev : 1.0) * e.alpha;
   const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
   const int row = r0 + tr, col = c0 + tc;
   if (row >= M || col >= N) return;
   const int o = tr * 17 + tc;
-  double v = ((part[0][o] + part[1][o]) + part[2][o] + part[3][o]) * al;
+  double v = 0.0;
+#pragma unroll
+  for (int q = 0; q < W; ++q) v += part[q][o];
+  v *= al;
   if (e.kind == 1) {
     const int kx = col >> 1;
     const double kp = kx * e.sx;  // slot 0: k' = 0 for both halves
@@ -116,7 +126,7 @@ template <typename R, bool AT = true>
 static void gemm(const R* A, int lda, const R* B, int ldb, R* C, int ldc, int M, int N, int K, const EpiArgs& e,
                  hipStream_t s) {
   dim3 grid((N + 15) / 16, (M + 15) / 16);
-  hipLaunchKernelGGL((k_gemm<R, AT>), grid, dim3(256), 0, s, A, lda, B, ldb, C, ldc, M, N, K, e);
+  hipLaunchKernelGGL((k_gemm<R, AT>), grid, dim3(64 * kGemmWaves), 0, s, A, lda, B, ldb, C, ldc, M, N, K, e);
 }
 
 static EpiArgs plain(double alpha = 1.0, const double* alpha_dev = nullptr) {

@@ -52,22 +52,35 @@ enum ColMode {
   COL_H_LAST,       // Q2, v -> Fz Q2 + nu |k|^2 M v
 };
 
-// Lines of 512 points: points per thread and threads per block (the tile is
-// NT / (512 / E) columns wide, and holds that many lines in LDS).  Measured
-// at 512^3 (pressure operator, FP64 / FP32 ms): E = 16 with 256 threads
-// (8 columns) 5.50 / 3.44, with 512 threads (16 columns, 136 KiB of LDS in
-// FP64, one block per CU) 5.42 / 2.89; E = 8 with 1024 threads 5.63 / 2.91.
-// The wider tile writes longer contiguous runs per line segment.
-template <typename R>
-constexpr int kColE512 = 16;
-constexpr int kColNT512 = 512;
+// Lines of 512 points: points per thread E and threads per block NT, per
+// pass (the tile is NT / (512 / E) columns wide and holds that many lines in
+// LDS; 16 columns take 136 KiB in FP64, one block per CU).  Measured at
+// 512^3, microseconds per pass for (E, NT) = (16, 256) / (16, 512) /
+// (8, 1024):
+//   FP64 pressure z-first 737 / 775 / 792, y-inverse 1086 / 1083 / 1241,
+//        y-forward 1105 / 1075 / 1121, z-last 819 / 745 / 739;
+//   FP64 Helmholtz z-first 525 / 562 / 511, z-last 1084 / 926 / 797, y
+//        transforms 426 / 419 / 410 and 407 / 404 / 395;
+//   FP32 pressure z-first 442 / 320 / 377, y-inverse 764 / 589 / 582,
+//        y-forward 770 / 598 / 571, z-last 470 / 411 / 405.
+// The wider tiles write longer contiguous runs of each line segment; the
+// FP64 pressure z-first pass (one field in, two out) keeps two blocks per CU.
+template <typename R, int MODE>
+struct Col512 {
+  static constexpr bool DBL = sizeof(R) == 8;
+  static constexpr bool WIDE = DBL ? (MODE == COL_H_FIRST || MODE == COL_H_LAST || MODE == COL_FFT_FWD ||
+                                      MODE == COL_FFT_INV)
+                                   : (MODE == COL_P_MIDINV || MODE == COL_P_MIDFWD || MODE == COL_P_LAST);
+  static constexpr int E = WIDE ? 8 : 16;
+  static constexpr int NT = WIDE ? 1024 : (DBL && MODE == COL_P_FIRST ? 256 : 512);
+};
 
 template <int L, typename R, int MODE>
 struct ColCfg {
   static constexpr bool E8 = sizeof(R) == 8 && L < 512 && MODE != COL_P_LAST && MODE != COL_P_MIDFWD;
-  static constexpr int E = L == 512 ? kColE512<R> : E8 ? (L >= 8 ? 8 : L) : (L >= 16 ? 16 : L);
+  static constexpr int E = L == 512 ? Col512<R, MODE>::E : E8 ? (L >= 8 ? 8 : L) : (L >= 16 ? 16 : L);
   static constexpr int T = L / E;
-  static constexpr int NT = L == 512 ? kColNT512 : 256;  // threads per block
+  static constexpr int NT = L == 512 ? Col512<R, MODE>::NT : 256;  // threads per block
   static constexpr int TC = NT / T;                      // columns per tile
 };
 

@@ -15,7 +15,7 @@ SHAPES = [
     ((16,), None), ((256,), None), ((1024,), (3.0,)),
     ((16, 16), None), ((32, 64), (2.0, 5.0)), ((128, 16), None), ((64, 256), None),
     ((16, 16, 16), None), ((32, 16, 64), (1.0, 2.0, 3.0)), ((16, 128, 32), None), ((64, 64, 64), None),
-    ((16, 16, 512), None), ((512, 16, 16), None),
+    ((16, 16, 512), None), ((512, 16, 16), None), ((512, 16), None),
     # the longest lines: 1024-point columns (z of a 2D grid) and 1024-point
     # rows (512 packed slots) in 2D and 3D
     ((1024, 16), None), ((16, 1024), None), ((16, 16, 1024), (1.0, 2.0, 6.0)),
