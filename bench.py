@@ -305,6 +305,31 @@ def oracle_check(grid, rho_dev, dens, inp, f_dev, g_dev, torch):
         operators.use_workers(None)
 
 
+def serving_oracle_check(reqs, rho_dev, f_dev, xs, got):
+    """Oracle-evaluated true relative residual of served results: the first
+    three requests of every grid size (FP32+refine, as served)."""
+    import numpy as np
+    from oracle import operators
+    status = {g["user_tag"]: g for g in got}
+    picked = {}
+    for i, r in enumerate(reqs):
+        if len(picked.setdefault(r["n"], [])) < 3:
+            picked[r["n"]].append(i)
+    out = {}
+    for n, idx in sorted(picked.items()):
+        worst = 0.0
+        for i in idx:
+            rho = rho_dev[i].cpu().numpy()
+            f = f_dev[n][reqs[i]["seed"] % 8].cpu().numpy()
+            x = xs[i].cpu().numpy()
+            b, _ = operators.project_range(-f, operators.nullspace_basis(f.shape))
+            rr = float(np.linalg.norm(operators.apply_pressure(x, rho) - b) / np.linalg.norm(b))
+            worst = max(worst, rr)
+            assert status[i]["status"] == 0
+        out[f"{n}^2"] = {"requests": len(idx), "max_oracle_rel_residual": worst}
+    return out
+
+
 def bench_serving(args):
     """Serving stream of 2D periodic pressure solves (FP32+FP64-refine, rtol
     1e-10): closed-loop saturation throughput, then Poisson arrivals at 0.8x
@@ -341,6 +366,14 @@ def bench_serving(args):
             got += srv.wait(timeout=5.0)
         return time.perf_counter() - t0, got
 
+    # the same closed loop with every request alone in its slot (no shared
+    # launches), for comparison
+    srv0 = Server(budget, max_slots=args.slots, batch=1)
+    closed(srv0, list(range(min(16, nreq))), "fp32_refine")
+    print("bench: closed loop, unbatched", file=sys.stderr, flush=True)
+    wall0, got0 = closed(srv0, list(range(nreq)), "fp32_refine")
+    lat0 = [g["t_done"] - g["t_arrive"] for g in got0]
+    srv0.close()
     srv = Server(budget, max_slots=args.slots)
     closed(srv, list(range(min(16, nreq))), "fp32_refine")            # warm-up: grids of every size
     print("bench: closed loop", file=sys.stderr, flush=True)
@@ -351,6 +384,13 @@ def bench_serving(args):
     sat = nreq / wall
     lat_closed = [g["t_done"] - g["t_arrive"] for g in got]
     iters = sum(g["iterations"] for g in got)
+    runs = {}
+    for g in got:
+        runs.setdefault((g["slot"], g["t_start"]), []).append(g)
+    batch_sizes = [len(v) for v in runs.values()]
+    oracle = None
+    if not args.no_oracle_check:
+        oracle = serving_oracle_check(reqs, rho, f_dev, xs, got)
     open_runs = {}
     for frac in (0.8, 0.5):
         qps = frac * sat
@@ -376,7 +416,7 @@ def bench_serving(args):
     srv.close()
     # reference mode: plain FP64, one solve at a time, same requests (first 512)
     nref = min(512, nreq)
-    srv1 = Server(budget, max_slots=1)
+    srv1 = Server(budget, max_slots=1, batch=1)
     closed(srv1, list(range(min(16, nref))), "fp64")
     wall1, got1 = closed(srv1, list(range(nref)), "fp64")
     srv1.close()
@@ -389,9 +429,15 @@ def bench_serving(args):
                                f"r log-uniform [1.5,10], tanh slab with 8-mode interface, GMRES(30)",
                    "slots": args.slots, "hbm_budget_GB": budget / 2 ** 30},
         "closed_loop": {"solves_per_s": round(sat, 2), "krylov_iters_per_s": round(iters / wall, 1),
-                        "p50_ms": round(1e3 * pct(lat_closed, 50), 3), "p99_ms": round(1e3 * pct(lat_closed, 99), 3)},
+                        "p50_ms": round(1e3 * pct(lat_closed, 50), 3), "p99_ms": round(1e3 * pct(lat_closed, 99), 3),
+                        "slot_runs": len(batch_sizes),
+                        "requests_per_slot_run": {str(k): batch_sizes.count(k) for k in sorted(set(batch_sizes))}},
+        "closed_loop_unbatched": {"solves_per_s": round(nreq / wall0, 2), "p50_ms": round(1e3 * pct(lat0, 50), 3),
+                                  "p99_ms": round(1e3 * pct(lat0, 99), 3)},
         "open_loop": open_runs,
-        "reference_fp64_single_slot": {"requests": nref, "solves_per_s": round(nref / wall1, 2)},
+        "oracle_check": oracle,
+        "reference_fp64_single_slot": {"requests": nref, "solves_per_s": round(nref / wall1, 2),
+                                       "mode": "plain FP64, one request at a time, no batching"},
         "speedup_vs_fp64_single_slot": round(sat / (nref / wall1), 2),
         "server": {"peak_busy_slots": st["peak_busy_slots"], "hbm_peak_GB": round(st["hbm_peak"] / 2 ** 30, 3),
                    "grids": st["grids"]},

@@ -160,7 +160,8 @@ vd_status vd_apply_precond(vd_grid* grid, int kind, int precision, double dt_nu,
  * are removed and their norm reported in info->rhs_null_norm); the
  * solution returned is the one orthogonal to that nullspace (zero mean).
  * The residual is measured in the Euclidean norm of grid values.
- * With opts->formulation = VD_FORM_K (Fourier grids; Sec. 4.2) the solve
+ * With opts->formulation = VD_FORM_K (eq. VDINSE.Krho of Sec. 3.2; Fourier
+ * grids, as the paper uses it in 3D in Sec. 4.2) the solve
  * runs on Phi = p / sqrt(rho): A = -K_rho, b = -sqrt(rho) f with its
  * component along rho^-1/2 removed (that norm goes to rhs_null_norm), the
  * preconditioner is the pseudo-inverse of -Lap, info->rel_residual is that
@@ -172,6 +173,24 @@ vd_status vd_apply_precond(vd_grid* grid, int kind, int precision, double dt_nu,
  * a Chebyshev grid. */
 vd_status vd_solve_pressure(vd_grid* grid, const double* f, double* p, const vd_solve_opts* opts,
                             vd_solve_info* info);
+
+/* Solve L_rho p = f on n <= 3 grids of one shape together, each with its own
+ * density (Sec. 3.2; grids[k], f[k], p[k] as in vd_solve_pressure; infos:
+ * n entries, filled for every grid).  With GMRES on a Fourier grid of two or
+ * three dimensions (direct form) the solves share their launches: one per
+ * operator pass and per Gram-Schmidt kernel for all of them, each grid
+ * keeping its own Krylov state and stopping test; a grid that has converged
+ * skips its part of the launches.  Otherwise the grids are solved one after
+ * another.  Either way every grid's p and info are bit for bit those of
+ * vd_solve_pressure on that grid alone (info.seconds aside: the batch's
+ * wall time; the history, if requested, is grid 0's).  The work runs on
+ * grids[0]'s stream; the other grids must not be in use by another thread.
+ * Returns the worst status (errors before VD_NOT_CONVERGED); infos[k].status
+ * is grid k's own.  VD_EINVAL: n outside [1, 3] or infos NULL (nothing
+ * written), a NULL pointer, a grid without a density or given twice (every
+ * info's status set to it). */
+vd_status vd_solve_pressure_batch(vd_grid* const* grids, int n, const double* const* f, double* const* p,
+                                  const vd_solve_opts* opts, vd_solve_info* infos);
 
 /* Solve rho u - dt_nu Lap u = g for ncomp independent components stored one
  * after another (g, u: [ncomp][nz][ny][nx]).  Lap keeps the Nyquist modes.
@@ -393,9 +412,15 @@ vd_status vd_ns_profile_read(vd_ns* h, double* ms, long long* count, double* byt
  * densities).  Requests are queued FIFO and admitted as soon as a worker
  * slot is free and their HBM footprint (vd_workspace_bytes) fits the budget
  * next to the grids already held; admitted requests run concurrently, each
- * on its own stream, with their Krylov state resident on the device.  A
- * result does not depend on what else is running (fixed launch
- * configurations and reduction orders).
+ * slot on its own stream, with their Krylov state resident on the device.
+ * Pressure requests that can share launches (GMRES, direct form, Fourier
+ * grids of two or three dimensions) are batched: when a slot takes such a
+ * request, up to two later queued requests of the same shape and options
+ * (no history) join it if grids for them fit without releasing others, and
+ * the slot solves them together (vd_solve_pressure_batch; each still on its
+ * own grid, charged as before).  A result does not depend on what else is
+ * running or on its batch (fixed launch configurations and reduction
+ * orders).
  * ---------------------------------------------------------------------- */
 typedef struct vd_server vd_server;
 
@@ -435,6 +460,10 @@ vd_status vd_server_create(vd_server** out, size_t hbm_budget, int max_slots);
  * seconds and returns VD_ENOTSUP): lets the admission policy be tested on a
  * machine without a GPU. */
 vd_status vd_server_create_dry(vd_server** out, size_t hbm_budget, int max_slots, double seconds_per_request);
+/* Requests per shared batch, 1..3 (default 3; 1 = every request alone in
+ * its slot).  Applies to batches formed after the call.  VD_EINVAL outside
+ * that range. */
+vd_status vd_server_set_batch(vd_server* s, int max_requests);
 /* Queue a request; never blocks.  VD_ETOOBIG if its footprint exceeds the
  * whole budget, VD_EINVAL for a bad descriptor/options/pointers. */
 vd_status vd_server_submit(vd_server* s, const vd_request* req, unsigned long long* ticket);

@@ -105,6 +105,8 @@ _SIGS = {
     "vd_solve_pressure": (_I, [_P, _P, _P, ctypes.POINTER(vd_solve_opts), ctypes.POINTER(vd_solve_info)]),
     "vd_solve_helmholtz": (_I, [_P, _D, _I, _P, _P, ctypes.POINTER(vd_solve_opts),
                                 ctypes.POINTER(vd_solve_info)]),
+    "vd_solve_pressure_batch": (_I, [ctypes.POINTER(_P), _I, ctypes.POINTER(_P), ctypes.POINTER(_P),
+                                     ctypes.POINTER(vd_solve_opts), ctypes.POINTER(vd_solve_info)]),
     "vd_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(vd_grid_desc), ctypes.POINTER(vd_solve_opts)]),
     "vd_workspace_bytes_helmholtz": (ctypes.c_size_t, [ctypes.POINTER(vd_grid_desc), ctypes.POINTER(vd_solve_opts),
                                                        ctypes.c_int]),
@@ -135,6 +137,7 @@ _SIGS = {
     "vd_server_create": (_I, [ctypes.POINTER(_P), ctypes.c_size_t, _I]),
     "vd_server_create_dry": (_I, [ctypes.POINTER(_P), ctypes.c_size_t, _I, _D]),
     "vd_server_submit": (_I, [_P, ctypes.POINTER(vd_request), ctypes.POINTER(ctypes.c_ulonglong)]),
+    "vd_server_set_batch": (_I, [_P, _I]),
     "vd_server_poll": (_I, [_P, ctypes.POINTER(vd_result), _I, ctypes.POINTER(_I)]),
     "vd_server_wait": (_I, [_P, ctypes.POINTER(vd_result), _I, ctypes.POINTER(_I), _D]),
     "vd_server_stats": (_I, [_P, ctypes.POINTER(vd_server_stats_t)]),
@@ -328,6 +331,25 @@ class Grid:
                                       _dev_f64(u, shp, "u"), ctypes.byref(o), ctypes.byref(info))
         _check(st, "vd_solve_helmholtz")
         return u, _with_history(info, opts)
+
+    @staticmethod
+    def solve_pressure_batch(grids, fs, ps=None, **opts):
+        """L_rho p = f on up to three grids of one shape together
+        (vd_solve_pressure_batch); returns the fields and one info per grid."""
+        import torch
+        n = len(grids)
+        if len(fs) != n or (ps is not None and len(ps) != n):
+            raise ValueError("one f (and p) per grid")
+        if ps is None:
+            ps = [torch.zeros_like(f) for f in fs]
+        hs = (_P * n)(*[g._h.value for g in grids])
+        fp = (_P * n)(*[_dev_f64(f, g.shape, "f").value for f, g in zip(fs, grids)])
+        pp = (_P * n)(*[_dev_f64(p, g.shape, "p").value for p, g in zip(ps, grids)])
+        o = make_opts(**opts)
+        infos = (vd_solve_info * n)()
+        st = lib().vd_solve_pressure_batch(hs, n, fp, pp, ctypes.byref(o), infos)
+        _check(st, "vd_solve_pressure_batch")
+        return ps, [_with_history(infos[k], opts if k == 0 else {}) for k in range(n)]
 
     def profile_enable(self, on=True):
         """on: True (every kernel class), False, or a bit mask of classes."""
@@ -527,7 +549,7 @@ class FractionalStep:
 class Server:
     """Continuous-batching solve server (vd_server_*)."""
 
-    def __init__(self, hbm_budget, max_slots=8, dry_seconds=None):
+    def __init__(self, hbm_budget, max_slots=8, dry_seconds=None, batch=3):
         h = ctypes.c_void_p()
         if dry_seconds is None:
             st = lib().vd_server_create(ctypes.byref(h), int(hbm_budget), int(max_slots))
@@ -536,6 +558,7 @@ class Server:
         _check(st, "vd_server_create", False)
         self._h = h
         self._keep = {}   # ticket -> tensors the server reads or writes
+        _check(lib().vd_server_set_batch(h, int(batch)), "vd_server_set_batch", False)
 
     def submit(self, shape, rho=None, f=None, x=None, lengths=None, kind="pressure", dt_nu=0.0, ncomp=1,
                user_tag=0, cheb=False, **opts):

@@ -22,8 +22,12 @@
 // lanes map to adjacent columns, so every global access is a contiguous run
 // of TC complex values.  The row pass loads whole rows.  All passes are
 // in-place safe except those that gather a mirror element (Helmholtz, kx = 0).
+#include <cstddef>
 #include <cstdio>
+#include <initializer_list>
+
 #include "fft_core.hpp"
+
 #include "passes.hpp"
 #include "spectral.hpp"
 
@@ -108,6 +112,20 @@ struct RowCfg {
 // ------------------------------------------------------ column kernels
 
 
+// One system's arguments in a batched launch: blockIdx.y selects system k
+// of nb, which has its own fields, coefficient rows, preconditioner
+// constant, input scale and gate (several independent systems solved
+// together: the components of a velocity solve, or pressure solves on grids
+// of one shape).
+struct SysArgs {
+  const void* in[3];
+  void* out[3];
+  const void* coef;  // row passes: the system's coefficient rows
+  double rho0;
+  const double* in_scale;
+  const int* gate;
+};
+
 struct ColArgs {
   const void* in[3];
   void* out[3];
@@ -119,15 +137,12 @@ struct ColArgs {
   int precond;
   const double* in_scale;
   const int* gate;  // nonzero *gate: the launch does nothing
-  // Batched launch (nb > 0): blockIdx.y selects field f of nb independent
-  // fields, with its own inputs, output, input scale and gate (the Helmholtz
-  // passes of several systems solved together; nf = 1 per field).
+  // The launch's systems: system blockIdx.y < nb reads its fields, scale,
+  // preconditioner constant and gate from sys[blockIdx.y] (a launch of one
+  // system has nb = 1, filled from in/out/rho0/in_scale/gate by the
+  // launcher; the plain FFT modes take fields 1..nf-1 from in/out).
   int nb;
-  const void* fin[kMaxBatch];
-  const void* fin2[kMaxBatch];
-  void* fout[kMaxBatch];
-  const double* fscale[kMaxBatch];
-  const int* fgate[kMaxBatch];
+  SysArgs sys[kMaxBatch];
 };
 
 template <int L, int E, int RPAT, typename R>
@@ -150,13 +165,17 @@ __device__ __forceinline__ void col_store(const C2<R>* reg, C2<R>* p, size_t bas
   }
 }
 
-// Entry f of a per-field argument array by constant indices only: indexing
-// a by-value kernel argument with a run-time index makes the compiler copy
-// the whole argument block to scratch memory first.
-template <typename T>
-__device__ __forceinline__ T pick(const T (&v)[kMaxBatch], int f) {
-  static_assert(kMaxBatch == 3, "one select per entry");
-  return f == 0 ? v[0] : (f == 1 ? v[1] : v[2]);
+// The block's system, sys[blockIdx.y] of the kernel's first argument (of
+// type Args, at the start of the kernel-argument segment), read in place:
+// constant memory at a uniform address, so scalar loads.  Indexing the
+// by-value argument itself with a run-time index would make the compiler
+// copy the whole argument block to scratch memory first.
+typedef __attribute__((address_space(4))) const SysArgs KSys;
+template <typename Args>
+__device__ __forceinline__ KSys* block_sys() {
+  typedef __attribute__((address_space(4))) const char KChar;
+  KChar* seg = (KChar*)__builtin_amdgcn_kernarg_segment_ptr();
+  return (KSys*)(seg + offsetof(Args, sys)) + blockIdx.y;
 }
 
 template <int L, typename R, int MODE>
@@ -167,14 +186,19 @@ __global__ __launch_bounds__((ColCfg<L, R, MODE>::NT)) void k_col(ColArgs a, con
   constexpr int R0 = S::template first_radix<false>();
   constexpr int R1 = S::template last_radix<false>();
   constexpr int LDSN = S::npass > 1 ? TC * L : 1;
-  // this block's field: the launch's own pointers, or field blockIdx.y of a batch
-  const int fb = a.nb ? (int)blockIdx.y : 0;
-  const int* gate = a.nb ? pick(a.fgate, fb) : a.gate;
+  // this block's system, read from the kernel-argument segment (one code
+  // path for a launch of one system and a batch)
+  KSys* sy = block_sys<ColArgs>();
+  const int* gate = sy->gate;
   if (gate && *gate) return;  // the flag is written before the launch
-  const void* in0 = a.nb ? pick(a.fin, fb) : a.in[0];
-  const void* in1 = a.nb ? pick(a.fin2, fb) : a.in[1];
-  void* out0 = a.nb ? pick(a.fout, fb) : a.out[0];
-  const double* iscale = a.nb ? pick(a.fscale, fb) : a.in_scale;
+  const void* in0 = sy->in[0];
+  const void* in1 = sy->in[1];
+  const void* in2 = sy->in[2];
+  void* out0 = sy->out[0];
+  void* out1 = sy->out[1];
+  void* out2 = sy->out[2];
+  const double* iscale = sy->in_scale;
+  const double rho0 = sy->rho0;
   __shared__ C2<R> lds_raw[LDSN];
   // twiddle table staged in LDS (see k_row)
   __shared__ C2<R> tw_lds[L];
@@ -193,7 +217,7 @@ __global__ __launch_bounds__((ColCfg<L, R, MODE>::NT)) void k_col(ColArgs a, con
 
   if constexpr (MODE == COL_FFT_FWD || MODE == COL_FFT_INV) {
     constexpr int DIR = MODE == COL_FFT_FWD ? -1 : +1;
-    const int nf = a.nb ? 1 : a.nf;
+    const int nf = a.nf;
     for (int f = 0; f < nf; ++f) {
       col_load<L, E, R0>(reg, (const C2<R>*)(f ? a.in[f] : in0), base, a.inner, t, ok);
       fft_line<L, E, DIR, false>(reg, lds, tw, t);
@@ -202,52 +226,52 @@ __global__ __launch_bounds__((ColCfg<L, R, MODE>::NT)) void k_col(ColArgs a, con
   } else if constexpr (MODE == COL_P_FIRST) {
     // z pass: line index = kz; column = ky * M + kx
     const int ky = col / a.g.M, kx = col % a.g.M;
-    const R sc = in_scale_of<R>(a.in_scale);
-    col_load<L, E, R0>(reg, (const C2<R>*)a.in[0], base, a.inner, t, ok);
+    const R sc = in_scale_of<R>(iscale);
+    col_load<L, E, R0>(reg, (const C2<R>*)in0, base, a.inner, t, ok);
     C2<R> r2[E];
 #pragma unroll
     for (int s = 0; s < E; ++s) {
       int kz = pat_index<L, E, R0>(t, s);
-      R m = a.precond ? mult_press<R>(kx, ky, kz, a.g, a.rho0) : R(1);
+      R m = a.precond ? mult_press<R>(kx, ky, kz, a.g, rho0) : R(1);
       reg[s] = cscale(reg[s], m * sc);
       r2[s] = cik(reg[s], kprime_of<R>(kz, L, R(a.g.sz)));
     }
     fft_line<L, E, +1, false>(reg, lds, tw, t);
-    col_store<L, E, R1>(reg, (C2<R>*)a.out[0], base, a.inner, t, ok);
+    col_store<L, E, R1>(reg, (C2<R>*)out0, base, a.inner, t, ok);
     fft_line<L, E, +1, false>(r2, lds, tw, t);
-    col_store<L, E, R1>(r2, (C2<R>*)a.out[1], base, a.inner, t, ok);
+    col_store<L, E, R1>(r2, (C2<R>*)out1, base, a.inner, t, ok);
   } else if constexpr (MODE == COL_P_MIDINV) {
     // y pass over z-physical data: line index = ky
-    col_load<L, E, R0>(reg, (const C2<R>*)a.in[0], base, a.inner, t, ok);
+    col_load<L, E, R0>(reg, (const C2<R>*)in0, base, a.inner, t, ok);
     C2<R> r2[E];
 #pragma unroll
     for (int s = 0; s < E; ++s) r2[s] = cik(reg[s], kprime_of<R>(pat_index<L, E, R0>(t, s), L, R(a.g.sy)));
     fft_line<L, E, +1, false>(reg, lds, tw, t);
-    col_store<L, E, R1>(reg, (C2<R>*)a.out[0], base, a.inner, t, ok);
+    col_store<L, E, R1>(reg, (C2<R>*)out0, base, a.inner, t, ok);
     fft_line<L, E, +1, false>(r2, lds, tw, t);
-    col_store<L, E, R1>(r2, (C2<R>*)a.out[1], base, a.inner, t, ok);
-    col_load<L, E, R0>(reg, (const C2<R>*)a.in[1], base, a.inner, t, ok);
+    col_store<L, E, R1>(r2, (C2<R>*)out1, base, a.inner, t, ok);
+    col_load<L, E, R0>(reg, (const C2<R>*)in1, base, a.inner, t, ok);
     fft_line<L, E, +1, false>(reg, lds, tw, t);
-    col_store<L, E, R1>(reg, (C2<R>*)a.out[2], base, a.inner, t, ok);
+    col_store<L, E, R1>(reg, (C2<R>*)out2, base, a.inner, t, ok);
   } else if constexpr (MODE == COL_P_MIDFWD || MODE == COL_P_LAST) {
     // forward y (MIDFWD) or z (LAST) with the divergence term of this axis
     constexpr bool LAST = MODE == COL_P_LAST;
     const R sk = LAST ? R(a.g.sz) : R(a.g.sy);
     C2<R> acc[E];
-    col_load<L, E, R0>(acc, (const C2<R>*)a.in[0], base, a.inner, t, ok);
+    col_load<L, E, R0>(acc, (const C2<R>*)in0, base, a.inner, t, ok);
     fft_line<L, E, -1, false>(acc, lds, tw, t);
-    col_load<L, E, R0>(reg, (const C2<R>*)a.in[1], base, a.inner, t, ok);
+    col_load<L, E, R0>(reg, (const C2<R>*)in1, base, a.inner, t, ok);
     fft_line<L, E, -1, false>(reg, lds, tw, t);
 #pragma unroll
     for (int s = 0; s < E; ++s) {
       C2<R> d = cik(reg[s], kprime_of<R>(pat_index<L, E, R1>(t, s), L, sk));
       acc[s] = LAST ? C2<R>{-(acc[s].x + d.x), -(acc[s].y + d.y)} : acc[s] + d;
     }
-    col_store<L, E, R1>(acc, (C2<R>*)a.out[0], base, a.inner, t, ok);
+    col_store<L, E, R1>(acc, (C2<R>*)out0, base, a.inner, t, ok);
     if constexpr (!LAST) {
-      col_load<L, E, R0>(reg, (const C2<R>*)a.in[2], base, a.inner, t, ok);
+      col_load<L, E, R0>(reg, (const C2<R>*)in2, base, a.inner, t, ok);
       fft_line<L, E, -1, false>(reg, lds, tw, t);
-      col_store<L, E, R1>(reg, (C2<R>*)a.out[1], base, a.inner, t, ok);
+      col_store<L, E, R1>(reg, (C2<R>*)out1, base, a.inner, t, ok);
     }
   } else if constexpr (MODE == COL_H_FIRST || MODE == COL_H_LAST) {
     constexpr bool FIRST = MODE == COL_H_FIRST;
@@ -266,7 +290,7 @@ __global__ __launch_bounds__((ColCfg<L, R, MODE>::NT)) void k_col(ColArgs a, con
       if (!a.precond && FIRST) {
         mv[s] = cscale(mv[s], sc);
       } else {
-        HelmMult<R> h = a.precond ? mult_helm<R>(kx, ky, kz, a.g, a.rho0, a.nu, !FIRST)
+        HelmMult<R> h = a.precond ? mult_helm<R>(kx, ky, kz, a.g, rho0, a.nu, !FIRST)
                                   : HelmMult<R>{R(0), R(0)};
         if (!a.precond) {  // last pass without preconditioner: nu |k|^2 v
           R kyz = ksq_yz<R>(ky, kz, a.g);
@@ -306,7 +330,6 @@ enum RowMode {
   ROW_P1,       // 1D pressure: y = -i k'_x F(a F^-1(i k'_x M v))
   ROW_H,        // Helmholtz x pass (rho times), one field
   ROW_H1,       // 1D Helmholtz: y = F(rho F^-1(M v)) + nu k^2 M v
-  ROW_HB,       // Helmholtz x pass of nf <= 3 independent fields (one wavefront each), gate per field
 };
 
 struct RowArgs {
@@ -321,15 +344,19 @@ struct RowArgs {
   int precond;
   const double* in_scale;
   const int* gate;  // nonzero *gate: the launch does nothing
-  const int* fgate[kMaxBatch];  // ROW_HB: field f's gate
+  // The operator x passes (ROW_P, ROW_H): system blockIdx.y < nb reads its
+  // fields, coefficient rows, scale, preconditioner constant and gate from
+  // sys[blockIdx.y] (nb = 1 for one system, filled by the launcher); the
+  // other modes use in/out/coef/... directly.
+  int nb;
+  SysArgs sys[kMaxBatch];
 };
 
 // Wavefronts per block: the pressure x pass runs its (up to three) fields as
-// one wavefront each over the same rows, and so does the batched Helmholtz
-// x pass (several systems); the other modes run four wavefronts over
-// consecutive row groups.
+// one wavefront each over the same rows; the other modes run four
+// wavefronts over consecutive row groups.
 template <int MODE>
-constexpr bool row_field_waves() { return MODE == ROW_P || MODE == ROW_HB; }
+constexpr bool row_field_waves() { return MODE == ROW_P; }
 template <int MODE>
 constexpr int row_waves() { return row_field_waves<MODE>() ? 3 : 4; }
 
@@ -345,7 +372,23 @@ __global__ __launch_bounds__(64 * row_waves<MODE>()) void k_row(RowArgs a, const
   constexpr int NW = row_waves<MODE>();
   constexpr bool FW = row_field_waves<MODE>();
   constexpr int RB = FW ? RW : NW * RW;  // rows per block
-  if (a.gate && *a.gate) return;
+  // the operator x passes: the block's system (one code path for a launch
+  // of one system and a batch); the other modes: the launch's arguments
+  constexpr bool SYS = MODE == ROW_P || MODE == ROW_H;
+  KSys* sy = SYS ? block_sys<RowArgs>() : nullptr;
+  const int* gate = SYS ? sy->gate : a.gate;
+  if (gate && *gate) return;
+  auto IN = [&](int f) -> const void* {
+    if constexpr (SYS) return sy->in[f];
+    else return a.in[f];
+  };
+  auto OUT = [&](int f) -> void* {
+    if constexpr (SYS) return sy->out[f];
+    else return a.out[f];
+  };
+  const void* coefp = SYS ? sy->coef : a.coef;
+  const double* iscale = SYS ? sy->in_scale : a.in_scale;
+  const double rho0 = SYS ? sy->rho0 : a.rho0;
   __shared__ C2<R> lds_all[NW * RW * LP];
   // twiddle tables in LDS: a load in every butterfly pass from global memory
   // (even an L1 hit) costs latency inside the transform and address registers
@@ -363,13 +406,6 @@ __global__ __launch_bounds__(64 * row_waves<MODE>()) void k_row(RowArgs a, const
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
   const int lane = threadIdx.x % 64;
   const int fsel = FW ? wave : 0;
-  // ROW_HB: a field whose system has stopped is skipped by its wavefront
-  // (after the block barrier above; the rest of the pass has wavefront-level
-  // synchronisation only)
-  if constexpr (MODE == ROW_HB) {
-    const int* fg = pick(a.fgate, fsel);
-    if (fg && *fg) return;
-  }
   const int t = lane % T;
   const int rr = (FW ? 0 : wave * RW) + lane / T;  // row within the block
   // The x passes sweep the rows last block first: the pass before them (a
@@ -378,8 +414,7 @@ __global__ __launch_bounds__(64 * row_waves<MODE>()) void k_row(RowArgs a, const
   // what this pass wrote last.  At 256^3 FP64 the three pressure fields
   // (384 MiB) exceed that cache; the reversed sweep takes the x pass from
   // 218 to 199 us and the following y pass from 130 to 114 us.
-  const int bx = (MODE == ROW_P || MODE == ROW_H || MODE == ROW_HB) ? (int)(gridDim.x - 1 - blockIdx.x)
-                                                                   : (int)blockIdx.x;
+  const int bx = (MODE == ROW_P || MODE == ROW_H) ? (int)(gridDim.x - 1 - blockIdx.x) : (int)blockIdx.x;
   const int row = bx * RB + rr;
   const bool ok = row < a.nrows;
   LdsRow<R> lds{lds_all + (FW ? fsel * RW + rr : rr) * LP};
@@ -391,12 +426,12 @@ __global__ __launch_bounds__(64 * row_waves<MODE>()) void k_row(RowArgs a, const
       if (f == 0) return cik(X, R(k) * sx);  // slot 0: k'_x = 0 for both halves
       return X;
     } else if constexpr (MODE == ROW_P1) {
-      R m = a.precond ? mult_press<R>(k, 0, 0, a.g, a.rho0) : R(1);
-      return cik(X, R(k) * sx * m * in_scale_of<R>(a.in_scale));
+      R m = a.precond ? mult_press<R>(k, 0, 0, a.g, rho0) : R(1);
+      return cik(X, R(k) * sx * m * in_scale_of<R>(iscale));
     } else if constexpr (MODE == ROW_H1) {
-      R sc = in_scale_of<R>(a.in_scale);
+      R sc = in_scale_of<R>(iscale);
       if (!a.precond) return cscale(X, sc);
-      HelmMult<R> h = mult_helm<R>(k, 0, 0, a.g, a.rho0, a.nu, false);
+      HelmMult<R> h = mult_helm<R>(k, 0, 0, a.g, rho0, a.nu, false);
       if (k == 0) return C2<R>{X.x * h.g0 * sc, X.y * h.gN * sc};
       return cscale(X, h.g0 * sc);
     } else {
@@ -458,12 +493,12 @@ __global__ __launch_bounds__(64 * row_waves<MODE>()) void k_row(RowArgs a, const
       } else if constexpr (MODE == ROW_H1) {
         // + nu |k|^2 M v (slot 0: halves kx = 0 and kx = nx/2)
         C2<R> V = ok ? ldg(vsrc + (size_t)row * L + k) : C2<R>{R(0), R(0)};
-        R sc = in_scale_of<R>(a.in_scale);
+        R sc = in_scale_of<R>(iscale);
         R k2 = R(k) * sx;
         k2 *= k2;
         R kn = R(a.g.M) * sx;
         if (a.precond) {
-          HelmMult<R> h = mult_helm<R>(k, 0, 0, a.g, a.rho0, a.nu, true);
+          HelmMult<R> h = mult_helm<R>(k, 0, 0, a.g, rho0, a.nu, true);
           if (k == 0) X = X + C2<R>{R(0), V.y * h.gN * sc};
           else X = X + cscale(V, h.g0 * sc);
         } else {
@@ -476,18 +511,18 @@ __global__ __launch_bounds__(64 * row_waves<MODE>()) void k_row(RowArgs a, const
   };
 
   if constexpr (MODE == ROW_R2C) {
-    const C2<R>* src = (const C2<R>*)a.in[0];  // real row viewed as complex pairs
+    const C2<R>* src = (const C2<R>*)IN(0);  // real row viewed as complex pairs
 #pragma unroll
     for (int s = 0; s < E; ++s) {
       int m = pat_index<L, E, RF0>(t, s);
       reg[s] = ok ? ldg(src + (size_t)row * L + m) : C2<R>{R(0), R(0)};
     }
     fft_line<L, E, -1, true, WV>(reg, lds, tw, t);
-    forward_post(0, (C2<R>*)a.out[0], nullptr);
+    forward_post(0, (C2<R>*)OUT(0), nullptr);
   } else if constexpr (MODE == ROW_C2R) {
-    inverse_row((const C2<R>*)a.in[0], 0);
+    inverse_row((const C2<R>*)IN(0), 0);
     const R cs = R(a.cscale);
-    C2<R>* dst = (C2<R>*)a.out[0];
+    C2<R>* dst = (C2<R>*)OUT(0);
     if (ok) {
 #pragma unroll
       for (int s = 0; s < E; ++s) {
@@ -496,7 +531,7 @@ __global__ __launch_bounds__(64 * row_waves<MODE>()) void k_row(RowArgs a, const
       }
     }
   } else {
-    const C2<R>* coef = (const C2<R>*)a.coef;
+    const C2<R>* coef = (const C2<R>*)coefp;
     const R cs = R(a.cscale);
     const int f = fsel;
     // pressure x pass: issue the coefficient row's loads before the inverse
@@ -511,7 +546,7 @@ __global__ __launch_bounds__(64 * row_waves<MODE>()) void k_row(RowArgs a, const
         qv[s] = ok ? ldg(coef + (size_t)row * L + m) : C2<R>{R(0), R(0)};
       }
     }
-    inverse_row((const C2<R>*)a.in[f], f);
+    inverse_row((const C2<R>*)IN(f), f);
 #pragma unroll
     for (int s = 0; s < E; ++s) {
       C2<R> q;
@@ -524,7 +559,7 @@ __global__ __launch_bounds__(64 * row_waves<MODE>()) void k_row(RowArgs a, const
       reg[s] = C2<R>{reg[s].x * (q.x * cs), reg[s].y * (q.y * cs)};
     }
     fft_line<L, E, -1, true, WV>(reg, lds, tw, t);
-    forward_post(f, (C2<R>*)a.out[f], (const C2<R>*)a.in[0]);
+    forward_post(f, (C2<R>*)OUT(f), (const C2<R>*)IN(0));
   }
 }
 
@@ -584,11 +619,28 @@ void lap_packed(const Geom& g, const void* x, void* y, hipStream_t st) {
 
 // ------------------------------------------------------------ launchers
 
+// A launch of one system carries it as sys[0] (the kernels read every
+// system's arguments from sys[blockIdx.y]).
+template <typename Args>
+static void as_systems(Args& a) {
+  if (a.nb > 0) return;
+  a.nb = 1;
+  SysArgs& y = a.sys[0];
+  for (int i = 0; i < 3; ++i) {
+    y.in[i] = a.in[i];
+    y.out[i] = a.out[i];
+  }
+  y.rho0 = a.rho0;
+  y.in_scale = a.in_scale;
+  y.gate = a.gate;
+}
+
 template <typename R, int MODE, int L>
 static void launch_col_L(const ColArgs& a0, const void* tw, hipStream_t st) {
   ColArgs a = a0;
+  as_systems(a);
   a.ntile = (a.inner + ColCfg<L, R, MODE>::TC - 1) / ColCfg<L, R, MODE>::TC;
-  dim3 grid(a.outer * a.ntile, a.nb > 0 ? a.nb : 1);
+  dim3 grid(a.outer * a.ntile, a.nb);
   hipLaunchKernelGGL((k_col<L, R, MODE>), grid, dim3(ColCfg<L, R, MODE>::NT), 0, st, a, (const C2<R>*)tw);
 }
 
@@ -607,11 +659,18 @@ static void launch_col(int L, const ColArgs& a, const void* tw, hipStream_t st) 
 }
 
 template <typename R, int MODE, int L>
-static void launch_row_L(const RowArgs& a, const void* tw, hipStream_t st) {
+static void launch_row_L(const RowArgs& a0, const void* tw, hipStream_t st) {
   constexpr int RW = RowCfg<L, R>::RW;
+  RowArgs a = a0;
+  int ny = 1;
+  if constexpr (MODE == ROW_P || MODE == ROW_H) {
+    if (a.nb == 0) a.sys[0].coef = a.coef;
+    as_systems(a);
+    ny = a.nb;
+  }
   const int rb = row_field_waves<MODE>() ? RW : row_waves<MODE>() * RW;
-  dim3 grid((a.nrows + rb - 1) / rb);
-  // ROW_P, ROW_HB: one wavefront per field (<= 3)
+  dim3 grid((a.nrows + rb - 1) / rb, ny);
+  // ROW_P: one wavefront per field (<= 3)
   const int waves = row_field_waves<MODE>() ? a.nf : row_waves<MODE>();
   hipLaunchKernelGGL((k_row<L, R, MODE>), grid, dim3(64 * waves), 0, st, a, (const C2<R>*)tw);
 }
@@ -784,75 +843,108 @@ void op_apply(const Geom& g, const OpParams& p, const void* v, void* y, const Op
 }
 
 template <typename R>
-void op_apply_helm_batch(const Geom& g, const OpParams& p, const OpBatch& b, const void* coef, const void* twtab,
-                         hipStream_t st, Prof* prof) {
+void op_apply_batch(const Geom& g, const OpParams& p, const OpBatch& b, const void* coef, const void* twtab,
+                    hipStream_t st, Prof* prof) {
   const int nb = b.nb;
   const bool pr = prof && prof->on;
   const double fb = (double)g.nz * g.ny * g.M * sizeof(C2<R>);  // one field
   const size_t zin = (size_t)g.ny * g.M;
-  // per-field inputs, outputs, scales and gates of a column launch
-  auto cset = [&](ColArgs& a, const void* const* in, const void* const* in2, void* const* out, bool scaled) {
+  const bool helm = p.kind == OP_HELMHOLTZ;
+  // system k's fields in[]/out[] of a launch, with its own scale (first
+  // pass only), preconditioner constant, coefficient rows and gate
+  auto sys_of = [&](int k, std::initializer_list<const void*> in, std::initializer_list<void*> out, bool scaled) {
+    SysArgs y{};
+    int i = 0;
+    for (const void* q : in) y.in[i++] = q;
+    i = 0;
+    for (void* q : out) y.out[i++] = q;
+    y.coef = b.coef[k] ? b.coef[k] : coef;
+    y.rho0 = helm ? p.rho0 : b.rho0[k];
+    y.in_scale = scaled ? b.in_scale[k] : nullptr;
+    y.gate = b.gate[k];
+    return y;
+  };
+  auto col = [&](bool fft) {
+    ColArgs a = fft ? col_args_fft(g, p) : col_args(g, &p);
     a.gate = nullptr;
     a.in_scale = nullptr;
     a.nb = nb;
-    for (int f = 0; f < nb; ++f) {
-      a.fin[f] = in[f];
-      a.fin2[f] = in2 ? in2[f] : nullptr;
-      a.fout[f] = out[f];
-      a.fscale[f] = scaled ? b.in_scale[f] : nullptr;
-      a.fgate[f] = b.gate[f];
-    }
+    return a;
   };
-  const void* tin[kMaxBatch];
-  for (int f = 0; f < nb; ++f) tin[f] = b.t[f];
-  ColArgs a = col_args(g, &p);
-  a.outer = 1;
-  a.inner = (int)zin;
-  cset(a, b.v, nullptr, b.t, true);
-  if (pr) prof->begin(5, st, 2 * nb * fb);
-  launch_col<R, COL_H_FIRST>(g.nz, a, twtab, st);
-  if (pr) prof->end(st);
-  if (g.ny > 1) {
-    ColArgs c = col_args_fft(g, p);
+  auto timed = [&](int cls, double fields, auto&& launch) {
+    if (pr) prof->begin(cls, st, fields * fb);
+    launch();
+    if (pr) prof->end(st);
+  };
+  if (helm) {
+    // one work field per system
+    ColArgs a = col(false);
+    a.outer = 1;
+    a.inner = (int)zin;
+    for (int k = 0; k < nb; ++k) a.sys[k] = sys_of(k, {b.v[k]}, {b.t[k][0]}, true);
+    timed(5, 2.0 * nb, [&] { launch_col<R, COL_H_FIRST>(g.nz, a, twtab, st); });
+    ColArgs c = col(true);
     c.outer = g.nz;
     c.inner = g.M;
     c.nf = 1;
-    cset(c, tin, nullptr, b.t, false);
-    if (pr) prof->begin(6, st, 2 * nb * fb);
-    launch_col<R, COL_FFT_INV>(g.ny, c, twtab, st);
-    if (pr) prof->end(st);
+    for (int k = 0; k < nb; ++k) c.sys[k] = sys_of(k, {b.t[k][0]}, {b.t[k][0]}, false);
+    if (g.ny > 1) timed(6, 2.0 * nb, [&] { launch_col<R, COL_FFT_INV>(g.ny, c, twtab, st); });
+    RowArgs r = row_args(g, &p);
+    r.gate = nullptr;
+    r.in_scale = nullptr;
+    r.coef = nullptr;
+    r.cscale = g.ntot_inv;
+    r.nb = nb;
+    for (int k = 0; k < nb; ++k) r.sys[k] = sys_of(k, {b.t[k][0]}, {b.t[k][0]}, false);
+    timed(7, 3.0 * nb, [&] { launch_row<R, ROW_H>(g.M, r, twtab, st); });
+    if (g.ny > 1) timed(8, 2.0 * nb, [&] { launch_col<R, COL_FFT_FWD>(g.ny, c, twtab, st); });
+    ColArgs d = col(false);
+    d.outer = 1;
+    d.inner = (int)zin;
+    for (int k = 0; k < nb; ++k) d.sys[k] = sys_of(k, {b.t[k][0], b.v[k]}, {b.y[k]}, true);
+    timed(9, 3.0 * nb, [&] { launch_col<R, COL_H_LAST>(g.nz, d, twtab, st); });
+    return;
   }
+  // pressure (2D and 3D grids): the passes of op_apply, system k on
+  // blockIdx.y with its own coefficient rows and preconditioner constant
+  ColArgs a = col(false);
+  a.outer = 1;
+  a.inner = (int)zin;
+  for (int k = 0; k < nb; ++k) a.sys[k] = sys_of(k, {b.v[k]}, {b.t[k][0], b.t[k][1]}, true);
+  timed(0, 3.0 * nb, [&] { launch_col<R, COL_P_FIRST>(g.nz, a, twtab, st); });
   RowArgs r = row_args(g, &p);
   r.gate = nullptr;
   r.in_scale = nullptr;
-  r.nf = nb;
-  for (int f = 0; f < nb; ++f) {
-    r.in[f] = b.t[f];
-    r.out[f] = b.t[f];
-    r.fgate[f] = b.gate[f];
-  }
-  r.coef = coef;
+  r.coef = nullptr;
   r.cscale = g.ntot_inv;
-  if (pr) prof->begin(7, st, (2 * nb + 1) * fb);  // the coefficient row is read once for every field
-  launch_row<R, ROW_HB>(g.M, r, twtab, st);
-  if (pr) prof->end(st);
+  r.nb = nb;
   if (g.ny > 1) {
-    ColArgs c = col_args_fft(g, p);
+    ColArgs c = col(false);
     c.outer = g.nz;
     c.inner = g.M;
-    c.nf = 1;
-    cset(c, tin, nullptr, b.t, false);
-    if (pr) prof->begin(8, st, 2 * nb * fb);
-    launch_col<R, COL_FFT_FWD>(g.ny, c, twtab, st);
-    if (pr) prof->end(st);
+    for (int k = 0; k < nb; ++k)
+      c.sys[k] = sys_of(k, {b.t[k][0], b.t[k][1]}, {b.t[k][0], b.t[k][2], b.t[k][1]}, false);
+    timed(1, 5.0 * nb, [&] { launch_col<R, COL_P_MIDINV>(g.ny, c, twtab, st); });
+    r.nf = 3;
+    for (int k = 0; k < nb; ++k)
+      r.sys[k] = sys_of(k, {b.t[k][0], b.t[k][2], b.t[k][1]}, {b.t[k][0], b.t[k][2], b.t[k][1]}, false);
+    timed(2, 7.0 * nb, [&] { launch_row<R, ROW_P>(g.M, r, twtab, st); });
+    ColArgs c2 = col(false);
+    c2.outer = g.nz;
+    c2.inner = g.M;
+    for (int k = 0; k < nb; ++k)
+      c2.sys[k] = sys_of(k, {b.t[k][0], b.t[k][2], b.t[k][1]}, {b.t[k][0], b.t[k][1]}, false);
+    timed(3, 5.0 * nb, [&] { launch_col<R, COL_P_MIDFWD>(g.ny, c2, twtab, st); });
+  } else {
+    r.nf = 2;
+    for (int k = 0; k < nb; ++k) r.sys[k] = sys_of(k, {b.t[k][0], b.t[k][1]}, {b.t[k][0], b.t[k][1]}, false);
+    timed(2, 5.0 * nb, [&] { launch_row<R, ROW_P>(g.M, r, twtab, st); });
   }
-  ColArgs d = col_args(g, &p);
+  ColArgs d = col(false);
   d.outer = 1;
   d.inner = (int)zin;
-  cset(d, tin, b.v, b.y, true);
-  if (pr) prof->begin(9, st, 3 * nb * fb);
-  launch_col<R, COL_H_LAST>(g.nz, d, twtab, st);
-  if (pr) prof->end(st);
+  for (int k = 0; k < nb; ++k) d.sys[k] = sys_of(k, {b.t[k][0], b.t[k][1]}, {b.y[k]}, false);
+  timed(4, 3.0 * nb, [&] { launch_col<R, COL_P_LAST>(g.nz, d, twtab, st); });
 }
 
 template <typename R>
@@ -1012,10 +1104,10 @@ template void op_apply<double>(const Geom&, const OpParams&, const void*, void*,
                                const void*, hipStream_t, Prof*);
 template void op_apply<float>(const Geom&, const OpParams&, const void*, void*, const OpWork&, const void*,
                               const void*, hipStream_t, Prof*);
-template void op_apply_helm_batch<double>(const Geom&, const OpParams&, const OpBatch&, const void*, const void*,
-                                          hipStream_t, Prof*);
-template void op_apply_helm_batch<float>(const Geom&, const OpParams&, const OpBatch&, const void*, const void*,
-                                         hipStream_t, Prof*);
+template void op_apply_batch<double>(const Geom&, const OpParams&, const OpBatch&, const void*, const void*,
+                                     hipStream_t, Prof*);
+template void op_apply_batch<float>(const Geom&, const OpParams&, const OpBatch&, const void*, const void*,
+                                    hipStream_t, Prof*);
 template void precond_apply<double>(const Geom&, const OpParams&, const void*, void*, hipStream_t);
 template void precond_apply<float>(const Geom&, const OpParams&, const void*, void*, hipStream_t);
 

@@ -76,23 +76,29 @@ void op_apply(const Geom& g, const OpParams& p, const void* v, void* y, const Op
               const void* coef /* real [nz][ny][nx]: 1/rho (pressure) or rho (Helmholtz) */,
               const void* twtab, hipStream_t st, Prof* prof = nullptr);
 
-// The Helmholtz-type operator for nb <= kMaxBatch independent fields
-// (3D or 2D grids): y[f] = A (M^-1 (s_f v[f])), one launch per pass for all
-// fields, the x pass reading each coefficient row once for every field.
-// t[f]: one work field each; in_scale[f]: device scalar or null; gate[f]:
-// device flag, nonzero = field f is skipped.  Each field's arithmetic is that
-// of op_apply (bitwise the same result).
+// The operator for nb <= kMaxBatch independent systems of one grid shape
+// (2D or 3D grids), y[k] = A_k (M_k^-1 (s_k v[k])), one launch per pass for
+// all of them (system k on blockIdx.y = k).  Every pass kernel reads its
+// system's arguments the same way for one system and for several, so each
+// system's result is bitwise that of op_apply.  t[k]: the system's work
+// fields (Helmholtz: t[k][0] only; pressure: two in 2D, three in 3D);
+// in_scale[k]: device scalar or null; gate[k]: device flag, nonzero =
+// system k is skipped.  Helmholtz: the systems share coef and p.rho0 (the
+// components of one velocity solve).  Pressure: system k uses coef[k] (its
+// rows of 1/rho) and rho0[k].
 struct OpBatch {
   int nb;
   const void* v[kMaxBatch];
   void* y[kMaxBatch];
-  void* t[kMaxBatch];
+  void* t[kMaxBatch][3];
+  const void* coef[kMaxBatch];
+  double rho0[kMaxBatch];
   const double* in_scale[kMaxBatch];
   const int* gate[kMaxBatch];
 };
 template <typename R>
-void op_apply_helm_batch(const Geom& g, const OpParams& p, const OpBatch& b, const void* coef, const void* twtab,
-                         hipStream_t st, Prof* prof = nullptr);
+void op_apply_batch(const Geom& g, const OpParams& p, const OpBatch& b, const void* coef, const void* twtab,
+                    hipStream_t st, Prof* prof = nullptr);
 
 // Diagonal preconditioner in spectral space: z = M^-1 r (separate buffers).
 template <typename R>

@@ -30,6 +30,7 @@
 namespace {
 
 using Clock = std::chrono::steady_clock;
+constexpr int kBatchMax = 3;  // requests per shared batch (vd_solve_pressure_batch)
 
 struct GridEntry {
   vd_grid* grid = nullptr;
@@ -76,12 +77,16 @@ struct vd_server {
   std::condition_variable cv_work, cv_done;
   std::deque<Job> queue;
   std::vector<GridEntry*> grids;
+  // a slot's work: one request, or a batch of pressure requests of one
+  // shape and options solved together (vd_solve_pressure_batch)
   struct Assign {
     bool has = false;
-    Job job;
-    GridEntry* ge = nullptr;
+    int nj = 0;
+    Job job[kBatchMax];
+    GridEntry* ge[kBatchMax] = {};
     double t_start = 0;
   };
+  int max_batch = kBatchMax;
   std::vector<Assign> slots;
   std::vector<std::thread> workers;
   std::deque<vd_result> done;
@@ -102,7 +107,67 @@ int busy_slots(vd_server* S) {
   return b;
 }
 
+// An idle grid that a job may use: its shape and footprint class (equal
+// charges: the same number of Helmholtz components solved together), or a
+// new one if the budget has room (evict: release idle grids of other shapes
+// while the budget blocks, for the head of the queue only).  nullptr if none.
+GridEntry* acquire_grid(vd_server* S, const Job& job, bool evict) {
+  for (auto* g : S->grids)
+    if (!g->busy && same_desc(g->desc, job.req.desc) && same_footprint(g->opts, job.req.opts) &&
+        g->bytes == job.bytes)
+      return g;
+  while (evict && S->used + job.bytes > S->budget) {
+    GridEntry* victim = nullptr;
+    for (auto* g : S->grids)
+      if (!g->busy) { victim = g; break; }
+    if (!victim) break;
+    if (!S->dry) {
+      vd_grid_destroy(victim->grid);
+      hipStreamDestroy(victim->stream);
+    }
+    S->used -= victim->bytes;
+    for (size_t i = 0; i < S->grids.size(); ++i)
+      if (S->grids[i] == victim) { S->grids.erase(S->grids.begin() + i); break; }
+    delete victim;
+  }
+  if (S->used + job.bytes > S->budget) return nullptr;
+  GridEntry* ge = new GridEntry();
+  ge->desc = job.req.desc;
+  ge->opts = job.req.opts;
+  ge->bytes = job.bytes;
+  S->used += job.bytes;
+  S->peak_used = S->used > S->peak_used ? S->used : S->peak_used;
+  S->grids.push_back(ge);
+  return ge;
+}
+
+// Requests that vd_solve_pressure_batch runs with shared launches: pressure,
+// GMRES, direct form, a Fourier grid of two or three dimensions.
+bool batchable(const vd_request& r) {
+  if (r.kind != VD_OP_PRESSURE || r.opts.solver != VD_GMRES || r.opts.formulation != VD_FORM_L) return false;
+  if (r.desc.ndim < 2) return false;
+  for (int i = 0; i < r.desc.ndim; ++i)
+    if (r.desc.basis[i] != VD_FOURIER) return false;
+  return true;
+}
+
+// Requests that can share one batch: the same grid shape and the same solve
+// options (no history)
+bool same_batch(const vd_request& a, const vd_request& b) {
+  if (!same_desc(a.desc, b.desc)) return false;
+  const vd_solve_opts &x = a.opts, &y = b.opts;
+  if (x.history || y.history) return false;
+  return x.solver == y.solver && x.restart == y.restart && x.max_iter == y.max_iter && x.rtol == y.rtol &&
+         x.precond == y.precond && x.precision == y.precision && x.inner_rtol == y.inner_rtol &&
+         x.max_outer == y.max_outer && x.use_x0 == y.use_x0 && x.formulation == y.formulation &&
+         (x.rho0 == y.rho0 || (x.rho0 != x.rho0 && y.rho0 != y.rho0));
+}
+
 // Admit queued jobs in FIFO order while they fit.  Caller holds the lock.
+// The head of the queue is admitted first; when it can share launches, up to
+// max_batch - 1 later requests of the same shape and options that find a
+// grid without evicting join its batch (they overtake requests of other
+// shapes, which wait for the next free slot as before).
 void admit(vd_server* S) {
   while (!S->queue.empty()) {
     Job& job = S->queue.front();
@@ -110,69 +175,84 @@ void admit(vd_server* S) {
     for (int i = 0; i < S->max_slots; ++i)
       if (!S->slots[i].has) { slot = i; break; }
     if (slot < 0) return;
-    GridEntry* ge = nullptr;
-    for (auto* g : S->grids)
-      // equal charges: the same number of Helmholtz components solved together
-      if (!g->busy && same_desc(g->desc, job.req.desc) && same_footprint(g->opts, job.req.opts) &&
-          g->bytes == job.bytes) {
-        ge = g;
-        break;
-      }
-    if (!ge) {
-      // release idle grids of other shapes while the budget blocks the head
-      while (S->used + job.bytes > S->budget) {
-        GridEntry* victim = nullptr;
-        for (auto* g : S->grids)
-          if (!g->busy) { victim = g; break; }
-        if (!victim) break;
-        if (!S->dry) {
-          vd_grid_destroy(victim->grid);
-          hipStreamDestroy(victim->stream);
-        }
-        S->used -= victim->bytes;
-        for (size_t i = 0; i < S->grids.size(); ++i)
-          if (S->grids[i] == victim) { S->grids.erase(S->grids.begin() + i); break; }
-        delete victim;
-      }
-      if (S->used + job.bytes > S->budget) return;  // head of line waits
-      ge = new GridEntry();
-      ge->desc = job.req.desc;
-      ge->opts = job.req.opts;
-      ge->bytes = job.bytes;
-      S->used += job.bytes;
-      S->peak_used = S->used > S->peak_used ? S->used : S->peak_used;
-      S->grids.push_back(ge);
-    }
+    GridEntry* ge = acquire_grid(S, job, true);
+    if (!ge) return;  // head of line waits
     ge->busy = true;
     auto& a = S->slots[slot];
     a.has = true;
-    a.job = job;
-    a.ge = ge;
+    a.nj = 1;
+    a.job[0] = job;
+    a.ge[0] = ge;
     a.t_start = S->now();
     S->queue.pop_front();
+    if (batchable(a.job[0].req)) {
+      for (size_t q = 0; q < S->queue.size() && a.nj < S->max_batch;) {
+        Job& cand = S->queue[q];
+        if (!same_batch(cand.req, a.job[0].req)) { ++q; continue; }
+        GridEntry* g2 = acquire_grid(S, cand, false);
+        if (!g2) break;
+        g2->busy = true;
+        a.job[a.nj] = cand;
+        a.ge[a.nj] = g2;
+        ++a.nj;
+        S->queue.erase(S->queue.begin() + (long)q);
+      }
+    }
     int b = busy_slots(S);
     S->peak_busy = b > S->peak_busy ? b : S->peak_busy;
     S->cv_work.notify_all();
   }
 }
 
-vd_status run_job(vd_server* S, GridEntry* ge, const vd_request& r, vd_solve_info* info) {
-  if (S->dry) {
-    if (S->dry_seconds > 0) std::this_thread::sleep_for(std::chrono::duration<double>(S->dry_seconds));
-    std::memset(info, 0, sizeof(*info));
-    info->status = VD_ENOTSUP;  // scheduler dry run: nothing was solved
-    return VD_ENOTSUP;
-  }
+vd_status ensure_grid(GridEntry* ge, const vd_request& r) {
   if (!ge->grid) {
     if (hipStreamCreateWithFlags(&ge->stream, hipStreamNonBlocking) != hipSuccess) return VD_EDEVICE;
     vd_status s = vd_grid_create(&ge->grid, &ge->desc, ge->stream);
     if (s != VD_OK) return s;
   }
-  vd_status s = vd_set_density(ge->grid, r.rho);
-  if (s != VD_OK) return s;
-  if (r.kind == VD_OP_HELMHOLTZ)
-    return vd_solve_helmholtz(ge->grid, r.dt_nu, r.ncomp > 0 ? r.ncomp : 1, r.f, r.x, &r.opts, info);
-  return vd_solve_pressure(ge->grid, r.f, r.x, &r.opts, info);
+  return vd_set_density(ge->grid, r.rho);
+}
+
+// Run a slot's requests; st[k], info[k] per request.
+void run_batch(vd_server* S, vd_server::Assign& a, vd_status* st, vd_solve_info* info) {
+  for (int k = 0; k < a.nj; ++k) std::memset(&info[k], 0, sizeof(info[k]));
+  if (S->dry) {
+    if (S->dry_seconds > 0) std::this_thread::sleep_for(std::chrono::duration<double>(S->dry_seconds));
+    for (int k = 0; k < a.nj; ++k) {  // scheduler dry run: nothing solved
+      st[k] = VD_ENOTSUP;
+      info[k].status = VD_ENOTSUP;
+    }
+    return;
+  }
+  // grids and densities; a request whose grid fails is reported alone
+  vd_grid* grids[kBatchMax];
+  const double* f[kBatchMax];
+  double* x[kBatchMax];
+  int idx[kBatchMax], n = 0;
+  for (int k = 0; k < a.nj; ++k) {
+    const vd_request& r = a.job[k].req;
+    st[k] = ensure_grid(a.ge[k], r);
+    if (st[k] != VD_OK) continue;
+    if (r.kind == VD_OP_HELMHOLTZ) {
+      st[k] = vd_solve_helmholtz(a.ge[k]->grid, r.dt_nu, r.ncomp > 0 ? r.ncomp : 1, r.f, r.x, &r.opts, &info[k]);
+      continue;
+    }
+    grids[n] = a.ge[k]->grid;
+    f[n] = r.f;
+    x[n] = r.x;
+    idx[n++] = k;
+  }
+  if (n == 1) {
+    const int k = idx[0];
+    st[k] = vd_solve_pressure(grids[0], f[0], x[0], &a.job[k].req.opts, &info[k]);
+  } else if (n > 1) {
+    vd_solve_info inf[kBatchMax] = {};
+    vd_solve_pressure_batch(grids, n, f, x, &a.job[idx[0]].req.opts, inf);  // fills every info
+    for (int q = 0; q < n; ++q) {
+      info[idx[q]] = inf[q];
+      st[idx[q]] = (vd_status)inf[q].status;
+    }
+  }
 }
 
 void worker_main(vd_server* S, int slot) {
@@ -184,34 +264,39 @@ void worker_main(vd_server* S, int slot) {
       if (!S->slots[slot].has && S->stop) return;
       a = S->slots[slot];
     }
-    vd_solve_info info{};
-    vd_status st = run_job(S, a.ge, a.job.req, &info);
-    vd_result res{};
-    res.ticket = a.job.ticket;
-    res.user_tag = a.job.req.user_tag;
-    res.status = st;
-    res.iterations = info.iterations;
-    res.refinements = info.refinements;
-    res.rel_residual = info.rel_residual;
-    res.t_arrive = a.job.t_arrive;
-    res.t_start = a.t_start;
-    res.slot = slot;
+    vd_solve_info info[kBatchMax];
+    vd_status st[kBatchMax];
+    run_batch(S, a, st, info);
     {
       std::lock_guard<std::mutex> lk(S->mu);
-      res.t_done = S->now();
-      if (st < 0 && a.ge->grid == nullptr && !S->dry) {
-        // grid could not be created: give its budget back
-        S->used -= a.ge->bytes;
-        for (size_t i = 0; i < S->grids.size(); ++i)
-          if (S->grids[i] == a.ge) { S->grids.erase(S->grids.begin() + i); break; }
-        if (a.ge->stream) hipStreamDestroy(a.ge->stream);
-        delete a.ge;
-      } else {
-        a.ge->busy = false;
+      const double t_done = S->now();
+      for (int k = 0; k < a.nj; ++k) {
+        vd_result res{};
+        res.ticket = a.job[k].ticket;
+        res.user_tag = a.job[k].req.user_tag;
+        res.status = st[k];
+        res.iterations = info[k].iterations;
+        res.refinements = info[k].refinements;
+        res.rel_residual = info[k].rel_residual;
+        res.t_arrive = a.job[k].t_arrive;
+        res.t_start = a.t_start;
+        res.t_done = t_done;
+        res.slot = slot;
+        GridEntry* ge = a.ge[k];
+        if (st[k] < 0 && ge->grid == nullptr && !S->dry) {
+          // grid could not be created: give its budget back
+          S->used -= ge->bytes;
+          for (size_t i = 0; i < S->grids.size(); ++i)
+            if (S->grids[i] == ge) { S->grids.erase(S->grids.begin() + i); break; }
+          if (ge->stream) hipStreamDestroy(ge->stream);
+          delete ge;
+        } else {
+          ge->busy = false;
+        }
+        S->done.push_back(res);
+        S->in_flight--;
       }
       S->slots[slot].has = false;
-      S->done.push_back(res);
-      S->in_flight--;
       admit(S);
     }
     S->cv_done.notify_all();
@@ -278,6 +363,13 @@ vd_status vd_server_submit(vd_server* S, const vd_request* r, unsigned long long
     if (ticket) *ticket = j.ticket;
     admit(S);
   }
+  return VD_OK;
+}
+
+vd_status vd_server_set_batch(vd_server* S, int max_requests) {
+  if (!S || max_requests < 1 || max_requests > kBatchMax) return VD_EINVAL;
+  std::lock_guard<std::mutex> lk(S->mu);
+  S->max_batch = max_requests;
   return VD_OK;
 }
 

@@ -668,54 +668,105 @@ DevState* sys_slots(vd_grid* G, int k) { return k ? G->hslotx[k] : G->hslot; }
 // each pass's output (one field) staying cached for the next pass.
 constexpr double kBatchOpBytes = 200.0 * (1 << 20);
 
+// The systems of a lockstep solve.  System k lives in grid gs[k]: its
+// Krylov vectors are that grid's buffers under role + roff[k], and it has
+// its own device state, partials, tail slots, coefficient rows (pressure)
+// and preconditioner constant.  All run on gs[0]'s stream; the other grids
+// must be idle meanwhile.  The components of one velocity solve are systems
+// of one grid (roff[k] = k * kSysRoles); pressure solves of several grids of
+// one shape are systems of their own grids.
+struct SysGroup {
+  int n = 0;
+  vd_grid* gs[kMaxBatch] = {};
+  int roff[kMaxBatch] = {};
+  DevState* dst[kMaxBatch] = {};
+  double* part[kMaxBatch] = {};
+  DevState* slots[kMaxBatch] = {};
+  double rho0[kMaxBatch] = {};
+};
+
+SysGroup components_of(vd_grid* G, int n, double rho0) {
+  ensure_systems(G, n);
+  SysGroup S;
+  S.n = n;
+  for (int k = 0; k < n; ++k) {
+    S.gs[k] = G;
+    S.roff[k] = k * kSysRoles;
+    S.dst[k] = sys_dst(G, k);
+    S.part[k] = sys_partial(G, k);
+    S.slots[k] = sys_slots(G, k);
+    S.rho0[k] = rho0;
+  }
+  return S;
+}
+
 template <typename R>
 struct KrylovBatch {
-  vd_grid* G;
+  const SysGroup& S;
+  vd_grid* G;  // gs[0]: stream, events, profile, twiddles
   int prec;
   const Geom& g;
   SolveCfg cfg;
-  const void* coef;
   const void* tw;
+  bool helm;
   bool batch_ops = false;  // one launch per pass for all systems
-  DevState* dst[kMaxBatch];
-  double* part[kMaxBatch];
-  DevState* slots[kMaxBatch];
-  void* t[kMaxBatch];
+  DevState* const* dst;
+  double* const* part;
+  DevState* const* slots;
+  const void* coef[kMaxBatch];
+  void* t[kMaxBatch][3];
   int max_iter[kMaxBatch];  // per system (refinement gives each its remaining budget)
 
-  KrylovBatch(vd_grid* G_, int prec_, const SolveCfg& c, int n) : G(G_), prec(prec_), g(G_->g), cfg(c) {
-    coef = prec == 64 ? (const void*)G->rho : (const void*)G->rho32;
+  KrylovBatch(const SysGroup& S_, int prec_, const SolveCfg& c)
+      : S(S_), G(S_.gs[0]), prec(prec_), g(S_.gs[0]->g), cfg(c), dst(S_.dst), part(S_.part), slots(S_.slots) {
     tw = prec == 64 ? G->tw64 : G->tw32;
-    for (int k = 0; k < n; ++k) {
-      dst[k] = sys_dst(G, k);
-      part[k] = sys_partial(G, k);
-      slots[k] = sys_slots(G, k);
-      t[k] = buf(G, prec, B_T0 + k * kSysRoles);
+    helm = cfg.op.kind == OP_HELMHOLTZ;
+    for (int k = 0; k < S.n; ++k) {
+      vd_grid* Gk = S.gs[k];
+      if (helm) coef[k] = prec == 64 ? (const void*)Gk->rho : (const void*)Gk->rho32;
+      else coef[k] = prec == 64 ? (const void*)Gk->a64 : (const void*)Gk->a32;
+      t[k][0] = vec(k, B_T0);
+      t[k][1] = helm ? nullptr : vec(k, B_T1);
+      t[k][2] = (helm || g.ny == 1) ? nullptr : vec(k, B_T2);
       max_iter[k] = cfg.max_iter;
     }
-    batch_ops = (double)n * G->nspec * elem_bytes(prec) <= kBatchOpBytes;
+    batch_ops = (double)S.n * G->nspec * elem_bytes(prec) <= kBatchOpBytes;
   }
-  void* vec(int k, int role) { return buf(G, prec, role + k * kSysRoles); }
+  void* vec(int k, int role) { return buf(S.gs[k], prec, role + S.roff[k]); }
+  void* basis(int k, int i) { return vec(k, B_V0 + i); }
+  OpParams params_of(int k) const {
+    OpParams p = cfg.op;
+    p.rho0 = S.rho0[k];
+    return p;
+  }
 
-  // y_q = A M^-1 v_q (with_prec) or A v_q for the systems of ob, each with
-  // its input scale and gate
-  void apply_set(const OpBatch& ob, bool with_prec) {
+  // y_q = A M^-1 v_q (with_prec) or A v_q for the systems sys[0..ob.nb) of
+  // ob (v, y, in_scale and gate filled in), each with its own work fields,
+  // coefficients and preconditioner constant
+  void apply_set(OpBatch& ob, const int* sys, bool with_prec) {
     OpParams p = cfg.op;
     p.precond = with_prec ? cfg.op.precond : 0;
+    for (int q = 0; q < ob.nb; ++q) {
+      const int k = sys[q];
+      for (int i = 0; i < 3; ++i) ob.t[q][i] = t[k][i];
+      ob.coef[q] = coef[k];
+      ob.rho0[q] = S.rho0[k];
+    }
     if (batch_ops) {
-      op_apply_helm_batch<R>(g, p, ob, coef, tw, G->st, &G->prof);
+      // Helmholtz systems share one density (the components of one grid)
+      op_apply_batch<R>(g, p, ob, coef[sys[0]], tw, G->st, &G->prof);
       return;
     }
     for (int q = 0; q < ob.nb; ++q) {
       OpParams pq = p;
+      pq.rho0 = ob.rho0[q];
       pq.in_scale = ob.in_scale[q];
       pq.gate = ob.gate[q];
       OpWork w{};
-      w.t[0] = ob.t[q];
-      op_apply<R>(g, pq, ob.v[q], ob.y[q], w, coef, tw, G->st, &G->prof);
+      for (int i = 0; i < 3; ++i) w.t[i] = ob.t[q][i];
+      op_apply<R>(g, pq, ob.v[q], ob.y[q], w, ob.coef[q], tw, G->st, &G->prof);
     }
   }
-  void* basis(int k, int i) { return vec(k, B_V0 + i); }
 
   // true residuals r_k = b_k - A x_k of the systems sys[0..ns), returned in rn
   void true_resid(const int* sys, int ns, void* const* b, void* const* x, void* const* r, double* rn) {
@@ -725,9 +776,8 @@ struct KrylovBatch {
       const int k = sys[q];
       ob.v[q] = x[k];
       ob.y[q] = vec(k, B_TMP);
-      ob.t[q] = t[k];
     }
-    apply_set(ob, false);
+    apply_set(ob, sys, false);
     for (int q = 0; q < ns; ++q) {
       const int k = sys[q];
       sub_norm<R>(g, b[k], vec(k, B_TMP), r[k], part[k], &dst[k]->nrm2, G->st);
@@ -753,7 +803,6 @@ struct KrylovBatch {
       const int k = sys[q];
       ob.v[q] = basis(k, j);
       ob.y[q] = basis(k, j + 1);
-      ob.t[q] = t[k];
       ob.in_scale[q] = &dst[k]->vs[j];
       ob.gate[q] = &dst[k]->halt;
       w[q] = basis(k, j + 1);
@@ -762,7 +811,7 @@ struct KrylovBatch {
       ds[q] = dst[k];
       ps[q] = part[k];
     }
-    apply_set(ob, true);
+    apply_set(ob, sys, true);
     gs_orthogonalize_batch<R>(g, w, V, j + 1, ds, ps, ns, G->st, &G->prof);
   }
   void post_tails(int j, const int* sys, int ns) {
@@ -882,7 +931,7 @@ struct KrylovBatch {
         for (int i = 0; i < steps[q]; ++i) P.p[i] = basis(k, i);
         void* tmp = vec(k, B_TMP);
         lincomb<R>(g, tmp, P, steps[q], dst[k]->coef, G->st);
-        OpParams plain = cfg.op;
+        OpParams plain = params_of(k);
         plain.gate = nullptr;
         precond_axpy<R>(g, plain, x[k], tmp, nullptr, 1.0, G->st);
         ++cycles[k];
@@ -904,10 +953,11 @@ struct KrylovBatch {
 // FP64 spectral buffers of the grid; GMRES, Helmholtz-type operator, 2D or
 // 3D grid), in FP64 or FP32 inside FP64 iterative refinement, as
 // solve_spectral does for one system.  hist: system 0's history.
-void solve_spectral_batch(vd_grid* G, const vd_solve_opts& o, const OpParams& op, int n, void* const* b64,
+void solve_spectral_batch(const SysGroup& S, const vd_solve_opts& o, const OpParams& op, void* const* b64,
                           void* const* x64, const double* bnorm, SolveOut* out, int* refinements,
                           std::vector<double>* hist) {
-  ensure_systems(G, n);
+  vd_grid* G = S.gs[0];
+  const int n = S.n;
   SolveCfg cfg{o.solver, o.restart, o.max_iter, o.rtol, op, -1};
   cfg.x_zero = !o.use_x0;
   int sys[kMaxBatch], ns = 0;
@@ -923,23 +973,23 @@ void solve_spectral_batch(vd_grid* G, const vd_solve_opts& o, const OpParams& op
   }
   if (ns == 0) return;
   if (o.precision == VD_FP64) {
-    KrylovBatch<double> K(G, 64, cfg, n);
+    KrylovBatch<double> K(S, 64, cfg);
     K.gmres(sys, ns, b64, x64, bnorm, out, hist);
     return;
   }
   // FP32 inner solves inside FP64 iterative refinement, per system
-  KrylovBatch<double> K64(G, 64, cfg, n);
+  KrylovBatch<double> K64(S, 64, cfg);
   SolveCfg c32 = cfg;
   c32.rtol = o.inner_rtol;
   c32.inner = true;
-  KrylovBatch<float> K32(G, 32, c32, n);
+  KrylovBatch<float> K32(S, 32, c32);
   void *r64[kMaxBatch], *r32[kMaxBatch], *d32[kMaxBatch];
   double rn[kMaxBatch] = {}, one[kMaxBatch];
   bool active[kMaxBatch] = {};
   for (int k = 0; k < n; ++k) {
-    r64[k] = buf(G, 64, B_R + k * kSysRoles);
-    r32[k] = buf(G, 32, B_B + k * kSysRoles);
-    d32[k] = buf(G, 32, B_X + k * kSysRoles);
+    r64[k] = buf(S.gs[k], 64, B_R + S.roff[k]);
+    r32[k] = buf(S.gs[k], 32, B_B + S.roff[k]);
+    d32[k] = buf(S.gs[k], 32, B_X + S.roff[k]);
     one[k] = 1.0;
   }
   if (o.use_x0) {
@@ -1404,7 +1454,8 @@ static vd_status solve_helm_batched(vd_grid* G, SolveCtx* s, const OpParams& op)
     int refin[kMaxBatch];
     std::vector<double> hist;
     const bool want_hist = c0 == 0 && s->o.history_cap > 0;
-    solve_spectral_batch(G, s->o, op, n, b64, x64, bnorm, so, refin, want_hist ? &hist : nullptr);
+    solve_spectral_batch(components_of(G, n, op.rho0), s->o, op, b64, x64, bnorm, so, refin,
+                         want_hist ? &hist : nullptr);
     if (want_hist) {
       const int nh = (int)std::min<size_t>(hist.size(), (size_t)s->o.history_cap);
       std::copy(hist.begin(), hist.begin() + nh, s->o.history);
@@ -1552,6 +1603,135 @@ static vd_status solve_common(vd_grid* G, int kind, double nu, int ncomp, const 
 
 vd_status vd_solve_pressure(vd_grid* G, const double* f, double* p, const vd_solve_opts* opts, vd_solve_info* info) {
   return solve_common(G, VD_OP_PRESSURE, 0.0, 1, f, p, opts, info);
+}
+
+// Pressure solves of n grids of one shape in lockstep (solve_spectral_batch
+// over the grids' own systems); the per-grid steps before and after the
+// Krylov loop are those of solve_impl for a Fourier grid, L form.
+struct PressureBatchCtx {
+  vd_grid* const* grids;
+  int n;
+  const double* const* f;
+  double* const* x;
+  vd_solve_opts o;
+  vd_solve_info* infos;
+  bool done;  // the infos were filled (no exception)
+};
+
+static vd_status pressure_batch_impl(vd_grid* G0, void* c) {
+  PressureBatchCtx* s = (PressureBatchCtx*)c;
+  auto t0 = std::chrono::steady_clock::now();
+  const int n = s->n;
+  SysGroup S;
+  S.n = n;
+  void *b64[kMaxBatch], *x64[kMaxBatch];
+  double bnorm[kMaxBatch];
+  OpParams op{};
+  op.kind = VD_OP_PRESSURE;
+  op.precond = s->o.precond ? 1 : 0;
+  for (int k = 0; k < n; ++k) {
+    vd_grid* G = s->grids[k];
+    s->infos[k] = vd_solve_info{};
+    S.gs[k] = G;
+    S.roff[k] = 0;
+    S.dst[k] = G->dst;
+    S.part[k] = G->partial;
+    S.slots[k] = G->hslot;
+    S.rho0[k] = std::isnan(s->o.rho0) ? G->rho_mean : s->o.rho0;
+    b64[k] = buf(G, 64, B_B);
+    x64[k] = buf(G, 64, B_X);
+    fwd_transform(G->g, s->f[k], b64[k], nullptr, G->tw64, G->st);
+    project_range(G->g, b64[k], G->dsmall, G->st);
+    scale<double>(G->g, b64[k], nullptr, -1.0, G->st);  // A = -L_rho, b = -f
+    s->infos[k].rhs_null_norm = read_scalar(G, G->dsmall);
+    if (s->o.use_x0) {
+      fwd_transform(G->g, s->x[k], x64[k], nullptr, G->tw64, G->st);
+      project_range(G->g, x64[k], G->dsmall + 1, G->st);
+    } else {
+      ck(hipMemsetAsync(x64[k], 0, G->nspec * 16, G->st));
+    }
+    bnorm[k] = host_norm_of(G, b64[k]);  // also waits for the grid's stream
+  }
+  op.rho0 = S.rho0[0];
+  SolveOut so[kMaxBatch];
+  int refin[kMaxBatch];
+  std::vector<double> hist;
+  const bool want_hist = s->o.history_cap > 0;
+  solve_spectral_batch(S, s->o, op, b64, x64, bnorm, so, refin, want_hist ? &hist : nullptr);
+  ck(hipStreamSynchronize(G0->st));
+  if (want_hist) {
+    const int nh = (int)std::min<size_t>(hist.size(), (size_t)s->o.history_cap);
+    std::copy(hist.begin(), hist.begin() + nh, s->o.history);
+    s->infos[0].history_len = nh;
+  }
+  vd_status worst = VD_OK;
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  for (int k = 0; k < n; ++k) {
+    vd_grid* G = s->grids[k];
+    inv_transform(G->g, x64[k], s->x[k], buf(G, 64, B_TMP), G->tw64, G->st);
+    ck(hipStreamSynchronize(G->st));
+    ck(hipGetLastError());
+    vd_solve_info& in = s->infos[k];
+    in.iterations = so[k].iters;
+    in.refinements = refin[k];
+    in.gs_second_passes = so[k].reorth;
+    in.rel_residual = so[k].relres;
+    in.status = so[k].status;
+    in.seconds = secs;
+    if (so[k].status < 0) worst = worst < 0 ? worst : (vd_status)so[k].status;
+    else if (so[k].status == VD_NOT_CONVERGED && worst == VD_OK) worst = VD_NOT_CONVERGED;
+  }
+  s->done = true;
+  return worst;
+}
+
+static bool same_shape(const vd_grid* a, const vd_grid* b) {
+  if (a->ndim != b->ndim) return false;
+  for (int i = 0; i < a->ndim; ++i)
+    if (a->n[i] != b->n[i] || a->len[i] != b->len[i]) return false;
+  return a->g.cheb == b->g.cheb;
+}
+
+vd_status vd_solve_pressure_batch(vd_grid* const* grids, int n, const double* const* f, double* const* p,
+                                  const vd_solve_opts* opts, vd_solve_info* infos) {
+  if (!grids || !f || !p || !infos || n < 1 || n > kMaxBatch) return VD_EINVAL;
+  auto fail = [&](vd_status st) {
+    for (int k = 0; k < n; ++k) {
+      infos[k] = vd_solve_info{};
+      infos[k].status = st;
+    }
+    return st;
+  };
+  vd_solve_opts o;
+  if (opts) o = *opts;
+  else vd_default_opts(&o);
+  if (!opts_ok(o)) return fail(VD_EINVAL);
+  for (int k = 0; k < n; ++k) {
+    if (!grids[k] || !f[k] || !p[k] || !grids[k]->has_rho) return fail(VD_EINVAL);
+    for (int q = 0; q < k; ++q)
+      if (grids[q] == grids[k]) return fail(VD_EINVAL);
+  }
+  vd_grid* G0 = grids[0];
+  bool together = n > 1 && o.solver == VD_GMRES && o.formulation == VD_FORM_L && !G0->g.cheb && G0->g.nz > 1;
+  for (int k = 1; k < n && together; ++k) together = same_shape(G0, grids[k]);
+  if (!together || (!std::isnan(o.rho0) && !(o.rho0 > 0.0))) {
+    vd_status worst = VD_OK;
+    for (int k = 0; k < n; ++k) {
+      vd_solve_opts ok = o;
+      if (k > 0) {  // the history is system 0's
+        ok.history = nullptr;
+        ok.history_cap = 0;
+      }
+      const vd_status st = vd_solve_pressure(grids[k], f[k], p[k], &ok, &infos[k]);
+      if (st < 0) worst = worst < 0 ? worst : st;
+      else if (st == VD_NOT_CONVERGED && worst == VD_OK) worst = VD_NOT_CONVERGED;
+    }
+    return worst;
+  }
+  PressureBatchCtx c{grids, n, f, p, o, infos, false};
+  const vd_status st = guard(G0, pressure_batch_impl, &c);
+  if (!c.done) return fail(st);  // a device error or allocation failure part way
+  return st;
 }
 
 vd_status vd_solve_helmholtz(vd_grid* G, double dt_nu, int ncomp, const double* g, double* u,

@@ -159,3 +159,18 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
         api.lib()
     with pytest.raises(RuntimeError, match="is missing"):
         api.vd_status_string(0)
+
+
+def test_batch_entry_points_reject_bad_arguments():
+    """Argument checks that need no device."""
+    L = api.lib()
+    assert L.vd_solve_pressure_batch(None, 2, None, None, None, None) == -1
+    g = (ctypes.c_void_p * 1)()
+    assert L.vd_solve_pressure_batch(g, 0, g, g, None, None) == -1
+    assert L.vd_server_set_batch(None, 2) == -1
+    srv = api.Server(hbm_budget=1 << 30, max_slots=1, dry_seconds=0.0)
+    for bad in (0, 4):
+        assert L.vd_server_set_batch(srv._h, bad) == -1
+    assert L.vd_server_set_batch(srv._h, 1) == 0
+    srv.close()
+

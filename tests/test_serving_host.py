@@ -20,7 +20,7 @@ def _drain(srv, count, timeout=30.0):
 
 
 def test_fifo_order_single_slot():
-    srv = api.Server(hbm_budget=1 << 40, max_slots=1, dry_seconds=0.01)
+    srv = api.Server(hbm_budget=1 << 40, max_slots=1, dry_seconds=0.01, batch=1)
     tickets = [srv.submit((128, 128), user_tag=i, precision="fp32_refine") for i in range(8)]
     res = _drain(srv, 8)
     assert [r["ticket"] for r in res] == tickets
@@ -69,13 +69,79 @@ def test_slot_limit_and_overlap():
     st = srv.stats()
     assert st["peak_busy_slots"] == 4
     assert wall < 16 * 0.05 * 0.6                   # requests overlapped
-    # never more than 4 running at any instant
-    events = sorted([(r["t_start"], 1) for r in res] + [(r["t_done"], -1) for r in res])
+    # never more than 4 slots busy at any instant (a batch's requests share
+    # their slot's start and end)
+    slots = {(r["slot"], r["t_start"], r["t_done"]) for r in res}
+    events = sorted([(a, 1) for _, a, _ in slots] + [(b, -1) for _, _, b in slots])
     run = peak = 0
     for _, d in events:
         run += d
         peak = max(peak, run)
     assert peak <= 4
+    srv.close()
+
+
+def _batches(res):
+    """Requests grouped by the slot run that served them."""
+    groups = {}
+    for r in res:
+        groups.setdefault((r["slot"], r["t_start"]), []).append(r)
+    return sorted(groups.values(), key=lambda g: g[0]["t_start"])
+
+
+def test_same_shape_requests_share_a_slot():
+    """One slot: the first request starts alone (nothing else is queued yet);
+    when the slot frees, the next three requests of its shape and options go
+    together, then the next three.  Each keeps its own grid (charge)."""
+    srv = api.Server(hbm_budget=1 << 40, max_slots=1, dry_seconds=0.05)
+    tickets = [srv.submit((128, 128), user_tag=i) for i in range(7)]
+    res = _drain(srv, 7)
+    groups = _batches(res)
+    assert [len(g) for g in groups] == [1, 3, 3]
+    assert [sorted(r["ticket"] for r in g) for g in groups] == [tickets[:1], tickets[1:4], tickets[4:7]]
+    for g in groups:
+        assert len({(r["t_start"], r["t_done"], r["slot"]) for r in g}) == 1
+    st = srv.stats()
+    assert st["grids"] == 3 and st["hbm_used"] == 3 * api.workspace_bytes((128, 128))
+    srv.close()
+
+
+def test_batches_group_only_what_can_share_launches():
+    """Only pressure GMRES requests of one shape and options share a batch:
+    another shape, another solver, a velocity request or a 1D grid each wait
+    for a slot of their own; a batched request may overtake those."""
+    srv = api.Server(hbm_budget=1 << 40, max_slots=1, dry_seconds=0.05)
+    t0 = srv.submit((64, 64))                                  # starts alone
+    others = [srv.submit((128, 128)), srv.submit((64, 64), solver="cg"),
+              srv.submit((64, 64), kind="helmholtz", dt_nu=1e-3, ncomp=2), srv.submit((256,)),
+              srv.submit((64, 64), rtol=1e-8)]
+    t1 = srv.submit((64, 64))                                  # the rtol 1e-8 request's shape, not its options
+    t2 = srv.submit((128, 128))                                # joins the queued 128^2 request
+    res = _drain(srv, 8)
+    by = {r["ticket"]: r for r in res}
+    groups = _batches(res)
+    sizes = [sorted(r["ticket"] for r in g) for g in groups]
+    assert sizes[0] == [t0]
+    assert sorted([others[0], t2]) in sizes                    # the two 128^2 requests together
+    for t in others[1:]:
+        assert [t] in sizes
+    assert [t1] in sizes
+    assert by[t2]["t_start"] < by[others[1]]["t_start"]        # batched past the queued CG request
+    srv.close()
+
+
+def test_batch_members_need_room_without_eviction():
+    """A request joins a batch only if a grid for it fits next to those held;
+    the budget here holds two 128^2 grids, so batches have two requests."""
+    one = api.workspace_bytes((128, 128))
+    srv = api.Server(hbm_budget=2 * one + one // 2, max_slots=1, dry_seconds=0.05)
+    for _ in range(5):
+        srv.submit((128, 128))
+    res = _drain(srv, 5)
+    assert [len(g) for g in _batches(res)] == [1, 2, 2]
+    assert srv.stats()["hbm_peak"] <= 2 * one + one // 2
+    with pytest.raises(api.VdError):
+        api.Server(hbm_budget=1 << 30, max_slots=1, dry_seconds=0.0, batch=4)
     srv.close()
 
 
