@@ -665,7 +665,11 @@ DevState* sys_slots(vd_grid* G, int k) { return k ? G->hslotx[k] : G->hslot; }
 // fields fit the 256 MB Infinity Cache together: a pass then finds much of
 // what the pass before it wrote still cached.  Larger fields (three FP64
 // components at 256^3: 3 x 134 MB) are applied one system after another,
-// each pass's output (one field) staying cached for the next pass.
+// each pass's output (one field) staying cached for the next pass
+// (measured, 3-component solves at 256^3, rj = 3: FP64 48.1 ms with the
+// passes applied one system after another, 49.3 ms batched; FP32+refine
+// 24.2 ms either way).  The Gram-Schmidt kernels always take all the
+// systems (one launch per system measured the same, within 0.2%).
 constexpr double kBatchOpBytes = 200.0 * (1 << 20);
 
 // The systems of a lockstep solve.  System k lives in grid gs[k]: its

@@ -375,7 +375,10 @@ __global__ __launch_bounds__(1024) void k_gs_check(DevStates S, int nv, double t
 
 template <typename R, int NV>
 __global__ __launch_bounds__(256) void k_gs_update(SysSet<R> S, int nv, size_t n, int M) {
-  const int sy = blockIdx.y;
+  // systems in reverse order and each swept last row first, so that the
+  // pass starts on what the dot pass read last (ascending systems and rows),
+  // still in the Infinity Cache
+  const int sy = (int)(gridDim.y - 1 - blockIdx.y);
   const DevState* __restrict__ st = S.st[sy];
   if (st->halt) return;
   C2<R>* __restrict__ x = S.x[sy];
