@@ -509,8 +509,8 @@ def bench_c5(args):
 def bench_pmc5(args):
     """Short 512^3 run for hardware-counter passes: the 1 GiB calibration
     copy, then `--steps` FP64 and FP32 pressure-operator applications and
-    one FP64 GMRES(30) pressure solve of the 512^3 workload capped at 12
-    iterations (its Gram-Schmidt kernels), without timing."""
+    one FP64 GMRES(30) pressure solve of the 512^3 workload, the solve that
+    the c5 workload times (the same launches), without timing."""
     import torch
     from paper_2403_06654_amd import workloads
     from paper_2403_06654_amd.api import Grid
@@ -530,7 +530,7 @@ def bench_pmc5(args):
     for prec in ("fp64", "fp32"):
         for _ in range(args.steps):
             grid.apply_operator("pressure", f, precision=prec)
-    _, info = grid.solve_pressure(f, max_iter=12)
+    _, info = grid.solve_pressure(f, p=torch.zeros_like(f), precision="fp64")
     torch.cuda.synchronize()
     grid.close()
     print(json.dumps({"pmc_run": True, "grid": n, "copy_bytes": nbytes, "applies": args.steps,

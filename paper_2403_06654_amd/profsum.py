@@ -9,6 +9,8 @@ drops those launches, and so does this summary (dispatches shorter than
 GATE_US, far below any working launch at these sizes).
 
     python -m paper_2403_06654_amd.profsum PROF_DIR BENCH_JSON N OUT.md TITLE COMMAND [TOP]
+
+BENCH_JSON "-": no class table (a run on other grids than n^3).
 """
 import csv
 import glob
@@ -71,8 +73,10 @@ def render(prof_dir, bench_line, n, title, command, top=20):
         lines.append(f"| {float(r['Percentage']):.2f} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
                      f"`{r['Name'][:110]}` |")
     lines += ["", f"Total kernel time: {total_ms:.1f} ms.", ""]
+    if bench_line is None:  # no bench line: kernels of other shapes than the n^3 classes
+        return "\n".join(lines + gemm_shapes(trace)) + "\n"
     durs = class_durations(trace, class_patterns(n))
-    fig = bench_figures(bench_line) if bench_line else {}
+    fig = bench_figures(bench_line)
     lines += [f"Timed kernel classes: average over the dispatches that did work (gated dispatches, shorter "
               f"than {GATE_US:g} us, left out and counted apart), beside bench.py's HIP-event figure for the class:", "",
               "| kernel class | rocprofv3 avg us (launches) | median us | gated | bench.py avg us (launches, where) | "
@@ -86,7 +90,33 @@ def render(prof_dir, bench_line, n, title, command, top=20):
         diff = f"{100.0 * (avg - b[0]) / b[0]:+.1f}%" if b else ""
         lines.append(f"| {name} | {avg:.2f} ({len(work)}) | {statistics.median(work):.2f} | {gated} | {bs} | {diff} |")
     lines.append("")
-    return "\n".join(lines)
+    lines += gemm_shapes(trace)
+    return "\n".join(lines) + "\n"
+
+
+def gemm_shapes(trace):
+    """The Chebyshev contractions (k_gemm) by launch shape: one 16 x 16 tile
+    of C per block, so the grid gives M (rows, 16 per block row) and N."""
+    groups = {}
+    for r in trace:
+        name = r["Kernel_Name"]
+        if "k_gemm" not in name:
+            continue
+        key = (name.split("(")[0], int(r["Grid_Size_X"]) // int(r["Workgroup_Size_X"]), int(r["Grid_Size_Y"]))
+        groups.setdefault(key, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    if not groups:
+        return []
+    out = ["Chebyshev contractions (k_gemm) by launch shape: durations of the dispatches that did work "
+           "(gated ones, shorter than 3 us, left out), percentiles in us:", "",
+           "| kernel | column tiles x row tiles | launches | p10 | p25 | p50 | p75 | p90 |", "|---|---:|---:|---:|---:|---:|---:|---:|"]
+    for (name, nx, ny), d in sorted(groups.items()):
+        w = sorted(x for x in d if x >= 3.0)
+        if not w:
+            continue
+        q = [w[min(len(w) - 1, int(f * len(w)))] for f in (0.10, 0.25, 0.50, 0.75, 0.90)]
+        out.append(f"| `{name}` | {nx} x {ny} | {len(w)} | " + " | ".join(f"{x:.2f}" for x in q) + " |")
+    out.append("")
+    return out
 
 
 def main(argv):
