@@ -182,7 +182,7 @@ def traffic_from_profiles(best_name, fname="traffic_counters.json"):
 # kernel sources of the 3D solves' passes and Krylov vector kernels: the
 # stored counter readings are used only while these are unchanged
 KERNEL_SOURCES_3D = ("fft_core.hpp", "passes.hip", "passes.hpp", "spectral.hpp", "vd_common.hpp", "vecops.hip",
-                     "vecops.hpp")
+                     "vecops.hpp", "vdsolve.cpp")  # the last decides which systems share a launch
 
 
 def csrc_hash():

@@ -415,10 +415,11 @@ vd_status vd_ns_profile_read(vd_ns* h, double* ms, long long* count, double* byt
  * slot on its own stream, with their Krylov state resident on the device.
  * Pressure requests that can share launches (GMRES, direct form, Fourier
  * grids of two or three dimensions) are batched: when a slot takes such a
- * request, up to two later queued requests of the same shape and options
- * (no history) join it if grids for them fit without releasing others, and
- * the slot solves them together (vd_solve_pressure_batch; each still on its
- * own grid, charged as before).  A result does not depend on what else is
+ * request while more requests wait than slots are free, up to two later
+ * queued requests of the same shape and options (no history) join it if
+ * grids for them fit without releasing others, and the slot solves them
+ * together (vd_solve_pressure_batch; each still on its own grid, charged as
+ * before).  A result does not depend on what else is
  * running or on its batch (fixed launch configurations and reduction
  * orders).
  * ---------------------------------------------------------------------- */

@@ -164,10 +164,12 @@ bool same_batch(const vd_request& a, const vd_request& b) {
 }
 
 // Admit queued jobs in FIFO order while they fit.  Caller holds the lock.
-// The head of the queue is admitted first; when it can share launches, up to
-// max_batch - 1 later requests of the same shape and options that find a
-// grid without evicting join its batch (they overtake requests of other
-// shapes, which wait for the next free slot as before).
+// The head of the queue is admitted first.  When more requests wait than
+// slots are free and the head can share launches, up to max_batch - 1 later
+// requests of the same shape and options that find a grid without evicting
+// join its batch (they overtake requests of other shapes, which wait for the
+// next free slot as before).  While slots are free for every waiting
+// request, each gets its own: a batch finishes with its slowest member.
 void admit(vd_server* S) {
   while (!S->queue.empty()) {
     Job& job = S->queue.front();
@@ -185,7 +187,9 @@ void admit(vd_server* S) {
     a.ge[0] = ge;
     a.t_start = S->now();
     S->queue.pop_front();
-    if (batchable(a.job[0].req)) {
+    int free_slots = 0;
+    for (int i = 0; i < S->max_slots; ++i) free_slots += S->slots[i].has ? 0 : 1;
+    if (batchable(a.job[0].req) && S->queue.size() > (size_t)free_slots) {
       for (size_t q = 0; q < S->queue.size() && a.nj < S->max_batch;) {
         Job& cand = S->queue[q];
         if (!same_batch(cand.req, a.job[0].req)) { ++q; continue; }

@@ -669,7 +669,9 @@ DevState* sys_slots(vd_grid* G, int k) { return k ? G->hslotx[k] : G->hslot; }
 // (measured, 3-component solves at 256^3, rj = 3: FP64 48.1 ms with the
 // passes applied one system after another, 49.3 ms batched; FP32+refine
 // 24.2 ms either way).  The Gram-Schmidt kernels always take all the
-// systems (one launch per system measured the same, within 0.2%).
+// systems: one launch per system measured the same within 0.2%, and each
+// system's operator followed at once by its own Gram-Schmidt (its dot pass
+// starting on the field just written) 0.3-0.7% slower.
 constexpr double kBatchOpBytes = 200.0 * (1 << 20);
 
 // The systems of a lockstep solve.  System k lives in grid gs[k]: its

@@ -106,6 +106,22 @@ def test_same_shape_requests_share_a_slot():
     srv.close()
 
 
+def test_free_slots_take_requests_alone():
+    """While a slot is free for every waiting request, none is batched (a
+    batch finishes with its slowest member); once requests outnumber the
+    free slots, same-shape requests share a slot."""
+    srv = api.Server(hbm_budget=1 << 40, max_slots=4, dry_seconds=0.1)
+    first = [srv.submit((128, 128)) for _ in range(4)]      # four free slots: four runs of one
+    later = [srv.submit((128, 128)) for _ in range(6)]      # all slots busy: these queue and batch
+    res = _drain(srv, 10)
+    groups = _batches(res)
+    by_ticket = {r["ticket"]: g for g in groups for r in g}
+    assert all(len(by_ticket[t]) == 1 for t in first)
+    assert len({by_ticket[t][0]["slot"] for t in first}) == 4
+    assert max(len(by_ticket[t]) for t in later) == 3
+    srv.close()
+
+
 def test_batches_group_only_what_can_share_launches():
     """Only pressure GMRES requests of one shape and options share a batch:
     another shape, another solver, a velocity request or a 1D grid each wait
