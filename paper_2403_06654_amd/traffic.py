@@ -5,6 +5,7 @@ profiles/traffic_counters.json (256^3) or profiles/traffic_counters_c5.json
 (512^3) for bench.py's roofline.
 
     python -m paper_2403_06654_amd.traffic FETCH_DIR WRITE_DIR [512]
+    python -m paper_2403_06654_amd.traffic --md COUNTERS_JSON BENCH_JSON OUT.md TITLE COMMAND...
 
 Calibration: the first device copy of the run moves exactly 1 GiB each way;
 the ratio of that to what each counter reports for it scales every other
@@ -93,5 +94,53 @@ def main(fetch_dir, write_dir, n=256):
     print(json.dumps(out, indent=1))
 
 
+# fields each pass moves (F = one half-spectrum field of the grid's precision)
+PASS_FIELDS = {"pressure z-first (k_col COL_P_FIRST)": 3, "pressure y-inverse (k_col COL_P_MIDINV)": 5,
+               "pressure x pass (k_row ROW_P)": 7, "pressure y-forward (k_col COL_P_MIDFWD)": 5,
+               "pressure z-last (k_col COL_P_LAST)": 3, "helmholtz z-first (k_col COL_H_FIRST)": 2,
+               "y inverse FFT, one field (k_col COL_FFT_INV)": 2, "helmholtz x pass (k_row ROW_H)": 3,
+               "y forward FFT, one field (k_col COL_FFT_FWD)": 2, "helmholtz z-last (k_col COL_H_LAST)": 3}
+
+
+def markdown(t, bench_line, commands, title):
+    """profiles/ summary of a counter summary t (the JSON main writes) beside
+    the algorithmic bytes per launch: the roofline kernel's from the bench
+    line, every pass's from its field count."""
+    n = t["grid"]
+    F = n * n * (n // 2) * 16
+    alg = {}
+    rf = (bench_line or {}).get("roofline") or {}
+    if rf.get("kernel"):
+        alg[rf["kernel"]] = rf["bytes_per_launch"]
+    lines = [f"# {title}", "", "Commands (repository root, one MI355X), one counter per pass:", "", "```"]
+    lines += commands + ["```", "",
+                         f"Calibration (1 GiB device copy): fetched bytes scaled by "
+                         f"{t['calibration']['fetch_factor']:.4f}, written bytes by {t['calibration']['write_factor']:.3f}. "
+                         f"F = one FP64 half-spectrum field = {F:,} B (FP32: F/2).", "",
+                         "| kernel class | fields moved | algorithmic bytes / launch | calibrated FETCH+WRITE / launch | "
+                         "ratio | launches | gated, left out |", "|---|---:|---:|---:|---:|---:|---:|"]
+    for name, v in t["per_launch_bytes"].items():
+        base = name[5:] if name.startswith("fp32 ") else name
+        a, fl = alg.get(name), "(nv+2)F per system" if "update" in name else "(nv+1)F per system"
+        if base in PASS_FIELDS:
+            k = PASS_FIELDS[base]
+            a = k * F // (2 if name.startswith("fp32 ") else 1)
+            fl = f"{k}F" + ("/2" if name.startswith("fp32 ") else "")
+        ratio = f"{v / a:.4f}" if a else "n/a"
+        lines.append(f"| {name} | {fl} | {f'{a:,}' if a else 'n/a'} | {v:,} | {ratio} | {t['launches'][name]} | "
+                     f"{t.get('gated_dispatches_left_out', {}).get(name, 0)} |")
+    lines += ["", f"Kernel-source hash `{t['csrc_sha256_16']}`: bench.py reports `roofline.traffic` from the JSON beside "
+              "this file only while the sources match.", ""]
+    return "\n".join(lines)
+
+
 if __name__ == "__main__":
-    main(sys.argv[1], sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 256)
+    if "--md" in sys.argv:
+        # python -m paper_2403_06654_amd.traffic --md COUNTERS_JSON BENCH_JSON OUT.md TITLE COMMAND...
+        i = sys.argv.index("--md")
+        cj, bj, out, title = sys.argv[i + 1:i + 5]
+        bench = json.loads(open(bj).read().strip().splitlines()[-1]) if bj != "-" else None
+        open(out, "w").write(markdown(json.load(open(cj)), bench, sys.argv[i + 5:], title))
+        print(out)
+    else:
+        main(sys.argv[1], sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 256)
