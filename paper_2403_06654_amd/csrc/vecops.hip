@@ -872,25 +872,47 @@ __global__ __launch_bounds__(256) void k_density(const double* __restrict__ rho,
     p[3] = ((sh[0][3] + sh[1][3]) + sh[2][3]) + sh[3][3];
   }
 }
-__global__ void k_density_fin(const double* __restrict__ partial, int nblk, double* out) {
-  if (threadIdx.x) return;
+// One thread per block partial, then fixed shuffle and LDS trees (a single
+// thread walking the 1024 partials took 233 us, one dependent load after
+// another).
+__global__ __launch_bounds__(1024) void k_density_fin(const double* __restrict__ partial, int nblk, double* out) {
+  __shared__ double sh[4][16];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   double sum = 0.0, mn = INFINITY, mx = -INFINITY, bad = 0.0;
-  for (int b = 0; b < nblk; ++b) {
+  for (int b = threadIdx.x; b < nblk; b += 1024) {
     const double* p = partial + (size_t)b * kRedStride;
     sum += p[0];
     mn = fmin(mn, p[1]);
     mx = fmax(mx, p[2]);
     bad += p[3];
   }
-  out[0] = sum;
-  out[1] = mn;
-  out[2] = mx;
-  out[3] = bad;
+  sum = wave_sum(sum);
+  bad = wave_sum(bad);
+  mn = -wave_max(-mn);
+  mx = wave_max(mx);
+  if (lane == 0) {
+    sh[0][w] = sum;
+    sh[1][w] = mn;
+    sh[2][w] = mx;
+    sh[3][w] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x) return;
+  for (int i = 1; i < 16; ++i) {
+    sh[0][0] += sh[0][i];
+    sh[1][0] = fmin(sh[1][0], sh[1][i]);
+    sh[2][0] = fmax(sh[2][0], sh[2][i]);
+    sh[3][0] += sh[3][i];
+  }
+  out[0] = sh[0][0];
+  out[1] = sh[1][0];
+  out[2] = sh[2][0];
+  out[3] = sh[3][0];
 }
 void density_setup(const double* rho, size_t n, double* a64, float* a32, float* rho32, double* partial, double* out,
                    hipStream_t s) {
   hipLaunchKernelGGL(k_density, dim3(nblk(n)), dim3(256), 0, s, rho, n, a64, a32, rho32, partial);
-  hipLaunchKernelGGL(k_density_fin, dim3(1), dim3(64), 0, s, partial, nblk(n), out);
+  hipLaunchKernelGGL(k_density_fin, dim3(1), dim3(1024), 0, s, partial, nblk(n), out);
 }
 
 // ----------------------------------------------- modified pressure form

@@ -64,7 +64,8 @@ def bench_figures(line):
 
 def render(prof_dir, bench_line, n, title, command, top=20):
     stats = _csv(prof_dir, "kernel_stats.csv")
-    trace = _csv(prof_dir, "kernel_trace.csv")
+    # the per-dispatch trace (large) may be left out of a run: then totals only
+    trace = _csv(prof_dir, "kernel_trace.csv") if glob.glob(os.path.join(prof_dir, "*kernel_trace.csv")) else []
     total_ms = sum(float(r["TotalDurationNs"]) for r in stats) / 1e6
     lines = [f"# {title}", "", "Command (repository root, one MI355X):", "", "```", command, "```", "",
              f"Per-kernel totals from rocprofv3 `--stats`, top {top} by time:", "",
