@@ -79,3 +79,47 @@ def test_alone_vs_mix_bitwise_and_oracle_checked():
         assert rr <= 1.01e-10, (i, n, prec, solver, rr)
         seen.add((n, prec))
     assert seen >= {(n, p) for n in SIZES for p in ("fp64", "fp32_refine")}
+
+
+def test_velocity_requests_served():
+    """Three-component velocity requests (ρu − δtν∇²u = g) through the
+    server, several at once on shared slots: each result equals its solve on
+    a grid of its own, and each component passes the oracle's residual."""
+    from paper_2403_06654_amd.api import Grid, Server
+    import torch
+    from tests.gpu_util import smooth_density
+    shape, nu = (32, 32, 32), 1e-3
+    reqs = []
+    for k in range(4):
+        rho = smooth_density(shape, 60 + k, 0.5, 4.0 + k)
+        g = np.stack([workloads.band_limited(shape, 6, seed=70 + 3 * k + c, keep_mean=True) for c in range(3)])
+        reqs.append((rho, g))
+    dev = [(to_dev(r), to_dev(g)) for r, g in reqs]
+    xs = [torch.zeros_like(gd) for _, gd in dev]
+    torch.cuda.synchronize()
+    srv = Server(hbm_budget=8 << 30, max_slots=2)
+    for i, (rd, gd) in enumerate(dev):
+        srv.submit(shape, rho=rd, f=gd, x=xs[i], kind="helmholtz", dt_nu=nu, ncomp=3, user_tag=i)
+    got = {}
+    while len(got) < len(dev):
+        for r in srv.wait(timeout=60.0):
+            got[r["user_tag"]] = r
+    st = srv.stats()
+    srv.close()
+    assert st["hbm_peak"] <= 2 * api_workspace_helmholtz(shape)
+    for i, (rho, g) in enumerate(reqs):
+        assert got[i]["status"] == 0
+        grid = Grid(shape)
+        grid.set_density(to_dev(rho))
+        u, info = grid.solve_helmholtz(to_dev(g), nu)
+        grid.close()
+        assert info["iterations"] == got[i]["iterations"]
+        assert np.array_equal(to_host(u), to_host(xs[i])), i
+        served = to_host(xs[i])
+        for c in range(3):
+            assert rel2(operators.apply_helmholtz(served[c], rho, nu), g[c]) <= 1.01e-10, (i, c)
+
+
+def api_workspace_helmholtz(shape):
+    from paper_2403_06654_amd import api
+    return api.workspace_bytes(shape, helmholtz_ncomp=3)
