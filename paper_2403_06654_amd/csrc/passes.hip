@@ -360,6 +360,22 @@ constexpr bool row_field_waves() { return MODE == ROW_P; }
 template <int MODE>
 constexpr int row_waves() { return row_field_waves<MODE>() ? 3 : 4; }
 
+// Row passes that loop over row groups in a grid capped at kRowGridCap
+// blocks.  In the loop the compiler keeps each thread's twiddle factors
+// (they depend only on its lane) in registers across rows instead of reading
+// them from LDS for every row, at the price of 40-60 more VGPRs.  Measured per
+// kernel against one row group per block: the FP64 pressure x pass on
+// 256-point rows (512^3 grid) 1733 -> 1628 us at two waves per SIMD instead
+// of three, the Helmholtz x pass on 128-point rows 72.0 -> 69.4 us (FP64) and
+// 40.0 -> 38.8 us (FP32).  Elsewhere the lost occupancy costs more (the FP64
+// pressure x pass on 128-point rows 205 -> 249 us).  Blocks that loop
+// without keeping the twiddles are slower still: many short blocks overlap
+// their load, transform and store phases better than a few long ones.
+template <int L, typename R, int MODE>
+constexpr bool row_loop() {
+  return (MODE == ROW_P && L == 256 && sizeof(R) == 8) || (MODE == ROW_H && L == 128);
+}
+
 template <int L, typename R, int MODE>
 __global__ __launch_bounds__(64 * row_waves<MODE>()) void k_row(RowArgs a, const C2<R>* __restrict__ twtab) {
   using Cf = RowCfg<L, R>;
@@ -408,15 +424,15 @@ __global__ __launch_bounds__(64 * row_waves<MODE>()) void k_row(RowArgs a, const
   const int fsel = FW ? wave : 0;
   const int t = lane % T;
   const int rr = (FW ? 0 : wave * RW) + lane / T;  // row within the block
-  // The x passes sweep the rows last block first: the pass before them (a
+  // The x passes sweep the rows last group first: the pass before them (a
   // y pass, ascending z) leaves its most recent output in the 256 MB
   // Infinity Cache, and the y pass after them (ascending z again) starts on
   // what this pass wrote last.  At 256^3 FP64 the three pressure fields
   // (384 MiB) exceed that cache; the reversed sweep takes the x pass from
   // 218 to 199 us and the following y pass from 130 to 114 us.
-  const int bx = (MODE == ROW_P || MODE == ROW_H) ? (int)(gridDim.x - 1 - blockIdx.x) : (int)blockIdx.x;
-  const int row = bx * RB + rr;
-  const bool ok = row < a.nrows;
+  const int ngroups = (a.nrows + RB - 1) / RB;
+  int row = 0;
+  bool ok = false;
   LdsRow<R> lds{lds_all + (FW ? fsel * RW + rr : rr) * LP};
   const R sx = R(a.g.sx);
   C2<R> reg[E];
@@ -510,6 +526,11 @@ __global__ __launch_bounds__(64 * row_waves<MODE>()) void k_row(RowArgs a, const
     }
   };
 
+  // row groups: one per block, or a loop over them (row_loop)
+  for (int grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+  const int bx = (MODE == ROW_P || MODE == ROW_H) ? ngroups - 1 - grp : grp;
+  row = bx * RB + rr;
+  ok = row < a.nrows;
   if constexpr (MODE == ROW_R2C) {
     const C2<R>* src = (const C2<R>*)IN(0);  // real row viewed as complex pairs
 #pragma unroll
@@ -560,6 +581,8 @@ __global__ __launch_bounds__(64 * row_waves<MODE>()) void k_row(RowArgs a, const
     }
     fft_line<L, E, -1, true, WV>(reg, lds, tw, t);
     forward_post(f, (C2<R>*)OUT(f), (const C2<R>*)IN(0));
+  }
+  if constexpr (!row_loop<L, R, MODE>()) break;  // no back edge: nothing is hoisted
   }
 }
 
@@ -658,6 +681,9 @@ static void launch_col(int L, const ColArgs& a, const void* tw, hipStream_t st) 
   }
 }
 
+// Blocks of a looping row pass (eight per CU on 256 CUs), per system.
+constexpr int kRowGridCap = 2048;
+
 template <typename R, int MODE, int L>
 static void launch_row_L(const RowArgs& a0, const void* tw, hipStream_t st) {
   constexpr int RW = RowCfg<L, R>::RW;
@@ -669,7 +695,8 @@ static void launch_row_L(const RowArgs& a0, const void* tw, hipStream_t st) {
     ny = a.nb;
   }
   const int rb = row_field_waves<MODE>() ? RW : row_waves<MODE>() * RW;
-  dim3 grid((a.nrows + rb - 1) / rb, ny);
+  const int ngroups = (a.nrows + rb - 1) / rb;
+  dim3 grid(row_loop<L, R, MODE>() && ngroups > kRowGridCap ? kRowGridCap : ngroups, ny);
   // ROW_P: one wavefront per field (<= 3)
   const int waves = row_field_waves<MODE>() ? a.nf : row_waves<MODE>();
   hipLaunchKernelGGL((k_row<L, R, MODE>), grid, dim3(64 * waves), 0, st, a, (const C2<R>*)tw);
