@@ -528,61 +528,61 @@ __global__ __launch_bounds__(64 * row_waves<MODE>()) void k_row(RowArgs a, const
 
   // row groups: one per block, or a loop over them (row_loop)
   for (int grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
-  const int bx = (MODE == ROW_P || MODE == ROW_H) ? ngroups - 1 - grp : grp;
-  row = bx * RB + rr;
-  ok = row < a.nrows;
-  if constexpr (MODE == ROW_R2C) {
-    const C2<R>* src = (const C2<R>*)IN(0);  // real row viewed as complex pairs
-#pragma unroll
-    for (int s = 0; s < E; ++s) {
-      int m = pat_index<L, E, RF0>(t, s);
-      reg[s] = ok ? ldg(src + (size_t)row * L + m) : C2<R>{R(0), R(0)};
-    }
-    fft_line<L, E, -1, true, WV>(reg, lds, tw, t);
-    forward_post(0, (C2<R>*)OUT(0), nullptr);
-  } else if constexpr (MODE == ROW_C2R) {
-    inverse_row((const C2<R>*)IN(0), 0);
-    const R cs = R(a.cscale);
-    C2<R>* dst = (C2<R>*)OUT(0);
-    if (ok) {
+    const int bx = (MODE == ROW_P || MODE == ROW_H) ? ngroups - 1 - grp : grp;
+    row = bx * RB + rr;
+    ok = row < a.nrows;
+    if constexpr (MODE == ROW_R2C) {
+      const C2<R>* src = (const C2<R>*)IN(0);  // real row viewed as complex pairs
 #pragma unroll
       for (int s = 0; s < E; ++s) {
-        int m = pat_index<L, E, RI1>(t, s);
-        stg(dst + (size_t)row * L + m, cscale(reg[s], cs));
+        int m = pat_index<L, E, RF0>(t, s);
+        reg[s] = ok ? ldg(src + (size_t)row * L + m) : C2<R>{R(0), R(0)};
       }
-    }
-  } else {
-    const C2<R>* coef = (const C2<R>*)coefp;
-    const R cs = R(a.cscale);
-    const int f = fsel;
-    // pressure x pass: issue the coefficient row's loads before the inverse
-    // transform so that their latency hides behind it (measured: 215 -> 204
-    // us at 256^3 FP64; the single-field Helmholtz pass is faster without)
-    constexpr bool PREFETCH = MODE == ROW_P;
-    C2<R> qv[PREFETCH ? E : 1];
-    if constexpr (PREFETCH) {
+      fft_line<L, E, -1, true, WV>(reg, lds, tw, t);
+      forward_post(0, (C2<R>*)OUT(0), nullptr);
+    } else if constexpr (MODE == ROW_C2R) {
+      inverse_row((const C2<R>*)IN(0), 0);
+      const R cs = R(a.cscale);
+      C2<R>* dst = (C2<R>*)OUT(0);
+      if (ok) {
 #pragma unroll
-      for (int s = 0; s < E; ++s) {
-        int m = pat_index<L, E, RI1>(t, s);
-        qv[s] = ok ? ldg(coef + (size_t)row * L + m) : C2<R>{R(0), R(0)};
+        for (int s = 0; s < E; ++s) {
+          int m = pat_index<L, E, RI1>(t, s);
+          stg(dst + (size_t)row * L + m, cscale(reg[s], cs));
+        }
       }
-    }
-    inverse_row((const C2<R>*)IN(f), f);
-#pragma unroll
-    for (int s = 0; s < E; ++s) {
-      C2<R> q;
+    } else {
+      const C2<R>* coef = (const C2<R>*)coefp;
+      const R cs = R(a.cscale);
+      const int f = fsel;
+      // pressure x pass: issue the coefficient row's loads before the inverse
+      // transform so that their latency hides behind it (measured: 215 -> 204
+      // us at 256^3 FP64; the single-field Helmholtz pass is faster without)
+      constexpr bool PREFETCH = MODE == ROW_P;
+      C2<R> qv[PREFETCH ? E : 1];
       if constexpr (PREFETCH) {
-        q = qv[s];
-      } else {
-        int m = pat_index<L, E, RI1>(t, s);
-        q = ok ? ldg(coef + (size_t)row * L + m) : C2<R>{R(0), R(0)};
+#pragma unroll
+        for (int s = 0; s < E; ++s) {
+          int m = pat_index<L, E, RI1>(t, s);
+          qv[s] = ok ? ldg(coef + (size_t)row * L + m) : C2<R>{R(0), R(0)};
+        }
       }
-      reg[s] = C2<R>{reg[s].x * (q.x * cs), reg[s].y * (q.y * cs)};
+      inverse_row((const C2<R>*)IN(f), f);
+#pragma unroll
+      for (int s = 0; s < E; ++s) {
+        C2<R> q;
+        if constexpr (PREFETCH) {
+          q = qv[s];
+        } else {
+          int m = pat_index<L, E, RI1>(t, s);
+          q = ok ? ldg(coef + (size_t)row * L + m) : C2<R>{R(0), R(0)};
+        }
+        reg[s] = C2<R>{reg[s].x * (q.x * cs), reg[s].y * (q.y * cs)};
+      }
+      fft_line<L, E, -1, true, WV>(reg, lds, tw, t);
+      forward_post(f, (C2<R>*)OUT(f), (const C2<R>*)IN(0));
     }
-    fft_line<L, E, -1, true, WV>(reg, lds, tw, t);
-    forward_post(f, (C2<R>*)OUT(f), (const C2<R>*)IN(0));
-  }
-  if constexpr (!row_loop<L, R, MODE>()) break;  // no back edge: nothing is hoisted
+    if constexpr (!row_loop<L, R, MODE>()) break;  // no back edge: nothing is hoisted
   }
 }
 
