@@ -36,7 +36,10 @@
  *     used by two threads at once; different handles are independent.
  *   - Status codes: VD_OK = 0; VD_NOT_CONVERGED = 1 is a warning (the best
  *     iterate is written and info is filled); negative codes are errors and
- *     leave outputs unspecified.  No C++ exception crosses this interface.
+ *     leave outputs unspecified, except that the info of vd_solve_pressure,
+ *     vd_solve_helmholtz and vd_solve_pressure_batch, when given, carries
+ *     the status (also for arguments rejected before any work).  No C++
+ *     exception crosses this interface.
  */
 #ifndef VDSOLVE_H
 #define VDSOLVE_H

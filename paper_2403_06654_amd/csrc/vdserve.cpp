@@ -350,6 +350,9 @@ vd_status vd_server_submit(vd_server* S, const vd_request* r, unsigned long long
   if (!S || !r) return VD_EINVAL;
   if (!S->dry && (!r->rho || !r->f || !r->x)) return VD_EINVAL;
   if (r->kind != VD_OP_PRESSURE && r->kind != VD_OP_HELMHOLTZ) return VD_EINVAL;
+  // options the solve would reject are rejected here, before queuing
+  if (!std::isnan(r->opts.rho0) && !(r->opts.rho0 > 0.0)) return VD_EINVAL;
+  if (r->kind == VD_OP_HELMHOLTZ && (!(r->dt_nu >= 0.0) || !std::isfinite(r->dt_nu))) return VD_EINVAL;
   size_t bytes = r->kind == VD_OP_HELMHOLTZ
                      ? vd_workspace_bytes_helmholtz(&r->desc, &r->opts, r->ncomp > 0 ? r->ncomp : 1)
                      : vd_workspace_bytes(&r->desc, &r->opts);

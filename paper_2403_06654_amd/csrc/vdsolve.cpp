@@ -1586,10 +1586,20 @@ static vd_status solve_impl(vd_grid* G, void* c) {
   return worst;
 }
 
+// A call rejected before it starts still reports its status in info (the
+// batch entry and the server read each request's status from there).
+static vd_status reject(vd_solve_info* info, vd_status s) {
+  if (info) {
+    *info = vd_solve_info{};
+    info->status = s;
+  }
+  return s;
+}
+
 static vd_status solve_common(vd_grid* G, int kind, double nu, int ncomp, const double* f, double* x,
                               const vd_solve_opts* opts, vd_solve_info* info) {
-  if (!G || !f || !x || ncomp < 1) return VD_EINVAL;
-  if (!G->has_rho) return VD_EINVAL;
+  if (!G || !f || !x || ncomp < 1) return reject(info, VD_EINVAL);
+  if (!G->has_rho) return reject(info, VD_EINVAL);
   SolveCtx c{};
   c.kind = kind;
   c.nu = nu;
@@ -1598,9 +1608,9 @@ static vd_status solve_common(vd_grid* G, int kind, double nu, int ncomp, const 
   c.x = x;
   if (opts) c.o = *opts;
   else vd_default_opts(&c.o);
-  if (!opts_ok(c.o)) return VD_EINVAL;
-  if (!std::isnan(c.o.rho0) && !(c.o.rho0 > 0.0)) return VD_EINVAL;
-  if (c.o.formulation == VD_FORM_K && G->g.cheb) return VD_ENOTSUP;
+  if (!opts_ok(c.o)) return reject(info, VD_EINVAL);
+  if (!std::isnan(c.o.rho0) && !(c.o.rho0 > 0.0)) return reject(info, VD_EINVAL);
+  if (c.o.formulation == VD_FORM_K && G->g.cheb) return reject(info, VD_ENOTSUP);
   vd_status s = guard(G, solve_impl, &c);
   c.info.status = s;
   if (info) *info = c.info;
@@ -1742,8 +1752,8 @@ vd_status vd_solve_pressure_batch(vd_grid* const* grids, int n, const double* co
 
 vd_status vd_solve_helmholtz(vd_grid* G, double dt_nu, int ncomp, const double* g, double* u,
                              const vd_solve_opts* opts, vd_solve_info* info) {
-  if (!(dt_nu >= 0.0) || !std::isfinite(dt_nu)) return VD_EINVAL;
-  if (G && G->g.cheb) return VD_ENOTSUP;
+  if (!(dt_nu >= 0.0) || !std::isfinite(dt_nu)) return reject(info, VD_EINVAL);
+  if (G && G->g.cheb) return reject(info, VD_ENOTSUP);
   return solve_common(G, VD_OP_HELMHOLTZ, dt_nu, ncomp, g, u, opts, info);
 }
 

@@ -153,6 +153,39 @@ def test_invalid_batches():
         g.close()
 
 
+def test_rejected_solves_report_their_status():
+    """Arguments rejected before any work still set every info's status:
+    through the batch entry, whose grids then run one by one, and through
+    the single-grid solves (the server reads each request's status there)."""
+    import ctypes
+    from paper_2403_06654_amd.api import lib, make_opts, vd_solve_info, _P
+    gs, fs, _ = _grids((32, 32), 2)
+    fd = [to_dev(f) for f in fs]
+    ps = [to_dev(np.zeros_like(f)) for f in fs]
+    o = make_opts(rho0=-1.0)
+    infos = (vd_solve_info * 2)()
+    for k in range(2):
+        infos[k].status, infos[k].iterations = 99, 77     # junk that must be overwritten
+    hs = (_P * 2)(*[g._h.value for g in gs])
+    fp = (_P * 2)(*[f.data_ptr() for f in fd])
+    pp = (_P * 2)(*[p.data_ptr() for p in ps])
+    st = lib().vd_solve_pressure_batch(hs, 2, fp, pp, ctypes.byref(o), infos)
+    assert st == -1
+    assert [infos[k].status for k in range(2)] == [-1, -1]
+    assert [infos[k].iterations for k in range(2)] == [0, 0]
+    one = vd_solve_info()
+    one.status = 99
+    st = lib().vd_solve_pressure(gs[0]._h, _P(fd[0].data_ptr()), _P(ps[0].data_ptr()), ctypes.byref(o),
+                                 ctypes.byref(one))
+    assert st == -1 and one.status == -1
+    one.status = 99
+    st = lib().vd_solve_helmholtz(gs[0]._h, ctypes.c_double(-1.0), 1, _P(fd[0].data_ptr()),
+                                  _P(ps[0].data_ptr()), None, ctypes.byref(one))
+    assert st == -1 and one.status == -1
+    for g in gs:
+        g.close()
+
+
 def test_server_batches_queued_requests():
     """Nine requests of one shape queued at once on one slot are served in
     batches; each result equals its solve alone (one slot, no batching)."""

@@ -181,6 +181,15 @@ def test_invalid_requests():
         srv.submit((100, 100))
     with pytest.raises(api.VdError):
         srv.submit((128, 128), restart=99)
+    # options a solve would reject are rejected at submit, not after queuing
+    # (a shared batch would otherwise fall back to solves that never start)
+    for bad in (dict(rho0=-1.0), dict(rho0=0.0), dict(kind="helmholtz", dt_nu=-1e-3),
+                dict(kind="helmholtz", dt_nu=float("inf"))):
+        with pytest.raises(api.VdError) as e:
+            srv.submit((128, 128), **bad)
+        assert e.value.status == -1, bad
+    srv.submit((128, 128), rho0=2.0)                  # a valid constant is accepted
+    assert len(_drain(srv, 1)) == 1
     srv.close()
     with pytest.raises(api.VdError):
         api.Server(hbm_budget=0, max_slots=1, dry_seconds=0.0)
