@@ -186,6 +186,36 @@ def test_rejected_solves_report_their_status():
         g.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_breakdown_of_one_grid_leaves_the_others_alone(precision):
+    """A non-finite right-hand side on one grid of a batch ends that grid's
+    solve with VD_EBREAKDOWN; the other grids share the same launches and
+    still return exactly their solves alone."""
+    import ctypes
+    from paper_2403_06654_amd.api import lib, make_opts, vd_solve_info, _P
+    shape = (64, 64)
+    gs, fs, _ = _grids(shape, 3)
+    bad = fs[1].copy()
+    bad[5, 7] = np.nan
+    fd = [to_dev(fs[0]), to_dev(bad), to_dev(workloads.band_limited(shape, 8, seed=81))]
+    ps = [to_dev(np.zeros(shape)) for _ in range(3)]
+    o = make_opts(precision=precision)
+    infos = (vd_solve_info * 3)()
+    hs = (_P * 3)(*[g._h.value for g in gs])
+    fp = (_P * 3)(*[f.data_ptr() for f in fd])
+    pp = (_P * 3)(*[p.data_ptr() for p in ps])
+    st = lib().vd_solve_pressure_batch(hs, 3, fp, pp, ctypes.byref(o), infos)
+    print(precision, st, [infos[k].status for k in range(3)], [infos[k].iterations for k in range(3)], flush=True)
+    assert st == -4 and infos[1].status == -4                  # VD_EBREAKDOWN
+    for k in (0, 2):
+        assert infos[k].status == 0 and infos[k].iterations > 0
+        pa, ia = gs[k].solve_pressure(fd[k], precision=precision)
+        assert np.array_equal(to_host(ps[k]), to_host(pa)), k
+        assert ia["iterations"] == infos[k].iterations and ia["rel_residual"] == infos[k].rel_residual
+    for g in gs:
+        g.close()
+
+
 def test_server_batches_queued_requests():
     """Nine requests of one shape queued at once on one slot are served in
     batches; each result equals its solve alone (one slot, no batching)."""
