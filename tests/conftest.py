@@ -14,7 +14,7 @@ def pytest_configure(config):
 
 def pytest_collection_modifyitems(config, items):
     # GPU tests cannot run without a device; skip them loudly instead of failing
-    # on a CPU-only machine.  On a GPU machine they run and must pass.
+    # on a CPU-only machine.  On a machine with the GPU they run and must pass.
     try:
         import torch
         has_gpu = torch.cuda.is_available()
