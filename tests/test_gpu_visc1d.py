@@ -164,6 +164,29 @@ def test_ragged_groups_restarts_and_mixed_outcomes():
     h.close()
 
 
+def test_results_of_batches_beyond_one_readback_chunk():
+    """More systems than the host staging buffer holds (16384): the per-system
+    iteration counts, residuals and fields of both chunks are those of the
+    same systems solved in small batches of their own."""
+    from paper_2403_06654_amd.api import Visc1d
+    n, a, nb = 33, 1e-2, 16384 + 100
+    ratios = [1.5, 3.0, 10.0, 2.0, 6.0, 8.0, 4.0]
+    _, base, _ = _case("cheb", n, ratios, a)
+    rho = base[np.arange(nb) % len(ratios)]
+    b = np.random.default_rng(17).standard_normal((nb, n))
+    h = Visc1d("cheb", n, a)
+    u, it, rr, info = h.solve(to_dev(rho), to_dev(b), solver="rmr", max_iter=2000)
+    print(info, sorted(set(int(v) for v in it[:len(ratios)])), flush=True)
+    assert info["status"] == 0 and len(set(int(v) for v in it[:len(ratios)])) > 2
+    u = to_host(u)
+    for lo in (0, 16384 - 50, nb - 100):          # the first chunk, across the boundary, the second chunk
+        hi = min(lo + 100, nb)
+        u1, it1, rr1, _ = h.solve(to_dev(rho[lo:hi]), to_dev(b[lo:hi]), solver="rmr", max_iter=2000)
+        assert np.array_equal(to_host(u1), u[lo:hi]), lo
+        assert np.array_equal(it1, it[lo:hi]) and np.array_equal(rr1, rr[lo:hi]), lo
+    h.close()
+
+
 @pytest.mark.parametrize("basis,n", [("cheb", 512), ("fourier", 512)])
 def test_largest_systems_solve(basis, n):
     """512 points (the kernel instantiations built apart, which spill)."""
